@@ -1,0 +1,698 @@
+/*
+ * oracle.c -- plain FP64 CPU oracle of the coupled lattice-Boltzmann / immersed-moving-boundary /
+ * discrete-element time step of Yang, Jing, Kwok & Sobral, "A comprehensive study of coupled
+ * LBM-DEM with immersed moving boundary" (arXiv:1809.07008).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the benchmark's CPU-baseline
+ * leg may load this library.  It shares no code, header, table or helper with the HIP
+ * implementation; it is written from the paper's equations so that the two can be compared.
+ *
+ * It is deliberately slow and literal: one cell at a time, every quantity computed the way the
+ * paper defines it, arrays of structures ([y][x][q]) so that nothing resembles the GPU layout.
+ * OpenMP only splits independent rows; it never changes the order of any floating-point sum.
+ *
+ * What each part follows (equation numbers of the paper):
+ *   Sec. 2, Eqs. (1)-(4)  BGK lattice Boltzmann equation, Maxwellian equilibrium, moments.
+ *                         The paper's lattice is D3Q19 (Table 1); this oracle is two-dimensional and
+ *                         uses the D2Q9 set with weights 4/9, 1/9, 1/36 and c_s^2 = 1/3.
+ *   Sec. 2.2             solid ratio of a cell = covered area / cell area (Fig. 3a), computed
+ *                         exactly for a disk (the paper estimates it by cell decomposition).
+ *   Eq. (12)             Noble-Torczynski solid collision operator.
+ *   Eq. (13), Eq. (14)   blended collision and its weight B(eps, tau).
+ *   Eqs. (15), (16)      hydrodynamic force and torque; the printed sum is the momentum the fluid
+ *                         gains, so the force on the particle is its negative.
+ *   Eqs. (7), (8)        DEM overlap and normal spring-dashpot force (no tangential force).
+ *   Eqs. (10), (11), (17) Newton's equations integrated by velocity Verlet with N_sub sub-cycles per
+ *                         lattice step, the hydrodynamic force and torque held fixed (Sec. 2.3).
+ *   Sec. 3.3.2           Smagorinsky sub-grid model (closed form of the Hou et al. model, see
+ *                         smagorinsky_tau below).
+ *
+ * Readings taken where the paper is silent (each one is also listed in the design notes):
+ *   - node (x,y) owns the unit cell [x-1/2,x+1/2]x[y-1/2,y+1/2]; x is periodic; with walls, the
+ *     walls are half-way (y = -1/2 and y = ny-1/2) and act by link-wise bounce-back (Sec. 3.1.1
+ *     states no-slip walls enforced by bounce-back).
+ *   - driving body force: first-order term G_i = 3 w_i rho (c_i . g), weighted by (1 - B_tot) so
+ *     solid interiors are not driven; u = m / rho.
+ *   - a cell covered by several disks: eps_tot = min(1, sum eps_p), B_tot = B(eps_tot),
+ *     B_p = B_tot * (eps_p / sum eps_p).
+ *   - cycle order: map disks -> collide -> stream -> forces -> DEM sub-cycles (Fig. 4 entered at the
+ *     mapping stage).
+ *   - DEM damping ratio zeta: c_n = 2 zeta sqrt(k_n m_eff); m = rho_s pi r^2, I = m r^2 / 2.
+ *
+ * Compile with -ffp-contract=off (no fused multiply-add) and without -ffast-math.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#pragma STDC FP_CONTRACT OFF
+
+#define NQ 9
+#define MAX_SLOTS 4 /* disks sharing one cell; three disks cannot share a unit cell unless they overlap */
+
+/* D2Q9 directions: rest, +x, +y, -x, -y, (+1,+1), (-1,+1), (-1,-1), (+1,-1). */
+static const int CX[NQ] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static const int CY[NQ] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+static const int OPP[NQ] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+static const double WQ[NQ] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0, 1.0 / 9.0,
+                              1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+
+enum { O_OK = 0, O_EINVAL = -1, O_ENOMEM = -2, O_EOVERFLOW = -3 };
+
+typedef struct {
+  int32_t nx, ny;
+  int32_t walls;  /* 1: half-way bounce-back walls in y; 0: periodic in y */
+  int32_t n_sub;  /* DEM sub-cycles per lattice step (Eq. 17) */
+  double tau0;    /* molecular relaxation time */
+  double cs;      /* Smagorinsky constant (0 disables the model) */
+  double gx, gy;  /* body-force acceleration on the fluid */
+  double rho0;    /* reference density (initial state) */
+  double kn;      /* normal contact stiffness */
+  double zeta;    /* normal damping ratio */
+  double rho_s;   /* particle density (mass per unit area) */
+} ocfg;
+
+typedef struct {
+  ocfg c;
+  double *f;    /* [ny][nx][NQ] post-stream populations */
+  double *fp;   /* [ny][nx][NQ] post-collision populations */
+  int *nslot;   /* [ny*nx] disks covering the cell */
+  int *spid;    /* [ny*nx][MAX_SLOTS] their ids, ascending */
+  double *seps; /* [ny*nx][MAX_SLOTS] their solid ratios */
+  double *sdx, *sdy;            /* lever arm cell - centre (nearest image) */
+  double *sfx, *sfy, *stz;      /* per-cell force / torque contributions */
+  int np;
+  double *x, *y, *r, *vx, *vy, *om;
+  int32_t *mode;                /* 0 free (DEM), 1 fixed, 2 prescribed velocity */
+  double *fcx, *fcy;            /* contact force at the last DEM evaluation */
+  double *Fx, *Fy, *Tz;         /* hydrodynamic force / torque of the last step */
+  long step;
+} osim;
+
+/* ---------------------------------------------------------------- equilibrium, Eq. (2) */
+static void equilibrium(double rho, double ux, double uy, double feq[NQ]) {
+  double uu = ux * ux + uy * uy;
+  for (int i = 0; i < NQ; ++i) {
+    double cu = CX[i] * ux + CY[i] * uy;
+    feq[i] = WQ[i] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+  }
+}
+
+/* Weight of Eq. (14): B(eps, tau) = eps (tau - 1/2) / ((1 - eps) + (tau - 1/2)). */
+double o_weight(double eps, double tau) {
+  double a = tau - 0.5;
+  return eps * a / ((1.0 - eps) + a);
+}
+
+/* Smagorinsky relaxation time (Sec. 3.3.2 cites Hou et al. 1996 without printing it).
+ * With dx = dt = 1: strain rate |S| = 3 sqrt(2) |Pi| / (2 rho tau_eff) from the non-equilibrium
+ * momentum flux Pi = sum_i c_i c_i (f_i - f_i^eq); eddy viscosity nu_t = C_s^2 |S|;
+ * tau_eff = tau0 + 3 nu_t.  Solving the resulting quadratic for tau_eff gives the expression below. */
+static double smagorinsky_tau(double tau0, double cs, double rho, const double f[NQ],
+                              const double feq[NQ]) {
+  if (cs <= 0.0) return tau0;
+  double pxx = 0.0, pxy = 0.0, pyy = 0.0;
+  for (int i = 0; i < NQ; ++i) {
+    double neq = f[i] - feq[i];
+    pxx += (CX[i] * CX[i]) * neq;
+    pxy += (CX[i] * CY[i]) * neq;
+    pyy += (CY[i] * CY[i]) * neq;
+  }
+  double pn = sqrt(pxx * pxx + 2.0 * pxy * pxy + pyy * pyy);
+  return 0.5 * (tau0 + sqrt(tau0 * tau0 + 18.0 * sqrt(2.0) * cs * cs * pn / rho));
+}
+
+/* ------------------------------------------------------- solid ratio of one cell (Sec. 2.2)
+ * Exact area of  disk(radius r, centre at the origin)  intersected with the unit cell
+ * [dx-1/2, dx+1/2] x [dy-1/2, dy+1/2], divided by the cell area (1).
+ * Written as the integral over x of the vertical chord clipped to the cell,
+ *   eps = int_{x0}^{x1} max(0, min(y1, s(x)) - max(y0, -s(x))) dx,   s(x) = sqrt(r^2 - x^2),
+ * split at every abscissa where the clipping changes, each piece integrated in closed form with
+ * int s dx = (x s(x) + r^2 asin(x/r)) / 2  (asin evaluated as atan2(x, s) for conditioning). */
+static double half_chord(double r, double x) { /* sqrt(r^2 - x^2), well conditioned near |x| = r */
+  double a = fabs(x);
+  return a >= r ? 0.0 : sqrt((r - a) * (r + a));
+}
+
+static double semicircle_primitive(double r, double x) {
+  if (x > r) x = r;
+  if (x < -r) x = -r;
+  double s = half_chord(r, x);
+  return 0.5 * (x * s + r * r * atan2(x, s)); /* atan2(x, s) = asin(x / r) */
+}
+
+double o_solid_fraction(double r, double dx, double dy) {
+  double x0 = dx - 0.5, x1 = dx + 0.5, y0 = dy - 0.5, y1 = dy + 0.5;
+  /* the cell lies outside the disk when its point nearest to the centre is not inside */
+  double nx = (x0 > 0.0) ? x0 : ((x1 < 0.0) ? x1 : 0.0);
+  double ny = (y0 > 0.0) ? y0 : ((y1 < 0.0) ? y1 : 0.0);
+  if (nx * nx + ny * ny >= r * r) return 0.0;
+  /* the cell lies inside the (convex) disk when its farthest corner does */
+  double fx = fabs(x0) > fabs(x1) ? fabs(x0) : fabs(x1);
+  double fy = fabs(y0) > fabs(y1) ? fabs(y0) : fabs(y1);
+  if (fx * fx + fy * fy <= r * r) return 1.0;
+
+  double bp[8];
+  int nb = 0;
+  bp[nb++] = x0;
+  bp[nb++] = x1;
+  double cand[6];
+  int nc = 0;
+  cand[nc++] = -r;
+  cand[nc++] = r;
+  if (fabs(y0) < r) {
+    double w = half_chord(r, y0);
+    cand[nc++] = -w;
+    cand[nc++] = w;
+  }
+  if (fabs(y1) < r) {
+    double w = half_chord(r, y1);
+    cand[nc++] = -w;
+    cand[nc++] = w;
+  }
+  for (int k = 0; k < nc; ++k)
+    if (cand[k] > x0 && cand[k] < x1) bp[nb++] = cand[k];
+  for (int a = 1; a < nb; ++a) { /* insertion sort */
+    double v = bp[a];
+    int b = a - 1;
+    while (b >= 0 && bp[b] > v) {
+      bp[b + 1] = bp[b];
+      --b;
+    }
+    bp[b + 1] = v;
+  }
+  double area = 0.0;
+  for (int k = 0; k + 1 < nb; ++k) {
+    double a = bp[k], b = bp[k + 1];
+    if (!(b > a)) continue;
+    double m = 0.5 * (a + b);
+    if (fabs(m) >= r) continue; /* no chord on this piece */
+    double s = half_chord(r, m);
+    int top_is_circle = s < y1;
+    int bot_is_circle = -s > y0;
+    double top_v = top_is_circle ? s : y1;
+    double bot_v = bot_is_circle ? -s : y0;
+    if (top_v <= bot_v) continue; /* chord misses the cell on this piece */
+    double semi = semicircle_primitive(r, b) - semicircle_primitive(r, a);
+    double top_int = top_is_circle ? semi : y1 * (b - a);
+    double bot_int = bot_is_circle ? -semi : y0 * (b - a);
+    area += top_int - bot_int;
+  }
+  return area;
+}
+
+/* ----------------------------------------------------------- collision of one cell
+ * Inputs: the 9 post-stream populations of the cell; for each disk covering it (ascending id)
+ * its solid ratio, the lever arm d = cell - centre, and the disk's velocity / angular velocity.
+ * Outputs: post-collision populations and, per disk, the force and torque it receives from this
+ * cell.  diag (optional) receives {tau_eff, B_tot}.
+ *
+ *   f*_i = f_i + (1 - B_tot) (Omega^f_i + G_i) + sum_p B_p Omega^s_{p,i}          Eq. (13)
+ *   Omega^f_i = -(f_i - f_i^eq(rho, u)) / tau_eff                                    Eq. (1)
+ *   Omega^s_{p,i} = f_{-i} - f_{-i}^eq(rho,u) + f_i^eq(rho,u_s) - f_i                Eq. (12)
+ *   dF_p = -B_p sum_i Omega^s_{p,i} c_i ,  dT_p = d x dF_p                           Eqs. (15), (16)
+ */
+int o_collide_cell(const double *f, int np, const double *eps, const double *dxs,
+                   const double *dys, const double *pvx, const double *pvy, const double *pom,
+                   double tau0, double cs, double gx, double gy, double *fout, double *dfx,
+                   double *dfy, double *dtz, double *diag) {
+  double rho = 0.0, mx = 0.0, my = 0.0;
+  for (int i = 0; i < NQ; ++i) rho += f[i];
+  for (int i = 0; i < NQ; ++i) {
+    mx += CX[i] * f[i];
+    my += CY[i] * f[i];
+  }
+  double ux = mx / rho, uy = my / rho;
+  double feq[NQ];
+  equilibrium(rho, ux, uy, feq);
+  double tau = smagorinsky_tau(tau0, cs, rho, f, feq);
+
+  double S = 0.0;
+  for (int p = 0; p < np; ++p) S += eps[p];
+  double et = S < 1.0 ? S : 1.0;
+  double Bt = o_weight(et, tau);
+
+  for (int i = 0; i < NQ; ++i) {
+    double G = 3.0 * WQ[i] * rho * (CX[i] * gx + CY[i] * gy);
+    double Of = -(f[i] - feq[i]) / tau;
+    fout[i] = f[i] + (1.0 - Bt) * (Of + G);
+  }
+  for (int p = 0; p < np; ++p) {
+    double Bp = S > 0.0 ? Bt * (eps[p] / S) : 0.0; /* no solid in the cell: no weight */
+    double usx = pvx[p] - pom[p] * dys[p];
+    double usy = pvy[p] + pom[p] * dxs[p];
+    double feqs[NQ];
+    equilibrium(rho, usx, usy, feqs);
+    double sx = 0.0, sy = 0.0;
+    for (int i = 0; i < NQ; ++i) {
+      int o = OPP[i];
+      double Os = f[o] - feq[o] + feqs[i] - f[i];
+      fout[i] += Bp * Os;
+      sx += CX[i] * Os;
+      sy += CY[i] * Os;
+    }
+    dfx[p] = -Bp * sx;
+    dfy[p] = -Bp * sy;
+    dtz[p] = dxs[p] * dfy[p] - dys[p] * dfx[p];
+  }
+  if (diag) {
+    diag[0] = tau;
+    diag[1] = Bt;
+  }
+  return O_OK;
+}
+
+/* ------------------------------------------------------------------ simulation object */
+static void *xcalloc(size_t n, size_t sz) { return n ? calloc(n, sz) : calloc(1, sz); }
+
+void o_destroy(osim *s);
+
+osim *o_create(const ocfg *c) {
+  if (!c || c->nx < 2 || c->ny < 2 || !(c->tau0 > 0.5) || c->cs < 0.0 || c->n_sub < 1) return NULL;
+  osim *s = (osim *)calloc(1, sizeof(osim));
+  if (!s) return NULL;
+  s->c = *c;
+  size_t nc = (size_t)c->nx * c->ny;
+  s->f = (double *)xcalloc(nc * NQ, sizeof(double));
+  s->fp = (double *)xcalloc(nc * NQ, sizeof(double));
+  s->nslot = (int *)xcalloc(nc, sizeof(int));
+  s->spid = (int *)xcalloc(nc * MAX_SLOTS, sizeof(int));
+  s->seps = (double *)xcalloc(nc * MAX_SLOTS, sizeof(double));
+  s->sdx = (double *)xcalloc(nc * MAX_SLOTS, sizeof(double));
+  s->sdy = (double *)xcalloc(nc * MAX_SLOTS, sizeof(double));
+  s->sfx = (double *)xcalloc(nc * MAX_SLOTS, sizeof(double));
+  s->sfy = (double *)xcalloc(nc * MAX_SLOTS, sizeof(double));
+  s->stz = (double *)xcalloc(nc * MAX_SLOTS, sizeof(double));
+  if (!s->f || !s->fp || !s->nslot || !s->spid || !s->seps || !s->sdx || !s->sdy || !s->sfx ||
+      !s->sfy || !s->stz) {
+    o_destroy(s);
+    return NULL;
+  }
+  return s;
+}
+
+static void free_particles(osim *s) {
+  free(s->x); free(s->y); free(s->r); free(s->vx); free(s->vy); free(s->om); free(s->mode);
+  free(s->fcx); free(s->fcy); free(s->Fx); free(s->Fy); free(s->Tz);
+  s->x = s->y = s->r = s->vx = s->vy = s->om = s->fcx = s->fcy = s->Fx = s->Fy = s->Tz = NULL;
+  s->mode = NULL;
+  s->np = 0;
+}
+
+void o_destroy(osim *s) {
+  if (!s) return;
+  free(s->f); free(s->fp); free(s->nslot); free(s->spid); free(s->seps); free(s->sdx);
+  free(s->sdy); free(s->sfx); free(s->sfy); free(s->stz);
+  free_particles(s);
+  free(s);
+}
+
+void o_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
+int o_get_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/* f = f^eq(rho, u) everywhere, including inside solids (initial state of every benchmark). */
+int o_init_equilibrium(osim *s, double rho, double ux, double uy) {
+  double feq[NQ];
+  equilibrium(rho, ux, uy, feq);
+  size_t nc = (size_t)s->c.nx * s->c.ny;
+  for (size_t k = 0; k < nc; ++k)
+    for (int i = 0; i < NQ; ++i) s->f[k * NQ + i] = feq[i];
+  return O_OK;
+}
+
+/* Exchange format for populations: [q][y][x], post-stream. */
+int o_set_populations(osim *s, const double *fq) {
+  int nx = s->c.nx, ny = s->c.ny;
+  for (int i = 0; i < NQ; ++i)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x)
+        s->f[((size_t)y * nx + x) * NQ + i] = fq[((size_t)i * ny + y) * nx + x];
+  return O_OK;
+}
+
+int o_get_populations(const osim *s, double *fq) {
+  int nx = s->c.nx, ny = s->c.ny;
+  for (int i = 0; i < NQ; ++i)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x)
+        fq[((size_t)i * ny + y) * nx + x] = s->f[((size_t)y * nx + x) * NQ + i];
+  return O_OK;
+}
+
+/* Density and velocity u = m / rho of the post-stream populations, Eqs. (3), (4). */
+int o_get_fields(const osim *s, double *rho, double *ux, double *uy) {
+  size_t nc = (size_t)s->c.nx * s->c.ny;
+  for (size_t k = 0; k < nc; ++k) {
+    const double *f = s->f + k * NQ;
+    double r = 0.0, mx = 0.0, my = 0.0;
+    for (int i = 0; i < NQ; ++i) r += f[i];
+    for (int i = 0; i < NQ; ++i) {
+      mx += CX[i] * f[i];
+      my += CY[i] * f[i];
+    }
+    if (rho) rho[k] = r;
+    if (ux) ux[k] = mx / r;
+    if (uy) uy[k] = my / r;
+  }
+  return O_OK;
+}
+
+/* ------------------------------------------------------------------ DEM (Sec. 2.1) */
+static double disk_mass(const osim *s, int p) { return s->c.rho_s * M_PI * s->r[p] * s->r[p]; }
+
+static double wrap_coord(double v, int n) {
+  if (v >= n) v -= n;
+  else if (v < 0.0) v += n;
+  return v;
+}
+
+static double nearest_image(double d, int n) {
+  if (d > 0.5 * n) d -= n;
+  else if (d < -0.5 * n) d += n;
+  return d;
+}
+
+/* Normal spring-dashpot contact forces (Eqs. 7, 8) on every free disk, from all other disks
+ * (ascending id) and then the two walls.  Force on i:  -(k_n delta + c_n v_n) n, with n the unit
+ * vector from i towards its partner, delta the overlap, v_n = (V_i - V_partner) . n the approach
+ * speed and c_n = 2 zeta sqrt(k_n m_eff). */
+static void contact_forces(osim *s) {
+  int np = s->np;
+  double kn = s->c.kn, zeta = s->c.zeta;
+  for (int i = 0; i < np; ++i) {
+    double fx = 0.0, fy = 0.0;
+    if (s->mode[i] == 0) {
+      double mi = disk_mass(s, i);
+      for (int j = 0; j < np; ++j) {
+        if (j == i) continue;
+        double dx = s->x[j] - s->x[i];
+        double dy = s->y[j] - s->y[i];
+        dx = nearest_image(dx, s->c.nx);
+        if (!s->c.walls) dy = nearest_image(dy, s->c.ny);
+        double dist = sqrt(dx * dx + dy * dy);
+        double delta = s->r[i] + s->r[j] - dist;
+        if (delta > 0.0 && dist > 0.0) {
+          double nxu = dx / dist, nyu = dy / dist;
+          double vn = (s->vx[i] - s->vx[j]) * nxu + (s->vy[i] - s->vy[j]) * nyu;
+          double mj = disk_mass(s, j);
+          double meff = mi * mj / (mi + mj);
+          double cn = 2.0 * zeta * sqrt(kn * meff);
+          double fn = kn * delta + cn * vn;
+          fx += -fn * nxu;
+          fy += -fn * nyu;
+        }
+      }
+      if (s->c.walls) {
+        double cn = 2.0 * zeta * sqrt(kn * mi);
+        double db = s->r[i] - (s->y[i] + 0.5); /* wall at y = -1/2, n = (0,-1) */
+        if (db > 0.0) {
+          double vn = -s->vy[i];
+          fy += kn * db + cn * vn;
+        }
+        double dt = s->r[i] - ((s->c.ny - 0.5) - s->y[i]); /* wall at y = ny-1/2, n = (0,1) */
+        if (dt > 0.0) {
+          double vn = s->vy[i];
+          fy += -(kn * dt + cn * vn);
+        }
+      }
+    }
+    s->fcx[i] = fx;
+    s->fcy[i] = fy;
+  }
+}
+
+/* One lattice step of DEM: N_sub velocity-Verlet (kick-drift-kick) sub-steps of dt = 1/N_sub
+ * (Eq. 17) for free disks with the hydrodynamic force and torque of this step held fixed; the
+ * contact force is evaluated after each drift from the new positions and half-step velocities
+ * and reused for the first kick of the next sub-step.  Prescribed disks move by V once per step;
+ * fixed disks stay. */
+static void dem_phase(osim *s) {
+  int np = s->np;
+  int any_free = 0;
+  for (int i = 0; i < np; ++i) any_free |= (s->mode[i] == 0);
+  if (any_free) {
+    double dt = 1.0 / s->c.n_sub, h = 0.5 * dt;
+    for (int k = 0; k < s->c.n_sub; ++k) {
+      for (int i = 0; i < np; ++i) {
+        if (s->mode[i] != 0) continue;
+        double m = disk_mass(s, i);
+        double I = 0.5 * m * s->r[i] * s->r[i];
+        double ax = (s->fcx[i] + s->Fx[i]) / m;
+        double ay = (s->fcy[i] + s->Fy[i]) / m;
+        s->vx[i] = s->vx[i] + h * ax;
+        s->vy[i] = s->vy[i] + h * ay;
+        s->x[i] = wrap_coord(s->x[i] + dt * s->vx[i], s->c.nx);
+        s->y[i] = s->y[i] + dt * s->vy[i];
+        if (!s->c.walls) s->y[i] = wrap_coord(s->y[i], s->c.ny);
+        s->om[i] = s->om[i] + h * (s->Tz[i] / I);
+      }
+      contact_forces(s);
+      for (int i = 0; i < np; ++i) {
+        if (s->mode[i] != 0) continue;
+        double m = disk_mass(s, i);
+        double I = 0.5 * m * s->r[i] * s->r[i];
+        double ax = (s->fcx[i] + s->Fx[i]) / m;
+        double ay = (s->fcy[i] + s->Fy[i]) / m;
+        s->vx[i] = s->vx[i] + h * ax;
+        s->vy[i] = s->vy[i] + h * ay;
+        s->om[i] = s->om[i] + h * (s->Tz[i] / I);
+      }
+    }
+  }
+  for (int i = 0; i < np; ++i) {
+    if (s->mode[i] != 2) continue;
+    s->x[i] = wrap_coord(s->x[i] + s->vx[i], s->c.nx);
+    s->y[i] = s->y[i] + s->vy[i];
+    if (!s->c.walls) s->y[i] = wrap_coord(s->y[i], s->c.ny);
+  }
+}
+
+int o_set_particles(osim *s, int n, const double *x, const double *y, const double *r,
+                    const double *vx, const double *vy, const double *om, const int32_t *mode) {
+  if (n < 0) return O_EINVAL;
+  for (int p = 0; p < n; ++p) {
+    if (!(r[p] > 0.0) || 2.0 * (r[p] + 2.0) >= s->c.nx || 2.0 * (r[p] + 2.0) >= s->c.ny)
+      return O_EINVAL;
+    if (!(x[p] >= 0.0 && x[p] < s->c.nx)) return O_EINVAL;
+    if (mode[p] < 0 || mode[p] > 2) return O_EINVAL;
+  }
+  free_particles(s);
+  size_t nn = (size_t)n;
+  s->x = (double *)xcalloc(nn, sizeof(double));
+  s->y = (double *)xcalloc(nn, sizeof(double));
+  s->r = (double *)xcalloc(nn, sizeof(double));
+  s->vx = (double *)xcalloc(nn, sizeof(double));
+  s->vy = (double *)xcalloc(nn, sizeof(double));
+  s->om = (double *)xcalloc(nn, sizeof(double));
+  s->mode = (int32_t *)xcalloc(nn, sizeof(int32_t));
+  s->fcx = (double *)xcalloc(nn, sizeof(double));
+  s->fcy = (double *)xcalloc(nn, sizeof(double));
+  s->Fx = (double *)xcalloc(nn, sizeof(double));
+  s->Fy = (double *)xcalloc(nn, sizeof(double));
+  s->Tz = (double *)xcalloc(nn, sizeof(double));
+  if (!s->x || !s->y || !s->r || !s->vx || !s->vy || !s->om || !s->mode || !s->fcx || !s->fcy ||
+      !s->Fx || !s->Fy || !s->Tz)
+    return O_ENOMEM;
+  s->np = n;
+  for (int p = 0; p < n; ++p) {
+    s->x[p] = x[p]; s->y[p] = y[p]; s->r[p] = r[p];
+    s->vx[p] = vx[p]; s->vy[p] = vy[p]; s->om[p] = om[p]; s->mode[p] = mode[p];
+  }
+  contact_forces(s);
+  return O_OK;
+}
+
+/* ------------------------------------------------------------ one coupled step (Sec. 2.3) */
+
+/* Map every disk onto the lattice: for each cell its covering disks (ascending id), their solid
+ * ratios and lever arms.  Only cells within one cell of a disk's bounding box can have eps > 0;
+ * the lever arm uses the disk image nearest to the cell, computed from the integer cell offset
+ * and the fractional part of the centre. */
+static int map_particles(osim *s) {
+  int nx = s->c.nx, ny = s->c.ny;
+  memset(s->nslot, 0, sizeof(int) * (size_t)nx * ny);
+  for (int p = 0; p < s->np; ++p) {
+    double X = s->x[p], Y = s->y[p], r = s->r[p];
+    double flx = floor(X), fly = floor(Y);
+    double fx = X - flx, fy = Y - fly;
+    int ix0 = (int)floor(X - r - 0.5), ix1 = (int)ceil(X + r + 0.5);
+    int iy0 = (int)floor(Y - r - 0.5), iy1 = (int)ceil(Y + r + 0.5);
+    if (s->c.walls) {
+      if (iy0 < 0) iy0 = 0;
+      if (iy1 > ny - 1) iy1 = ny - 1;
+    }
+    for (int iy = iy0; iy <= iy1; ++iy) {
+      int yw = ((iy % ny) + ny) % ny;
+      long dj = (long)yw - (long)fly;
+      if (!s->c.walls) {
+        if (dj > ny / 2) dj -= ny;
+        else if (dj < -(ny / 2)) dj += ny;
+      }
+      double dy = (double)dj - fy;
+      for (int ix = ix0; ix <= ix1; ++ix) {
+        int xw = ((ix % nx) + nx) % nx;
+        long di = (long)xw - (long)flx;
+        if (di > nx / 2) di -= nx;
+        else if (di < -(nx / 2)) di += nx;
+        double dx = (double)di - fx;
+        double e = o_solid_fraction(r, dx, dy);
+        if (e > 0.0) {
+          size_t k = (size_t)yw * nx + xw;
+          int ns = s->nslot[k];
+          if (ns >= MAX_SLOTS) return O_EOVERFLOW;
+          s->spid[k * MAX_SLOTS + ns] = p;
+          s->seps[k * MAX_SLOTS + ns] = e;
+          s->sdx[k * MAX_SLOTS + ns] = dx;
+          s->sdy[k * MAX_SLOTS + ns] = dy;
+          s->nslot[k] = ns + 1;
+        }
+      }
+    }
+  }
+  return O_OK;
+}
+
+static void collide_all(osim *s) {
+  int nx = s->c.nx, ny = s->c.ny;
+#pragma omp parallel for schedule(static)
+  for (int y = 0; y < ny; ++y) {
+    double pvx[MAX_SLOTS], pvy[MAX_SLOTS], pom[MAX_SLOTS];
+    for (int x = 0; x < nx; ++x) {
+      size_t k = (size_t)y * nx + x;
+      int ns = s->nslot[k];
+      for (int q = 0; q < ns; ++q) {
+        int p = s->spid[k * MAX_SLOTS + q];
+        pvx[q] = s->vx[p];
+        pvy[q] = s->vy[p];
+        pom[q] = s->om[p];
+      }
+      o_collide_cell(s->f + k * NQ, ns, s->seps + k * MAX_SLOTS, s->sdx + k * MAX_SLOTS,
+                     s->sdy + k * MAX_SLOTS, pvx, pvy, pom, s->c.tau0, s->c.cs, s->c.gx, s->c.gy,
+                     s->fp + k * NQ, s->sfx + k * MAX_SLOTS, s->sfy + k * MAX_SLOTS,
+                     s->stz + k * MAX_SLOTS, NULL);
+    }
+  }
+}
+
+/* Streaming, left-hand side of Eq. (1): f_i(x + c_i) <- f*_i(x); a link leaving through a wall
+ * returns to its own node in the opposite direction (half-way bounce-back, resting wall). */
+static void stream_all(osim *s) {
+  int nx = s->c.nx, ny = s->c.ny;
+#pragma omp parallel for schedule(static)
+  for (int y = 0; y < ny; ++y) {
+    for (int x = 0; x < nx; ++x) {
+      const double *fp = s->fp + ((size_t)y * nx + x) * NQ;
+      for (int i = 0; i < NQ; ++i) {
+        int xn = (x + CX[i] + nx) % nx;
+        int yn = y + CY[i];
+        if (yn < 0 || yn >= ny) {
+          if (s->c.walls) {
+            s->f[((size_t)y * nx + x) * NQ + OPP[i]] = fp[i];
+            continue;
+          }
+          yn = (yn + ny) % ny;
+        }
+        s->f[((size_t)yn * nx + xn) * NQ + i] = fp[i];
+      }
+    }
+  }
+}
+
+/* Force and torque on each disk: sum of the per-cell contributions over the covered cells in
+ * row-major cell order (Eqs. 15, 16, sign on the particle). */
+static void sum_forces(osim *s) {
+  for (int p = 0; p < s->np; ++p) s->Fx[p] = s->Fy[p] = s->Tz[p] = 0.0;
+  size_t nc = (size_t)s->c.nx * s->c.ny;
+  for (size_t k = 0; k < nc; ++k) {
+    for (int q = 0; q < s->nslot[k]; ++q) {
+      int p = s->spid[k * MAX_SLOTS + q];
+      s->Fx[p] += s->sfx[k * MAX_SLOTS + q];
+      s->Fy[p] += s->sfy[k * MAX_SLOTS + q];
+      s->Tz[p] += s->stz[k * MAX_SLOTS + q];
+    }
+  }
+}
+
+int o_step(osim *s, int nsteps) {
+  for (int n = 0; n < nsteps; ++n) {
+    int rc = map_particles(s);
+    if (rc) return rc;
+    collide_all(s);
+    stream_all(s);
+    sum_forces(s);
+    dem_phase(s);
+    s->step++;
+  }
+  return O_OK;
+}
+
+/* Steps while accumulating J += sum_p (wfx_p Fx_p + wfy_p Fy_p + wt_p T_p) after every step. */
+int o_step_accumulate(osim *s, int nsteps, const double *wfx, const double *wfy, const double *wt,
+                      double *J) {
+  double acc = *J;
+  for (int n = 0; n < nsteps; ++n) {
+    int rc = o_step(s, 1);
+    if (rc) return rc;
+    for (int p = 0; p < s->np; ++p) {
+      if (wfx) acc += wfx[p] * s->Fx[p];
+      if (wfy) acc += wfy[p] * s->Fy[p];
+      if (wt) acc += wt[p] * s->Tz[p];
+    }
+  }
+  *J = acc;
+  return O_OK;
+}
+
+/* DEM alone (no fluid): nsteps lattice steps of DEM with the stored hydrodynamic force. */
+int o_dem_steps(osim *s, int nsteps) {
+  for (int n = 0; n < nsteps; ++n) dem_phase(s);
+  return O_OK;
+}
+
+int o_get_forces(const osim *s, double *fx, double *fy, double *tz) {
+  for (int p = 0; p < s->np; ++p) {
+    fx[p] = s->Fx[p];
+    fy[p] = s->Fy[p];
+    tz[p] = s->Tz[p];
+  }
+  return O_OK;
+}
+
+int o_get_particles(const osim *s, double *x, double *y, double *vx, double *vy, double *om) {
+  for (int p = 0; p < s->np; ++p) {
+    x[p] = s->x[p]; y[p] = s->y[p]; vx[p] = s->vx[p]; vy[p] = s->vy[p]; om[p] = s->om[p];
+  }
+  return O_OK;
+}
+
+/* Solid ratio field of the current particle state: eps_tot per cell ([y][x]). */
+int o_solid_field(osim *s, double *eps_tot) {
+  int rc = map_particles(s);
+  if (rc) return rc;
+  size_t nc = (size_t)s->c.nx * s->c.ny;
+  for (size_t k = 0; k < nc; ++k) {
+    double S = 0.0;
+    for (int q = 0; q < s->nslot[k]; ++q) S += s->seps[k * MAX_SLOTS + q];
+    eps_tot[k] = S;
+  }
+  return O_OK;
+}
+
+long o_step_count(const osim *s) { return s->step; }

@@ -1,0 +1,231 @@
+"""ctypes wrapper of the FP64 CPU oracle (``oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's CPU-baseline leg
+may import this module; the product package never does.  It imports nothing from the product
+package either.  The library is compiled with gcc (``-ffp-contract=off``, OpenMP) on first use if
+it is missing or older than its source.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+GCC_FLAGS = ["-O2", "-fPIC", "-shared", "-std=c99", "-D_GNU_SOURCE", "-ffp-contract=off",
+             "-fno-fast-math", "-fopenmp", "-Wall", "-Wno-unknown-pragmas"]
+
+
+def build(force: bool = False) -> str:
+    """Compile liboracle.so (always when ``force``)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", *GCC_FLAGS, _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Cfg(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("walls", C.c_int32),
+                ("n_sub", C.c_int32), ("tau0", C.c_double), ("cs", C.c_double),
+                ("gx", C.c_double), ("gy", C.c_double), ("rho0", C.c_double),
+                ("kn", C.c_double), ("zeta", C.c_double), ("rho_s", C.c_double)]
+
+
+_lib = None
+_D = C.POINTER(C.c_double)
+_I = C.POINTER(C.c_int32)
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        lib = C.CDLL(build())
+        lib.o_create.restype = C.c_void_p
+        lib.o_create.argtypes = [C.POINTER(_Cfg)]
+        lib.o_destroy.argtypes = [C.c_void_p]
+        lib.o_set_threads.argtypes = [C.c_int]
+        lib.o_get_threads.restype = C.c_int
+        lib.o_init_equilibrium.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double]
+        lib.o_set_populations.argtypes = [C.c_void_p, _D]
+        lib.o_get_populations.argtypes = [C.c_void_p, _D]
+        lib.o_get_fields.argtypes = [C.c_void_p, _D, _D, _D]
+        lib.o_set_particles.argtypes = [C.c_void_p, C.c_int, _D, _D, _D, _D, _D, _D, _I]
+        lib.o_step.argtypes = [C.c_void_p, C.c_int]
+        lib.o_step_accumulate.argtypes = [C.c_void_p, C.c_int, _D, _D, _D, _D]
+        lib.o_dem_steps.argtypes = [C.c_void_p, C.c_int]
+        lib.o_get_forces.argtypes = [C.c_void_p, _D, _D, _D]
+        lib.o_get_particles.argtypes = [C.c_void_p, _D, _D, _D, _D, _D]
+        lib.o_solid_field.argtypes = [C.c_void_p, _D]
+        lib.o_solid_fraction.restype = C.c_double
+        lib.o_solid_fraction.argtypes = [C.c_double, C.c_double, C.c_double]
+        lib.o_weight.restype = C.c_double
+        lib.o_weight.argtypes = [C.c_double, C.c_double]
+        lib.o_collide_cell.argtypes = [_D, C.c_int, _D, _D, _D, _D, _D, _D, C.c_double,
+                                       C.c_double, C.c_double, C.c_double, _D, _D, _D, _D, _D]
+        lib.o_step_count.restype = C.c_long
+        lib.o_step_count.argtypes = [C.c_void_p]
+        _lib = lib
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(_D)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def set_threads(n: int) -> None:
+    _load().o_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(_load().o_get_threads())
+
+
+def solid_fraction(r: float, dx: float, dy: float) -> float:
+    """Exact covered fraction of the unit cell centred at (dx, dy) relative to a disk of radius r
+    centred at the origin."""
+    return float(_load().o_solid_fraction(r, dx, dy))
+
+
+def weight(eps: float, tau: float) -> float:
+    """Noble-Torczynski weight B(eps, tau), Eq. (14)."""
+    return float(_load().o_weight(eps, tau))
+
+
+def collide_cell(f, eps=(), dx=(), dy=(), vx=(), vy=(), om=(), tau0=0.6, cs=0.0, gx=0.0, gy=0.0):
+    """One-cell collision (Eqs. 1, 12-16).  Returns (f_out[9], dF[n,2], dT[n], tau_eff, B_tot)."""
+    lib = _load()
+    f = _f64(f)
+    n = len(eps)
+    eps, dx, dy, vx, vy, om = (_f64(a) if n else np.zeros(1) for a in (eps, dx, dy, vx, vy, om))
+    fout = np.zeros(9)
+    dfx = np.zeros(max(n, 1)); dfy = np.zeros(max(n, 1)); dtz = np.zeros(max(n, 1))
+    diag = np.zeros(2)
+    lib.o_collide_cell(_dp(f), n, _dp(eps), _dp(dx), _dp(dy), _dp(vx), _dp(vy), _dp(om),
+                       tau0, cs, gx, gy, _dp(fout), _dp(dfx), _dp(dfy), _dp(dtz), _dp(diag))
+    return fout, np.stack([dfx[:n], dfy[:n]], axis=1), dtz[:n].copy(), diag[0], diag[1]
+
+
+@dataclass
+class OracleConfig:
+    nx: int
+    ny: int
+    tau0: float
+    walls: bool = True
+    cs: float = 0.0
+    gx: float = 0.0
+    gy: float = 0.0
+    rho0: float = 1.0
+    n_sub: int = 10
+    kn: float = 1.0e3
+    zeta: float = 0.1
+    rho_s: float = 1.0
+
+
+class OracleSim:
+    """One oracle simulation (FP64, CPU)."""
+
+    def __init__(self, cfg: OracleConfig):
+        lib = _load()
+        self.cfg = cfg
+        c = _Cfg(cfg.nx, cfg.ny, 1 if cfg.walls else 0, cfg.n_sub, cfg.tau0, cfg.cs, cfg.gx,
+                 cfg.gy, cfg.rho0, cfg.kn, cfg.zeta, cfg.rho_s)
+        self._h = lib.o_create(C.byref(c))
+        if not self._h:
+            raise ValueError("oracle: invalid configuration %r" % (cfg,))
+        self.np = 0
+        lib.o_init_equilibrium(self._h, cfg.rho0, 0.0, 0.0)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.o_destroy(h)
+            self._h = None
+
+    def init_equilibrium(self, rho=1.0, ux=0.0, uy=0.0):
+        _load().o_init_equilibrium(self._h, rho, ux, uy)
+
+    def set_populations(self, f):
+        f = _f64(f)
+        assert f.shape == (9, self.cfg.ny, self.cfg.nx)
+        _load().o_set_populations(self._h, _dp(f))
+
+    def populations(self) -> np.ndarray:
+        f = np.zeros((9, self.cfg.ny, self.cfg.nx))
+        _load().o_get_populations(self._h, _dp(f))
+        return f
+
+    def fields(self):
+        shp = (self.cfg.ny, self.cfg.nx)
+        rho, ux, uy = np.zeros(shp), np.zeros(shp), np.zeros(shp)
+        _load().o_get_fields(self._h, _dp(rho), _dp(ux), _dp(uy))
+        return rho, ux, uy
+
+    def set_particles(self, x, y, r, vx=None, vy=None, om=None, mode=None):
+        n = len(x)
+        z = np.zeros(n)
+        x, y, r = _f64(x), _f64(y), _f64(r)
+        vx = _f64(z if vx is None else vx)
+        vy = _f64(z if vy is None else vy)
+        om = _f64(z if om is None else om)
+        mode = np.ascontiguousarray(np.zeros(n, np.int32) if mode is None else mode, np.int32)
+        if n == 0:
+            x = y = r = vx = vy = om = np.zeros(1)
+            mode = np.zeros(1, np.int32)
+        rc = _load().o_set_particles(self._h, n, _dp(x), _dp(y), _dp(r), _dp(vx), _dp(vy),
+                                     _dp(om), mode.ctypes.data_as(_I))
+        if rc:
+            raise ValueError("oracle: invalid particles (code %d)" % rc)
+        self.np = n
+
+    def step(self, n: int = 1):
+        rc = _load().o_step(self._h, int(n))
+        if rc:
+            raise RuntimeError("oracle: step failed (code %d)" % rc)
+
+    def step_accumulate(self, n, wfx=None, wfy=None, wt=None, J=0.0) -> float:
+        def opt(w):
+            return None if w is None else _dp(_f64(w))
+        keep = [None if w is None else _f64(w) for w in (wfx, wfy, wt)]
+        Jc = C.c_double(J)
+        rc = _load().o_step_accumulate(self._h, int(n), *(None if k is None else _dp(k) for k in keep),
+                                       C.byref(Jc))
+        if rc:
+            raise RuntimeError("oracle: step failed (code %d)" % rc)
+        return Jc.value
+
+    def dem_steps(self, n: int = 1):
+        _load().o_dem_steps(self._h, int(n))
+
+    def forces(self):
+        n = max(self.np, 1)
+        fx, fy, tz = np.zeros(n), np.zeros(n), np.zeros(n)
+        _load().o_get_forces(self._h, _dp(fx), _dp(fy), _dp(tz))
+        return fx[: self.np], fy[: self.np], tz[: self.np]
+
+    def particles(self):
+        n = max(self.np, 1)
+        a = [np.zeros(n) for _ in range(5)]
+        _load().o_get_particles(self._h, *(_dp(v) for v in a))
+        return tuple(v[: self.np] for v in a)
+
+    def solid_field(self) -> np.ndarray:
+        e = np.zeros((self.cfg.ny, self.cfg.nx))
+        rc = _load().o_solid_field(self._h, _dp(e))
+        if rc:
+            raise RuntimeError("oracle: mapping failed (code %d)" % rc)
+        return e
+
+    @property
+    def step_count(self) -> int:
+        return int(_load().o_step_count(self._h))
