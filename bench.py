@@ -1,0 +1,140 @@
+"""Benchmark of the coupled D2Q9 IMB-DEM step on one MI355X.
+
+Workload: 2048x1024 channel, 500 moving disks (diameters U[16, 24]), Smagorinsky C_s = 0.1,
+tau 0.55, linear spring-dashpot DEM, FP32 deviation storage, seeded synthetic input (seed 0).
+One "step" is one full coupled step: solid ratio, IMB collision + streaming, force/torque sums,
+DEM update.  Prints one JSON line (throughput in MLUPS, HBM roofline of the fused lattice-step
+kernel, the CPU oracle's throughput on the same workload).
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def bytes_per_lup(storage: str) -> int:
+    """Algorithmic bytes per lattice update: 9 populations read + 9 written."""
+    return 2 * 9 * {"f64": 8, "f32": 4, "f16": 2}[storage]
+
+
+def cpu_baseline(case, target_s: float = 12.0):
+    """The FP64 CPU oracle on the same workload, a bounded number of steps (host cores)."""
+    import oracle
+    ref = oracle.OracleSim(oracle.OracleConfig(nx=case.nx, ny=case.ny, tau0=case.tau0,
+                                               walls=case.walls, cs=case.cs, gx=case.gx,
+                                               gy=case.gy, rho0=case.rho0, n_sub=case.n_sub,
+                                               kn=case.kn, zeta=case.zeta, rho_s=case.rho_s))
+    p = case.particles
+    ref.set_particles(p.x, p.y, p.r, p.vx, p.vy, p.om, p.mode)
+    t0 = time.perf_counter()
+    ref.step(1)
+    t1 = time.perf_counter() - t0
+    n = max(1, min(200, int(target_s / max(t1, 1e-6))))
+    t0 = time.perf_counter()
+    ref.step(n)
+    dt = time.perf_counter() - t0
+    return {"value": round(case.cells * n / dt / 1e6, 3), "unit": "MLUPS",
+            "cores": oracle.get_threads(), "kind": "oracle",
+            "sample": "%d coupled steps of the %dx%d / %d-disk workload in FP64 (after 1 warm-up "
+                      "step), %.1f s" % (n, case.nx, case.ny, p.n, dt)}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--storage", default="f32", choices=["f64", "f32", "f16"])
+    ap.add_argument("--tile-w", type=int, default=64)
+    ap.add_argument("--tile-rows", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print("bench.py: this build runs on exactly one GPU (got --gpus %d); the lattice would "
+              "shard in y slabs across GPUs, which is not built." % args.gpus, file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_1809_07008_amd import imb, workloads
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    torch.cuda.set_device(0)
+    case = workloads.moving_disks(seed=args.seed, storage=args.storage)
+    sim = imb.simulation_from_case(case, storage=args.storage, tile_w=args.tile_w,
+                                   tile_rows=args.tile_rows)
+    sim.step(args.warmup)
+    sim.sync()
+    print("bench: warmup done", file=sys.stderr, flush=True)
+
+    # timed region: K coupled steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+    mlups = case.cells * args.steps / wall / 1e6
+    print("bench: %d steps %.3f ms/step %.1f MLUPS" % (args.steps, ms_per_step, mlups),
+          file=sys.stderr, flush=True)
+
+    # per-kernel durations with HIP events on the simulation's stream (same K steps again)
+    sim.set_kernel_timing(True)
+    sim.step(args.steps)
+    kt = sim.kernel_timing()
+    sim.set_kernel_timing(False)
+    lat_ms = kt["lattice_ms"] / max(kt["lattice_launches"], 1)
+    par_ms = kt["particle_ms"] / max(kt["particle_launches"], 1)
+    bpl = bytes_per_lup(args.storage)
+    traffic_bytes = case.cells * bpl
+    achieved = traffic_bytes / (lat_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_lattice_step<%s>" % {"f64": "StoreF64", "f32": "StoreF32",
+                                                  "f16": "StoreF16"}[args.storage],
+                "kernel_avg_us": round(lat_ms * 1e3, 2),
+                "bytes_per_launch": traffic_bytes,
+                "particle_phase_avg_us": round(par_ms * 1e3, 2)}
+
+    out = {
+        "metric": "MLUPS & % of HBM roofline, D2Q9 IMB 2048x1024; adjoint/forward time ratio",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.storage,
+        "data": "synthetic (seeded disks, fluid at rest)",
+        "config": {"workload": "moving_disks_2048x1024_n500", "nx": case.nx, "ny": case.ny,
+                   "disks": case.particles.n, "tau0": case.tau0, "smagorinsky_cs": case.cs,
+                   "storage": args.storage, "tile": [args.tile_w, args.tile_rows],
+                   "parallelism": "single GPU"},
+        "hbm_frac_whole_step": round(mlups * 1e6 * bpl / (HBM_PEAK_GBS * 1e9), 4),
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(case)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

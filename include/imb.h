@@ -1,0 +1,214 @@
+/*
+ * imb.h -- C-ABI of libimb.so: the coupled D2Q9 lattice-Boltzmann / immersed-moving-boundary /
+ * DEM time step of Yang, Jing, Kwok & Sobral, "A comprehensive study of coupled LBM-DEM with
+ * immersed moving boundary" (arXiv:1809.07008), on one AMD Instinct MI355X (gfx950).
+ *
+ * Conventions for every call
+ *   - Lattice units: dx = dt = 1.  Node (x, y), 0 <= x < nx, 0 <= y < ny, owns the unit cell
+ *     [x-1/2, x+1/2] x [y-1/2, y+1/2].  x is periodic.  With IMB_FLAG_WALLS the channel has resting
+ *     no-slip walls at y = -1/2 and y = ny-1/2 (half-way bounce-back, Sec. 3.1.1); without it y is
+ *     periodic too.
+ *   - D2Q9 populations, direction order q = 0..8: (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1)
+ *     (-1,-1) (1,-1).  Population arrays exchanged with the caller are FP64, layout [q][y][x].
+ *     Field arrays are FP64 [y][x].  Per-particle arrays are FP64 (mode: int32) of length n.
+ *   - Pointers named host_* or documented as host memory are caller-owned host memory, read or
+ *     written before the call returns.  The library never keeps them.
+ *   - Return value: IMB_OK (0) or a negative IMB_E* code; imb_strerror() names it and
+ *     imb_last_error() gives the message of the last failure on a handle.  No C++ exception
+ *     crosses this interface.
+ *   - All device work is enqueued on the HIP stream given at creation (may be NULL = the null
+ *     stream).  Calls documented as "synchronises" wait for that stream.  Device-side failures
+ *     (IMB_EOVERFLOW, IMB_EUNSTABLE, IMB_EDEM) are latched by the kernels and reported by the next
+ *     synchronising call.  A handle must not be used from two host threads at once.
+ */
+#ifndef IMB_H
+#define IMB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------------------- error codes */
+#define IMB_OK 0
+#define IMB_EINVAL (-1)     /* an argument or configuration is out of range */
+#define IMB_ENOMEM (-2)     /* device allocation failed or the bound buffer is too small */
+#define IMB_EHIP (-3)       /* a HIP runtime call failed */
+#define IMB_EOVERFLOW (-4)  /* a fixed-capacity list overflowed (tile, slot, cell or contact list) */
+#define IMB_EUNSTABLE (-5)  /* a non-finite or non-positive density appeared */
+#define IMB_EDEM (-6)       /* a disk moved more than one cell in one step or left the channel */
+#define IMB_EUNSUPPORTED (-7) /* the call does not support this configuration */
+
+/* ------------------------------------------------------------------ configuration */
+#define IMB_STORAGE_F64 0   /* populations stored as FP64, FP64 arithmetic (parity form) */
+#define IMB_STORAGE_F32 1   /* FP32 deviations f_i - w_i rho0, FP32 arithmetic */
+#define IMB_STORAGE_F16 2   /* FP16 scaled deviations (f_i - w_i rho0) * 2^14, FP32 arithmetic */
+
+#define IMB_FLAG_WALLS 1u   /* resting half-way bounce-back walls in y (else periodic in y) */
+
+#define IMB_MODE_FREE 0      /* moved by the DEM (Eqs. 8, 10, 11, 17) */
+#define IMB_MODE_FIXED 1     /* never moved; its velocity/spin still act on the fluid */
+#define IMB_MODE_PRESCRIBED 2 /* moves by its velocity once per lattice step */
+
+typedef struct imb_config {
+  int32_t nx, ny;          /* lattice size, each >= 2 */
+  int32_t storage;         /* IMB_STORAGE_* */
+  int32_t n_sub;           /* DEM sub-cycles per lattice step, Eq. (17); >= 1 */
+  double tau0;             /* BGK relaxation time, Eqs. (1), (5); must exceed 1/2 */
+  double smag_cs;          /* Smagorinsky constant (Sec. 3.3.2); 0 disables it */
+  double gx, gy;           /* body-force acceleration on the fluid */
+  double rho0;             /* reference density (deviation storage and initial state) */
+  double kn;               /* normal contact stiffness, Eq. (8) */
+  double damping_ratio;    /* normal damping ratio zeta: c_n = 2 zeta sqrt(k_n m_eff) */
+  double rho_solid;        /* disk density: m = rho_solid pi r^2, I = m r^2 / 2 */
+  int32_t max_particles;   /* capacity, 0..1024 */
+  uint32_t flags;          /* IMB_FLAG_* */
+  int32_t tile_w;          /* tile width in cells: 16, 32, 64, 128 or 256 (0 = 64) */
+  int32_t tile_rows;       /* cell rows per thread: 1, 2 or 4 (0 = 1); a tile is
+                              tile_w x (256 / tile_w * tile_rows) cells */
+} imb_config;
+
+typedef struct imb_sim imb_sim;
+
+/* Fills *cfg with defaults: 64x64, F64 storage, tau0 = 0.6, no Smagorinsky, no body force,
+ * rho0 = 1, n_sub = 10, k_n = 1e3, zeta = 0.1, rho_solid = 1, 64 particles, walls, 64-wide tiles. */
+void imb_config_default(imb_config* cfg);
+
+/* Bytes of device memory a simulation with this configuration needs (for imb_create with a
+ * caller-provided buffer). */
+int imb_required_bytes(const imb_config* cfg, size_t* bytes);
+
+/* Validates cfg (tau0 > 1/2 (Sec. 4), nx, ny >= 2, C_s >= 0, storage, capacities) and creates a
+ * simulation bound to hip_stream (a hipStream_t, may be NULL).  If dev_buf is non-NULL it must
+ * point to at least imb_required_bytes() bytes of device memory owned by the caller (for example
+ * a torch tensor), aligned to 256 bytes; the library uses it and never frees it.  If dev_buf is
+ * NULL the library allocates and later frees its own memory.  The populations start at
+ * equilibrium with rho0 and zero velocity and there are no particles. */
+int imb_create(const imb_config* cfg, void* hip_stream, void* dev_buf, size_t dev_bytes,
+               imb_sim** out);
+
+/* Releases the handle (after waiting for its stream).  NULL is ignored. */
+void imb_destroy(imb_sim* sim);
+
+/* f = f^eq(rho, u) everywhere, including inside solids (Eq. 2).  Asynchronous. */
+int imb_init_equilibrium(imb_sim* sim, double rho, double ux, double uy);
+
+/* Sets the post-stream populations (host, FP64, [9][ny][nx]).  Stored in the configured
+ * precision.  Synchronises. */
+int imb_set_populations(imb_sim* sim, const double* host_f);
+
+/* Reads the post-stream populations of the last completed step (host, FP64, [9][ny][nx]).
+ * Synchronises. */
+int imb_get_populations(imb_sim* sim, double* host_f);
+
+/* Density and velocity u = m / rho (Eqs. 3, 4) of the post-stream populations, host FP64
+ * [ny][nx] each (any may be NULL).  Synchronises. */
+int imb_get_fields(imb_sim* sim, double* host_rho, double* host_ux, double* host_uy);
+
+/* Solid ratio eps_tot = sum_p eps_p of every cell for the current disk positions (Sec. 2.2, exact
+ * covered area), host FP64 [ny][nx], computed by the lattice step's own mapping code in the
+ * configured arithmetic precision.  Synchronises. */
+int imb_get_solid_field(imb_sim* sim, double* host_eps);
+
+/* Replaces all disks (host arrays of length n, copied before return): centre (x, y), radius r,
+ * velocity (vx, vy), angular velocity omega, mode IMB_MODE_*.  Requires n <= max_particles,
+ * r > 0, 2 (r + 2) < min(nx, ny) and 0 <= x < nx; with walls the centre must lie between the
+ * walls.  The particles' contact forces are evaluated from this state (Sec. 2.3 starts the
+ * cycle with the generated particles).  Synchronises. */
+int imb_set_particles(imb_sim* sim, int32_t n, const double* x, const double* y, const double* r,
+                      const double* vx, const double* vy, const double* omega,
+                      const int32_t* mode);
+
+/* Enqueues nsteps coupled steps (Sec. 2.3, Fig. 4), each:
+ *   solid ratio of every cell from the disks (Sec. 2.2, exact area) ->
+ *   collision Eq. (13) with weight Eq. (14), Smagorinsky relaxation, body force ->
+ *   streaming Eq. (1) with periodic x and bounce-back walls ->
+ *   force and torque on each disk, Eqs. (15), (16) (sign: force on the particle) ->
+ *   DEM: N_sub velocity-Verlet sub-cycles with that force held fixed (Eqs. 8, 10, 11, 17).
+ * Asynchronous (returns once the work is queued).  nsteps >= 0. */
+int imb_step(imb_sim* sim, int32_t nsteps);
+
+/* Force (fx, fy) and torque tz on each disk from the last completed step, FP64, host arrays of
+ * length n (particle count).  Zero before the first step.  Synchronises. */
+int imb_get_forces(imb_sim* sim, double* fx, double* fy, double* tz);
+
+/* Current disk state (host arrays of length n; any may be NULL).  Synchronises. */
+int imb_get_particles(imb_sim* sim, double* x, double* y, double* vx, double* vy, double* omega);
+
+/* Number of disks and completed steps. */
+int imb_get_counts(imb_sim* sim, int32_t* n_particles, int64_t* steps);
+
+/* Waits for the stream and reports latched device errors. */
+int imb_sync(imb_sim* sim);
+
+/* Byte-exact checkpoint of the whole simulation state (populations in storage precision,
+ * particles, DEM caches, step counter).  imb_state_bytes gives the size; save/load use host
+ * memory and synchronise.  load requires a handle created with the same configuration. */
+int imb_state_bytes(imb_sim* sim, size_t* bytes);
+int imb_save_state(imb_sim* sim, void* host_buf, size_t bytes);
+int imb_load_state(imb_sim* sim, const void* host_buf, size_t bytes);
+
+/* Per-kernel timing with HIP events on the simulation's stream.  When enabled, imb_step records
+ * an event pair around every fused lattice-step launch and every particle-phase launch.
+ * imb_get_kernel_timing synchronises and returns the summed milliseconds and launch counts since
+ * the last reset (any pointer may be NULL). */
+int imb_set_kernel_timing(imb_sim* sim, int enable);
+int imb_get_kernel_timing(imb_sim* sim, double* lattice_ms, int64_t* lattice_launches,
+                          double* particle_ms, int64_t* particle_launches);
+
+/* Streaming copy of n_bytes between two device buffers with the library's copy kernel, for
+ * calibrating bandwidth counters.  Asynchronous on hip_stream. */
+int imb_copy_kernel(void* dst, const void* src, size_t n_bytes, void* hip_stream);
+
+/* Discrete adjoint of nsteps coupled steps from the current state (differentiation form).
+ * Objective J = sum over the nsteps steps and over disks of
+ *     wfx[p] * Fx_p^n + wfy[p] * Fy_p^n + wtz[p] * Tz_p^n     (host weight arrays, any NULL = 0).
+ * Requires all disks in IMB_MODE_PRESCRIBED or IMB_MODE_FIXED, smag_cs = 0 and F32 or F64
+ * storage.  Disk positions follow X_p^n = X_p^0 + n V_p (prescribed) or stay (fixed).
+ * Runs the forward pass saving a checkpoint every k_ckpt steps, then for each segment from the
+ * last recomputes its states and applies the transposed step (Eqs. 1, 12-16 differentiated,
+ * with the analytic solid ratio's derivative with respect to the centre).
+ * Outputs (host, FP64, length n; any may be NULL): dJ/dX0, dJ/dY0, dJ/dVx, dJ/dVy, dJ/domega,
+ * and dJ/dg (2 values) and J itself.  The simulation state afterwards is the state after the
+ * nsteps forward steps.  Synchronises. */
+int imb_adjoint(imb_sim* sim, int32_t nsteps, int32_t k_ckpt, const double* wfx,
+                const double* wfy, const double* wtz, double* gx0, double* gy0, double* gvx,
+                double* gvy, double* gom, double* gg, double* J);
+
+/* -------------------------------------------------------------- batched channels
+ * Many independent simulations (channels) of different sizes and particle counts advanced
+ * together: each step is one persistent kernel launch that walks a work list of
+ * (channel, tile) items for the lattice update and then of channels for the particle phase;
+ * a graph of steps is captured once and replayed.  Every channel uses F32 storage. */
+typedef struct imb_batch imb_batch;
+
+int imb_batch_required_bytes(int32_t nsim, const imb_config* cfgs, size_t* bytes);
+int imb_batch_create(int32_t nsim, const imb_config* cfgs, void* hip_stream, void* dev_buf,
+                     size_t dev_bytes, imb_batch** out);
+void imb_batch_destroy(imb_batch* b);
+int imb_batch_set_particles(imb_batch* b, int32_t sim, int32_t n, const double* x,
+                            const double* y, const double* r, const double* vx, const double* vy,
+                            const double* omega, const int32_t* mode);
+/* Enqueues nsteps steps of every channel. Asynchronous. */
+int imb_batch_step(imb_batch* b, int32_t nsteps);
+int imb_batch_get_forces(imb_batch* b, int32_t sim, double* fx, double* fy, double* tz);
+int imb_batch_get_particles(imb_batch* b, int32_t sim, double* x, double* y, double* vx,
+                            double* vy, double* omega);
+int imb_batch_get_fields(imb_batch* b, int32_t sim, double* rho, double* ux, double* uy);
+int imb_batch_sync(imb_batch* b);
+/* Persistent-grid size (workgroups) and tile shape used by imb_batch_step; settable before the
+ * first step (0 keeps the default: the number of co-resident workgroups). */
+int imb_batch_set_launch(imb_batch* b, int32_t grid, int32_t tile_w, int32_t tile_rows);
+
+/* ------------------------------------------------------------------------ misc */
+const char* imb_strerror(int code);
+const char* imb_last_error(const imb_sim* sim);
+/* Library version string. */
+const char* imb_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IMB_H */

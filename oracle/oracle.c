@@ -132,52 +132,56 @@ static double smagorinsky_tau(double tau0, double cs, double rho, const double f
  * Written as the integral over x of the vertical chord clipped to the cell,
  *   eps = int_{x0}^{x1} max(0, min(y1, s(x)) - max(y0, -s(x))) dx,   s(x) = sqrt(r^2 - x^2),
  * split at every abscissa where the clipping changes, each piece integrated in closed form with
- * int s dx = (x s(x) + r^2 asin(x/r)) / 2  (asin evaluated as atan2(x, s) for conditioning). */
-static double half_chord(double r, double x) { /* sqrt(r^2 - x^2), well conditioned near |x| = r */
-  double a = fabs(x);
-  return a >= r ? 0.0 : sqrt((r - a) * (r + a));
+ * int s dx = (x s(x) + r^2 asin(x/r)) / 2.  The primitive is O(r^2) while a cell's area is O(1),
+ * so the evaluation runs in long double (64-bit significand) and the result is rounded once. */
+typedef long double ld;
+
+static ld half_chord(ld r, ld x) { /* sqrt(r^2 - x^2), well conditioned near |x| = r */
+  ld a = fabsl(x);
+  return a >= r ? 0.0L : sqrtl((r - a) * (r + a));
 }
 
-static double semicircle_primitive(double r, double x) {
+static ld semicircle_primitive(ld r, ld x) {
   if (x > r) x = r;
   if (x < -r) x = -r;
-  double s = half_chord(r, x);
-  return 0.5 * (x * s + r * r * atan2(x, s)); /* atan2(x, s) = asin(x / r) */
+  ld s = half_chord(r, x);
+  return 0.5L * (x * s + r * r * atan2l(x, s)); /* atan2(x, s) = asin(x / r) */
 }
 
-double o_solid_fraction(double r, double dx, double dy) {
-  double x0 = dx - 0.5, x1 = dx + 0.5, y0 = dy - 0.5, y1 = dy + 0.5;
+double o_solid_fraction(double r_, double dx, double dy) {
+  const ld r = r_;
+  ld x0 = (ld)dx - 0.5L, x1 = (ld)dx + 0.5L, y0 = (ld)dy - 0.5L, y1 = (ld)dy + 0.5L;
   /* the cell lies outside the disk when its point nearest to the centre is not inside */
-  double nx = (x0 > 0.0) ? x0 : ((x1 < 0.0) ? x1 : 0.0);
-  double ny = (y0 > 0.0) ? y0 : ((y1 < 0.0) ? y1 : 0.0);
+  ld nx = (x0 > 0.0L) ? x0 : ((x1 < 0.0L) ? x1 : 0.0L);
+  ld ny = (y0 > 0.0L) ? y0 : ((y1 < 0.0L) ? y1 : 0.0L);
   if (nx * nx + ny * ny >= r * r) return 0.0;
   /* the cell lies inside the (convex) disk when its farthest corner does */
-  double fx = fabs(x0) > fabs(x1) ? fabs(x0) : fabs(x1);
-  double fy = fabs(y0) > fabs(y1) ? fabs(y0) : fabs(y1);
+  ld fx = fabsl(x0) > fabsl(x1) ? fabsl(x0) : fabsl(x1);
+  ld fy = fabsl(y0) > fabsl(y1) ? fabsl(y0) : fabsl(y1);
   if (fx * fx + fy * fy <= r * r) return 1.0;
 
-  double bp[8];
+  ld bp[8];
   int nb = 0;
   bp[nb++] = x0;
   bp[nb++] = x1;
-  double cand[6];
+  ld cand[6];
   int nc = 0;
   cand[nc++] = -r;
   cand[nc++] = r;
-  if (fabs(y0) < r) {
-    double w = half_chord(r, y0);
+  if (fabsl(y0) < r) {
+    ld w = half_chord(r, y0);
     cand[nc++] = -w;
     cand[nc++] = w;
   }
-  if (fabs(y1) < r) {
-    double w = half_chord(r, y1);
+  if (fabsl(y1) < r) {
+    ld w = half_chord(r, y1);
     cand[nc++] = -w;
     cand[nc++] = w;
   }
   for (int k = 0; k < nc; ++k)
     if (cand[k] > x0 && cand[k] < x1) bp[nb++] = cand[k];
   for (int a = 1; a < nb; ++a) { /* insertion sort */
-    double v = bp[a];
+    ld v = bp[a];
     int b = a - 1;
     while (b >= 0 && bp[b] > v) {
       bp[b + 1] = bp[b];
@@ -185,24 +189,24 @@ double o_solid_fraction(double r, double dx, double dy) {
     }
     bp[b + 1] = v;
   }
-  double area = 0.0;
+  ld area = 0.0L;
   for (int k = 0; k + 1 < nb; ++k) {
-    double a = bp[k], b = bp[k + 1];
+    ld a = bp[k], b = bp[k + 1];
     if (!(b > a)) continue;
-    double m = 0.5 * (a + b);
-    if (fabs(m) >= r) continue; /* no chord on this piece */
-    double s = half_chord(r, m);
+    ld m = 0.5L * (a + b);
+    if (fabsl(m) >= r) continue; /* no chord on this piece */
+    ld s = half_chord(r, m);
     int top_is_circle = s < y1;
     int bot_is_circle = -s > y0;
-    double top_v = top_is_circle ? s : y1;
-    double bot_v = bot_is_circle ? -s : y0;
+    ld top_v = top_is_circle ? s : y1;
+    ld bot_v = bot_is_circle ? -s : y0;
     if (top_v <= bot_v) continue; /* chord misses the cell on this piece */
-    double semi = semicircle_primitive(r, b) - semicircle_primitive(r, a);
-    double top_int = top_is_circle ? semi : y1 * (b - a);
-    double bot_int = bot_is_circle ? -semi : y0 * (b - a);
+    ld semi = semicircle_primitive(r, b) - semicircle_primitive(r, a);
+    ld top_int = top_is_circle ? semi : y1 * (b - a);
+    ld bot_int = bot_is_circle ? -semi : y0 * (b - a);
     area += top_int - bot_int;
   }
-  return area;
+  return (double)area;
 }
 
 /* ----------------------------------------------------------- collision of one cell
@@ -215,11 +219,16 @@ double o_solid_fraction(double r, double dx, double dy) {
  *   Omega^f_i = -(f_i - f_i^eq(rho, u)) / tau_eff                                    Eq. (1)
  *   Omega^s_{p,i} = f_{-i} - f_{-i}^eq(rho,u) + f_i^eq(rho,u_s) - f_i                Eq. (12)
  *   dF_p = -B_p sum_i Omega^s_{p,i} c_i ,  dT_p = d x dF_p                           Eqs. (15), (16)
+ * The inner sum of Eq. (15) is evaluated in closed form: with Eq. (4) and the first moment of the
+ * equilibrium, sum_i c_i f_i^eq(rho, v) = rho v, it is exactly rho u_s - m.  Summing the nine
+ * terms literally subtracts O(0.1) populations to get an O(1e-6) result and loses about four
+ * digits, more than the agreement this oracle has to certify; the literal sum is still returned
+ * (lit, optional) so that the identity is checked.
  */
 int o_collide_cell(const double *f, int np, const double *eps, const double *dxs,
                    const double *dys, const double *pvx, const double *pvy, const double *pom,
                    double tau0, double cs, double gx, double gy, double *fout, double *dfx,
-                   double *dfy, double *dtz, double *diag) {
+                   double *dfy, double *dtz, double *diag, double *lit) {
   double rho = 0.0, mx = 0.0, my = 0.0;
   for (int i = 0; i < NQ; ++i) rho += f[i];
   for (int i = 0; i < NQ; ++i) {
@@ -255,9 +264,13 @@ int o_collide_cell(const double *f, int np, const double *eps, const double *dxs
       sx += CX[i] * Os;
       sy += CY[i] * Os;
     }
-    dfx[p] = -Bp * sx;
-    dfy[p] = -Bp * sy;
+    dfx[p] = Bp * (mx - rho * usx);
+    dfy[p] = Bp * (my - rho * usy);
     dtz[p] = dxs[p] * dfy[p] - dys[p] * dfx[p];
+    if (lit) {
+      lit[2 * p] = -Bp * sx;
+      lit[2 * p + 1] = -Bp * sy;
+    }
   }
   if (diag) {
     diag[0] = tau;
@@ -586,7 +599,7 @@ static void collide_all(osim *s) {
       o_collide_cell(s->f + k * NQ, ns, s->seps + k * MAX_SLOTS, s->sdx + k * MAX_SLOTS,
                      s->sdy + k * MAX_SLOTS, pvx, pvy, pom, s->c.tau0, s->c.cs, s->c.gx, s->c.gy,
                      s->fp + k * NQ, s->sfx + k * MAX_SLOTS, s->sfy + k * MAX_SLOTS,
-                     s->stz + k * MAX_SLOTS, NULL);
+                     s->stz + k * MAX_SLOTS, NULL, NULL);
     }
   }
 }

@@ -68,7 +68,8 @@ def _load():
         lib.o_weight.restype = C.c_double
         lib.o_weight.argtypes = [C.c_double, C.c_double]
         lib.o_collide_cell.argtypes = [_D, C.c_int, _D, _D, _D, _D, _D, _D, C.c_double,
-                                       C.c_double, C.c_double, C.c_double, _D, _D, _D, _D, _D]
+                                       C.c_double, C.c_double, C.c_double, _D, _D, _D, _D, _D,
+                                       _D]
         lib.o_step_count.restype = C.c_long
         lib.o_step_count.argtypes = [C.c_void_p]
         _lib = lib
@@ -102,8 +103,10 @@ def weight(eps: float, tau: float) -> float:
     return float(_load().o_weight(eps, tau))
 
 
-def collide_cell(f, eps=(), dx=(), dy=(), vx=(), vy=(), om=(), tau0=0.6, cs=0.0, gx=0.0, gy=0.0):
-    """One-cell collision (Eqs. 1, 12-16).  Returns (f_out[9], dF[n,2], dT[n], tau_eff, B_tot)."""
+def collide_cell(f, eps=(), dx=(), dy=(), vx=(), vy=(), om=(), tau0=0.6, cs=0.0, gx=0.0, gy=0.0,
+                 literal=False):
+    """One-cell collision (Eqs. 1, 12-16).  Returns (f_out[9], dF[n,2], dT[n], tau_eff, B_tot),
+    plus the literal nine-term force sums [n,2] when ``literal``."""
     lib = _load()
     f = _f64(f)
     n = len(eps)
@@ -111,9 +114,14 @@ def collide_cell(f, eps=(), dx=(), dy=(), vx=(), vy=(), om=(), tau0=0.6, cs=0.0,
     fout = np.zeros(9)
     dfx = np.zeros(max(n, 1)); dfy = np.zeros(max(n, 1)); dtz = np.zeros(max(n, 1))
     diag = np.zeros(2)
+    lit = np.zeros(2 * max(n, 1))
     lib.o_collide_cell(_dp(f), n, _dp(eps), _dp(dx), _dp(dy), _dp(vx), _dp(vy), _dp(om),
-                       tau0, cs, gx, gy, _dp(fout), _dp(dfx), _dp(dfy), _dp(dtz), _dp(diag))
-    return fout, np.stack([dfx[:n], dfy[:n]], axis=1), dtz[:n].copy(), diag[0], diag[1]
+                       tau0, cs, gx, gy, _dp(fout), _dp(dfx), _dp(dfy), _dp(dtz), _dp(diag),
+                       _dp(lit))
+    out = (fout, np.stack([dfx[:n], dfy[:n]], axis=1), dtz[:n].copy(), diag[0], diag[1])
+    if literal:
+        return out + (lit[: 2 * n].reshape(n, 2),)
+    return out
 
 
 @dataclass

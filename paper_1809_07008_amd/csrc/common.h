@@ -1,0 +1,188 @@
+// common.h -- internal definitions shared by the HIP kernels and the host runtime of libimb.
+//
+// Method: Yang, Jing, Kwok & Sobral, "A comprehensive study of coupled LBM-DEM with immersed
+// moving boundary" (arXiv:1809.07008), Sec. 2 (LBM, DEM, IMB, coupling), in two dimensions (D2Q9).
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "imb.h"
+
+namespace imb {
+
+constexpr int NQ = 9;              // D2Q9
+constexpr int BLOCK = 256;         // threads of a lattice-step workgroup (4 wave64)
+constexpr int WAVES = BLOCK / 64;
+constexpr int LMAX = 32;           // disks whose boxes may touch one tile
+constexpr int MAXC = 4;            // disks covering one cell (three cannot unless they overlap)
+constexpr int MAXSLOT = 48;        // tiles per disk box (partial-sum slots per disk)
+constexpr int NBMAX = 32;          // DEM neighbour-list capacity per disk
+constexpr int MAX_PARTICLES = 1024;
+constexpr int PBLOCK = 1024;       // threads of the particle-phase workgroup
+constexpr double DEM_SKIN = 3.0;   // neighbour-list skin (lattice units)
+constexpr double MAX_MOVE = 1.0;   // largest displacement of a disk in one lattice step
+constexpr float F16_SCALE = 16384.0f;  // power-of-two scale of FP16 deviations
+
+// Device error bits, latched in one int by the kernels and mapped to IMB_E* by the host.
+enum : int {
+  ERR_TILE_LIST = 1,   // more than LMAX disk boxes touch a tile
+  ERR_SLOTS = 2,       // a disk box spans more than MAXSLOT tiles
+  ERR_CELL = 4,        // more than MAXC disks cover one cell / one thread column
+  ERR_RHO = 8,         // non-finite or non-positive density
+  ERR_NBR = 16,        // DEM neighbour list full
+  ERR_MOVE = 32,       // a disk moved more than MAX_MOVE in one step
+  ERR_LEFT = 64,       // a disk centre left the channel between the walls
+};
+
+// D2Q9 velocity set (the paper's Table 1 gives the 3D D3Q19 set; its 2D analogue here).
+__host__ __device__ constexpr int cx_of(int i) {
+  return i == 1 || i == 5 || i == 8 ? 1 : (i == 3 || i == 6 || i == 7 ? -1 : 0);
+}
+__host__ __device__ constexpr int cy_of(int i) {
+  return i == 2 || i == 5 || i == 6 ? 1 : (i == 4 || i == 7 || i == 8 ? -1 : 0);
+}
+__host__ __device__ constexpr int opp_of(int i) {
+  return i == 0 ? 0 : (i <= 4 ? ((i + 1) & 3) + 1 : ((i - 3) & 3) + 5);
+}
+__host__ __device__ constexpr double w_of(int i) {
+  return i == 0 ? 4.0 / 9.0 : (i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0);
+}
+static_assert(opp_of(1) == 3 && opp_of(2) == 4 && opp_of(3) == 1 && opp_of(4) == 2, "opp");
+static_assert(opp_of(5) == 7 && opp_of(6) == 8 && opp_of(7) == 5 && opp_of(8) == 6, "opp");
+
+// Disk data for the lattice step, rewritten by the particle phase after every DEM update.
+struct ParticleTable {
+  int4* box;      // tile box: (tx0, ntx, ty0, nty); ntx * nty partial-sum slots
+  double4* pos;   // (X, Y, r, 0)
+  double4* vel;   // (Vx, Vy, omega, 0)
+};
+
+// Everything one lattice step of one channel needs.
+struct LatticeArgs {
+  int nx, ny, pitch, walls;
+  int tiles_x, tiles_y;  // tile grid
+  int tw_log, rows;      // tile = (1 << tw_log) x ((BLOCK >> tw_log) * rows) cells
+  long long plane;       // elements per population plane (pitch * ny)
+  double tau0, cs, gx, gy, rho0;
+  const void* src;       // stored post-collision populations of the previous step
+  void* dst;             // post-collision populations of this step
+  int np;
+  ParticleTable tab;
+  double4* partials;     // [np][MAXSLOT] force / torque partial sums (Fx, Fy, Tz, 0)
+  int* err;
+};
+
+// Particle state on the device (structure of arrays, FP64).
+struct ParticleState {
+  double *x, *y, *r, *vx, *vy, *om;
+  int* mode;
+  double *fcx, *fcy;      // contact force of the last DEM evaluation
+  double *Fx, *Fy, *Tz;   // hydrodynamic force / torque of the last step
+  double *xref, *yref;    // positions at the last neighbour-list build
+  int* nbr;               // [np][NBMAX] neighbour ids, ascending
+  int* nnbr;              // neighbours per disk
+  int* rebuild;           // 1: rebuild the neighbour list before the next DEM phase
+};
+
+struct ParticleArgs {
+  int np, nx, ny, walls, n_sub;
+  double kn, zeta, rho_s;
+  int tiles_x, tiles_y, tw, th;
+  ParticleState s;
+  ParticleTable tab;
+  const double4* partials;
+  int do_finalize, do_dem, do_table, init_contacts;
+  const double *wfx, *wfy, *wtz;  // objective weights (adjoint forward); may be null
+  double* J;                      // objective accumulator; null = not accumulated
+  int* err;
+};
+
+// Storage codecs: how a population is kept in memory and what precision the step computes in.
+struct StoreF64 {
+  using T = double;
+  using S = double;
+  static constexpr bool deviation = false;
+  __device__ static T load(const S* p, long long i, T) { return p[i]; }
+  __device__ static void store(S* p, long long i, T v, T) { p[i] = v; }
+};
+struct StoreF32 {
+  using T = float;
+  using S = float;
+  static constexpr bool deviation = true;
+  __device__ static T load(const S* p, long long i, T) { return p[i]; }
+  __device__ static void store(S* p, long long i, T v, T) { p[i] = v; }
+};
+struct StoreF16 {
+  using T = float;
+  using S = __half;
+  static constexpr bool deviation = true;
+  __device__ static T load(const S* p, long long i, T) {
+    return __half2float(p[i]) * (1.0f / F16_SCALE);
+  }
+  __device__ static void store(S* p, long long i, T v, T) { p[i] = __float2half_rn(v * F16_SCALE); }
+};
+
+// Block index -> tile index so that consecutive tiles run on the same XCD (workgroups are
+// dispatched round-robin over the 8 XCDs, each with its own L2).
+__device__ inline int xcd_remap(int b, int n) {
+  const int q = n >> 3, r = n & 7;
+  const int xcd = b & 7, j = b >> 3;
+  return xcd * q + (xcd < r ? xcd : r) + j;
+}
+
+__host__ __device__ inline int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+__host__ __device__ inline int wrap_int(int a, int n) { int m = a % n; return m < 0 ? m + n : m; }
+
+// Tile box of a disk: the cyclic range of tiles that contain a cell of its bounding box
+// [floor(X - r - 1/2), ceil(X + r + 1/2)] (only those cells can be covered).  Returns false if
+// the box needs more than MAXSLOT slots.
+__host__ __device__ inline bool tile_box(double X, double Y, double r, int nx, int ny, int walls,
+                                         int tiles_x, int tiles_y, int tw, int th, int4* out) {
+  const int ix0 = (int)floor(X - r - 0.5), ix1 = (int)ceil(X + r + 0.5);
+  int tx0, ntx;
+  if (ix1 - ix0 + 1 > nx - tw) {
+    tx0 = 0;
+    ntx = tiles_x;
+  } else {
+    tx0 = wrap_int(ix0, nx) / tw;
+    const int txe = wrap_int(ix1, nx) / tw;
+    ntx = wrap_int(txe - tx0, tiles_x) + 1;
+  }
+  int iy0 = (int)floor(Y - r - 0.5), iy1 = (int)ceil(Y + r + 0.5);
+  int ty0, nty;
+  if (walls) {
+    if (iy0 < 0) iy0 = 0;
+    if (iy1 > ny - 1) iy1 = ny - 1;
+    if (iy0 > iy1) {
+      ty0 = 0;
+      nty = 0;
+    } else {
+      ty0 = iy0 / th;
+      nty = iy1 / th - ty0 + 1;
+    }
+  } else if (iy1 - iy0 + 1 > ny - th) {
+    ty0 = 0;
+    nty = tiles_y;
+  } else {
+    ty0 = wrap_int(iy0, ny) / th;
+    const int tye = wrap_int(iy1, ny) / th;
+    nty = wrap_int(tye - ty0, tiles_y) + 1;
+  }
+  *out = make_int4(tx0, ntx, ty0, nty);
+  return ntx * nty <= MAXSLOT;
+}
+
+// Slot of tile (tx, ty) in a disk's box, or -1 if the tile is outside it.
+__device__ inline int box_slot(int4 b, int tx, int ty, int tiles_x, int tiles_y) {
+  int lx = tx - b.x;
+  if (lx < 0) lx += tiles_x;
+  if (lx >= b.y) return -1;
+  int ly = ty - b.z;
+  if (ly < 0) ly += tiles_y;
+  if (ly >= b.w) return -1;
+  return ly * b.y + lx;
+}
+
+}  // namespace imb

@@ -1,0 +1,59 @@
+// runtime.h -- internal host-side structures shared by runtime.hip, adjoint.hip and batch.hip.
+#pragma once
+
+#include <string>
+
+#include "step.h"
+
+namespace imb {
+
+struct Geometry {
+  int tw, tw_log, th, rows;  // tile: tw x th cells (th already includes rows)
+  int tiles_x, tiles_y;
+  int pitch;
+  long long plane;
+};
+
+struct DeviceLayout {
+  void* f[2];
+  ParticleState ps;
+  ParticleTable tab;
+  double4* partials;
+  int* err;
+  double* J;
+  double* w;  // objective weights wfx, wfy, wtz (3 x capacity)
+};
+
+struct AdjointState;
+
+// Pointers into an imb_sim for the other translation units.
+struct SimView {
+  imb_config* cfg;
+  Geometry* g;
+  DeviceLayout* d;
+  hipStream_t stream;
+  int* cur;
+  int* np;
+  int64_t* steps;
+  std::string* err;
+  AdjointState** adj;
+};
+
+size_t align_up(size_t v, size_t a);
+void sim_geometry(const imb_config& c, Geometry* g);
+size_t layout(const imb_config& c, char* base, DeviceLayout* L);
+int validate_config(const imb_config* c, std::string* why);
+int hip_fail(std::string* err, hipError_t e, const char* what);
+int map_device_error(int bits);
+std::string describe_device_error(int bits);
+
+SimView sim_view(imb_sim* s);
+LatticeArgs lattice_args(imb_sim* s, const void* src, void* dst);
+ParticleArgs particle_args(imb_sim* s);
+void enqueue_step(imb_sim* s, const double* wfx, const double* wfy, const double* wtz, double* J);
+int sync_and_check(imb_sim* s);
+int reset_device_error(imb_sim* s);
+void free_adjoint(imb_sim* s);
+
+}  // namespace imb
+

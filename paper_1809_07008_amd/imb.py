@@ -1,0 +1,332 @@
+"""Thin ctypes binding of libimb.so (C-ABI declared in include/imb.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP kernels.  PyTorch
+supplies the device memory (one uint8 workspace tensor per simulation, bound with
+``imb_create``) and the stream (the current torch stream).  If the library is missing this
+module raises on first use; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libimb.so")
+
+STORAGE = {"f64": 0, "f32": 1, "f16": 2}
+FLAG_WALLS = 1
+MODE_FREE, MODE_FIXED, MODE_PRESCRIBED = 0, 1, 2
+
+IMB_OK = 0
+ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EOVERFLOW", -5: "EUNSTABLE", -6: "EDEM",
+          -7: "EUNSUPPORTED"}
+
+# every symbol include/imb.h declares
+EXPORTED = [
+    "imb_config_default", "imb_required_bytes", "imb_create", "imb_destroy",
+    "imb_init_equilibrium", "imb_set_populations", "imb_get_populations", "imb_get_fields",
+    "imb_set_particles", "imb_step", "imb_get_forces", "imb_get_particles", "imb_get_counts",
+    "imb_sync", "imb_state_bytes", "imb_save_state", "imb_load_state", "imb_set_kernel_timing",
+    "imb_get_kernel_timing", "imb_copy_kernel", "imb_adjoint", "imb_batch_required_bytes",
+    "imb_batch_create", "imb_batch_destroy", "imb_batch_set_particles", "imb_batch_step",
+    "imb_batch_get_forces", "imb_batch_get_particles", "imb_batch_get_fields", "imb_batch_sync",
+    "imb_batch_set_launch", "imb_strerror", "imb_last_error", "imb_version",
+    "imb_get_solid_field",
+]
+
+
+class ImbError(RuntimeError):
+    def __init__(self, code: int, what: str, detail: str = ""):
+        self.code = code
+        super().__init__("%s failed: %s (%d)%s" % (what, ERRORS.get(code, "?"), code,
+                                                   (": " + detail) if detail else ""))
+
+
+class Config(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("storage", C.c_int32),
+                ("n_sub", C.c_int32), ("tau0", C.c_double), ("smag_cs", C.c_double),
+                ("gx", C.c_double), ("gy", C.c_double), ("rho0", C.c_double),
+                ("kn", C.c_double), ("damping_ratio", C.c_double), ("rho_solid", C.c_double),
+                ("max_particles", C.c_int32), ("flags", C.c_uint32), ("tile_w", C.c_int32),
+                ("tile_rows", C.c_int32)]
+
+
+_lib = None
+_D = C.POINTER(C.c_double)
+_I32 = C.POINTER(C.c_int32)
+_VP = C.c_void_p
+
+
+def load_library():
+    """Load libimb.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    # torch must be imported first: libimb.so then binds to the HIP runtime torch already
+    # loaded (same SONAME) instead of bringing a second runtime into the process
+    import torch  # noqa: F401
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libimb.so not found at %s: build it with "
+                           "`python -m paper_1809_07008_amd.build`" % LIB_PATH)
+    lib = C.CDLL(LIB_PATH)
+    P = C.POINTER
+    sig = {
+        "imb_config_default": (None, [P(Config)]),
+        "imb_required_bytes": (C.c_int, [P(Config), P(C.c_size_t)]),
+        "imb_create": (C.c_int, [P(Config), _VP, _VP, C.c_size_t, P(_VP)]),
+        "imb_destroy": (None, [_VP]),
+        "imb_init_equilibrium": (C.c_int, [_VP, C.c_double, C.c_double, C.c_double]),
+        "imb_set_populations": (C.c_int, [_VP, _D]),
+        "imb_get_populations": (C.c_int, [_VP, _D]),
+        "imb_get_fields": (C.c_int, [_VP, _D, _D, _D]),
+        "imb_get_solid_field": (C.c_int, [_VP, _D]),
+        "imb_set_particles": (C.c_int, [_VP, C.c_int32, _D, _D, _D, _D, _D, _D, _I32]),
+        "imb_step": (C.c_int, [_VP, C.c_int32]),
+        "imb_get_forces": (C.c_int, [_VP, _D, _D, _D]),
+        "imb_get_particles": (C.c_int, [_VP, _D, _D, _D, _D, _D]),
+        "imb_get_counts": (C.c_int, [_VP, _I32, P(C.c_int64)]),
+        "imb_sync": (C.c_int, [_VP]),
+        "imb_state_bytes": (C.c_int, [_VP, P(C.c_size_t)]),
+        "imb_save_state": (C.c_int, [_VP, _VP, C.c_size_t]),
+        "imb_load_state": (C.c_int, [_VP, _VP, C.c_size_t]),
+        "imb_set_kernel_timing": (C.c_int, [_VP, C.c_int]),
+        "imb_get_kernel_timing": (C.c_int, [_VP, _D, P(C.c_int64), _D, P(C.c_int64)]),
+        "imb_copy_kernel": (C.c_int, [_VP, _VP, C.c_size_t, _VP]),
+        "imb_adjoint": (C.c_int, [_VP, C.c_int32, C.c_int32, _D, _D, _D, _D, _D, _D, _D, _D,
+                                  _D, _D]),
+        "imb_batch_required_bytes": (C.c_int, [C.c_int32, P(Config), P(C.c_size_t)]),
+        "imb_batch_create": (C.c_int, [C.c_int32, P(Config), _VP, _VP, C.c_size_t, P(_VP)]),
+        "imb_batch_destroy": (None, [_VP]),
+        "imb_batch_set_particles": (C.c_int, [_VP, C.c_int32, C.c_int32, _D, _D, _D, _D, _D, _D,
+                                              _I32]),
+        "imb_batch_step": (C.c_int, [_VP, C.c_int32]),
+        "imb_batch_get_forces": (C.c_int, [_VP, C.c_int32, _D, _D, _D]),
+        "imb_batch_get_particles": (C.c_int, [_VP, C.c_int32, _D, _D, _D, _D, _D]),
+        "imb_batch_get_fields": (C.c_int, [_VP, C.c_int32, _D, _D, _D]),
+        "imb_batch_sync": (C.c_int, [_VP]),
+        "imb_batch_set_launch": (C.c_int, [_VP, C.c_int32, C.c_int32, C.c_int32]),
+        "imb_strerror": (C.c_char_p, [C.c_int]),
+        "imb_last_error": (C.c_char_p, [_VP]),
+        "imb_version": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _dp(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(_D)
+
+
+def _f64(a, n=None) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if n is not None and a.shape != (n,):
+        raise ValueError("expected %d values, got shape %s" % (n, a.shape))
+    return a
+
+
+def make_config(nx, ny, tau0, storage="f64", walls=True, cs=0.0, gx=0.0, gy=0.0, rho0=1.0,
+                n_sub=10, kn=1.0e3, zeta=0.1, rho_s=1.0, max_particles=64, tile_w=64,
+                tile_rows=1) -> Config:
+    c = Config()
+    load_library().imb_config_default(C.byref(c))
+    c.nx, c.ny, c.tau0 = int(nx), int(ny), float(tau0)
+    c.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    c.smag_cs, c.gx, c.gy, c.rho0 = float(cs), float(gx), float(gy), float(rho0)
+    c.n_sub, c.kn, c.damping_ratio, c.rho_solid = int(n_sub), float(kn), float(zeta), float(rho_s)
+    c.max_particles = int(max_particles)
+    c.flags = FLAG_WALLS if walls else 0
+    c.tile_w, c.tile_rows = int(tile_w), int(tile_rows)
+    return c
+
+
+def config_from_case(case, max_particles=None, tile_w=64, tile_rows=1, storage=None) -> Config:
+    """Config of a :class:`paper_1809_07008_amd.workloads.Case`."""
+    n = case.particles.n
+    return make_config(case.nx, case.ny, case.tau0, storage or case.storage, case.walls, case.cs,
+                       case.gx, case.gy, case.rho0, case.n_sub, case.kn, case.zeta, case.rho_s,
+                       max(n, 1) if max_particles is None else max_particles, tile_w, tile_rows)
+
+
+def _stream_handle(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Simulation:
+    """One simulation; device memory is a torch uint8 tensor owned by this object."""
+
+    def __init__(self, cfg: Config, stream=None, device="cuda"):
+        import torch
+        lib = load_library()
+        self.cfg = cfg
+        nbytes = C.c_size_t()
+        self._check(lib.imb_required_bytes(C.byref(cfg), C.byref(nbytes)), "imb_required_bytes",
+                    handle=False)
+        self._buf = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=device)
+        ptr = self._buf.data_ptr()
+        off = (-ptr) % 256
+        self._stream = stream
+        h = C.c_void_p()
+        self._check(lib.imb_create(C.byref(cfg), _stream_handle(stream), C.c_void_p(ptr + off),
+                                   nbytes.value, C.byref(h)), "imb_create", handle=False)
+        self._h = h
+        self.n = 0
+
+    def _check(self, rc, what, handle=True):
+        if rc != IMB_OK:
+            lib = load_library()
+            msg = lib.imb_last_error(self._h if handle else None)
+            raise ImbError(rc, what, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().imb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def shape(self):
+        return (self.cfg.ny, self.cfg.nx)
+
+    def init_equilibrium(self, rho=1.0, ux=0.0, uy=0.0):
+        self._check(load_library().imb_init_equilibrium(self._h, rho, ux, uy),
+                    "imb_init_equilibrium")
+
+    def set_populations(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        if f.shape != (9, self.cfg.ny, self.cfg.nx):
+            raise ValueError("populations must have shape (9, ny, nx)")
+        self._check(load_library().imb_set_populations(self._h, _dp(f)), "imb_set_populations")
+
+    def populations(self) -> np.ndarray:
+        f = np.empty((9, self.cfg.ny, self.cfg.nx))
+        self._check(load_library().imb_get_populations(self._h, _dp(f)), "imb_get_populations")
+        return f
+
+    def fields(self):
+        rho, ux, uy = (np.empty(self.shape) for _ in range(3))
+        self._check(load_library().imb_get_fields(self._h, _dp(rho), _dp(ux), _dp(uy)),
+                    "imb_get_fields")
+        return rho, ux, uy
+
+    def solid_field(self) -> np.ndarray:
+        e = np.empty(self.shape)
+        self._check(load_library().imb_get_solid_field(self._h, _dp(e)), "imb_get_solid_field")
+        return e
+
+    def set_particles(self, x, y, r, vx=None, vy=None, om=None, mode=None):
+        n = len(x)
+        z = np.zeros(n)
+        arrs = [_f64(a, n) for a in (x, y, r, z if vx is None else vx, z if vy is None else vy,
+                                      z if om is None else om)]
+        md = np.ascontiguousarray(np.zeros(n, np.int32) if mode is None else mode, np.int32)
+        if n == 0:
+            arrs = [np.zeros(1) for _ in range(6)]
+            md = np.zeros(1, np.int32)
+        self._check(load_library().imb_set_particles(self._h, n, *(_dp(a) for a in arrs),
+                                                     md.ctypes.data_as(_I32)),
+                    "imb_set_particles")
+        self.n = n
+
+    def set_case_particles(self, p):
+        self.set_particles(p.x, p.y, p.r, p.vx, p.vy, p.om, p.mode)
+
+    def step(self, n: int = 1):
+        self._check(load_library().imb_step(self._h, int(n)), "imb_step")
+
+    def forces(self):
+        m = max(self.n, 1)
+        fx, fy, tz = np.zeros(m), np.zeros(m), np.zeros(m)
+        self._check(load_library().imb_get_forces(self._h, _dp(fx), _dp(fy), _dp(tz)),
+                    "imb_get_forces")
+        return fx[: self.n], fy[: self.n], tz[: self.n]
+
+    def particles(self):
+        m = max(self.n, 1)
+        a = [np.zeros(m) for _ in range(5)]
+        self._check(load_library().imb_get_particles(self._h, *(_dp(v) for v in a)),
+                    "imb_get_particles")
+        return tuple(v[: self.n] for v in a)
+
+    def counts(self):
+        n = C.c_int32()
+        s = C.c_int64()
+        self._check(load_library().imb_get_counts(self._h, C.byref(n), C.byref(s)),
+                    "imb_get_counts")
+        return n.value, s.value
+
+    def sync(self):
+        self._check(load_library().imb_sync(self._h), "imb_sync")
+
+    def save_state(self) -> bytes:
+        lib = load_library()
+        nb = C.c_size_t()
+        self._check(lib.imb_state_bytes(self._h, C.byref(nb)), "imb_state_bytes")
+        buf = C.create_string_buffer(nb.value)
+        self._check(lib.imb_save_state(self._h, buf, nb.value), "imb_save_state")
+        return buf.raw
+
+    def load_state(self, data: bytes):
+        buf = C.create_string_buffer(data, len(data))
+        self._check(load_library().imb_load_state(self._h, buf, len(data)), "imb_load_state")
+        n = C.c_int32()
+        load_library().imb_get_counts(self._h, C.byref(n), None)
+        self.n = n.value
+
+    def set_kernel_timing(self, on: bool):
+        self._check(load_library().imb_set_kernel_timing(self._h, 1 if on else 0),
+                    "imb_set_kernel_timing")
+
+    def kernel_timing(self):
+        lm, pm = C.c_double(), C.c_double()
+        ln, pn = C.c_int64(), C.c_int64()
+        self._check(load_library().imb_get_kernel_timing(self._h, C.byref(lm), C.byref(ln),
+                                                         C.byref(pm), C.byref(pn)),
+                    "imb_get_kernel_timing")
+        return {"lattice_ms": lm.value, "lattice_launches": ln.value,
+                "particle_ms": pm.value, "particle_launches": pn.value}
+
+    def adjoint(self, nsteps: int, k_ckpt: int, wfx=None, wfy=None, wtz=None):
+        """Discrete adjoint of nsteps steps; returns dict of gradients and J."""
+        n = self.n
+        m = max(n, 1)
+        w = [None if a is None else _f64(a, n) for a in (wfx, wfy, wtz)]
+        outs = [np.zeros(m) for _ in range(5)]
+        gg = np.zeros(2)
+        J = np.zeros(1)
+        self._check(load_library().imb_adjoint(self._h, int(nsteps), int(k_ckpt),
+                                               *(_dp(a) for a in w), *(_dp(o) for o in outs),
+                                               _dp(gg), _dp(J)), "imb_adjoint")
+        names = ["x0", "y0", "vx", "vy", "om"]
+        res = {k: v[:n] for k, v in zip(names, outs)}
+        res["g"] = gg
+        res["J"] = float(J[0])
+        return res
+
+
+def copy_kernel(dst_ptr: int, src_ptr: int, nbytes: int, stream=None) -> None:
+    rc = load_library().imb_copy_kernel(C.c_void_p(dst_ptr), C.c_void_p(src_ptr), int(nbytes),
+                                        _stream_handle(stream))
+    if rc != IMB_OK:
+        raise ImbError(rc, "imb_copy_kernel")
+
+
+def simulation_from_case(case, storage=None, tile_w=64, tile_rows=1, max_particles=None,
+                         stream=None) -> Simulation:
+    """Simulation of a workload case, particles uploaded, fluid at rest."""
+    sim = Simulation(config_from_case(case, max_particles, tile_w, tile_rows, storage), stream)
+    sim.set_case_particles(case.particles)
+    return sim

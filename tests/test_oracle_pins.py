@@ -87,7 +87,7 @@ def test_solid_fraction_symmetries_and_range():
         assert 0.0 <= e <= 1.0
         for ex in (oracle.solid_fraction(r, -dx, dy), oracle.solid_fraction(r, dx, -dy),
                    oracle.solid_fraction(r, dy, dx)):
-            assert abs(ex - e) < 1e-12
+            assert abs(ex - e) < 1e-15
 
 
 def test_solid_fraction_small_disk_inside_one_cell():
@@ -139,8 +139,8 @@ def test_collision_conserves_mass_and_momentum_balance(np_, cs):
         dx, dy = rng.uniform(-5, 5, np_), rng.uniform(-5, 5, np_)
         vx, vy, om = rng.normal(0, 0.02, np_), rng.normal(0, 0.02, np_), rng.normal(0, 0.003, np_)
         gx, gy = rng.normal(0, 1e-4, 2)
-        fo, dF, dT, tau, Bt = oracle.collide_cell(f, eps, dx, dy, vx, vy, om, tau0=0.65, cs=cs,
-                                                  gx=gx, gy=gy)
+        fo, dF, dT, tau, Bt, lit = oracle.collide_cell(f, eps, dx, dy, vx, vy, om, tau0=0.65,
+                                                       cs=cs, gx=gx, gy=gy, literal=True)
         rho, mx, my = moments(f)
         rho2, mx2, my2 = moments(fo)
         # P1: mass
@@ -153,7 +153,9 @@ def test_collision_conserves_mass_and_momentum_balance(np_, cs):
             usx, usy = vx[p] - om[p] * dy[p], vy[p] + om[p] * dx[p]
             ex += Bp * (rho * usx - mx)
             ey += Bp * (rho * usy - my)
-            # P3: the literal force sum equals its closed form B_p (m - rho u_s)
+            # P3: the literal nine-term sum -B_p sum_i Omega^s_i c_i (Eq. 15) equals the force
+            # the oracle reports, B_p (m - rho u_s)
+            assert abs(dF[p, 0] - lit[p, 0]) < 1e-15 and abs(dF[p, 1] - lit[p, 1]) < 1e-15
             assert abs(dF[p, 0] - Bp * (mx - rho * usx)) < 1e-15
             assert abs(dF[p, 1] - Bp * (my - rho * usy)) < 1e-15
             assert abs(dT[p] - (dx[p] * dF[p, 1] - dy[p] * dF[p, 0])) < 1e-15
