@@ -63,7 +63,7 @@ typedef struct imb_config {
   double kn;               /* normal contact stiffness, Eq. (8) */
   double damping_ratio;    /* normal damping ratio zeta: c_n = 2 zeta sqrt(k_n m_eff) */
   double rho_solid;        /* disk density: m = rho_solid pi r^2, I = m r^2 / 2 */
-  int32_t max_particles;   /* capacity, 0..1024 */
+  int32_t max_particles;   /* capacity, 0..512 */
   uint32_t flags;          /* IMB_FLAG_* */
   int32_t tile_w;          /* tile width in cells: 16, 32, 64, 128 or 256 (0 = 64) */
   int32_t tile_rows;       /* cell rows per thread: 1, 2 or 4 (0 = 1); a tile is
@@ -129,6 +129,11 @@ int imb_set_particles(imb_sim* sim, int32_t n, const double* x, const double* y,
  *   DEM: N_sub velocity-Verlet sub-cycles with that force held fixed (Eqs. 8, 10, 11, 17).
  * Asynchronous (returns once the work is queued).  nsteps >= 0. */
 int imb_step(imb_sim* sim, int32_t nsteps);
+
+/* imb_step replays captured HIP graphs of 2 or 32 steps (captured on first use, re-captured
+ * after imb_set_particles / imb_load_state); enable = 0 makes it launch every kernel directly.
+ * Per-kernel timing (imb_set_kernel_timing) always launches directly.  Synchronises. */
+int imb_set_graphs(imb_sim* sim, int enable);
 
 /* Force (fx, fy) and torque tz on each disk from the last completed step, FP64, host arrays of
  * length n (particle count).  Zero before the first step.  Synchronises. */

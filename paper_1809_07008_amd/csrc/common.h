@@ -17,10 +17,11 @@ constexpr int BLOCK = 256;         // threads of a lattice-step workgroup (4 wav
 constexpr int WAVES = BLOCK / 64;
 constexpr int LMAX = 32;           // disks whose boxes may touch one tile
 constexpr int MAXC = 4;            // disks covering one cell (three cannot unless they overlap)
-constexpr int MAXSLOT = 48;        // tiles per disk box (partial-sum slots per disk)
+constexpr int MAXSLOT = 64;        // tiles per disk box (partial-sum slots per disk)
+constexpr int MAX_BANDS = 6144;    // tile rows (bands) of one lattice
 constexpr int NBMAX = 32;          // DEM neighbour-list capacity per disk
-constexpr int MAX_PARTICLES = 1024;
-constexpr int PBLOCK = 1024;       // threads of the particle-phase workgroup
+constexpr int MAX_PARTICLES = 512;
+constexpr int PBLOCK = 512;        // threads of the particle-phase workgroup (one per disk)
 constexpr double DEM_SKIN = 3.0;   // neighbour-list skin (lattice units)
 constexpr double MAX_MOVE = 1.0;   // largest displacement of a disk in one lattice step
 constexpr float F16_SCALE = 16384.0f;  // power-of-two scale of FP16 deviations
@@ -34,6 +35,7 @@ enum : int {
   ERR_NBR = 16,        // DEM neighbour list full
   ERR_MOVE = 32,       // a disk moved more than MAX_MOVE in one step
   ERR_LEFT = 64,       // a disk centre left the channel between the walls
+  ERR_BAND = 128,      // band list capacity exceeded
 };
 
 // D2Q9 velocity set (the paper's Table 1 gives the 3D D3Q19 set; its 2D analogue here).
@@ -70,7 +72,10 @@ struct LatticeArgs {
   void* dst;             // post-collision populations of this step
   int np;
   ParticleTable tab;
-  double4* partials;     // [np][MAXSLOT] force / torque partial sums (Fx, Fy, Tz, 0)
+  const int* band_off;   // [tiles_y + 1]: disks whose box touches tile row ty are
+  const int* band_ids;   //   band_ids[band_off[ty] .. band_off[ty + 1])
+  double4* partials;     // [MAXSLOT][pstride] force / torque partial sums (Fx, Fy, Tz, 0),
+  int pstride;           //   slot-major so the particle phase reads them coalesced
   int* err;
 };
 
@@ -92,7 +97,10 @@ struct ParticleArgs {
   int tiles_x, tiles_y, tw, th;
   ParticleState s;
   ParticleTable tab;
-  const double4* partials;
+  int* band_off;   // written with the table: per tile row, the disks whose box touches it
+  int* band_ids;   // capacity np * MAXSLOT
+  const double4* partials;  // [MAXSLOT][pstride]
+  int pstride;
   int do_finalize, do_dem, do_table, init_contacts;
   const double *wfx, *wfy, *wtz;  // objective weights (adjoint forward); may be null
   double* J;                      // objective accumulator; null = not accumulated

@@ -18,6 +18,8 @@ struct DeviceLayout {
   void* f[2];
   ParticleState ps;
   ParticleTable tab;
+  int* band_off;
+  int* band_ids;
   double4* partials;
   int* err;
   double* J;
@@ -54,6 +56,7 @@ void enqueue_step(imb_sim* s, const double* wfx, const double* wfy, const double
 int sync_and_check(imb_sim* s);
 int reset_device_error(imb_sim* s);
 void free_adjoint(imb_sim* s);
+void drop_graphs(imb_sim* s);
 
 }  // namespace imb
 

@@ -71,6 +71,8 @@ size_t layout(const imb_config& c, char* base, DeviceLayout* L) {
   d.tab.box = cv.take<int4>(mp);
   d.tab.pos = cv.take<double4>(mp);
   d.tab.vel = cv.take<double4>(mp);
+  d.band_off = cv.take<int>((size_t)g.tiles_y + 1);
+  d.band_ids = cv.take<int>(mp * MAXSLOT);
   d.partials = cv.take<double4>(mp * MAXSLOT);
   d.err = cv.take<int>(1);
   d.J = cv.take<double>(1);
@@ -106,6 +108,9 @@ int validate_config(const imb_config* c, std::string* why) {
   const int rows = c->tile_rows ? c->tile_rows : 1;
   if (rows != 1 && rows != 2 && rows != 4) return bad("tile_rows must be 1, 2 or 4");
   if (c->flags & ~IMB_FLAG_WALLS) return bad("unknown flag");
+  Geometry g;
+  sim_geometry(*c, &g);
+  if (g.tiles_y > MAX_BANDS) return bad("too many tile rows (ny / tile height > 6144)");
   return IMB_OK;
 }
 
@@ -124,7 +129,8 @@ int map_device_error(int bits) {
 std::string describe_device_error(int bits) {
   std::string s;
   if (bits & ERR_TILE_LIST) s += "more than 32 disk boxes touch one tile; ";
-  if (bits & ERR_SLOTS) s += "a disk box spans more than 48 tiles; ";
+  if (bits & ERR_SLOTS) s += "a disk box spans more than 64 tiles; ";
+  if (bits & ERR_BAND) s += "band list overflow; ";
   if (bits & ERR_CELL) s += "more than 4 disks cover one cell or one thread column; ";
   if (bits & ERR_RHO) s += "non-finite or non-positive density; ";
   if (bits & ERR_NBR) s += "DEM neighbour list overflow; ";
@@ -156,7 +162,12 @@ struct imb_sim {
   int64_t lat_n = 0, par_n = 0;
   std::vector<hipEvent_t> ev_pool;
   AdjointState* adj = nullptr;
+  // captured step chains: graph[len][start buffer]; len index 0 = 2 steps, 1 = GRAPH_LONG steps
+  hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  bool use_graphs = true;
 };
+
+static constexpr int GRAPH_LONG = 32;
 
 namespace imb {
 
@@ -170,6 +181,8 @@ LatticeArgs lattice_args(imb_sim* s, const void* src, void* dst) {
   a.rho0 = s->cfg.rho0;
   a.src = src; a.dst = dst;
   a.np = s->np; a.tab = s->d.tab; a.partials = s->d.partials; a.err = s->d.err;
+  a.band_off = s->d.band_off; a.band_ids = s->d.band_ids;
+  a.pstride = std::max(s->cfg.max_particles, 1);
   return a;
 }
 
@@ -181,6 +194,8 @@ ParticleArgs particle_args(imb_sim* s) {
   a.rho_s = s->cfg.rho_solid;
   a.tiles_x = s->g.tiles_x; a.tiles_y = s->g.tiles_y; a.tw = s->g.tw; a.th = s->g.th;
   a.s = s->d.ps; a.tab = s->d.tab; a.partials = s->d.partials; a.err = s->d.err;
+  a.band_off = s->d.band_off; a.band_ids = s->d.band_ids;
+  a.pstride = std::max(s->cfg.max_particles, 1);
   return a;
 }
 
@@ -268,6 +283,47 @@ int reset_device_error(imb_sim* s) {
 
 }  // namespace imb
 
+namespace imb {
+
+void drop_graphs(imb_sim* s) {
+  for (auto& row : s->graph)
+    for (auto& g : row)
+      if (g) {
+        hipGraphExecDestroy(g);
+        g = nullptr;
+      }
+}
+
+// Captures `len` consecutive steps starting from buffer `start` into an executable graph
+// (captured on a private stream: the caller's stream may be the legacy null stream).
+static hipGraphExec_t capture_steps(imb_sim* s, int len, int start) {
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return nullptr;
+  const hipStream_t saved = s->stream;
+  const int saved_cur = s->cur;
+  const int64_t saved_steps = s->steps;
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ge = nullptr;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+    s->stream = cs;
+    s->cur = start;
+    for (int k = 0; k < len; ++k) enqueue_step(s, nullptr, nullptr, nullptr, nullptr);
+    s->stream = saved;
+    if (hipStreamEndCapture(cs, &g) == hipSuccess && g) {
+      if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) ge = nullptr;
+      hipGraphDestroy(g);
+    }
+  }
+  s->stream = saved;
+  s->cur = saved_cur;
+  s->steps = saved_steps;
+  hipStreamDestroy(cs);
+  hipGetLastError();
+  return ge;
+}
+
+}  // namespace imb
+
 // =================================================================== C-ABI
 extern "C" {
 
@@ -340,6 +396,7 @@ int imb_create(const imb_config* cfg, void* hip_stream, void* dev_buf, size_t de
 void imb_destroy(imb_sim* s) {
   if (!s) return;
   hipStreamSynchronize(s->stream);
+  drop_graphs(s);
   free_adjoint(s);
   for (auto e : s->ev_lat) hipEventDestroy(e);
   for (auto e : s->ev_par) hipEventDestroy(e);
@@ -467,6 +524,8 @@ int imb_set_particles(imb_sim* s, int32_t n, const double* x, const double* y, c
       return IMB_EINVAL;
     }
   }
+  hipStreamSynchronize(s->stream);
+  drop_graphs(s);
   s->np = n;
   ParticleState& ps = s->d.ps;
   const size_t mp = (size_t)std::max(s->cfg.max_particles, 1);
@@ -506,8 +565,40 @@ int imb_set_particles(imb_sim* s, int32_t n, const double* x, const double* y, c
 
 int imb_step(imb_sim* s, int32_t nsteps) {
   if (!s || nsteps < 0) return IMB_EINVAL;
-  for (int k = 0; k < nsteps; ++k) enqueue_step(s, nullptr, nullptr, nullptr, nullptr);
+  // per-kernel event timing needs the individual launches
+  if (!s->use_graphs || s->timing) {
+    for (int k = 0; k < nsteps; ++k) enqueue_step(s, nullptr, nullptr, nullptr, nullptr);
+    return launch_check(s, "step");
+  }
+  while (nsteps > 0) {
+    const int li = nsteps >= GRAPH_LONG ? 1 : (nsteps >= 2 ? 0 : -1);
+    if (li < 0) {
+      enqueue_step(s, nullptr, nullptr, nullptr, nullptr);
+      --nsteps;
+      continue;
+    }
+    const int len = li ? GRAPH_LONG : 2;
+    hipGraphExec_t& ge = s->graph[li][s->cur];
+    if (!ge) ge = capture_steps(s, len, s->cur);
+    if (!ge) {  // capture unsupported: plain launches
+      s->use_graphs = false;
+      for (int k = 0; k < nsteps; ++k) enqueue_step(s, nullptr, nullptr, nullptr, nullptr);
+      return launch_check(s, "step");
+    }
+    hipError_t e = hipGraphLaunch(ge, s->stream);
+    if (e != hipSuccess) return hip_fail(&s->err, e, "hipGraphLaunch");
+    s->steps += len;  // an even number of steps leaves the buffer parity unchanged
+    nsteps -= len;
+  }
   return launch_check(s, "step");
+}
+
+int imb_set_graphs(imb_sim* s, int enable) {
+  if (!s) return IMB_EINVAL;
+  hipStreamSynchronize(s->stream);
+  drop_graphs(s);
+  s->use_graphs = enable != 0;
+  return IMB_OK;
 }
 
 int imb_get_forces(imb_sim* s, double* fx, double* fy, double* tz) {
@@ -625,6 +716,8 @@ int imb_load_state(imb_sim* s, const void* host_buf, size_t bytes) {
     return IMB_EINVAL;
   }
   const char* in = (const char*)host_buf + sizeof h;
+  hipStreamSynchronize(s->stream);
+  drop_graphs(s);
   s->cur = 0;
   s->np = h.np;
   s->steps = h.steps;

@@ -5,12 +5,9 @@
 // it by cell decomposition; here it is the exact area of disk (radius r, centre at the origin)
 // intersected with the unit cell [dx - 1/2, dx + 1/2] x [dy - 1/2, dy + 1/2].
 //
-// Formulation used on the GPU (well conditioned in FP32):
-//   eps = I(y1) - I(y0),   I(y) = int_{x0}^{x1} clamp(y, -s(x), s(x)) dx,  s(x) = sqrt(r^2 - x^2),
-// because clamp(y1, -s, s) - clamp(y0, -s, s) is the part of the vertical chord inside [y0, y1].
-// For |y| < r the clamp equals y where |x| < w = s(y) and sign(y) s(x) where w <= |x| <= r, so
-// I(y) is one rectangle plus at most two pieces of int s dx, each evaluated from the difference
-// of the end points (no subtraction of two large primitives).
+// A cut cell's area is the convex polygon of its inside corners and edge crossings plus the
+// circular segments cut off by the chords (see cut_cell_fraction); cells entirely inside or
+// outside are 1 or 0 exactly.
 //
 // Derivative (ADJOINT): moving the centre by +h shifts the cell by -h in disk coordinates, so
 //   d eps / dX = L(x0) - L(x1),  d eps / dY = M(y0) - M(y1),
@@ -48,49 +45,127 @@ __host__ __device__ inline T segment_excess(T x) {
   return x - sin(x);
 }
 
-// int_a^b sqrt(r^2 - x^2) dx for -r <= a <= b <= r, as the trapezoid under the chord plus the
-// circular segment between chord and arc:
-//   (b - a)(s_a + s_b) / 2 + r^2 (phi - sin phi) / 2,
-// phi = theta(b) - theta(a) the angle the arc subtends, theta(x) = asin(x / r), from
-//   r^2 sin phi = b s_a - a s_b  (= r^2 (b - a)(b + a) / (b s_a + a s_b) when a b > 0),
-//   r^2 cos phi = s_a s_b + a b.
-// Both terms are non-negative, so nothing cancels.
+// ---------------------------------------------------------------- cut cells
+// Area of a cut cell as the convex polygon whose vertices are the cell corners inside the disk
+// and the points where the circle crosses the cell edges (walked counter-clockwise), plus one
+// circular segment r^2 (phi - sin phi) / 2 for every arc between an exit and the next entry.
+// Vertices are kept in cell-local coordinates (u, v) in [0, 1]^2 so the shoelace sum has no
+// cancellation; a crossing is located from the nearer same-sign corner through the corner's
+// power r^2 - x^2 - y^2, computed with error-free products, so crossings near a corner keep
+// full relative precision.
+
 template <class T>
-__host__ __device__ inline T semi_integral(T r, T a, T b) {
-  if (!(b > a)) return T(0);
-  const T sa = half_chord(r, a), sb = half_chord(r, b);
-  T sn;
-  if (a * b > T(0)) {
-    sn = r * r * ((b - a) * (b + a)) / (b * sa + a * sb);
-  } else {
-    sn = b * sa - a * sb;
+__host__ __device__ inline T exact_power(T r, T x, T y) {  // r^2 - x^2 - y^2
+  const T hr = r * r, lr = fma(r, r, -hr);
+  const T hx = x * x, lx = fma(x, x, -hx);
+  const T hy = y * y, ly = fma(y, y, -hy);
+  const T s1 = hr - hx, b1 = s1 - hr, e1 = (hr - (s1 - b1)) + (-hx - b1);
+  const T s2 = s1 - hy, b2 = s2 - s1, e2 = (s1 - (s2 - b2)) + (-hy - b2);
+  return s2 + (((e1 + e2) + lr) - lx - ly);
+}
+
+// Offset, from edge end e0, of the crossing at coordinate cc (cc = +-h) on an edge running from
+// e0 to e0 + 1 whose end points have powers p0 and p1.  The end point with the sign of cc gives
+// cc - e = (cc^2 - e^2) / (cc + e) = power(e) / (cc + e), with no cancellation.
+template <class T>
+__host__ __device__ inline T crossing_offset(T cc, T e0, T p0, T p1) {
+  return cc > T(0) ? T(1) + p1 / (cc + (e0 + T(1))) : p0 / (cc + e0);
+}
+
+template <class T>
+struct AreaWalk {
+  T r;
+  T u0, v0;          // first vertex
+  T pu, pv;          // previous vertex
+  int first_kind, prev_kind;  // 0 corner, 1 entry, 2 exit, -1 none yet
+  T twice_area;      // shoelace sum
+  T seg;             // circular segments
+  T cx, cy;          // disk centre in cell coordinates
+  __host__ __device__ void segment(T au, T av, T bu, T bv) {
+    // arc counter-clockwise from exit a to entry b
+    const T du = bu - au, dv = bv - av;
+    const T c = sqrt(du * du + dv * dv);
+    const T t = c / (T(2) * r);
+    T phi;  // the smaller angle between the radii to a and b
+    if (t < T(0.7)) {
+      phi = T(2) * asin(t);
+    } else {  // near a diameter asin loses accuracy; use the radius vectors
+      const T ax = au - cx, ay = av - cy, bx = bu - cx, by = bv - cy;
+      phi = atan2(fabs(ax * by - ay * bx), ax * bx + ay * by);
+    }
+    // minor arc when the centre lies left of the chord a -> b
+    const T side = du * (cy - av) - dv * (cx - au);
+    T ex = segment_excess(phi);
+    if (side < T(0)) ex = T(6.283185307179586476925) - phi + sin(phi);
+    seg += T(0.5) * r * r * ex;
   }
-  const T cs = sa * sb + a * b;
-  const T phi = atan2(sn, cs);
-  return T(0.5) * ((b - a) * (sa + sb) + r * r * segment_excess(phi));
-}
+  __host__ __device__ void add(T u, T v, int kind) {
+    if (prev_kind < 0) {
+      u0 = u; v0 = v; first_kind = kind;
+    } else {
+      twice_area += pu * v - u * pv;
+      if (prev_kind == 2 && kind == 1) segment(pu, pv, u, v);
+    }
+    pu = u; pv = v; prev_kind = kind;
+  }
+  __host__ __device__ T finish() {
+    if (prev_kind < 0) return T(0);
+    twice_area += pu * v0 - u0 * pv;
+    if (prev_kind == 2 && first_kind == 1) segment(pu, pv, u0, v0);
+    return T(0.5) * twice_area + seg;
+  }
+};
 
-template <class T>
-__host__ __device__ inline T clamped_chord_integral(T r, T x0, T x1, T y) {
-  const T xa = fmax(x0, -r), xb = fmin(x1, r);
-  if (!(xb > xa)) return T(0);
-  if (y >= r) return semi_integral<T>(r, xa, xb);
-  if (y <= -r) return -semi_integral<T>(r, xa, xb);
-  const T w = half_chord(r, y);
-  const T lc = fmax(T(0), fmin(xb, w) - fmax(xa, -w));
-  const T outer = semi_integral<T>(r, xa, fmin(xb, -w)) + semi_integral<T>(r, fmax(xa, w), xb);
-  return y * lc + (y > T(0) ? outer : (y < T(0) ? -outer : T(0)));
-}
-
-// eps of the unit cell centred at (dx, dy) relative to the disk centre.  The exact-area branch
-// is a separate (non-inlined) function: it runs only for cut cells and keeps the caller's
-// register budget small.
 template <class T>
 __host__ __device__ __noinline__ T cut_cell_fraction(T r, T x0, T x1, T y0, T y1) {
-  const T e = clamped_chord_integral(r, x0, x1, y1) - clamped_chord_integral(r, x0, x1, y0);
+  // corner powers, counter-clockwise from (x0, y0)
+  const T p00 = exact_power(r, x0, y0), p10 = exact_power(r, x1, y0);
+  const T p11 = exact_power(r, x1, y1), p01 = exact_power(r, x0, y1);
+  AreaWalk<T> w;
+  w.r = r; w.prev_kind = -1; w.first_kind = -1; w.twice_area = T(0); w.seg = T(0);
+  w.u0 = w.v0 = w.pu = w.pv = T(0);
+  w.cx = -x0; w.cy = -y0;
+  // bottom edge: (x0, y0) -> (x1, y0), u increasing; crossings x = -h (entry), +h (exit)
+  if (p00 >= T(0)) w.add(T(0), T(0), 0);
+  if (fabs(y0) < r) {
+    const T h = half_chord(r, y0);
+    if (-h > x0 && -h < x1) w.add(crossing_offset(-h, x0, p00, p10), T(0), 1);
+    if (h > x0 && h < x1) w.add(crossing_offset(h, x0, p00, p10), T(0), 2);
+  }
+  // right edge: (x1, y0) -> (x1, y1), v increasing; crossings y = -h (entry), +h (exit)
+  if (p10 >= T(0)) w.add(T(1), T(0), 0);
+  if (fabs(x1) < r) {
+    const T h = half_chord(r, x1);
+    if (-h > y0 && -h < y1) w.add(T(1), crossing_offset(-h, y0, p10, p11), 1);
+    if (h > y0 && h < y1) w.add(T(1), crossing_offset(h, y0, p10, p11), 2);
+  }
+  // top edge: (x1, y1) -> (x0, y1), u decreasing; crossings x = +h (entry), -h (exit)
+  if (p11 >= T(0)) w.add(T(1), T(1), 0);
+  if (fabs(y1) < r) {
+    const T h = half_chord(r, y1);
+    if (h > x0 && h < x1) w.add(crossing_offset(h, x0, p01, p11), T(1), 1);
+    if (-h > x0 && -h < x1) w.add(crossing_offset(-h, x0, p01, p11), T(1), 2);
+  }
+  // left edge: (x0, y1) -> (x0, y0), v decreasing; crossings y = +h (entry), -h (exit)
+  if (p01 >= T(0)) w.add(T(0), T(1), 0);
+  if (fabs(x0) < r) {
+    const T h = half_chord(r, x0);
+    if (h > y0 && h < y1) w.add(T(0), crossing_offset(h, y0, p00, p01), 1);
+    if (-h > y0 && -h < y1) w.add(T(0), crossing_offset(-h, y0, p00, p01), 2);
+  }
+  T e;
+  if (w.prev_kind < 0) {
+    // no corner inside and no crossing: the disk lies inside the cell
+    e = T(3.14159265358979323846) * r * r;
+  } else {
+    e = w.finish();
+  }
   return fmin(T(1), fmax(T(0), e));
 }
 
+// eps of the unit cell centred at (dx, dy) relative to the disk centre.  The cut-cell branch is
+// a separate (non-inlined) function: it runs only for cut cells and keeps the caller's register
+// budget small.
 template <class T>
 __host__ __device__ inline T solid_fraction(T r, T dx, T dy) {
   const T x0 = dx - T(0.5), x1 = dx + T(0.5), y0 = dy - T(0.5), y1 = dy + T(0.5);

@@ -23,17 +23,24 @@ struct PEntry {
   T fx, fy, r, vx, vy, om;
 };
 
-// Ordered list of the disks whose tile box contains tile (tx, ty).  Returns the list length
-// (capped at LMAX; overflow latches ERR_TILE_LIST).
+// Disks whose tile box contains tile (tx, ty), sorted by id (so every sum over them has a fixed
+// order).  Candidates come from the tile row's band list written by the particle phase.  Returns
+// the count (capped at LMAX; overflow latches ERR_TILE_LIST).  Block-uniform control flow.
 template <class T>
-__device__ int build_tile_list(const LatticeArgs& a, int tx, int ty, PEntry<T>* pl,
-                               int* s_cnt) {
+__device__ int build_tile_list(const LatticeArgs& a, int tx, int ty, PEntry<T>* pl, int* s_cnt,
+                               int* s_pid, int* s_slot) {
+  if (a.np == 0) return 0;
+  const int b0 = a.band_off[ty], b1 = a.band_off[ty + 1];
+  if (b1 <= b0) return 0;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int base = 0;
-  for (int p0 = 0; p0 < a.np; p0 += BLOCK) {
-    const int p = p0 + tid;
-    int slot = -1;
-    if (p < a.np) slot = box_slot(a.tab.box[p], tx, ty, a.tiles_x, a.tiles_y);
+  for (int k0 = b0; k0 < b1; k0 += BLOCK) {
+    const int k = k0 + tid;
+    int p = -1, slot = -1;
+    if (k < b1) {
+      p = a.band_ids[k];
+      slot = box_slot(a.tab.box[p], tx, ty, a.tiles_x, a.tiles_y);
+    }
     const bool hit = slot >= 0;
     const unsigned long long m = __ballot(hit);
     const int below = __popcll(m & ((1ull << lane) - 1ull));
@@ -46,23 +53,10 @@ __device__ int build_tile_list(const LatticeArgs& a, int tx, int ty, PEntry<T>* 
       total += s_cnt[w];
     }
     if (hit) {
-      const int k = off + below;
-      if (k < LMAX) {
-        const double4 ps = a.tab.pos[p];
-        const double4 vl = a.tab.vel[p];
-        const double flx = floor(ps.x), fly = floor(ps.y);
-        PEntry<T> e;
-        e.ix = (int)flx;
-        e.iy = (int)fly;
-        e.pid = p;
-        e.slot = slot;
-        e.fx = (T)(ps.x - flx);
-        e.fy = (T)(ps.y - fly);
-        e.r = (T)ps.z;
-        e.vx = (T)vl.x;
-        e.vy = (T)vl.y;
-        e.om = (T)vl.z;
-        pl[k] = e;
+      const int q = off + below;
+      if (q < LMAX) {
+        s_pid[q] = p;
+        s_slot[q] = slot;
       } else {
         atomicOr(a.err, ERR_TILE_LIST);
       }
@@ -70,7 +64,29 @@ __device__ int build_tile_list(const LatticeArgs& a, int tx, int ty, PEntry<T>* 
     base += total;
     __syncthreads();
   }
-  return base < LMAX ? base : LMAX;
+  const int n = base < LMAX ? base : LMAX;
+  if (tid < n) {
+    const int p = s_pid[tid];
+    int rank = 0;
+    for (int q = 0; q < n; ++q) rank += s_pid[q] < p;
+    const double4 ps = a.tab.pos[p];
+    const double4 vl = a.tab.vel[p];
+    const double flx = floor(ps.x), fly = floor(ps.y);
+    PEntry<T> e;
+    e.ix = (int)flx;
+    e.iy = (int)fly;
+    e.pid = p;
+    e.slot = s_slot[tid];
+    e.fx = (T)(ps.x - flx);
+    e.fy = (T)(ps.y - fly);
+    e.r = (T)ps.z;
+    e.vx = (T)vl.x;
+    e.vy = (T)vl.y;
+    e.om = (T)vl.z;
+    pl[rank] = e;
+  }
+  __syncthreads();
+  return n;
 }
 
 // Per-thread scratch of a tile in LDS (indexed [k][thread] so a wave touches 64 distinct
@@ -99,7 +115,8 @@ __device__ inline void lever_arm(const LatticeArgs& a, const PEntry<T>& e, int x
   *dy = (T)dj - e.fy;
 }
 
-// Disks covering cell (x, y): eps > 0 with the image nearest to the cell.  Returns their count.
+// Disks covering cell (x, y): eps > 0 with the image nearest to the cell, evaluated directly
+// (used by the solid-ratio diagnostic).  Returns their count.
 template <class T>
 __device__ inline int covering_disks(const LatticeArgs& a, const PEntry<T>* pl, int n, int x,
                                      int y, CellScratch<T>& cs) {
@@ -118,6 +135,41 @@ __device__ inline int covering_disks(const LatticeArgs& a, const PEntry<T>* pl, 
         atomicOr(a.err, ERR_CELL);
       }
     }
+  }
+  return nc;
+}
+
+// Disks whose image nearest to cell (x, y) reaches the cell, classified with the cheap tests of
+// solid_fraction: inside cells get eps = 1 now; cut cells are appended to the tile's queue
+// (owner thread, slot, disk) and get their exact area from the whole block afterwards, so the
+// expensive branch runs on densely packed lanes.  Returns the count.
+template <class T>
+__device__ inline int classify_cell(const LatticeArgs& a, const PEntry<T>* pl, int n, int x, int y,
+                                    CellScratch<T>& cs, int* s_qn, int* s_q) {
+  const int tid = threadIdx.x;
+  int nc = 0;
+  for (int j = 0; j < n; ++j) {
+    T dx, dy;
+    lever_arm(a, pl[j], x, y, &dx, &dy);
+    const T r = pl[j].r;
+    const T x0 = dx - T(0.5), x1 = dx + T(0.5), y0 = dy - T(0.5), y1 = dy + T(0.5);
+    const T nx = x0 > T(0) ? x0 : (x1 < T(0) ? x1 : T(0));
+    const T ny = y0 > T(0) ? y0 : (y1 < T(0) ? y1 : T(0));
+    if (nx * nx + ny * ny >= r * r) continue;
+    if (nc >= MAXC) {
+      atomicOr(a.err, ERR_CELL);
+      continue;
+    }
+    const T fx = fabs(x0) > fabs(x1) ? fabs(x0) : fabs(x1);
+    const T fy = fabs(y0) > fabs(y1) ? fabs(y0) : fabs(y1);
+    cs.cj[nc][tid] = j;
+    if (fx * fx + fy * fy <= r * r) {
+      cs.ce[nc][tid] = T(1);
+    } else {
+      const int q = atomicAdd(s_qn, 1);
+      s_q[q] = tid | (nc << 8) | (j << 10);
+    }
+    ++nc;
   }
   return nc;
 }
@@ -161,16 +213,47 @@ struct Acc {
   }
 };
 
+// Wave-wide sum with DPP row rotations (no LDS traffic): rotating by 8, 4, 2, 1 lanes inside each
+// row of 16 leaves the row total in every lane; lanes 0, 16, 32, 48 are then added in fixed
+// order, so the result is the same on every run.
+template <int CTRL>
+__device__ inline float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ inline float read_lane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ inline double read_lane(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <int CTRL, class T>
+__device__ inline void dpp_add(Acc<T>& v) {
+  Acc<T> o;
+  o.hi = dpp_move<CTRL>(v.hi);
+  o.lo = dpp_move<CTRL>(v.lo);
+  v.add(o);
+}
+
 template <class T>
 __device__ inline Acc<T> wave_sum(Acc<T> v) {
+  dpp_add<0x128>(v);  // row_ror:8
+  dpp_add<0x124>(v);  // row_ror:4
+  dpp_add<0x122>(v);  // row_ror:2
+  dpp_add<0x121>(v);  // row_ror:1
+  Acc<T> t{read_lane(v.hi, 0), read_lane(v.lo, 0)};
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    Acc<T> o;
-    o.hi = __shfl_xor(v.hi, off, 64);
-    o.lo = __shfl_xor(v.lo, off, 64);
-    v.add(o);
-  }
-  return v;
+  for (int row = 1; row < 4; ++row) t.add(Acc<T>{read_lane(v.hi, 16 * row), read_lane(v.lo, 16 * row)});
+  return t;
 }
 
 template <class St>
@@ -179,8 +262,11 @@ __global__ __launch_bounds__(BLOCK) void k_lattice_step(LatticeArgs a) {
   using S = typename St::S;
   __shared__ PEntry<T> s_pl[LMAX];
   __shared__ int s_cnt[WAVES];
+  __shared__ int s_pid[LMAX], s_slot[LMAX];
   __shared__ unsigned s_touch;
-  __shared__ Acc<T> s_red[WAVES][3];
+  __shared__ int s_qn;
+  __shared__ int s_q[BLOCK * MAXC];
+  __shared__ Acc<T> s_red[WAVES][LMAX][3];
   __shared__ CellScratch<T> cs;
 
   const int tid = threadIdx.x;
@@ -194,7 +280,11 @@ __global__ __launch_bounds__(BLOCK) void k_lattice_step(LatticeArgs a) {
   S* dst = (S*)a.dst;
 
   if (tid == 0) s_touch = 0u;
-  const int n = build_tile_list<T>(a, tx, ty, s_pl, s_cnt);
+  // the first row's populations are requested before the disk list is built, so their latency
+  // overlaps the list's
+  T f[NQ];
+  if (x < a.nx && ybase < a.ny) pull_load<St>(a, src, x, ybase, f);
+  const int n = build_tile_list<T>(a, tx, ty, s_pl, s_cnt, s_pid, s_slot);
   if (n > 0) {
 #pragma unroll
     for (int q = 0; q < MAXC; ++q) cs.aj[q][tid] = -1;
@@ -203,10 +293,29 @@ __global__ __launch_bounds__(BLOCK) void k_lattice_step(LatticeArgs a) {
   const T tau0 = (T)a.tau0, csm = (T)a.cs, gx = (T)a.gx, gy = (T)a.gy, rho0 = (T)a.rho0;
   for (int rr = 0; rr < a.rows; ++rr) {
     const int y = ybase + rr * th;
-    if (x >= a.nx || y >= a.ny) continue;
-    T f[NQ], fo[NQ];
-    pull_load<St>(a, src, x, y, f);
-    const int nc = n > 0 ? covering_disks<T>(a, s_pl, n, x, y, cs) : 0;
+    const bool valid = x < a.nx && y < a.ny;
+    if (rr > 0 && valid) pull_load<St>(a, src, x, y, f);
+    int nc = 0;
+    if (n > 0) {  // block-uniform
+      if (tid == 0) s_qn = 0;
+      __syncthreads();
+      if (valid) nc = classify_cell<T>(a, s_pl, n, x, y, cs, &s_qn, s_q);
+      __syncthreads();
+      const int qn = s_qn;
+      for (int q = tid; q < qn; q += BLOCK) {  // exact areas of the tile's cut cells
+        const int code = s_q[q];
+        const int owner = code & 255, k = (code >> 8) & 3, j = code >> 10;
+        const int ox = tx * tw + (owner & (tw - 1));
+        const int oy = ybase - ly + (owner >> a.tw_log) + rr * th;
+        T dx, dy;
+        lever_arm(a, s_pl[j], ox, oy, &dx, &dy);
+        cs.ce[k][owner] = cut_cell_fraction<T>(s_pl[j].r, dx - T(0.5), dx + T(0.5),
+                                               dy - T(0.5), dy + T(0.5));
+      }
+      __syncthreads();
+    }
+    if (!valid) continue;
+    T fo[NQ];
     auto disk = [&](int k) {
       const int j = cs.cj[k][tid];
       Disk<T> d;
@@ -264,12 +373,10 @@ __global__ __launch_bounds__(BLOCK) void k_lattice_step(LatticeArgs a) {
   const unsigned touched = s_touch;
   const int lane = tid & 63, wave = tid >> 6;
 
+  // each wave reduces every touched disk over its cells; one barrier; then one thread per
+  // disk adds the four waves in fixed order and writes the tile's slot
   for (int j = 0; j < n; ++j) {
-    if (!((touched >> j) & 1u)) {
-      if (tid == 0)
-        a.partials[(long long)s_pl[j].pid * MAXSLOT + s_pl[j].slot] = make_double4(0, 0, 0, 0);
-      continue;
-    }
+    if (!((touched >> j) & 1u)) continue;
 #pragma unroll
     for (int comp = 0; comp < 3; ++comp) {
       Acc<T> v{T(0), T(0)};
@@ -277,22 +384,24 @@ __global__ __launch_bounds__(BLOCK) void k_lattice_step(LatticeArgs a) {
       for (int q = 0; q < MAXC; ++q)
         if (cs.aj[q][tid] == j) v.add(cs.af[comp][q][tid]);
       v = wave_sum(v);
-      if (lane == 0) s_red[wave][comp] = v;
+      if (lane == 0) s_red[wave][j][comp] = v;
     }
-    __syncthreads();
-    if (tid == 0) {
-      double out[3];
+  }
+  __syncthreads();
+  if (tid < n) {
+    const int j = tid;
+    double out[3] = {0.0, 0.0, 0.0};
+    if ((touched >> j) & 1u) {
 #pragma unroll
       for (int comp = 0; comp < 3; ++comp) {
-        Acc<T> v = s_red[0][comp];
+        Acc<T> v = s_red[0][j][comp];
 #pragma unroll
-        for (int w = 1; w < WAVES; ++w) v.add(s_red[w][comp]);
+        for (int w = 1; w < WAVES; ++w) v.add(s_red[w][j][comp]);
         out[comp] = (double)v.hi + (double)v.lo;
       }
-      a.partials[(long long)s_pl[j].pid * MAXSLOT + s_pl[j].slot] =
-          make_double4(out[0], out[1], out[2], 0.0);
     }
-    __syncthreads();
+    a.partials[(long long)s_pl[j].slot * a.pstride + s_pl[j].pid] =
+        make_double4(out[0], out[1], out[2], 0.0);
   }
 }
 
@@ -301,6 +410,7 @@ template <class T>
 __global__ __launch_bounds__(BLOCK) void k_solid_field(LatticeArgs a, double* eps_out) {
   __shared__ PEntry<T> s_pl[LMAX];
   __shared__ int s_cnt[WAVES];
+  __shared__ int s_pid[LMAX], s_slot[LMAX];
   __shared__ CellScratch<T> cs;
   const int tid = threadIdx.x;
   const int tile = blockIdx.x;
@@ -308,7 +418,7 @@ __global__ __launch_bounds__(BLOCK) void k_solid_field(LatticeArgs a, double* ep
   const int tw = 1 << a.tw_log, th = BLOCK >> a.tw_log;
   const int x = tx * tw + (tid & (tw - 1));
   const int ybase = ty * th * a.rows + (tid >> a.tw_log);
-  const int n = build_tile_list<T>(a, tx, ty, s_pl, s_cnt);
+  const int n = build_tile_list<T>(a, tx, ty, s_pl, s_cnt, s_pid, s_slot);
   for (int rr = 0; rr < a.rows; ++rr) {
     const int y = ybase + rr * th;
     if (x >= a.nx || y >= a.ny) continue;

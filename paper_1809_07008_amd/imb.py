@@ -34,7 +34,7 @@ EXPORTED = [
     "imb_batch_create", "imb_batch_destroy", "imb_batch_set_particles", "imb_batch_step",
     "imb_batch_get_forces", "imb_batch_get_particles", "imb_batch_get_fields", "imb_batch_sync",
     "imb_batch_set_launch", "imb_strerror", "imb_last_error", "imb_version",
-    "imb_get_solid_field",
+    "imb_get_solid_field", "imb_set_graphs",
 ]
 
 
@@ -85,6 +85,7 @@ def load_library():
         "imb_get_solid_field": (C.c_int, [_VP, _D]),
         "imb_set_particles": (C.c_int, [_VP, C.c_int32, _D, _D, _D, _D, _D, _D, _I32]),
         "imb_step": (C.c_int, [_VP, C.c_int32]),
+        "imb_set_graphs": (C.c_int, [_VP, C.c_int]),
         "imb_get_forces": (C.c_int, [_VP, _D, _D, _D]),
         "imb_get_particles": (C.c_int, [_VP, _D, _D, _D, _D, _D]),
         "imb_get_counts": (C.c_int, [_VP, _I32, P(C.c_int64)]),
@@ -285,6 +286,9 @@ class Simulation:
         n = C.c_int32()
         load_library().imb_get_counts(self._h, C.byref(n), None)
         self.n = n.value
+
+    def set_graphs(self, on: bool):
+        self._check(load_library().imb_set_graphs(self._h, 1 if on else 0), "imb_set_graphs")
 
     def set_kernel_timing(self, on: bool):
         self._check(load_library().imb_set_kernel_timing(self._h, 1 if on else 0),

@@ -64,7 +64,9 @@ def test_single_disk_channel_fp64_full_parity():
     assert fxo[0] > 0
     assert abs(fxg[0] - fxo[0]) <= 1e-12 * abs(fxo[0])
     assert abs(fyg[0] - fyo[0]) <= 1e-12 * abs(fxo[0])
-    assert abs(tzg[0] - tzo[0]) <= 1e-12 * abs(tzo[0]) + 1e-12 * abs(fxo[0])
+    # the torque on this nearly centred disk is a 1e-5 cancellation of lever-arm terms; its
+    # natural scale is r |F|
+    assert abs(tzg[0] - tzo[0]) <= 1e-12 * 10.0 * abs(fxo[0])
     rg, uxg, uyg = sim.fields()
     ro, uxo, uyo = ref.fields()
     assert rel_inf(uxg, uxo) < 1e-12 and rel_inf(rg, ro) < 1e-12
@@ -229,3 +231,18 @@ def test_fp32_full_size_against_oracle():
     _, uxg, _ = sim.fields()
     _, uxo, _ = ref.fields()
     assert np.abs(uxg - uxo).max() < 1e-4 * np.abs(uxo).max()
+
+
+def test_graph_replays_match_direct_launches():
+    """imb_step replays captured graphs (2- and 32-step chains); each replay, with readbacks and
+    syncs in between, must equal direct kernel launches bit for bit."""
+    case = W.moving_disks(seed=4, nx=320, ny=160, n=14, storage="f32")
+    g, d = gpu_for(case), gpu_for(case)
+    d.set_graphs(False)
+    for n in (37, 2, 33, 1, 64):
+        g.step(n)
+        d.step(n)
+        assert np.array_equal(g.populations(), d.populations())
+        for a, b in zip(g.forces() + g.particles(), d.forces() + d.particles()):
+            assert np.array_equal(a, b)
+    assert g.counts() == d.counts() == (14, 137)
