@@ -21,6 +21,107 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+CSRC = os.path.join(ROOT, "paper_1809_07008_amd", "csrc")
+LATTICE_SOURCES = ("step.hip", "lattice_tile.h", "tile.h", "collide.h", "solid.h", "common.h")
+COUNTERS = os.path.join(ROOT, "profiles", "k_lattice_step_2048x1024_n500_counters.txt")
+
+
+def lattice_source_hash() -> str:
+    """sha256 over the sources the fused lattice-step kernel is compiled from."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in LATTICE_SOURCES:
+        with open(os.path.join(CSRC, name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(storage: str, tile) -> float | None:
+    """HBM-side bytes per lattice-step launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, each scaled by what the counter reads for a copy kernel of known
+    size), or None when the summary is missing, was taken for another storage format or tile,
+    or the kernel's sources have changed since."""
+    try:
+        with open(COUNTERS) as fh:
+            kv = dict(line.split(":", 1) for line in fh if ":" in line and not line.startswith("#"))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    try:
+        if (kv["kernel_source_sha256"] != lattice_source_hash() or kv["storage"] != storage
+                or kv["tile"] != "%dx%d" % tuple(tile)):
+            return None
+        fetch_scale = float(kv["copy_bytes"]) / (float(kv["copy_fetch_kib"]) * 1024.0)
+        write_scale = float(kv["copy_bytes"]) / (float(kv["copy_write_kib"]) * 1024.0)
+        return (float(kv["fetch_kib"]) * 1024.0 * fetch_scale
+                + float(kv["write_kib"]) * 1024.0 * write_scale)
+    except (KeyError, ValueError, ZeroDivisionError):
+        return None
+
+
+def adjoint_ratio(tile, reps: int = 3):
+    """Differentiation form on the 512x256 / 20-disk channel (FP32, 200 steps, checkpoint every
+    20): GPU time per reverse step (recomputation + adjoint step) over the forward step time."""
+    import numpy as np
+    from paper_1809_07008_amd import imb, workloads
+    case = workloads.adjoint_channel(seed=0, storage="f32")
+    n = case.particles.n
+    fwd = imb.simulation_from_case(case, storage="f32", tile_w=tile[0], tile_rows=tile[1])
+    fwd.step(20)
+    fwd.sync()
+    t0 = time.perf_counter()
+    fwd.step(case.steps)
+    fwd.sync()
+    fwd_us = (time.perf_counter() - t0) / case.steps * 1e6
+    fwd.set_kernel_timing(True)
+    fwd.step(case.steps)
+    kt = fwd.kernel_timing()
+    fwd.close()
+    sim = imb.simulation_from_case(case, storage="f32", tile_w=tile[0], tile_rows=tile[1])
+    sim.adjoint(case.steps, 20, wfx=np.ones(n))  # allocation and warm-up
+    best = None
+    for _ in range(reps):
+        sim.adjoint(case.steps, 20, wfx=np.ones(n))
+        t = sim.adjoint_timing()
+        if best is None or t["reverse_ms"] < best["reverse_ms"]:
+            best = t
+    sim.set_kernel_timing(True)
+    sim.adjoint(case.steps, 20, wfx=np.ones(n))
+    kk = sim.adjoint_timing()
+    sim.close()
+    rev_us = best["reverse_ms"] * 1e3 / case.steps
+    return {"workload": "adjoint_512x256_n20", "storage": "f32", "steps": case.steps,
+            "k_ckpt": 20, "forward_step_us": round(fwd_us, 2),
+            "forward_pass_in_adjoint_us_per_step": round(best["forward_ms"] * 1e3 / case.steps, 2),
+            "reverse_step_us": round(rev_us, 2), "ratio": round(rev_us / fwd_us, 3),
+            "adjoint_kernel_us": round(kk["adjoint_kernel_ms"] * 1e3 /
+                                       max(kk["adjoint_kernels"], 1), 2),
+            "recompute_kernel_us": round(kk["recompute_kernel_ms"] * 1e3 /
+                                         max(kk["recompute_kernels"], 1), 2),
+            "forward_lattice_kernel_us": round(kt["lattice_ms"] * 1e3 /
+                                               max(kt["lattice_launches"], 1), 2),
+            "forward_particle_kernel_us": round(kt["particle_ms"] * 1e3 /
+                                                max(kt["particle_launches"], 1), 2)}
+
+
+def copy_calibration(nbytes: int, reps: int = 10) -> int:
+    """Runs only the plain copy kernel over nbytes (the counter calibration of the traffic
+    figure) and prints its bandwidth."""
+    import torch
+    from paper_1809_07008_amd import imb
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    imb.copy_kernel(b.data_ptr(), a.data_ptr(), nbytes)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        imb.copy_kernel(b.data_ptr(), a.data_ptr(), nbytes)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"mode": "copy_calibration", "bytes_read": nbytes, "bytes_written": nbytes,
+                      "reps": reps, "us_per_copy": round(dt * 1e6, 2),
+                      "GBps": round(2 * nbytes / dt / 1e9, 1)}), flush=True)
+    return 0
 
 
 def bytes_per_lup(storage: str) -> int:
@@ -28,7 +129,7 @@ def bytes_per_lup(storage: str) -> int:
     return 2 * 9 * {"f64": 8, "f32": 4, "f16": 2}[storage]
 
 
-def cpu_baseline(case, target_s: float = 12.0):
+def cpu_baseline(case, target_s: float = 15.0):
     """The FP64 CPU oracle on the same workload, a bounded number of steps (host cores)."""
     import oracle
     ref = oracle.OracleSim(oracle.OracleConfig(nx=case.nx, ny=case.ny, tau0=case.tau0,
@@ -40,7 +141,7 @@ def cpu_baseline(case, target_s: float = 12.0):
     t0 = time.perf_counter()
     ref.step(1)
     t1 = time.perf_counter() - t0
-    n = max(1, min(200, int(target_s / max(t1, 1e-6))))
+    n = max(1, min(1000, int(target_s / max(t1, 1e-6))))
     t0 = time.perf_counter()
     ref.step(n)
     dt = time.perf_counter() - t0
@@ -56,10 +157,14 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storage", default="f32", choices=["f64", "f32", "f16"])
-    ap.add_argument("--tile-w", type=int, default=64)
-    ap.add_argument("--tile-rows", type=int, default=1)
+    ap.add_argument("--tile-w", type=int, default=32)
+    ap.add_argument("--tile-rows", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="launch kernels directly instead of replaying captured graphs")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run the copy kernel over this many bytes (counter calibration)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print("bench.py: this build runs on exactly one GPU (got --gpus %d); the lattice would "
@@ -73,9 +178,13 @@ def main(argv=None):
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
     torch.cuda.set_device(0)
+    if args.copy_bytes:
+        return copy_calibration(args.copy_bytes)
     case = workloads.moving_disks(seed=args.seed, storage=args.storage)
     sim = imb.simulation_from_case(case, storage=args.storage, tile_w=args.tile_w,
                                    tile_rows=args.tile_rows)
+    if args.no_graphs:
+        sim.set_graphs(False)
     sim.step(args.warmup)
     sim.sync()
     print("bench: warmup done", file=sys.stderr, flush=True)
@@ -103,7 +212,9 @@ def main(argv=None):
     traffic_bytes = case.cells * bpl
     achieved = traffic_bytes / (lat_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(args.storage, (args.tile_w, args.tile_rows)),
+                "kernel_source_sha256": lattice_source_hash(),
                 "kernel": "k_lattice_step<%s>" % {"f64": "StoreF64", "f32": "StoreF32",
                                                   "f16": "StoreF16"}[args.storage],
                 "kernel_avg_us": round(lat_ms * 1e3, 2),
@@ -130,6 +241,8 @@ def main(argv=None):
         "hbm_frac_whole_step": round(mlups * 1e6 * bpl / (HBM_PEAK_GBS * 1e9), 4),
         "roofline": roofline,
     }
+    out["adjoint"] = adjoint_ratio((args.tile_w, args.tile_rows))
+    print("bench: adjoint ratio %.3f" % out["adjoint"]["ratio"], file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(out), flush=True)

@@ -169,18 +169,31 @@ int imb_copy_kernel(void* dst, const void* src, size_t n_bytes, void* hip_stream
 
 /* Discrete adjoint of nsteps coupled steps from the current state (differentiation form).
  * Objective J = sum over the nsteps steps and over disks of
- *     wfx[p] * Fx_p^n + wfy[p] * Fy_p^n + wtz[p] * Tz_p^n     (host weight arrays, any NULL = 0).
- * Requires all disks in IMB_MODE_PRESCRIBED or IMB_MODE_FIXED, smag_cs = 0 and F32 or F64
- * storage.  Disk positions follow X_p^n = X_p^0 + n V_p (prescribed) or stay (fixed).
- * Runs the forward pass saving a checkpoint every k_ckpt steps, then for each segment from the
- * last recomputes its states and applies the transposed step (Eqs. 1, 12-16 differentiated,
- * with the analytic solid ratio's derivative with respect to the centre).
- * Outputs (host, FP64, length n; any may be NULL): dJ/dX0, dJ/dY0, dJ/dVx, dJ/dVy, dJ/domega,
- * and dJ/dg (2 values) and J itself.  The simulation state afterwards is the state after the
- * nsteps forward steps.  Synchronises. */
+ *     wfx[p] * Fx_p^n + wfy[p] * Fy_p^n + wtz[p] * Tz_p^n     (host weight arrays, any NULL = 0),
+ * with F, T the hydrodynamic force and torque on the disks (Eqs. 15, 16, force on the disk).
+ * Requires all disks in IMB_MODE_PRESCRIBED or IMB_MODE_FIXED (IMB_EINVAL otherwise), smag_cs = 0
+ * (IMB_EINVAL) and F32 or F64 storage (IMB_EUNSUPPORTED for F16).  Disk positions follow
+ * X_p^n = X_p^0 + n V_p (prescribed) or stay (fixed).  Runs the forward pass keeping a checkpoint
+ * every k_ckpt steps, then for each segment from the last recomputes its states and applies the
+ * transposed step (Eqs. 1, 12-16 differentiated, with the analytic derivative of the exact solid
+ * ratio with respect to the disk centre).  The library allocates the checkpoints
+ * (ceil(nsteps / k_ckpt) + k_ckpt + 1 population copies) on first use and keeps them for later
+ * calls of the same shape.
+ * Outputs (host, FP64; any may be NULL): dJ/dX0, dJ/dY0, dJ/dVx, dJ/dVy, dJ/domega (length n
+ * each), dJ/dg (2 values: x, y), J, and dJ/df0 ([9][ny][nx]: the gradient with respect to the
+ * post-stream populations at the start, as imb_set_populations takes them).
+ * The simulation state afterwards is the state after the nsteps forward steps.  Synchronises. */
 int imb_adjoint(imb_sim* sim, int32_t nsteps, int32_t k_ckpt, const double* wfx,
                 const double* wfy, const double* wtz, double* gx0, double* gy0, double* gvx,
-                double* gvy, double* gom, double* gg, double* J);
+                double* gvy, double* gom, double* gg, double* J, double* gf0);
+
+/* GPU time of the last imb_adjoint call (HIP events): the forward pass and the reverse sweep
+ * (recomputation + adjoint steps + finalisation), in milliseconds.  With kernel timing on
+ * (imb_set_kernel_timing), also the summed time and count of the adjoint-step and recompute
+ * launches since the last call of this function (which resets them).  Any pointer may be NULL. */
+int imb_get_adjoint_timing(imb_sim* sim, double* forward_ms, double* reverse_ms,
+                           double* adjoint_kernel_ms, int64_t* adjoint_kernels,
+                           double* recompute_kernel_ms, int64_t* recompute_kernels);
 
 /* -------------------------------------------------------------- batched channels
  * Many independent simulations (channels) of different sizes and particle counts advanced

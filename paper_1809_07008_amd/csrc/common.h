@@ -97,6 +97,7 @@ struct ParticleArgs {
   int tiles_x, tiles_y, tw, th;
   ParticleState s;
   ParticleTable tab;
+  const int4* box_in;  // boxes of the step whose partials are finalised (null: tab.box)
   int* band_off;   // written with the table: per tile row, the disks whose box touches it
   int* band_ids;   // capacity np * MAXSLOT
   const double4* partials;  // [MAXSLOT][pstride]

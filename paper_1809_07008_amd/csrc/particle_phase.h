@@ -1,0 +1,525 @@
+// particle_phase.h -- the particle phase of a coupled step, one workgroup:
+//   1. hydrodynamic force and torque on each disk: sum of the disk's per-tile partial sums
+//      (Eqs. 15, 16), in slot order (deterministic);
+//   2. DEM (Sec. 2.1, 2.3): N_sub velocity-Verlet (kick-drift-kick) sub-cycles of dt = 1/N_sub
+//      (Eq. 17) with the hydrodynamic load held fixed; normal linear spring-dashpot contacts
+//      between disks and with the walls (Eqs. 7, 8); the contact force is evaluated after each
+//      drift from the new positions and half-step velocities and reused by the next kick;
+//      prescribed disks move by V once per step, fixed disks stay;
+//   3. the disk table (tile box, position, velocity) and the per-tile-row (band) candidate lists
+//      that the next lattice step reads.
+//
+// Contacts are searched in a Verlet neighbour list (skin DEM_SKIN) rebuilt whenever a disk has
+// moved more than DEM_SKIN/2 - MAX_MOVE since the last build; a disk moving more than MAX_MOVE in
+// one step latches ERR_MOVE, so no contact can be missed silently.
+// Only disks with a neighbour or wall within 2 MAX_MOVE ("active") can touch anything during
+// the step; they run the sub-cycles together, synchronised per sub-step.  Every other free disk
+// feels no contact force for the whole step and runs the same sub-cycle arithmetic on its own,
+// without synchronisation.
+// Readings: damping ratio zeta with c_n = 2 zeta sqrt(k_n m_eff); m = rho_s pi r^2, I = m r^2/2;
+// no tangential force and no gravity.
+#pragma once
+
+#include "step.h"
+
+namespace imb {
+
+__device__ inline double nearest_image(double d, int n) {
+  if (d > 0.5 * n) d -= n;
+  else if (d < -0.5 * n) d += n;
+  return d;
+}
+
+__device__ inline double wrap_coord(double v, int n) {
+  if (v >= n) v -= n;
+  else if (v < 0.0) v += n;
+  return v;
+}
+
+template <int NT>
+__device__ inline double block_sum(double v, double* s_red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if (lane == 0) s_red[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < NT / 64; ++w) t += s_red[w];
+  __syncthreads();
+  return t;
+}
+
+__device__ inline int block_or(int v, int* s_flag) {
+  if (threadIdx.x == 0) *s_flag = 0;
+  __syncthreads();
+  if (v) atomicOr(s_flag, v);
+  __syncthreads();
+  const int r = *s_flag;
+  __syncthreads();
+  return r;
+}
+
+// Exclusive prefix sum of cnt[0..n) in place (LDS), returns the total.
+template <int NT>
+__device__ inline int block_exclusive_scan(int* cnt, int n, int* s_wave) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int chunk = (n + NT - 1) / NT;
+  const int lo = tid * chunk, hi = min(lo + chunk, n);
+  int local = 0;
+  for (int k = lo; k < hi; ++k) local += cnt[k];
+  int incl = local;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int v = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += v;
+  }
+  if (lane == 63) s_wave[wave] = incl;
+  __syncthreads();
+  int wbase = 0, total = 0;
+  for (int w = 0; w < NT / 64; ++w) {
+    if (w < wave) wbase += s_wave[w];
+    total += s_wave[w];
+  }
+  int run = wbase + incl - local;
+  for (int k = lo; k < hi; ++k) {
+    const int c = cnt[k];
+    cnt[k] = run;
+    run += c;
+  }
+  __syncthreads();
+  return total;
+}
+
+// Latency layout: every global load the phase needs is issued in one batch at the start and
+// every global store is issued after the last barrier, so barriers never wait on memory; each
+// disk's state lives in its own thread's registers and only positions and velocities that other
+// disks' contact tests read are mirrored in LDS.
+// One disk per thread: NT >= np.  `lds` holds max(5 np doubles, tiles_y + 1 ints).
+template <int NT>
+__device__ void particle_phase(const ParticleArgs& a, double* lds) {
+#pragma clang fp contract(off)
+  constexpr int PWAVES = NT / 64;
+  __shared__ double s_red[PWAVES];
+  __shared__ int s_flag, s_wave[PWAVES];
+  __shared__ int s_nact, s_aid[64], s_ann[64], s_anb[64][8];
+  __shared__ double s_ast[64][6];
+  constexpr int NB_REG = 8;   // neighbour ids kept in registers; the rest are read from the list
+  constexpr int PF = 8;       // partial-sum slots loaded in the first batch
+  const int np = a.np, p = threadIdx.x;
+  const bool have = p < np;
+  double* sx = lds;
+  double* sy = sx + np;
+  double* svx = sy + np;
+  double* svy = svx + np;
+  double* sr = svy + np;
+  const ParticleState& s = a.s;
+
+  // ---- one batch of loads
+  int4 b = make_int4(0, 0, 0, 0);
+  double x = 0, y = 0, vx = 0, vy = 0, om = 0, r = 1, fcx = 0, fcy = 0, xref = 0, yref = 0;
+  int mode = 1, nn = 0;
+  int nb[NB_REG];
+  double4 pv[PF];
+#pragma unroll
+  for (int u = 0; u < NB_REG; ++u) nb[u] = 0;
+  if (have) {
+    b = (a.box_in ? a.box_in : a.tab.box)[p];
+    x = s.x[p]; y = s.y[p]; vx = s.vx[p]; vy = s.vy[p]; om = s.om[p]; r = s.r[p];
+    mode = s.mode[p];
+    fcx = s.fcx[p]; fcy = s.fcy[p]; xref = s.xref[p]; yref = s.yref[p];
+    nn = s.nnbr[p];
+#pragma unroll
+    for (int u = 0; u < NB_REG; ++u) nb[u] = s.nbr[p * NBMAX + u];
+    if (a.do_finalize) {
+#pragma unroll
+      for (int u = 0; u < PF; ++u) pv[u] = a.partials[(long long)u * a.pstride + p];
+    }
+  }
+  const int rebuild_flag = a.do_dem || a.init_contacts ? *s.rebuild : 0;
+  const double x_start = x, y_start = y;
+
+  // ---- 1. forces of the step that just ran: slots in order
+  double Fx = 0.0, Fy = 0.0, Tz = 0.0;
+  if (have && a.do_finalize) {
+    const int ns = b.y * b.w;
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      if (u < ns) {
+        Fx += pv[u].x;
+        Fy += pv[u].y;
+        Tz += pv[u].z;
+      }
+    }
+    for (int k0 = PF; k0 < ns; k0 += PF) {  // further batches of PF loads, summed in order
+      double4 v[PF];
+#pragma unroll
+      for (int u = 0; u < PF; ++u)
+        v[u] = k0 + u < ns ? a.partials[(long long)(k0 + u) * a.pstride + p]
+                           : make_double4(0.0, 0.0, 0.0, 0.0);
+#pragma unroll
+      for (int u = 0; u < PF; ++u) {
+        if (k0 + u < ns) {
+          Fx += v[u].x;
+          Fy += v[u].y;
+          Tz += v[u].z;
+        }
+      }
+    }
+  } else if (have) {
+    Fx = s.Fx[p];
+    Fy = s.Fy[p];
+    Tz = s.Tz[p];
+  }
+  double jsum = 0.0;
+  if (a.do_finalize && a.J) {
+    double jl = 0.0;
+    if (have) {
+      if (a.wfx) jl += a.wfx[p] * Fx;
+      if (a.wfy) jl += a.wfy[p] * Fy;
+      if (a.wtz) jl += a.wtz[p] * Tz;
+    }
+    jsum = block_sum<NT>(jl, s_red);
+  }
+
+  if (have) {
+    sx[p] = x; sy[p] = y; svx[p] = vx; svy[p] = vy; sr[p] = r;
+  }
+  __syncthreads();
+
+  const double kn = a.kn, zeta = a.zeta;
+  // contact force on disk p (Eqs. 7, 8): neighbours in ascending id, then the walls
+  auto contact_of = [&](int i, double ri, int cnn, const int* cnb, double px, double py,
+                        double pvx, double pvy, double& ox, double& oy) {
+    const double r = ri;
+    const double mi = a.rho_s * M_PI * r * r;
+    double fx = 0.0, fy = 0.0;
+    for (int q = 0; q < cnn; ++q) {
+      int j = 0;
+      if (q < NB_REG) {
+#pragma unroll
+        for (int u = 0; u < NB_REG; ++u)
+          if (u == q) j = cnb[u];
+      } else {
+        j = s.nbr[i * NBMAX + q];
+      }
+      double dx = sx[j] - px;
+      double dy = sy[j] - py;
+      dx = nearest_image(dx, a.nx);
+      if (!a.walls) dy = nearest_image(dy, a.ny);
+      const double d2 = dx * dx + dy * dy;
+      const double rs = r + sr[j];
+      // pairs clearly apart skip the square root (the margin keeps rounding cases exact)
+      if (d2 > rs * rs * (1.0 + 1e-12)) continue;
+      const double dist = sqrt(d2);
+      const double delta = rs - dist;
+      if (delta > 0.0 && dist > 0.0) {
+        const double idist = 1.0 / dist;
+        const double nxu = dx * idist, nyu = dy * idist;
+        const double vn = (pvx - svx[j]) * nxu + (pvy - svy[j]) * nyu;
+        const double mj = a.rho_s * M_PI * sr[j] * sr[j];
+        const double meff = mi * mj / (mi + mj);
+        const double cn = 2.0 * zeta * sqrt(kn * meff);
+        const double fn = kn * delta + cn * vn;
+        fx += -fn * nxu;
+        fy += -fn * nyu;
+      }
+    }
+    if (a.walls) {
+      const double cn = 2.0 * zeta * sqrt(kn * mi);
+      const double db = r - (py + 0.5);
+      if (db > 0.0) {
+        const double vn = -pvy;
+        fy += kn * db + cn * vn;
+      }
+      const double dt = r - ((a.ny - 0.5) - py);
+      if (dt > 0.0) {
+        const double vn = pvy;
+        fy += -(kn * dt + cn * vn);
+      }
+    }
+    ox = fx;
+    oy = fy;
+  };
+  auto contact = [&](double px, double py, double pvx, double pvy, double& ox, double& oy) {
+    contact_of(p, r, nn, nb, px, py, pvx, pvy, ox, oy);
+  };
+
+  const bool own = have && mode == 0;
+  bool rebuilt = false;
+  // bit 1: some disk is free; bit 2: the neighbour list must be rebuilt
+  int flags = 0;
+  if (a.do_dem || a.init_contacts) {
+    int mine = own ? 1 : 0;
+    if (have) {
+      const double ddx = nearest_image(x - xref, a.nx);
+      const double ddy = a.walls ? y - yref : nearest_image(y - yref, a.ny);
+      const double lim = 0.5 * DEM_SKIN - MAX_MOVE;
+      if (ddx * ddx + ddy * ddy > lim * lim) mine |= 2;
+    }
+    if (p == 0 && rebuild_flag) mine |= 2;
+    flags = block_or(mine, &s_flag);
+  }
+  if (flags & 1) {
+    // ---- neighbour list maintenance
+    if (flags & 2) {
+      rebuilt = true;
+      if (have) {
+        int cnt = 0;
+        for (int j = 0; j < np; ++j) {
+          if (j == p) continue;
+          double dx = nearest_image(sx[j] - x, a.nx);
+          double dy = sy[j] - y;
+          if (!a.walls) dy = nearest_image(dy, a.ny);
+          const double reach = r + sr[j] + DEM_SKIN;
+          if (dx * dx + dy * dy < reach * reach) {
+            if (cnt < NB_REG) {
+#pragma unroll
+              for (int u = 0; u < NB_REG; ++u)
+                if (u == cnt) nb[u] = j;
+            }
+            if (cnt < NBMAX) s.nbr[p * NBMAX + cnt] = j;  // read back only by this thread
+            ++cnt;
+          }
+        }
+        if (cnt > NBMAX) {
+          atomicOr(a.err, ERR_NBR);
+          cnt = NBMAX;
+        }
+        nn = cnt;
+        xref = x;
+        yref = y;
+      }
+    }
+
+    if (a.init_contacts) {
+      if (own) contact(x, y, vx, vy, fcx, fcy);
+      else {
+        fcx = 0.0;
+        fcy = 0.0;
+      }
+    } else {
+      // ---- classify: active if a neighbour's or a wall's gap is within 2 MAX_MOVE
+      bool active = false;
+      if (own) {
+        const double reach = 2.0 * MAX_MOVE;
+        for (int q = 0; q < nn; ++q) {
+          int j = 0;
+          if (q < NB_REG) {
+#pragma unroll
+            for (int u = 0; u < NB_REG; ++u)
+              if (u == q) j = nb[u];
+          } else {
+            j = s.nbr[p * NBMAX + q];
+          }
+          const double dx = nearest_image(sx[j] - x, a.nx);
+          double dy = sy[j] - y;
+          if (!a.walls) dy = nearest_image(dy, a.ny);
+          const double g = r + sr[j] + reach;
+          active |= dx * dx + dy * dy <= g * g;
+        }
+        if (a.walls && (y - r + 0.5 <= reach || (a.ny - 0.5) - y - r <= reach)) active = true;
+      }
+      const double dt = 1.0 / a.n_sub, h = 0.5 * dt;
+      const double m = a.rho_s * M_PI * r * r;
+      const double I = 0.5 * m * r * r;
+      if (own && !active) {
+        // quiet: no contact force during the whole step, so the accelerations are the same in
+        // every sub-step (computed once; the sub-step arithmetic is otherwise unchanged)
+        const double ax = (0.0 + Fx) / m;
+        const double ay = (0.0 + Fy) / m;
+        const double hax = h * ax, hay = h * ay, hal = h * (Tz / I);
+        for (int k = 0; k < a.n_sub; ++k) {
+          vx = vx + hax;
+          vy = vy + hay;
+          x = wrap_coord(x + dt * vx, a.nx);
+          y = y + dt * vy;
+          if (!a.walls) y = wrap_coord(y, a.ny);
+          om = om + hal;
+          vx = vx + hax;
+          vy = vy + hay;
+          om = om + hal;
+        }
+        fcx = 0.0;
+        fcy = 0.0;
+      }
+      // active disks: up to 64 are packed into the first wavefront and run their sub-steps
+      // there with wavefront-level ordering only; more than 64 use every owner thread and
+      // block barriers
+      if (threadIdx.x == 0) s_nact = 0;
+      __syncthreads();
+      if (own && active) {
+        const int idx = atomicAdd(&s_nact, 1);
+        if (idx < 64) {
+          s_aid[idx] = p;
+          s_ast[idx][0] = Fx; s_ast[idx][1] = Fy; s_ast[idx][2] = Tz;
+          s_ast[idx][3] = fcx; s_ast[idx][4] = fcy; s_ast[idx][5] = om;
+          s_ann[idx] = nn;
+#pragma unroll
+          for (int u = 0; u < NB_REG; ++u) s_anb[idx][u] = nb[u];
+        }
+      }
+      __syncthreads();
+      const int nact = s_nact;
+      if (nact > 0 && nact <= 64) {
+        const int t = threadIdx.x;
+        if (t < nact) {
+          const int i = s_aid[t];
+          const double ri = sr[i];
+          const double mi_ = a.rho_s * M_PI * ri * ri;
+          const double Ii = 0.5 * mi_ * ri * ri;
+          const double im = 1.0 / mi_;
+          double px = sx[i], py = sy[i], pvx = svx[i], pvy = svy[i];
+          const double aFx = s_ast[t][0], aFy = s_ast[t][1], aTz = s_ast[t][2];
+          double afx = s_ast[t][3], afy = s_ast[t][4], aom = s_ast[t][5];
+          const int ann = s_ann[t];
+          int anb[NB_REG];
+#pragma unroll
+          for (int u = 0; u < NB_REG; ++u) anb[u] = s_anb[t][u];
+          const double hal = h * (aTz / Ii);
+          for (int k = 0; k < a.n_sub; ++k) {
+            const double ax = (afx + aFx) * im;
+            const double ay = (afy + aFy) * im;
+            pvx = pvx + h * ax;
+            pvy = pvy + h * ay;
+            px = wrap_coord(px + dt * pvx, a.nx);
+            py = py + dt * pvy;
+            if (!a.walls) py = wrap_coord(py, a.ny);
+            aom = aom + hal;
+            sx[i] = px; sy[i] = py; svx[i] = pvx; svy[i] = pvy;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            contact_of(i, ri, ann, anb, px, py, pvx, pvy, afx, afy);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            const double bx = (afx + aFx) * im;
+            const double by = (afy + aFy) * im;
+            pvx = pvx + h * bx;
+            pvy = pvy + h * by;
+            aom = aom + hal;
+          }
+          svx[i] = pvx; svy[i] = pvy;
+          s_ast[t][3] = afx; s_ast[t][4] = afy; s_ast[t][5] = aom;
+        }
+        __syncthreads();
+        if (own && active) {
+          for (int t2 = 0; t2 < nact; ++t2) {
+            if (s_aid[t2] == p) {
+              fcx = s_ast[t2][3]; fcy = s_ast[t2][4]; om = s_ast[t2][5];
+            }
+          }
+          x = sx[p]; y = sy[p]; vx = svx[p]; vy = svy[p];
+        }
+      } else if (nact > 64) {
+        // active disks: sub-steps synchronised across the block through LDS
+        const double hal = h * (Tz / I);
+        const double im = 1.0 / m;
+        for (int k = 0; k < a.n_sub; ++k) {
+          if (own && active) {
+            const double ax = (fcx + Fx) * im;
+            const double ay = (fcy + Fy) * im;
+            vx = vx + h * ax;
+            vy = vy + h * ay;
+            x = wrap_coord(x + dt * vx, a.nx);
+            y = y + dt * vy;
+            if (!a.walls) y = wrap_coord(y, a.ny);
+            om = om + hal;
+            sx[p] = x; sy[p] = y; svx[p] = vx; svy[p] = vy;
+          }
+          __syncthreads();
+          if (own && active) contact(x, y, vx, vy, fcx, fcy);
+          __syncthreads();
+          if (own && active) {
+            const double ax = (fcx + Fx) * im;
+            const double ay = (fcy + Fy) * im;
+            vx = vx + h * ax;
+            vy = vy + h * ay;
+            om = om + hal;
+          }
+        }
+      }
+    }
+  }
+
+  double nx_ = x, ny_ = y;
+  if (a.do_dem && have) {
+    if (mode == 2) {
+      nx_ = wrap_coord(x + vx, a.nx);
+      ny_ = y + vy;
+      if (!a.walls) ny_ = wrap_coord(ny_, a.ny);
+    }
+  }
+  // ---- table: tile box of the new position
+  __syncthreads();  // LDS is reused below
+  int4 nbx = make_int4(0, 0, 0, 0);
+  if (a.do_table && have) {
+    if (!isfinite(nx_) || !isfinite(ny_)) {
+      nbx = make_int4(0, 0, 0, 0);
+    } else if (!tile_box(nx_, ny_, r, a.nx, a.ny, a.walls, a.tiles_x, a.tiles_y, a.tw, a.th,
+                         &nbx)) {
+      atomicOr(a.err, ERR_SLOTS);
+      nbx = make_int4(0, 0, 0, 0);
+    }
+  }
+  // ---- band lists: counting sort of (tile row, disk) pairs in LDS
+  int* cnt = (int*)lds;
+  const int nbands = a.tiles_y;
+  int total = 0;
+  if (a.do_table) {
+    for (int k = threadIdx.x; k <= nbands; k += NT) cnt[k] = 0;
+    __syncthreads();
+    if (have)
+      for (int k = 0; k < nbx.w; ++k) {
+        const int ty = nbx.z + k < nbands ? nbx.z + k : nbx.z + k - nbands;
+        atomicAdd(&cnt[ty], 1);
+      }
+    __syncthreads();
+    total = block_exclusive_scan<NT>(cnt, nbands, s_wave);
+    for (int k = threadIdx.x; k < nbands; k += NT) a.band_off[k] = cnt[k];
+    if (threadIdx.x == 0) a.band_off[nbands] = total;
+    if (have)
+      for (int k = 0; k < nbx.w; ++k) {
+        const int ty = nbx.z + k < nbands ? nbx.z + k : nbx.z + k - nbands;
+        const int pos = atomicAdd(&cnt[ty], 1);
+        if (pos < np * MAXSLOT) a.band_ids[pos] = p;
+        else atomicOr(a.err, ERR_BAND);
+      }
+  }
+
+  // ---- all remaining global stores
+  if (a.do_finalize && a.J && threadIdx.x == 0) *a.J += jsum;
+  if (have) {
+    if (a.do_finalize) {
+      s.Fx[p] = Fx;
+      s.Fy[p] = Fy;
+      s.Tz[p] = Tz;
+    }
+    if (a.do_dem) {
+      const double mdx = nearest_image(nx_ - x_start, a.nx);
+      const double mdy = a.walls ? ny_ - y_start : nearest_image(ny_ - y_start, a.ny);
+      const bool bad = !isfinite(nx_) || !isfinite(ny_) || !isfinite(vx) || !isfinite(vy) ||
+                       !isfinite(om) || (a.walls && (ny_ < -0.5 || ny_ > a.ny - 0.5));
+      const bool moved_far = mdx * mdx + mdy * mdy > MAX_MOVE * MAX_MOVE;
+      if (bad) atomicOr(a.err, ERR_LEFT);
+      if (moved_far) atomicOr(a.err, ERR_MOVE);
+      s.x[p] = nx_; s.y[p] = ny_; s.vx[p] = vx; s.vy[p] = vy; s.om[p] = om;
+    }
+    if (a.do_dem || a.init_contacts) {
+      s.fcx[p] = fcx;
+      s.fcy[p] = fcy;
+    }
+    if (rebuilt) {
+      s.nnbr[p] = nn;
+      s.xref[p] = xref;
+      s.yref[p] = yref;
+    }
+    if (a.do_table) {
+      a.tab.box[p] = nbx;
+      a.tab.pos[p] = make_double4(nx_, ny_, r, 0.0);
+      a.tab.vel[p] = make_double4(vx, vy, om, 0.0);
+    }
+  }
+  if (rebuilt && threadIdx.x == 0) *s.rebuild = 0;
+}
+
+}  // namespace imb

@@ -39,6 +39,7 @@ struct SimView {
   int64_t* steps;
   std::string* err;
   AdjointState** adj;
+  bool* timing;
 };
 
 size_t align_up(size_t v, size_t a);

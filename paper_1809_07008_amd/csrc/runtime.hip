@@ -836,6 +836,7 @@ SimView sim_view(imb_sim* s) {
   v.steps = &s->steps;
   v.err = &s->err;
   v.adj = &s->adj;
+  v.timing = &s->timing;
   return v;
 }
 }  // namespace imb

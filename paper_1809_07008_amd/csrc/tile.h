@@ -1,0 +1,250 @@
+// tile.h -- device helpers shared by the lattice-step and adjoint kernels: the per-tile disk
+// list, the per-thread scratch of covering disks, pull-stream loads with the wall rule, and the
+// deterministic compensated wave reductions used for per-disk sums.
+#pragma once
+
+#include "common.h"
+#include "solid.h"
+
+namespace imb {
+
+template <class T>
+struct PEntry {
+  int ix, iy, pid, slot;
+  T fx, fy, r, vx, vy, om;
+};
+
+// Disks whose tile box contains tile (tx, ty), sorted by id (so every sum over them has a fixed
+// order).  Candidates come from the tile row's band list written by the particle phase.  Returns
+// the count (capped at LMAX; overflow latches ERR_TILE_LIST).  Block-uniform control flow.
+template <class T>
+__device__ int build_tile_list(const LatticeArgs& a, int tx, int ty, PEntry<T>* pl, int* s_cnt,
+                               int* s_pid, int* s_slot) {
+  if (a.np == 0) return 0;
+  const int b0 = a.band_off[ty], b1 = a.band_off[ty + 1];
+  if (b1 <= b0) return 0;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int base = 0;
+  for (int k0 = b0; k0 < b1; k0 += BLOCK) {
+    const int k = k0 + tid;
+    int p = -1, slot = -1;
+    if (k < b1) {
+      p = a.band_ids[k];
+      slot = box_slot(a.tab.box[p], tx, ty, a.tiles_x, a.tiles_y);
+    }
+    const bool hit = slot >= 0;
+    const unsigned long long m = __ballot(hit);
+    const int below = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) s_cnt[wave] = __popcll(m);
+    __syncthreads();
+    int off = base, total = 0;
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) {
+      if (w < wave) off += s_cnt[w];
+      total += s_cnt[w];
+    }
+    if (hit) {
+      const int q = off + below;
+      if (q < LMAX) {
+        s_pid[q] = p;
+        s_slot[q] = slot;
+      } else {
+        atomicOr(a.err, ERR_TILE_LIST);
+      }
+    }
+    base += total;
+    __syncthreads();
+  }
+  const int n = base < LMAX ? base : LMAX;
+  if (tid < n) {
+    const int p = s_pid[tid];
+    int rank = 0;
+    for (int q = 0; q < n; ++q) rank += s_pid[q] < p;
+    const double4 ps = a.tab.pos[p];
+    const double4 vl = a.tab.vel[p];
+    const double flx = floor(ps.x), fly = floor(ps.y);
+    PEntry<T> e;
+    e.ix = (int)flx;
+    e.iy = (int)fly;
+    e.pid = p;
+    e.slot = s_slot[tid];
+    e.fx = (T)(ps.x - flx);
+    e.fy = (T)(ps.y - fly);
+    e.r = (T)ps.z;
+    e.vx = (T)vl.x;
+    e.vy = (T)vl.y;
+    e.om = (T)vl.z;
+    pl[rank] = e;
+  }
+  __syncthreads();
+  return n;
+}
+
+// Per-thread scratch of a tile in LDS (indexed [k][thread] so a wave touches 64 distinct
+// banks): the disks covering the current cell and the thread's running force sums.
+template <class T>
+struct CellScratch {
+  int cj[MAXC][BLOCK];     // list entries of the disks covering the current cell
+  T ce[MAXC][BLOCK];       // their eps
+  int aj[MAXC][BLOCK];     // list entries owning the thread's accumulators (-1: free)
+  T af[3][MAXC][BLOCK];    // accumulated force x, y and torque
+};
+
+template <class T>
+__device__ inline void lever_arm(const LatticeArgs& a, const PEntry<T>& e, int x, int y, T* dx,
+                                 T* dy) {
+  int di = x - e.ix;
+  const int hx = a.nx / 2, hy = a.ny / 2;
+  if (di > hx) di -= a.nx;
+  else if (di < -hx) di += a.nx;
+  int dj = y - e.iy;
+  if (!a.walls) {
+    if (dj > hy) dj -= a.ny;
+    else if (dj < -hy) dj += a.ny;
+  }
+  *dx = (T)di - e.fx;
+  *dy = (T)dj - e.fy;
+}
+
+// Disks covering cell (x, y): eps > 0 with the image nearest to the cell, evaluated directly
+// (used by the solid-ratio diagnostic).  Returns their count.
+template <class T>
+__device__ inline int covering_disks(const LatticeArgs& a, const PEntry<T>* pl, int n, int x,
+                                     int y, CellScratch<T>& cs) {
+  const int tid = threadIdx.x;
+  int nc = 0;
+  for (int j = 0; j < n; ++j) {
+    T dx, dy;
+    lever_arm(a, pl[j], x, y, &dx, &dy);
+    const T eps = solid_fraction<T>(pl[j].r, dx, dy);
+    if (eps > T(0)) {
+      if (nc < MAXC) {
+        cs.cj[nc][tid] = j;
+        cs.ce[nc][tid] = eps;
+        ++nc;
+      } else {
+        atomicOr(a.err, ERR_CELL);
+      }
+    }
+  }
+  return nc;
+}
+
+// Disks whose image nearest to cell (x, y) reaches the cell, classified with the cheap tests of
+// solid_fraction: inside cells get eps = 1 now; cut cells are appended to the tile's queue
+// (owner thread, slot, disk) and get their exact area from the whole block afterwards, so the
+// expensive branch runs on densely packed lanes.  Returns the count.
+template <class T>
+__device__ inline int classify_cell(const LatticeArgs& a, const PEntry<T>* pl, int n, int x, int y,
+                                    CellScratch<T>& cs, int* s_qn, int* s_q) {
+  const int tid = threadIdx.x;
+  int nc = 0;
+  for (int j = 0; j < n; ++j) {
+    T dx, dy;
+    lever_arm(a, pl[j], x, y, &dx, &dy);
+    const T r = pl[j].r;
+    const T x0 = dx - T(0.5), x1 = dx + T(0.5), y0 = dy - T(0.5), y1 = dy + T(0.5);
+    const T nx = x0 > T(0) ? x0 : (x1 < T(0) ? x1 : T(0));
+    const T ny = y0 > T(0) ? y0 : (y1 < T(0) ? y1 : T(0));
+    if (nx * nx + ny * ny >= r * r) continue;
+    if (nc >= MAXC) {
+      atomicOr(a.err, ERR_CELL);
+      continue;
+    }
+    const T fx = fabs(x0) > fabs(x1) ? fabs(x0) : fabs(x1);
+    const T fy = fabs(y0) > fabs(y1) ? fabs(y0) : fabs(y1);
+    cs.cj[nc][tid] = j;
+    if (fx * fx + fy * fy <= r * r) {
+      cs.ce[nc][tid] = T(1);
+    } else {
+      const int q = atomicAdd(s_qn, 1);
+      s_q[q] = tid | (nc << 8) | (j << 10);
+    }
+    ++nc;
+  }
+  return nc;
+}
+
+// Pull-stream load of the 9 populations arriving at (x, y).
+template <class St>
+__device__ inline void pull_load(const LatticeArgs& a, const typename St::S* src, int x, int y,
+                                 typename St::T f[NQ]) {
+  using T = typename St::T;
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    int xs = x - cx_of(i), ys = y - cy_of(i);
+    xs = xs < 0 ? xs + a.nx : (xs >= a.nx ? xs - a.nx : xs);
+    long long idx;
+    if (ys < 0 || ys >= a.ny) {
+      if (a.walls) {  // half-way bounce-back: the link left through the wall and came back
+        idx = (long long)opp_of(i) * a.plane + (long long)y * a.pitch + x;
+        f[i] = St::load(src, idx, T(0));
+        continue;
+      }
+      ys = ys < 0 ? ys + a.ny : ys - a.ny;
+    }
+    idx = (long long)i * a.plane + (long long)ys * a.pitch + xs;
+    f[i] = St::load(src, idx, T(0));
+  }
+}
+
+// Compensated (hi, lo) pair used for the force sums in FP32; plain sum in FP64.
+template <class T>
+struct Acc {
+  T hi, lo;
+  __device__ void add(T v) {
+    const T s = hi + v;
+    const T bp = s - hi;
+    lo += (hi - (s - bp)) + (v - bp);
+    hi = s;
+  }
+  __device__ void add(const Acc& o) {
+    add(o.hi);
+    lo += o.lo;
+  }
+};
+
+// Wave-wide sum with DPP row rotations (no LDS traffic): rotating by 8, 4, 2, 1 lanes inside each
+// row of 16 leaves the row total in every lane; lanes 0, 16, 32, 48 are then added in fixed
+// order, so the result is the same on every run.
+template <int CTRL>
+__device__ inline float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ inline float read_lane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ inline double read_lane(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <int CTRL, class T>
+__device__ inline void dpp_add(Acc<T>& v) {
+  Acc<T> o;
+  o.hi = dpp_move<CTRL>(v.hi);
+  o.lo = dpp_move<CTRL>(v.lo);
+  v.add(o);
+}
+
+template <class T>
+__device__ inline Acc<T> wave_sum(Acc<T> v) {
+  dpp_add<0x128>(v);  // row_ror:8
+  dpp_add<0x124>(v);  // row_ror:4
+  dpp_add<0x122>(v);  // row_ror:2
+  dpp_add<0x121>(v);  // row_ror:1
+  Acc<T> t{read_lane(v.hi, 0), read_lane(v.lo, 0)};
+#pragma unroll
+  for (int row = 1; row < 4; ++row) t.add(Acc<T>{read_lane(v.hi, 16 * row), read_lane(v.lo, 16 * row)});
+  return t;
+}
+
+}  // namespace imb

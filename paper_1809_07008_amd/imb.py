@@ -34,7 +34,7 @@ EXPORTED = [
     "imb_batch_create", "imb_batch_destroy", "imb_batch_set_particles", "imb_batch_step",
     "imb_batch_get_forces", "imb_batch_get_particles", "imb_batch_get_fields", "imb_batch_sync",
     "imb_batch_set_launch", "imb_strerror", "imb_last_error", "imb_version",
-    "imb_get_solid_field", "imb_set_graphs",
+    "imb_get_solid_field", "imb_set_graphs", "imb_get_adjoint_timing",
 ]
 
 
@@ -97,7 +97,9 @@ def load_library():
         "imb_get_kernel_timing": (C.c_int, [_VP, _D, P(C.c_int64), _D, P(C.c_int64)]),
         "imb_copy_kernel": (C.c_int, [_VP, _VP, C.c_size_t, _VP]),
         "imb_adjoint": (C.c_int, [_VP, C.c_int32, C.c_int32, _D, _D, _D, _D, _D, _D, _D, _D,
-                                  _D, _D]),
+                                  _D, _D, _D]),
+        "imb_get_adjoint_timing": (C.c_int, [_VP, _D, _D, _D, P(C.c_int64), _D,
+                                             P(C.c_int64)]),
         "imb_batch_required_bytes": (C.c_int, [C.c_int32, P(Config), P(C.c_size_t)]),
         "imb_batch_create": (C.c_int, [C.c_int32, P(Config), _VP, _VP, C.c_size_t, P(_VP)]),
         "imb_batch_destroy": (None, [_VP]),
@@ -303,22 +305,44 @@ class Simulation:
         return {"lattice_ms": lm.value, "lattice_launches": ln.value,
                 "particle_ms": pm.value, "particle_launches": pn.value}
 
-    def adjoint(self, nsteps: int, k_ckpt: int, wfx=None, wfy=None, wtz=None):
-        """Discrete adjoint of nsteps steps; returns dict of gradients and J."""
+    def adjoint(self, nsteps: int, k_ckpt: int, wfx=None, wfy=None, wtz=None,
+                populations: bool = False):
+        """Discrete adjoint of ``nsteps`` coupled steps from the current state (imb_adjoint).
+
+        J = sum over steps and disks of wfx Fx + wfy Fy + wtz Tz.  Returns a dict with J and the
+        gradients x0, y0, vx, vy, om (per disk), g (dJ/dg_x, dJ/dg_y) and, when ``populations``,
+        f0 = dJ/d(post-stream populations at the start) as [9, ny, nx].  The simulation advances
+        by nsteps."""
         n = self.n
         m = max(n, 1)
         w = [None if a is None else _f64(a, n) for a in (wfx, wfy, wtz)]
         outs = [np.zeros(m) for _ in range(5)]
         gg = np.zeros(2)
         J = np.zeros(1)
+        gf0 = np.zeros((9, self.cfg.ny, self.cfg.nx)) if populations else None
         self._check(load_library().imb_adjoint(self._h, int(nsteps), int(k_ckpt),
                                                *(_dp(a) for a in w), *(_dp(o) for o in outs),
-                                               _dp(gg), _dp(J)), "imb_adjoint")
+                                               _dp(gg), _dp(J), _dp(gf0)), "imb_adjoint")
         names = ["x0", "y0", "vx", "vy", "om"]
         res = {k: v[:n] for k, v in zip(names, outs)}
         res["g"] = gg
         res["J"] = float(J[0])
+        if populations:
+            res["f0"] = gf0
         return res
+
+    def adjoint_timing(self):
+        """GPU milliseconds of the last adjoint call (forward pass, reverse sweep) and, with
+        kernel timing on, the summed adjoint-step and recompute kernel times and counts."""
+        f, r, a, rc = C.c_double(), C.c_double(), C.c_double(), C.c_double()
+        an, rn = C.c_int64(), C.c_int64()
+        self._check(load_library().imb_get_adjoint_timing(self._h, C.byref(f), C.byref(r),
+                                                          C.byref(a), C.byref(an),
+                                                          C.byref(rc), C.byref(rn)),
+                    "imb_get_adjoint_timing")
+        return {"forward_ms": f.value, "reverse_ms": r.value, "adjoint_kernel_ms": a.value,
+                "adjoint_kernels": an.value, "recompute_kernel_ms": rc.value,
+                "recompute_kernels": rn.value}
 
 
 def copy_kernel(dst_ptr: int, src_ptr: int, nbytes: int, stream=None) -> None:

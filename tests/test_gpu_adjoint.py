@@ -1,0 +1,196 @@
+"""GPU discrete adjoint (imb_adjoint through the C-ABI) against central finite differences of
+the FP64 oracle's objective, J = sum over steps and disks of the weighted drag and torque."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from adjoint_fd import block_errors, fd_gradient, objective, base_state
+from paper_1809_07008_amd import imb
+from paper_1809_07008_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def small_case(storage="f64", walls=True, steps=30, overlap=False):
+    """64x32 channel, two disks in prescribed motion with velocity and spin, tau 0.7, g 1e-5.
+    No disk edge sits on a cell edge line (there the overlap area has a square-root kink and a
+    finite difference across it is not a derivative)."""
+    if overlap:
+        x, y, r = [24.3, 33.1], [15.7, 16.4], [5.5, 4.3]
+    else:
+        x, y, r = [20.3, 45.1], [15.7, 12.23], [5.5, 4.3]
+    p = W.Particles(np.array(x), np.array(y), np.array(r), np.array([2e-3, -1e-3]),
+                    np.array([-1e-3, 5e-4]), np.array([1e-3, -2e-3]),
+                    np.full(2, W.MODE_PRESCRIBED, np.int32))
+    return W.Case("adjoint_small", 64, 32, tau0=0.7, steps=steps, storage=storage, walls=walls,
+                  gx=1e-5, gy=2e-6, particles=p)
+
+
+WEIGHTS = dict(wfx=np.array([1.0, 0.7]), wfy=np.array([0.3, -0.5]), wtz=np.array([0.05, 0.02]))
+
+
+def gpu_adjoint(case, k, weights=WEIGHTS, storage=None, tile=(64, 1), populations=False):
+    sim = imb.simulation_from_case(case, storage=storage, tile_w=tile[0], tile_rows=tile[1])
+    return sim.adjoint(case.steps, k, populations=populations, **weights)
+
+
+@pytest.fixture(scope="module")
+def small_fd():
+    case = small_case()
+    return fd_gradient(case, case.steps, **WEIGHTS)
+
+
+def test_adjoint_fp64_matches_finite_differences(small_fd):
+    res = gpu_adjoint(small_case("f64"), k=7)
+    assert abs(res["J"] - small_fd["J"]) <= 1e-12 * abs(small_fd["J"])
+    errs = block_errors(res, small_fd)
+    print("fp64 block errors", errs)
+    for name, e in errs.items():
+        assert e < 2e-6, (name, e)
+
+
+def test_adjoint_fp32_matches_finite_differences(small_fd):
+    res = gpu_adjoint(small_case("f32"), k=7)
+    errs = block_errors(res, small_fd)
+    print("fp32 block errors", errs)
+    for name, e in errs.items():
+        assert e < 1e-4, (name, e)
+
+
+def test_adjoint_periodic_and_tiles():
+    case = small_case(walls=False, steps=20)
+    fd = fd_gradient(case, case.steps, **WEIGHTS)
+    for tile in ((64, 1), (32, 2), (16, 4)):
+        res = gpu_adjoint(case, k=6, tile=tile)
+        errs = block_errors(res, fd)
+        for name, e in errs.items():
+            assert e < 2e-6, (tile, name, e)
+
+
+def test_adjoint_overlapping_disks():
+    """Two overlapping disks: cells covered by both (split weights, saturated cover)."""
+    case = small_case(overlap=True, steps=20)
+    fd = fd_gradient(case, case.steps, **WEIGHTS)
+    res = gpu_adjoint(case, k=5)
+    errs = block_errors(res, fd)
+    print("overlap block errors", errs)
+    for name, e in errs.items():
+        assert e < 1e-5, (name, e)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_adjoint_checkpoint_interval_is_exact(storage):
+    """Recomputation reproduces the forward states bit for bit, so the gradient does not depend
+    on the checkpoint interval."""
+    case = small_case(storage, steps=23)
+    ref = gpu_adjoint(case, k=1)
+    for k in (2, 5, 23, 40):
+        res = gpu_adjoint(case, k=k)
+        for name in ("x0", "y0", "vx", "vy", "om", "g"):
+            assert np.array_equal(res[name], ref[name]), (k, name)
+        assert res["J"] == ref["J"]
+
+
+def test_adjoint_initial_populations_directional():
+    """dJ/df0 against a directional central difference of the oracle."""
+    case = small_case(steps=15)
+    rng = np.random.default_rng(3)
+    f0 = W.random_populations(rng, case.nx, case.ny, amplitude=0.02)
+    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    f0 = f0 * (w[:, None, None] * 9.0)
+    sim = imb.simulation_from_case(case, storage="f64")
+    sim.set_populations(f0)
+    res = sim.adjoint(case.steps, 4, populations=True, **WEIGHTS)
+    d = rng.normal(size=f0.shape) * w[:, None, None]
+    h = 1e-6
+    s0 = base_state(case)
+    jp = objective(case, s0, case.gx, case.gy, case.steps, f0=f0 + h * d, **WEIGHTS)
+    jm = objective(case, s0, case.gx, case.gy, case.steps, f0=f0 - h * d, **WEIGHTS)
+    fd = (jp - jm) / (2 * h)
+    ad = float(np.sum(res["f0"] * d))
+    assert abs(ad - fd) <= 1e-7 * abs(fd), (ad, fd)
+
+
+def test_adjoint_state_after_call_equals_forward():
+    """After imb_adjoint the simulation holds the state after nsteps forward steps."""
+    case = small_case(steps=12)
+    a = imb.simulation_from_case(case)
+    a.adjoint(case.steps, 5, **WEIGHTS)
+    b = imb.simulation_from_case(case)
+    b.step(case.steps)
+    assert np.array_equal(a.populations(), b.populations())
+    for u, v in zip(a.particles(), b.particles()):
+        assert np.array_equal(u, v)
+    a.step(3)
+    b.step(3)
+    assert np.array_equal(a.populations(), b.populations())
+    for u, v in zip(a.forces(), b.forces()):
+        assert np.array_equal(u, v)
+
+
+def test_adjoint_rejects_unsupported():
+    case = small_case(steps=4)
+    with pytest.raises(imb.ImbError):  # Smagorinsky term
+        gpu_adjoint(case.with_(cs=0.1), k=2)
+    with pytest.raises(imb.ImbError):  # FP16 storage
+        gpu_adjoint(case, k=2, storage="f16")
+    p = case.particles.copy()
+    p.mode[0] = W.MODE_FREE
+    with pytest.raises(imb.ImbError):  # a disk under DEM
+        gpu_adjoint(case.with_(particles=p), k=2)
+    with pytest.raises(imb.ImbError):
+        gpu_adjoint(case, k=0)
+
+
+def test_adjoint_no_disks_body_force_only():
+    """Without disks J = 0 and every gradient vanishes."""
+    case = small_case(steps=5).with_(particles=W.Particles.empty())
+    sim = imb.simulation_from_case(case)
+    res = sim.adjoint(5, 2)
+    assert res["J"] == 0.0
+    assert np.all(res["g"] == 0.0)
+
+
+def test_adjoint_512x256_fp32_against_golden():
+    """20 disks of diameter 20 at rest in a 512x256 channel, 200 steps, checkpoint every 20:
+    gradient of the summed x-drag against the stored FP64 finite differences."""
+    with open(os.path.join(HERE, "golden", "adjoint_512x256_n20.json")) as fh:
+        gold = json.load(fh)
+    case = W.adjoint_channel(seed=gold["seed"])
+    n = case.particles.n
+    sim = imb.simulation_from_case(case, storage="f32", tile_w=32, tile_rows=2)
+    res = sim.adjoint(case.steps, 20, wfx=np.ones(n))
+    assert abs(res["J"] - gold["J"]) <= 1e-4 * abs(gold["J"])
+    fd = {k: np.array(v) for k, v in gold["gradient"].items()}
+    errs = block_errors(res, fd)
+    print("512x256 fp32 block errors", errs)
+    for name in ("x", "y", "vx", "vy", "g"):
+        assert errs[name] < 1e-4, (name, errs[name])
+
+
+def test_autograd_function_matches_library_and_gradcheck():
+    import torch
+    from paper_1809_07008_amd.adjoint import AdjointSetup, drag_objective
+    case = small_case(steps=10)
+    p = case.particles
+    setup = AdjointSetup(nx=case.nx, ny=case.ny, radii=p.r, tau0=case.tau0, steps=case.steps,
+                         k_ckpt=4, storage="f64", wfx=WEIGHTS["wfx"], wfy=WEIGHTS["wfy"],
+                         wtz=WEIGHTS["wtz"], tile=(64, 1))
+    t = [torch.tensor(a, dtype=torch.float64, requires_grad=True)
+         for a in (p.x, p.y, p.vx, p.vy, p.om)]
+    g = torch.tensor([case.gx, case.gy], dtype=torch.float64, requires_grad=True)
+    J = drag_objective(*t, g, setup)
+    J.backward()
+    ref = gpu_adjoint(case, k=4)
+    assert J.item() == ref["J"]
+    for name, v in zip(("x0", "y0", "vx", "vy", "om"), t):
+        assert np.array_equal(v.grad.numpy(), ref[name])
+    assert np.array_equal(g.grad.numpy(), ref["g"])
+    # numerical Jacobian of the Function's own forward against its backward
+    assert torch.autograd.gradcheck(lambda *a: drag_objective(*a, setup), (*t, g), eps=1e-6,
+                                    atol=1e-7, rtol=1e-4, fast_mode=True)
