@@ -196,29 +196,62 @@ int imb_get_adjoint_timing(imb_sim* sim, double* forward_ms, double* reverse_ms,
                            double* recompute_kernel_ms, int64_t* recompute_kernels);
 
 /* -------------------------------------------------------------- batched channels
- * Many independent simulations (channels) of different sizes and particle counts advanced
- * together: each step is one persistent kernel launch that walks a work list of
- * (channel, tile) items for the lattice update and then of channels for the particle phase;
- * a graph of steps is captured once and replayed.  Every channel uses F32 storage. */
+ * Many independent simulations (channels), each with its own configuration (lattice size,
+ * relaxation time, disks), advanced together by ONE persistent kernel per imb_batch_step call,
+ * captured once per (nsteps, buffer parity) in a hipGraph and replayed.  Inside the kernel the
+ * channels are split into two halves of about equal tile counts; every step is two phases
+ * separated by grid-wide barriers (lattice tiles of one half while the particle phases of the
+ * other half run), with workgroups pulling work items (a channel's particle phase, or one
+ * (channel, tile)) from an atomic counter.
+ * The method per channel is the coupled step of imb_step (Sec. 2; Eqs. 1-2, 12-17), and a
+ * channel evolves bit for bit as the same channel would alone with the same tile shape.
+ * Limits: 1..128 channels, F32 storage, at most 256 disks and ny <= 2559 per channel
+ * (IMB_EINVAL / IMB_EUNSUPPORTED otherwise).  A barrier that does not open within 2 s aborts
+ * the kernel (every workgroup exits) and the next synchronising call returns IMB_EHIP. */
 typedef struct imb_batch imb_batch;
 
+/* Device bytes for a batch of nsim channels (the caller may bind a buffer of this size). */
 int imb_batch_required_bytes(int32_t nsim, const imb_config* cfgs, size_t* bytes);
+/* Creates the batch (every channel at rest at rho0, no disks).  dev_buf: caller-owned device
+ * buffer of imb_batch_required_bytes (256-byte aligned) or NULL for a library allocation.  The
+ * tile shape of cfgs[0] is the initial shape of every channel.  Synchronises. */
 int imb_batch_create(int32_t nsim, const imb_config* cfgs, void* hip_stream, void* dev_buf,
                      size_t dev_bytes, imb_batch** out);
 void imb_batch_destroy(imb_batch* b);
+/* As imb_set_particles for channel `sim`. Synchronises. */
 int imb_batch_set_particles(imb_batch* b, int32_t sim, int32_t n, const double* x,
                             const double* y, const double* r, const double* vx, const double* vy,
                             const double* omega, const int32_t* mode);
-/* Enqueues nsteps steps of every channel. Asynchronous. */
+/* Enqueues nsteps coupled steps of every channel (one persistent launch).  Asynchronous. */
 int imb_batch_step(imb_batch* b, int32_t nsteps);
+/* Per-channel readback, as the single-simulation calls (host FP64 arrays).  Synchronise. */
 int imb_batch_get_forces(imb_batch* b, int32_t sim, double* fx, double* fy, double* tz);
 int imb_batch_get_particles(imb_batch* b, int32_t sim, double* x, double* y, double* vx,
                             double* vy, double* omega);
 int imb_batch_get_fields(imb_batch* b, int32_t sim, double* rho, double* ux, double* uy);
+int imb_batch_get_populations(imb_batch* b, int32_t sim, double* host_f);
+/* Waits for the batch and reports an abort or any channel's device error. */
 int imb_batch_sync(imb_batch* b);
-/* Persistent-grid size (workgroups) and tile shape used by imb_batch_step; settable before the
- * first step (0 keeps the default: the number of co-resident workgroups). */
+/* Persistent-grid size (workgroups; 0 = every co-resident workgroup, larger values are
+ * clamped to that) and tile shape of every channel (0 keeps the current value).  Rebuilds the
+ * disk tables for a new shape.  Synchronises. */
 int imb_batch_set_launch(imb_batch* b, int32_t grid, int32_t tile_w, int32_t tile_rows);
+/* Current grid, tile shape and the co-resident maximum (any pointer may be NULL). */
+int imb_batch_get_launch(imb_batch* b, int32_t* grid, int32_t* tile_w, int32_t* tile_rows,
+                         int32_t* max_grid);
+/* Autotuner: times trial_steps steps (after 2 warm-up steps) for each candidate tile shape
+ * (16x4, 32x1/2/4, 64x1/2/4, 128x1/2: tile width x rows per thread) and grid size (every
+ * co-resident workgroup, or one workgroup fewer per compute unit), rebuilding the disk tables
+ * for the shape and restoring the channels' state after every trial, and keeps the fastest.
+ * max_trials > 0 caps the number of trials.  *trial_ms (may be NULL) receives the best time per
+ * step.  Needs a temporary device copy of the channels' memory.  Synchronises; the simulation
+ * state is unchanged. */
+int imb_batch_autotune(imb_batch* b, int32_t trial_steps, double* trial_ms, int32_t max_trials);
+/* Runs nsteps steps as one graph replay bracketed by HIP events and returns the elapsed
+ * milliseconds.  Synchronises. */
+int imb_batch_get_timing(imb_batch* b, int32_t nsteps, double* ms);
+/* Message of the last failure on this batch (b = NULL: of the last failed create). */
+const char* imb_batch_last_error(const imb_batch* b);
 
 /* ------------------------------------------------------------------------ misc */
 const char* imb_strerror(int code);

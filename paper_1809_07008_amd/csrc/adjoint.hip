@@ -51,7 +51,7 @@ __device__ inline void finalise_disks(int np, int pstride, int step, const doubl
                                       const int4* box, const int* mode, double* gacc) {
   for (int p = threadIdx.x; p < np; p += blockDim.x) {
     const int4 b = box[p];
-    const int ns = b.y * b.w;
+    const int ns = box_slots(b);
     double g[NG] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int s = 0; s < ns; ++s)
 #pragma unroll

@@ -77,6 +77,8 @@ struct LatticeArgs {
   double4* partials;     // [MAXSLOT][pstride] force / torque partial sums (Fx, Fy, Tz, 0),
   int pstride;           //   slot-major so the particle phase reads them coalesced
   int* err;
+  unsigned* seed;        // [2] step counters of the stochastic rounding: this step reads
+  int seed_slot;         //   seed[seed_slot], tile 0 writes seed[seed_slot ^ 1] = it + 1
 };
 
 // Particle state on the device (structure of arrays, FP64).
@@ -113,6 +115,7 @@ struct StoreF64 {
   using T = double;
   using S = double;
   static constexpr bool deviation = false;
+  static constexpr bool stochastic = false;
   __device__ static T load(const S* p, long long i, T) { return p[i]; }
   __device__ static void store(S* p, long long i, T v, T) { p[i] = v; }
 };
@@ -120,18 +123,47 @@ struct StoreF32 {
   using T = float;
   using S = float;
   static constexpr bool deviation = true;
+  static constexpr bool stochastic = false;
   __device__ static T load(const S* p, long long i, T) { return p[i]; }
   __device__ static void store(S* p, long long i, T v, T) { p[i] = v; }
 };
+// FP16: h * 2^14 in binary16.  store() rounds to nearest even (used for set-up); store_sr()
+// rounds stochastically: up with probability equal to the fractional position between the two
+// neighbouring binary16 values, from a counter-based random word, so the rounding error of the
+// step-to-step updates has zero mean instead of the systematic bias of round-to-nearest on
+// increments of about one unit in the last place.
 struct StoreF16 {
   using T = float;
   using S = __half;
   static constexpr bool deviation = true;
+  static constexpr bool stochastic = true;
   __device__ static T load(const S* p, long long i, T) {
     return __half2float(p[i]) * (1.0f / F16_SCALE);
   }
   __device__ static void store(S* p, long long i, T v, T) { p[i] = __float2half_rn(v * F16_SCALE); }
+  __device__ static void store_sr(S* p, long long i, T v, unsigned rnd) {
+    const float s = v * F16_SCALE;
+    const __half lo = __float2half_rz(s);  // neighbour toward zero
+    const float flo = __half2float(lo);
+    if (flo == s) {
+      p[i] = lo;
+      return;
+    }
+    const __half hi = __ushort_as_half((unsigned short)(__half_as_ushort(lo) + 1u));  // away
+    const float fhi = __half2float(hi);
+    const float frac = (s - flo) / (fhi - flo);
+    const float u = (float)(rnd >> 8) * (1.0f / 16777216.0f);
+    p[i] = u < frac ? hi : lo;
+  }
 };
+
+// 32-bit integer hash "pcg_hash" (Jarzynski & Olano, Hash Functions for GPU Rendering, JCGT 9(3),
+// 2020): one PCG step followed by the RXS-M-XS output permutation.
+__host__ __device__ inline unsigned pcg_hash(unsigned v) {
+  const unsigned state = v * 747796405u + 2891336453u;
+  const unsigned word = ((state >> ((state >> 28u) + 4u)) ^ state) * 277803737u;
+  return (word >> 22u) ^ word;
+}
 
 // Block index -> tile index so that consecutive tiles run on the same XCD (workgroups are
 // dispatched round-robin over the 8 XCDs, each with its own L2).
@@ -183,15 +215,24 @@ __host__ __device__ inline bool tile_box(double X, double Y, double r, int nx, i
   return ntx * nty <= MAXSLOT;
 }
 
-// Slot of tile (tx, ty) in a disk's box, or -1 if the tile is outside it.
+// Slot of tile (tx, ty) in a disk's box, or -1 if the tile is outside it.  The result is always
+// -1 or in [0, MAXSLOT), whatever the box holds (a box is only meaningful for the tile grid it
+// was built for).
 __device__ inline int box_slot(int4 b, int tx, int ty, int tiles_x, int tiles_y) {
   int lx = tx - b.x;
   if (lx < 0) lx += tiles_x;
-  if (lx >= b.y) return -1;
+  if (lx < 0 || lx >= b.y) return -1;
   int ly = ty - b.z;
   if (ly < 0) ly += tiles_y;
-  if (ly >= b.w) return -1;
-  return ly * b.y + lx;
+  if (ly < 0 || ly >= b.w) return -1;
+  const int slot = ly * b.y + lx;
+  return slot < MAXSLOT ? slot : -1;
+}
+
+// Number of partial-sum slots of a box, bounded by MAXSLOT.
+__host__ __device__ inline int box_slots(int4 b) {
+  const int n = b.y * b.w;
+  return n < 0 ? 0 : (n > MAXSLOT ? MAXSLOT : n);
 }
 
 }  // namespace imb

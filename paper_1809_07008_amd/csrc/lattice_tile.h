@@ -43,6 +43,8 @@ __device__ void lattice_tile(const LatticeArgs& a, int tile) {
   S* dst = (S*)a.dst;
 
   if (tid == 0) s_touch = 0u;
+  unsigned seed = 0u;
+  if constexpr (St::stochastic) seed = a.seed[a.seed_slot];
   // the first row's populations are requested before the disk list is built, so their latency
   // overlaps the list's
   T f[NQ];
@@ -119,8 +121,18 @@ __device__ void lattice_tile(const LatticeArgs& a, int tile) {
     }
     if (!(rho > T(0)) || !isfinite(rho)) atomicOr(a.err, ERR_RHO);
     const long long base = (long long)y * a.pitch + x;
+    if constexpr (St::stochastic) {
+      const unsigned r0 = pcg_hash(seed * 0x9E3779B9u + (unsigned)base);
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) St::store(dst, (long long)i * a.plane + base, fo[i], T(0));
+      for (int i = 0; i < NQ; ++i)
+        St::store_sr(dst, (long long)i * a.plane + base, fo[i], pcg_hash(r0 + (unsigned)i));
+    } else {
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) St::store(dst, (long long)i * a.plane + base, fo[i], T(0));
+    }
+  }
+  if constexpr (St::stochastic) {
+    if (tile == 0 && tid == 0) a.seed[a.seed_slot ^ 1] = seed + 1u;
   }
   if (n == 0) return;  // block-uniform: no disk touches this tile
 

@@ -142,7 +142,7 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
   // ---- 1. forces of the step that just ran: slots in order
   double Fx = 0.0, Fy = 0.0, Tz = 0.0;
   if (have && a.do_finalize) {
-    const int ns = b.y * b.w;
+    const int ns = box_slots(b);
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
       if (u < ns) {
@@ -477,6 +477,7 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
     total = block_exclusive_scan<NT>(cnt, nbands, s_wave);
     for (int k = threadIdx.x; k < nbands; k += NT) a.band_off[k] = cnt[k];
     if (threadIdx.x == 0) a.band_off[nbands] = total;
+    __syncthreads();  // every offset is read before the fill below advances cnt
     if (have)
       for (int k = 0; k < nbx.w; ++k) {
         const int ty = nbx.z + k < nbands ? nbx.z + k : nbx.z + k - nbands;

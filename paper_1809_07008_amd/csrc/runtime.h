@@ -24,6 +24,7 @@ struct DeviceLayout {
   int* err;
   double* J;
   double* w;  // objective weights wfx, wfy, wtz (3 x capacity)
+  unsigned* seed;  // [2] stochastic-rounding step counters
 };
 
 struct AdjointState;
@@ -58,6 +59,16 @@ int sync_and_check(imb_sim* s);
 int reset_device_error(imb_sim* s);
 void free_adjoint(imb_sim* s);
 void drop_graphs(imb_sim* s);
+
+// Simulation whose memory is carved for `layout_cfg` (same lattice and particle capacity as
+// cfg; its tile shape only sets how many tile rows the band lists can hold), so that the tile
+// shape can later change in place (set_tile_shape).
+int create_sim(const imb_config* cfg, const imb_config* layout_cfg, void* hip_stream,
+               void* dev_buf, size_t dev_bytes, imb_sim** out);
+// Changes the tile shape (geometry only; the band capacity must cover the new tile rows) and
+// rebuilds the disk tables for it.  Asynchronous.
+int set_tile_shape(imb_sim* s, int tile_w, int tile_rows);
+int tile_rows_capacity(const imb_sim* s);
 
 }  // namespace imb
 

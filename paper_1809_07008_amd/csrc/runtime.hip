@@ -77,6 +77,7 @@ size_t layout(const imb_config& c, char* base, DeviceLayout* L) {
   d.err = cv.take<int>(1);
   d.J = cv.take<double>(1);
   d.w = cv.take<double>(3 * mp);
+  d.seed = cv.take<unsigned>(2);
   if (L) *L = d;
   return align_up(cv.off, 256);
 }
@@ -144,6 +145,7 @@ std::string describe_device_error(int bits) {
 // ======================================================================= imb_sim
 struct imb_sim {
   imb_config cfg;
+  imb_config layout_cfg;  // configuration the device memory was carved for
   hipStream_t stream = nullptr;
   char* mem = nullptr;
   size_t mem_bytes = 0;
@@ -183,6 +185,8 @@ LatticeArgs lattice_args(imb_sim* s, const void* src, void* dst) {
   a.np = s->np; a.tab = s->d.tab; a.partials = s->d.partials; a.err = s->d.err;
   a.band_off = s->d.band_off; a.band_ids = s->d.band_ids;
   a.pstride = std::max(s->cfg.max_particles, 1);
+  a.seed = s->d.seed;
+  a.seed_slot = src == s->d.f[1] ? 1 : 0;
   return a;
 }
 
@@ -324,6 +328,95 @@ static hipGraphExec_t capture_steps(imb_sim* s, int len, int start) {
 
 }  // namespace imb
 
+namespace imb {
+
+int create_sim(const imb_config* cfg, const imb_config* layout_cfg, void* hip_stream,
+               void* dev_buf, size_t dev_bytes, imb_sim** out) {
+  if (!out) return IMB_EINVAL;
+  *out = nullptr;
+  std::string why;
+  int rc = validate_config(cfg, &why);
+  if (rc) {
+    g_create_error = why;
+    return rc;
+  }
+  imb_sim* s = new (std::nothrow) imb_sim();
+  if (!s) return IMB_ENOMEM;
+  s->cfg = *cfg;
+  if (!s->cfg.tile_w) s->cfg.tile_w = 64;
+  if (!s->cfg.tile_rows) s->cfg.tile_rows = 1;
+  s->stream = (hipStream_t)hip_stream;
+  sim_geometry(s->cfg, &s->g);
+  s->layout_cfg = *layout_cfg;
+  if (!s->layout_cfg.tile_w) s->layout_cfg.tile_w = 64;
+  if (!s->layout_cfg.tile_rows) s->layout_cfg.tile_rows = 1;
+  const size_t need = layout(s->layout_cfg, nullptr, nullptr);
+  if (dev_buf) {
+    if (dev_bytes < need || ((uintptr_t)dev_buf & 255)) {
+      g_create_error = "bound device buffer too small or not 256-byte aligned";
+      delete s;
+      return IMB_ENOMEM;
+    }
+    s->mem = (char*)dev_buf;
+    s->owns = false;
+  } else {
+    hipError_t e = hipMalloc((void**)&s->mem, need);
+    if (e != hipSuccess) {
+      g_create_error = std::string("hipMalloc: ") + hipGetErrorString(e);
+      delete s;
+      return IMB_ENOMEM;
+    }
+    s->owns = true;
+  }
+  s->mem_bytes = need;
+  layout(s->layout_cfg, s->mem, &s->d);
+  launch_fill_zero(s->mem, need, s->stream);
+  rc = imb_init_equilibrium(s, s->cfg.rho0, 0.0, 0.0);
+  if (!rc) rc = sync_and_check(s);
+  if (rc) {
+    g_create_error = s->err;
+    imb_destroy(s);
+    return rc;
+  }
+  *out = s;
+  return IMB_OK;
+}
+
+int tile_rows_capacity(const imb_sim* s) {
+  Geometry g;
+  sim_geometry(s->layout_cfg, &g);
+  return g.tiles_y;
+}
+
+int set_tile_shape(imb_sim* s, int tile_w, int tile_rows) {
+  imb_config c = s->cfg;
+  c.tile_w = tile_w;
+  c.tile_rows = tile_rows;
+  std::string why;
+  if (validate_config(&c, &why)) {
+    s->err = why;
+    return IMB_EINVAL;
+  }
+  Geometry g;
+  sim_geometry(c, &g);
+  if (g.tiles_y > tile_rows_capacity(s)) {
+    s->err = "tile shape needs more tile rows than the memory layout holds";
+    return IMB_EINVAL;
+  }
+  hipStreamSynchronize(s->stream);
+  drop_graphs(s);
+  s->cfg = c;
+  s->g = g;
+  if (s->np > 0) {
+    ParticleArgs pa = particle_args(s);
+    pa.do_table = 1;
+    launch_particle_phase(pa, s->stream);
+  }
+  return launch_check(s, "set_tile_shape");
+}
+
+}  // namespace imb
+
 // =================================================================== C-ABI
 extern "C" {
 
@@ -346,51 +439,7 @@ int imb_required_bytes(const imb_config* cfg, size_t* bytes) {
 
 int imb_create(const imb_config* cfg, void* hip_stream, void* dev_buf, size_t dev_bytes,
                imb_sim** out) {
-  if (!out) return IMB_EINVAL;
-  *out = nullptr;
-  std::string why;
-  int rc = validate_config(cfg, &why);
-  if (rc) {
-    g_create_error = why;
-    return rc;
-  }
-  imb_sim* s = new (std::nothrow) imb_sim();
-  if (!s) return IMB_ENOMEM;
-  s->cfg = *cfg;
-  if (!s->cfg.tile_w) s->cfg.tile_w = 64;
-  if (!s->cfg.tile_rows) s->cfg.tile_rows = 1;
-  s->stream = (hipStream_t)hip_stream;
-  sim_geometry(s->cfg, &s->g);
-  const size_t need = layout(s->cfg, nullptr, nullptr);
-  if (dev_buf) {
-    if (dev_bytes < need || ((uintptr_t)dev_buf & 255)) {
-      g_create_error = "bound device buffer too small or not 256-byte aligned";
-      delete s;
-      return IMB_ENOMEM;
-    }
-    s->mem = (char*)dev_buf;
-    s->owns = false;
-  } else {
-    hipError_t e = hipMalloc((void**)&s->mem, need);
-    if (e != hipSuccess) {
-      g_create_error = std::string("hipMalloc: ") + hipGetErrorString(e);
-      delete s;
-      return IMB_ENOMEM;
-    }
-    s->owns = true;
-  }
-  s->mem_bytes = need;
-  layout(s->cfg, s->mem, &s->d);
-  launch_fill_zero(s->mem, need, s->stream);
-  rc = imb_init_equilibrium(s, s->cfg.rho0, 0.0, 0.0);
-  if (!rc) rc = sync_and_check(s);
-  if (rc) {
-    g_create_error = s->err;
-    imb_destroy(s);
-    return rc;
-  }
-  *out = s;
-  return IMB_OK;
+  return imb::create_sim(cfg, cfg, hip_stream, dev_buf, dev_bytes, out);
 }
 
 void imb_destroy(imb_sim* s) {
@@ -647,7 +696,7 @@ struct StateHeader {
   char magic[8];
   imb_config cfg;
   int32_t np;
-  int32_t pad;
+  uint32_t seed;  // stochastic-rounding step counter of the stored state
   int64_t steps;
   uint64_t pop_bytes;
 };
@@ -677,6 +726,10 @@ int imb_save_state(imb_sim* s, void* host_buf, size_t bytes) {
   h.np = s->np;
   h.steps = s->steps;
   h.pop_bytes = NQ * (size_t)s->g.plane * storage_bytes(s->cfg.storage);
+  hipStreamSynchronize(s->stream);
+  if (hipMemcpy(&h.seed, s->d.seed + s->cur, sizeof(unsigned), hipMemcpyDeviceToHost) !=
+      hipSuccess)
+    return hip_fail(&s->err, hipGetLastError(), "save_state seed");
   char* out = (char*)host_buf;
   std::memcpy(out, &h, sizeof h);
   out += sizeof h;
@@ -724,6 +777,8 @@ int imb_load_state(imb_sim* s, const void* host_buf, size_t bytes) {
   ParticleState& ps = s->d.ps;
   launch_fill_zero(ps.x, (char*)(s->d.tab.box) - (char*)ps.x, s->stream);
   hipError_t e = hipMemcpyAsync(s->d.f[0], in, pop, hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess)
+    e = hipMemcpy(s->d.seed, &h.seed, sizeof(unsigned), hipMemcpyHostToDevice);
   in += pop;
   double* arrs[11] = {ps.x, ps.y, ps.r, ps.vx, ps.vy, ps.om, ps.fcx, ps.fcy, ps.Fx, ps.Fy, ps.Tz};
   for (int k = 0; k < 11 && e == hipSuccess && s->np; ++k) {

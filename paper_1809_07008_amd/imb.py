@@ -35,6 +35,8 @@ EXPORTED = [
     "imb_batch_get_forces", "imb_batch_get_particles", "imb_batch_get_fields", "imb_batch_sync",
     "imb_batch_set_launch", "imb_strerror", "imb_last_error", "imb_version",
     "imb_get_solid_field", "imb_set_graphs", "imb_get_adjoint_timing",
+    "imb_batch_get_populations", "imb_batch_get_launch", "imb_batch_autotune",
+    "imb_batch_get_timing", "imb_batch_last_error",
 ]
 
 
@@ -111,6 +113,11 @@ def load_library():
         "imb_batch_get_fields": (C.c_int, [_VP, C.c_int32, _D, _D, _D]),
         "imb_batch_sync": (C.c_int, [_VP]),
         "imb_batch_set_launch": (C.c_int, [_VP, C.c_int32, C.c_int32, C.c_int32]),
+        "imb_batch_get_populations": (C.c_int, [_VP, C.c_int32, _D]),
+        "imb_batch_get_launch": (C.c_int, [_VP, _I32, _I32, _I32, _I32]),
+        "imb_batch_autotune": (C.c_int, [_VP, C.c_int32, _D, C.c_int32]),
+        "imb_batch_get_timing": (C.c_int, [_VP, C.c_int32, _D]),
+        "imb_batch_last_error": (C.c_char_p, [_VP]),
         "imb_strerror": (C.c_char_p, [C.c_int]),
         "imb_last_error": (C.c_char_p, [_VP]),
         "imb_version": (C.c_char_p, []),
@@ -358,3 +365,133 @@ def simulation_from_case(case, storage=None, tile_w=64, tile_rows=1, max_particl
     sim = Simulation(config_from_case(case, max_particles, tile_w, tile_rows, storage), stream)
     sim.set_case_particles(case.particles)
     return sim
+
+
+class Batch:
+    """Independent channels advanced by one persistent kernel per step call (imb_batch_*).
+    Device memory is a torch uint8 tensor owned by this object."""
+
+    def __init__(self, cfgs, stream=None, device="cuda"):
+        import torch
+        lib = load_library()
+        self.cfgs = list(cfgs)
+        arr = (Config * len(self.cfgs))(*self.cfgs)
+        self._arr = arr
+        nbytes = C.c_size_t()
+        self._h = None
+        self._check(lib.imb_batch_required_bytes(len(self.cfgs), arr, C.byref(nbytes)),
+                    "imb_batch_required_bytes", handle=False)
+        self._buf = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=device)
+        ptr = self._buf.data_ptr()
+        off = (-ptr) % 256
+        h = C.c_void_p()
+        self._check(lib.imb_batch_create(len(self.cfgs), arr, _stream_handle(stream),
+                                         C.c_void_p(ptr + off), nbytes.value, C.byref(h)),
+                    "imb_batch_create", handle=False)
+        self._h = h
+        self.n = [0] * len(self.cfgs)
+
+    def _check(self, rc, what, handle=True):
+        if rc != IMB_OK:
+            msg = load_library().imb_batch_last_error(self._h if handle else None)
+            raise ImbError(rc, what, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().imb_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __len__(self):
+        return len(self.cfgs)
+
+    def set_particles(self, sim, x, y, r, vx=None, vy=None, om=None, mode=None):
+        n = len(x)
+        z = np.zeros(n)
+        arrs = [_f64(a, n) for a in (x, y, r, z if vx is None else vx, z if vy is None else vy,
+                                      z if om is None else om)]
+        md = np.ascontiguousarray(np.zeros(n, np.int32) if mode is None else mode, np.int32)
+        if n == 0:
+            arrs = [np.zeros(1) for _ in range(6)]
+            md = np.zeros(1, np.int32)
+        self._check(load_library().imb_batch_set_particles(
+            self._h, int(sim), n, *(_dp(a) for a in arrs), md.ctypes.data_as(_I32)),
+            "imb_batch_set_particles")
+        self.n[sim] = n
+
+    def set_case_particles(self, sim, p):
+        self.set_particles(sim, p.x, p.y, p.r, p.vx, p.vy, p.om, p.mode)
+
+    def step(self, n: int = 1):
+        self._check(load_library().imb_batch_step(self._h, int(n)), "imb_batch_step")
+
+    def sync(self):
+        self._check(load_library().imb_batch_sync(self._h), "imb_batch_sync")
+
+    def forces(self, sim):
+        m = max(self.n[sim], 1)
+        a = [np.zeros(m) for _ in range(3)]
+        self._check(load_library().imb_batch_get_forces(self._h, int(sim), *(_dp(v) for v in a)),
+                    "imb_batch_get_forces")
+        return tuple(v[: self.n[sim]] for v in a)
+
+    def particles(self, sim):
+        m = max(self.n[sim], 1)
+        a = [np.zeros(m) for _ in range(5)]
+        self._check(load_library().imb_batch_get_particles(self._h, int(sim),
+                                                           *(_dp(v) for v in a)),
+                    "imb_batch_get_particles")
+        return tuple(v[: self.n[sim]] for v in a)
+
+    def fields(self, sim):
+        c = self.cfgs[sim]
+        a = [np.zeros((c.ny, c.nx)) for _ in range(3)]
+        self._check(load_library().imb_batch_get_fields(self._h, int(sim), *(_dp(v) for v in a)),
+                    "imb_batch_get_fields")
+        return tuple(a)
+
+    def populations(self, sim):
+        c = self.cfgs[sim]
+        f = np.zeros((9, c.ny, c.nx))
+        self._check(load_library().imb_batch_get_populations(self._h, int(sim), _dp(f)),
+                    "imb_batch_get_populations")
+        return f
+
+    def set_launch(self, grid=0, tile_w=0, tile_rows=0):
+        self._check(load_library().imb_batch_set_launch(self._h, int(grid), int(tile_w),
+                                                        int(tile_rows)), "imb_batch_set_launch")
+
+    def launch(self):
+        v = [C.c_int32() for _ in range(4)]
+        self._check(load_library().imb_batch_get_launch(self._h, *(C.byref(x) for x in v)),
+                    "imb_batch_get_launch")
+        return {"grid": v[0].value, "tile_w": v[1].value, "tile_rows": v[2].value,
+                "max_grid": v[3].value}
+
+    def autotune(self, trial_steps: int = 5, max_trials: int = 0) -> float:
+        """Runs the library's autotuner; returns the best time per step (ms)."""
+        ms = C.c_double()
+        self._check(load_library().imb_batch_autotune(self._h, int(trial_steps), C.byref(ms),
+                                                      int(max_trials)), "imb_batch_autotune")
+        return ms.value
+
+    def timed_steps(self, n: int) -> float:
+        """Runs n steps as one graph replay; returns the GPU milliseconds (HIP events)."""
+        ms = C.c_double()
+        self._check(load_library().imb_batch_get_timing(self._h, int(n), C.byref(ms)),
+                    "imb_batch_get_timing")
+        return ms.value
+
+
+def batch_from_cases(cases, tile_w=32, tile_rows=2, stream=None) -> Batch:
+    """Batch of workload cases (F32 storage), particles uploaded, fluid at rest."""
+    cfgs = [config_from_case(c, None, tile_w, tile_rows, "f32") for c in cases]
+    b = Batch(cfgs, stream)
+    for k, c in enumerate(cases):
+        b.set_case_particles(k, c.particles)
+    return b

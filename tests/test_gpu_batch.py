@@ -1,0 +1,144 @@
+"""Batched form (imb_batch_* through the C-ABI): one persistent kernel advancing many channels.
+A channel in a batch must evolve bit for bit like the same channel alone with the same tile
+shape, and match the FP64 oracle within the FP32 tolerance."""
+import numpy as np
+import pytest
+
+from oracle import OracleConfig, OracleSim
+from paper_1809_07008_amd import imb
+from paper_1809_07008_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def mixed_cases():
+    """Five channels of different size, relaxation time, boundaries and disk count."""
+    rng = np.random.default_rng(11)
+    cases = []
+    for k, (nx, ny, n, tau, walls) in enumerate([(128, 64, 6, 0.55, True), (96, 48, 0, 0.7, True),
+                                                (160, 80, 12, 0.62, False),
+                                                (64, 32, 2, 0.8, True), (256, 128, 25, 0.52, True)]):
+        if n:
+            x, y, r = W.place_disks(rng, nx, ny, n, 8.0, 14.0, gap=1.0, wall_gap=1.0, walls=walls)
+            p = W.Particles(x, y, r, rng.normal(0, 0.01, n), rng.normal(0, 0.01, n), np.zeros(n),
+                            np.zeros(n, np.int32))
+        else:
+            p = W.Particles.empty()
+        cases.append(W.Case("mixed%d" % k, nx, ny, tau0=tau, steps=0, storage="f32", walls=walls,
+                            gx=1e-5, particles=p))
+    return cases
+
+
+def single(case, tile):
+    return imb.simulation_from_case(case, storage="f32", tile_w=tile[0], tile_rows=tile[1])
+
+
+def assert_same(b, k, sim):
+    assert np.array_equal(b.populations(k), sim.populations()), k
+    if b.n[k]:
+        for u, v in zip(b.forces(k), sim.forces()):
+            assert np.array_equal(u, v), k
+        for u, v in zip(b.particles(k), sim.particles()):
+            assert np.array_equal(u, v), k
+
+
+@pytest.mark.parametrize("tile", [(32, 2), (64, 1), (16, 4)])
+def test_batch_channels_match_single_simulations(tile):
+    cases = mixed_cases()
+    b = imb.batch_from_cases(cases, tile_w=tile[0], tile_rows=tile[1])
+    b.step(17)
+    b.step(13)  # other buffer parity, other graph
+    b.sync()
+    for k, c in enumerate(cases):
+        s = single(c, tile)
+        s.step(30)
+        assert_same(b, k, s)
+
+
+def test_batch_against_fp64_oracle():
+    cases = mixed_cases()
+    b = imb.batch_from_cases(cases)
+    steps = 300
+    b.step(steps)
+    b.sync()
+    for k in (0, 2, 4):
+        c = cases[k]
+        ref = OracleSim(OracleConfig(nx=c.nx, ny=c.ny, tau0=c.tau0, walls=c.walls, gx=c.gx))
+        p = c.particles
+        ref.set_particles(p.x, p.y, p.r, p.vx, p.vy, p.om, p.mode)
+        ref.step(steps)
+        fo = np.stack(ref.forces()[:2], 1)
+        fg = np.stack(b.forces(k)[:2], 1)
+        scale = np.abs(fo).max()
+        assert np.abs(fg - fo).max() / scale < 1e-4, (k, np.abs(fg - fo).max() / scale)
+        _, uxo, uyo = ref.fields()
+        _, uxg, uyg = b.fields(k)
+        umax = max(np.abs(uxo).max(), np.abs(uyo).max())
+        assert max(np.abs(uxg - uxo).max(), np.abs(uyg - uyo).max()) / umax < 1e-4, k
+
+
+def test_autotune_leaves_state_and_picks_a_valid_shape():
+    cases = mixed_cases()
+    b = imb.batch_from_cases(cases)
+    b.step(5)
+    before = [b.populations(k) for k in range(len(cases))]
+    ms = b.autotune(trial_steps=3, max_trials=6)
+    assert ms > 0
+    launch = b.launch()
+    assert launch["tile_w"] in (16, 32, 64, 128) and launch["tile_rows"] in (1, 2, 4)
+    assert 0 < launch["grid"] <= launch["max_grid"]
+    for k in range(len(cases)):
+        assert np.array_equal(b.populations(k), before[k]), k
+    b.step(10)
+    b.sync()
+    # the same history without tuning: 5 steps with the initial shape, 10 with the chosen one
+    r = imb.batch_from_cases(cases)
+    r.step(5)
+    r.set_launch(grid=launch["grid"], tile_w=launch["tile_w"], tile_rows=launch["tile_rows"])
+    r.step(10)
+    r.sync()
+    for k in range(len(cases)):
+        assert np.array_equal(b.populations(k), r.populations(k)), k
+        if b.n[k]:
+            for u, v in zip(b.particles(k), r.particles(k)):
+                assert np.array_equal(u, v), k
+
+
+def test_batched_channel_workload_sampled_against_single():
+    """64 channels of 128x64 .. 1024x512 with 1-200 moving disks each (seeded), 8 steps; a
+    sample of channels compared bit for bit with the same channels run alone."""
+    cases = W.batch_channels(seed=0)
+    b = imb.batch_from_cases(cases)
+    b.step(8)
+    b.sync()
+    for k in (0, 7, 31, 63):
+        s = single(cases[k], (32, 2))
+        s.step(8)
+        assert_same(b, k, s)
+
+
+def test_reduced_grid_gives_identical_results():
+    cases = mixed_cases()[:3]
+    a = imb.batch_from_cases(cases)
+    b = imb.batch_from_cases(cases)
+    b.set_launch(grid=7)
+    assert b.launch()["grid"] == 7
+    a.step(12)
+    b.step(12)
+    for k in range(3):
+        assert np.array_equal(a.populations(k), b.populations(k))
+
+
+def test_batch_rejects_invalid():
+    c = imb.make_config(64, 32, 0.6, storage="f64")
+    with pytest.raises(imb.ImbError):
+        imb.Batch([c])
+    c = imb.make_config(64, 32, 0.6, storage="f32", max_particles=300)
+    with pytest.raises(imb.ImbError):
+        imb.Batch([c])
+    with pytest.raises(imb.ImbError):
+        imb.Batch([])
+    b = imb.Batch([imb.make_config(64, 32, 0.6, storage="f32")])
+    z = np.zeros(1)
+    assert imb.load_library().imb_batch_get_forces(b._h, 3, imb._dp(z), imb._dp(z),
+                                                   imb._dp(z)) == -1
