@@ -342,6 +342,8 @@ struct AdjointState {
   double4* h_vel = nullptr;
   int* h_boff = nullptr;
   int* h_bids = nullptr;
+  int* h_nbr = nullptr;     // neighbour lists of every step (the lattice step's covering tests)
+  int* h_nnbr = nullptr;
   double* part = nullptr;   // 2 x [MAXSLOT][NG][pstride]
   double* gacc = nullptr;   // [NG][pstride]
   double2* gg_blk = nullptr;
@@ -422,6 +424,8 @@ static int ensure_adjoint(SimView& v, int nsteps, int k) {
   if (!rc) rc = take_t(A, slots * pstride, &A->h_vel);
   if (!rc) rc = take_t(A, slots * (v.g->tiles_y + 1), &A->h_boff);
   if (!rc) rc = take_t(A, slots * (size_t)pstride * MAXSLOT, &A->h_bids);
+  if (!rc) rc = take_t(A, slots * (size_t)pstride * NBMAX, &A->h_nbr);
+  if (!rc) rc = take_t(A, slots * (size_t)pstride, &A->h_nnbr);
   if (!rc) rc = take_t(A, 2 * (size_t)MAXSLOT * NG * pstride, &A->part);
   if (!rc) rc = take_t(A, (size_t)NG * pstride, &A->gacc);
   if (!rc) rc = take_t(A, (size_t)v.g->tiles_x * v.g->tiles_y, &A->gg_blk);
@@ -444,6 +448,8 @@ struct TableSlot {
   ParticleTable tab;
   int* boff;
   int* bids;
+  int* nbr;
+  int* nnbr;
 };
 
 static TableSlot table_slot(const SimView& v, AdjointState* A, int n) {
@@ -454,6 +460,8 @@ static TableSlot table_slot(const SimView& v, AdjointState* A, int n) {
   t.tab.vel = A->h_vel + (size_t)n * pstride;
   t.boff = A->h_boff + (size_t)n * (v.g->tiles_y + 1);
   t.bids = A->h_bids + (size_t)n * pstride * MAXSLOT;
+  t.nbr = A->h_nbr + (size_t)n * pstride * NBMAX;
+  t.nnbr = A->h_nnbr + (size_t)n * pstride;
   return t;
 }
 
@@ -466,6 +474,13 @@ static void copy_table(const SimView& v, const ParticleTable& dt, int* dboff, in
   launch_copy(dt.vel, st.vel, sizeof(double4) * pstride, s);
   launch_copy(dboff, sboff, sizeof(int) * (v.g->tiles_y + 1), s);
   launch_copy(dbids, sbids, sizeof(int) * (size_t)pstride * MAXSLOT, s);
+}
+
+static void copy_lists(const SimView& v, int* dnbr, int* dnnbr, const int* snbr, const int* snnbr,
+                       hipStream_t s) {
+  const int pstride = std::max(v.cfg->max_particles, 1);
+  launch_copy(dnbr, snbr, sizeof(int) * (size_t)pstride * NBMAX, s);
+  launch_copy(dnnbr, snnbr, sizeof(int) * (size_t)pstride, s);
 }
 
 template <class St>
@@ -541,6 +556,7 @@ extern "C" int imb_adjoint(imb_sim* sim, int32_t nsteps, int32_t k, const double
   {
     TableSlot t0 = table_slot(v, A, 0);
     copy_table(v, t0.tab, t0.boff, t0.bids, live, live_boff, live_bids, st);
+    copy_lists(v, t0.nbr, t0.nnbr, d.ps.nbr, d.ps.nnbr, st);
   }
   launch_copy(A->ckpt[0], d.f[*v.cur], A->state_bytes, st);
   hipEventRecord(A->ev[0], st);
@@ -559,6 +575,8 @@ extern "C" int imb_adjoint(imb_sim* sim, int32_t nsteps, int32_t k, const double
     la.tab = tn.tab;
     la.band_off = tn.boff;
     la.band_ids = tn.bids;
+    la.nbr = tn.nbr;
+    la.nnbr = tn.nnbr;
     launch_lattice_step(cfg.storage, la, st);
     if (np > 0) {
       const TableSlot tn1 = table_slot(v, A, n + 1);
@@ -575,6 +593,7 @@ extern "C" int imb_adjoint(imb_sim* sim, int32_t nsteps, int32_t k, const double
       pa.wtz = wd[2];
       pa.J = d.J;
       launch_particle_phase(pa, st);
+      copy_lists(v, tn1.nbr, tn1.nnbr, d.ps.nbr, d.ps.nnbr, st);
     }
     src = dst;
   }
@@ -618,6 +637,8 @@ extern "C" int imb_adjoint(imb_sim* sim, int32_t nsteps, int32_t k, const double
       la.tab = tn.tab;
       la.band_off = tn.boff;
       la.band_ids = tn.bids;
+      la.nbr = tn.nbr;
+      la.nnbr = tn.nnbr;
       timed(false, [&] { launch_lattice_step(cfg.storage, la, st); });
       if (timing) kind.push_back(0);
       rs = dst;

@@ -11,7 +11,8 @@
 // the one-workgroup DEM never idles the grid, and every dependency (tiles of a step -> that
 // step's particle phase -> the next step's tiles) crosses at least one barrier.  Inside a phase
 // the workgroups pull work items from an atomic counter: the half's particle phases first (the
-// long items), then its (channel, tile) items in channel order.
+// long items), then its (channel, disk) items (a disk's covered cells and force), then its
+// (channel, tile) items (the uncovered cells), each in channel order.
 //
 // The persistent grid is sized to the number of co-resident workgroups; every wait is bounded
 // (a barrier that does not open within the time limit sets an abort flag that every workgroup
@@ -26,7 +27,7 @@
 #include <map>
 #include <vector>
 
-#include "lattice_tile.h"
+#include "disk_block.h"
 #include "particle_phase.h"
 #include "runtime.h"
 
@@ -45,7 +46,8 @@ struct BatchArgs {
   const BatchChannel* ch;
   const int* half_ch;    // [2][MAX_BATCH] channels of each half
   const int* half_pref;  // [2][MAX_BATCH + 1] tile prefix sums of each half
-  int half_n0, half_n1, half_t0, half_t1;
+  const int* half_dpref; // [2][MAX_BATCH + 1] disk prefix sums of each half
+  int half_n0, half_n1, half_t0, half_t1, half_d0, half_d1;
   int nsteps, parity0, nblocks;
   unsigned* sync;
   long long spin_ticks;  // longest barrier wait, wall-clock ticks
@@ -95,10 +97,23 @@ __device__ bool grid_barrier(unsigned* sync, int nblocks, int reset_word, long l
   return s_ok != 0;
 }
 
+// Channel slot k of half h holding item i of a prefix table: the last k < n with pref[k] <= i
+// (channels whose range is empty are skipped).
+__device__ inline int find_slot(const int* pref, int n, int i) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pref[mid] <= i) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
 __global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs B) {
   __shared__ int s_item, s_abort;
   __shared__ int s_hch[2][MAX_BATCH];
   __shared__ int s_hpref[2][MAX_BATCH + 1];
+  __shared__ int s_hdpref[2][MAX_BATCH + 1];
   __shared__ double pp_lds[PP_LDS];
   const int tid = threadIdx.x;
   for (int k = tid; k < MAX_BATCH; k += BLOCK) {
@@ -108,16 +123,21 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs B) {
   for (int k = tid; k <= MAX_BATCH; k += BLOCK) {
     s_hpref[0][k] = B.half_pref[k];
     s_hpref[1][k] = B.half_pref[MAX_BATCH + 1 + k];
+    s_hdpref[0][k] = B.half_dpref[k];
+    s_hdpref[1][k] = B.half_dpref[MAX_BATCH + 1 + k];
   }
   __syncthreads();  // the tables are complete before any wave reads them
   const int hn[2] = {B.half_n0, B.half_n1};
   const int ht[2] = {B.half_t0, B.half_t1};
+  const int hd[2] = {B.half_d0, B.half_d1};
   const int nphase = 2 * B.nsteps + 1;
   for (int p = 0; p < nphase; ++p) {
     const int n = p >> 1, h = p & 1;
     const int ph = 1 - h;  // half whose particle phase runs now
     const int npart = (h == 1 || n >= 1) ? hn[ph] : 0;
-    const int nlat = p < 2 * B.nsteps ? ht[h] : 0;
+    const bool lat = p < 2 * B.nsteps;
+    const int ndisk = lat ? hd[h] : 0;
+    const int nlat = lat ? ht[h] : 0;
     unsigned* ctr = &B.sync[2 + (p & 1)];
     for (;;) {
       __syncthreads();
@@ -127,26 +147,23 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs B) {
       }
       __syncthreads();
       const int i = s_item;
-      if (s_abort || i >= npart + nlat) break;
+      if (s_abort || i >= npart + ndisk + nlat) break;
       if (i < npart) {
         particle_phase<BLOCK>(B.ch[s_hch[ph][i]].pa, pp_lds);
-      } else {
-        const int t = i - npart;
-        int lo = 0, hi = hn[h];
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (s_hpref[h][mid] <= t) lo = mid;
-          else hi = mid;
-        }
-        LatticeArgs la = B.ch[s_hch[h][lo]].la;
-        if ((B.parity0 + n) & 1) {
-          const void* s = la.src;
-          la.src = la.dst;
-          la.dst = (void*)s;
-          la.seed_slot ^= 1;
-        }
-        lattice_tile<StoreF32>(la, t - s_hpref[h][lo]);
+        continue;
       }
+      const bool is_disk = i < npart + ndisk;
+      const int t = is_disk ? i - npart : i - npart - ndisk;
+      const int k = find_slot(is_disk ? s_hdpref[h] : s_hpref[h], hn[h], t);
+      LatticeArgs la = B.ch[s_hch[h][k]].la;
+      if ((B.parity0 + n) & 1) {
+        const void* s = la.src;
+        la.src = la.dst;
+        la.dst = (void*)s;
+        la.seed_slot ^= 1;
+      }
+      if (is_disk) disk_cells<StoreF32>(la, t - s_hdpref[h][k]);
+      else fluid_tile<StoreF32>(la, t - s_hpref[h][k]);
     }
     if (p + 1 < nphase && !grid_barrier(B.sync, B.nblocks, 2 + (p & 1), B.spin_ticks)) return;
   }
@@ -169,7 +186,7 @@ struct imb_batch {
   unsigned* d_sync = nullptr;
   std::vector<BatchChannel> h_ch;
   std::vector<int> h_half;
-  int half_n[2] = {0, 0}, half_t[2] = {0, 0};
+  int half_n[2] = {0, 0}, half_t[2] = {0, 0}, half_d[2] = {0, 0};
   int grid = 0, grid_user = 0, occupancy = 0;
   int tile_w = 32, tile_rows = 2;
   int cur = 0;
@@ -226,7 +243,7 @@ int validate_batch(int32_t nsim, const imb_config* cfgs, std::string* why) {
 
 size_t table_bytes(int nsim) {
   return align_up(sizeof(BatchChannel) * nsim, 256) +
-         align_up(sizeof(int) * 2 * (2 * MAX_BATCH + 1), 256) +
+         align_up(sizeof(int) * 2 * (3 * MAX_BATCH + 2), 256) +
          align_up(sizeof(unsigned) * SYNC_WORDS, 256);
 }
 
@@ -265,20 +282,26 @@ int refresh(imb_batch* b) {
     load[h] += tiles[c];
   }
   for (int h = 0; h < 2; ++h) std::sort(hc[h].begin(), hc[h].end());
-  b->h_half.assign(2 * (2 * MAX_BATCH + 1), 0);
+  b->h_half.assign(2 * (3 * MAX_BATCH + 2), 0);
   int* hch = b->h_half.data();
   int* hpref = hch + 2 * MAX_BATCH;
+  int* hdpref = hpref + 2 * (MAX_BATCH + 1);
   for (int h = 0; h < 2; ++h) {
-    int acc = 0;
+    int acc = 0, dacc = 0;
     for (size_t k = 0; k < hc[h].size(); ++k) {
       hch[h * MAX_BATCH + k] = hc[h][k];
       hpref[h * (MAX_BATCH + 1) + k] = acc;
+      hdpref[h * (MAX_BATCH + 1) + k] = dacc;
       acc += tiles[hc[h][k]];
+      dacc += b->h_ch[hc[h][k]].la.np;
     }
-    for (size_t k = hc[h].size(); k <= (size_t)MAX_BATCH; ++k)
+    for (size_t k = hc[h].size(); k <= (size_t)MAX_BATCH; ++k) {
       hpref[h * (MAX_BATCH + 1) + k] = acc;
+      hdpref[h * (MAX_BATCH + 1) + k] = dacc;
+    }
     b->half_n[h] = (int)hc[h].size();
     b->half_t[h] = acc;
+    b->half_d[h] = dacc;
   }
   hipError_t e = hipMemcpyAsync(b->d_ch, b->h_ch.data(), sizeof(BatchChannel) * b->nch,
                                 hipMemcpyHostToDevice, b->stream);
@@ -300,10 +323,13 @@ BatchArgs batch_args(imb_batch* b, int nsteps, int parity) {
   a.ch = b->d_ch;
   a.half_ch = b->d_half;
   a.half_pref = b->d_half + 2 * MAX_BATCH;
+  a.half_dpref = b->d_half + 2 * MAX_BATCH + 2 * (MAX_BATCH + 1);
   a.half_n0 = b->half_n[0];
   a.half_n1 = b->half_n[1];
   a.half_t0 = b->half_t[0];
   a.half_t1 = b->half_t[1];
+  a.half_d0 = b->half_d[0];
+  a.half_d1 = b->half_d[1];
   a.nsteps = nsteps;
   a.parity0 = parity;
   a.nblocks = b->grid;
@@ -477,7 +503,7 @@ int imb_batch_create(int32_t nsim, const imb_config* cfgs, void* hip_stream, voi
   b->d_ch = (BatchChannel*)(b->mem + off);
   off += align_up(sizeof(BatchChannel) * nsim, 256);
   b->d_half = (int*)(b->mem + off);
-  off += align_up(sizeof(int) * 2 * (2 * MAX_BATCH + 1), 256);
+  off += align_up(sizeof(int) * 2 * (3 * MAX_BATCH + 2), 256);
   b->d_sync = (unsigned*)(b->mem + off);
   off += align_up(sizeof(unsigned) * SYNC_WORDS, 256);
   launch_fill_zero(b->mem, off, b->stream);

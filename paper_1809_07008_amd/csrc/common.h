@@ -22,7 +22,7 @@ constexpr int MAX_BANDS = 6144;    // tile rows (bands) of one lattice
 constexpr int NBMAX = 32;          // DEM neighbour-list capacity per disk
 constexpr int MAX_PARTICLES = 512;
 constexpr int PBLOCK = 512;        // threads of the particle-phase workgroup (one per disk)
-constexpr double DEM_SKIN = 3.0;   // neighbour-list skin (lattice units)
+constexpr double DEM_SKIN = 5.0;   // neighbour-list skin (lattice units)
 constexpr double MAX_MOVE = 1.0;   // largest displacement of a disk in one lattice step
 constexpr float F16_SCALE = 16384.0f;  // power-of-two scale of FP16 deviations
 
@@ -79,6 +79,9 @@ struct LatticeArgs {
   int* err;
   unsigned* seed;        // [2] step counters of the stochastic rounding: this step reads
   int seed_slot;         //   seed[seed_slot], tile 0 writes seed[seed_slot ^ 1] = it + 1
+  const int* nbr;        // [np][NBMAX] neighbour lists (ascending ids) and their lengths
+  const int* nnbr;
+  double4* force;        // [np] force and torque of this step (Fx, Fy, Tz, 0)
 };
 
 // Particle state on the device (structure of arrays, FP64).
@@ -100,6 +103,8 @@ struct ParticleArgs {
   ParticleState s;
   ParticleTable tab;
   const int4* box_in;  // boxes of the step whose partials are finalised (null: tab.box)
+  const double4* direct;  // per-disk force of the step (null: sum the partial slots instead)
+  int build_lists;        // maintain the neighbour lists even when no disk is free
   int* band_off;   // written with the table: per tile row, the disks whose box touches it
   int* band_ids;   // capacity np * MAXSLOT
   const double4* partials;  // [MAXSLOT][pstride]

@@ -1,0 +1,227 @@
+// disk_block.h -- the lattice step split by who owns a cell.
+//
+// A cell that no disk covers is a fluid cell: its tile collides it with the plain BGK + body-force
+// update and stores it (fluid_tile).  A cell covered by one or more disks (the covering test of
+// covers_cell, the one every kernel uses) belongs to the covering disk with the lowest id; that
+// disk's workgroup (disk_cells) pulls its populations, evaluates the exact solid ratio of every
+// covering disk, applies the IMB collision (Eqs. 1, 2, 12-14, with the several-disk reading of
+// collide.h) and stores it.  Every covering disk's workgroup also evaluates the cell to obtain
+// its own share of the hydrodynamic force and torque (Eqs. 15, 16), so each workgroup reduces
+// exactly its own disk's sums; there is no cross-workgroup accumulation and no atomic, and the
+// results do not depend on scheduling.
+//
+// Disks that can cover a common cell are neighbours in the DEM neighbour list (its skin keeps
+// every pair closer than r_p + r_q + sqrt 2 listed until the next rebuild), so a disk's workgroup
+// finds the other covering disks among its neighbours.  Tiles still use the per-tile candidate
+// lists to know which of their cells are covered.
+#pragma once
+
+#include "collide.h"
+#include "tile.h"
+
+namespace imb {
+
+// Plain update of the uncovered cells of one tile (one BLOCK-thread workgroup).
+template <class St>
+__device__ void fluid_tile(const LatticeArgs& a, int tile) {
+  using T = typename St::T;
+  using S = typename St::S;
+  __shared__ PEntry<T> s_pl[LMAX];
+  __shared__ int s_cnt[WAVES];
+  __shared__ int s_pid[LMAX], s_slot[LMAX];
+
+  const int tid = threadIdx.x;
+  const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+  const int tw = 1 << a.tw_log, th = BLOCK >> a.tw_log;
+  const int lx = tid & (tw - 1), ly = tid >> a.tw_log;
+  const int x = tx * tw + lx;
+  const int ybase = ty * th * a.rows + ly;
+  const S* src = (const S*)a.src;
+  S* dst = (S*)a.dst;
+
+  unsigned seed = 0u;
+  if constexpr (St::stochastic) seed = a.seed[a.seed_slot];
+  T f[NQ];
+  if (x < a.nx && ybase < a.ny) pull_load<St>(a, src, x, ybase, f);
+  const int n = build_tile_list<T>(a, tx, ty, s_pl, s_cnt, s_pid, s_slot);
+
+  const T tau0 = (T)a.tau0, csm = (T)a.cs, gx = (T)a.gx, gy = (T)a.gy, rho0 = (T)a.rho0;
+  for (int rr = 0; rr < a.rows; ++rr) {
+    const int y = ybase + rr * th;
+    if (x >= a.nx || y >= a.ny) continue;
+    if (rr > 0) pull_load<St>(a, src, x, y, f);
+    bool covered = false;
+    for (int j = 0; j < n && !covered; ++j) {
+      T dx, dy;
+      lever_arm(a, s_pl[j], x, y, &dx, &dy);
+      covered = covers_cell<T>(s_pl[j].r, dx, dy);
+    }
+    if (covered) continue;  // stored by the workgroup of its lowest-id covering disk
+    T fo[NQ];
+    auto none = [&](int) { return Disk<T>{}; };
+    auto drop = [&](int, T, T, T) {};
+    T rho;
+    if constexpr (St::deviation) {
+      rho = collide_dev(f, 0, none, drop, rho0, tau0, csm, gx, gy, fo);
+    } else {
+      rho = collide_plain(f, 0, none, drop, tau0, csm, gx, gy, fo);
+    }
+    if (!(rho > T(0)) || !isfinite(rho)) atomicOr(a.err, ERR_RHO);
+    const long long base = (long long)y * a.pitch + x;
+    if constexpr (St::stochastic) {
+      const unsigned r0 = pcg_hash(seed * 0x9E3779B9u + (unsigned)base);
+#pragma unroll
+      for (int i = 0; i < NQ; ++i)
+        St::store_sr(dst, (long long)i * a.plane + base, fo[i], pcg_hash(r0 + (unsigned)i));
+    } else {
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) St::store(dst, (long long)i * a.plane + base, fo[i], T(0));
+    }
+  }
+  if constexpr (St::stochastic) {
+    if (tile == 0 && tid == 0) a.seed[a.seed_slot ^ 1] = seed + 1u;
+  }
+}
+
+// Covered cells of disk p's box (one BLOCK-thread workgroup): IMB collision of the cells p owns,
+// p's own force and torque over every cell it covers, written to a.force[p].
+template <class St>
+__device__ void disk_cells(const LatticeArgs& a, int p) {
+  using T = typename St::T;
+  using S = typename St::S;
+  __shared__ PEntry<T> s_de[NBMAX + 1];  // disk p and its neighbours, ascending id
+  __shared__ int s_cj[MAXC][BLOCK];       // covering entries of each thread's current cell
+  __shared__ T s_ce[MAXC][BLOCK];         //   and their solid ratios
+  __shared__ Acc<T> s_fr[WAVES][3];
+
+  const int tid = threadIdx.x;
+  const S* src = (const S*)a.src;
+  S* dst = (S*)a.dst;
+  int nn = a.nnbr[p];
+  if (nn > NBMAX) nn = NBMAX;
+  if (nn < 0) nn = 0;
+  const int nd = nn + 1;
+  // entry k: p itself or neighbour k - 1, placed at its rank by id
+  if (tid < nd) {
+    const int q = tid == 0 ? p : a.nbr[(long long)p * NBMAX + tid - 1];
+    int rank = 0;
+    if (tid == 0) {
+      for (int k = 0; k < nn; ++k) rank += a.nbr[(long long)p * NBMAX + k] < p;
+    } else {
+      rank = (tid - 1) + (q > p ? 1 : 0);
+    }
+    const double4 ps = a.tab.pos[q];
+    const double4 vl = a.tab.vel[q];
+    const double flx = floor(ps.x), fly = floor(ps.y);
+    PEntry<T> e;
+    e.ix = (int)flx;
+    e.iy = (int)fly;
+    e.pid = q;
+    e.slot = 0;
+    e.fx = (T)(ps.x - flx);
+    e.fy = (T)(ps.y - fly);
+    e.r = (T)ps.z;
+    e.vx = (T)vl.x;
+    e.vy = (T)vl.y;
+    e.om = (T)vl.z;
+    if (rank >= 0 && rank < nd) s_de[rank] = e;
+  }
+  unsigned seed = 0u;
+  if constexpr (St::stochastic) seed = a.seed[a.seed_slot];
+  __syncthreads();
+
+  // the cells the disk can cover: [floor(X - r - 1/2), ceil(X + r + 1/2)] in x and y
+  const double4 pp = a.tab.pos[p];
+  const int ix0 = (int)floor(pp.x - pp.z - 0.5), ix1 = (int)ceil(pp.x + pp.z + 0.5);
+  int iy0 = (int)floor(pp.y - pp.z - 0.5), iy1 = (int)ceil(pp.y + pp.z + 0.5);
+  if (a.walls) {
+    if (iy0 < 0) iy0 = 0;
+    if (iy1 > a.ny - 1) iy1 = a.ny - 1;
+  }
+  const int bw = ix1 - ix0 + 1, bh = iy1 - iy0 + 1;
+  const int ncell = (bw > 0 && bh > 0 && bw <= a.nx && bh <= a.ny) ? bw * bh : 0;
+
+  const T tau0 = (T)a.tau0, csm = (T)a.cs, gx = (T)a.gx, gy = (T)a.gy, rho0 = (T)a.rho0;
+  Acc<T> afx{T(0), T(0)}, afy{T(0), T(0)}, atz{T(0), T(0)};
+  for (int c = tid; c < ncell; c += BLOCK) {
+    int x = ix0 + c % bw, y = iy0 + c / bw;
+    x = x < 0 ? x + a.nx : (x >= a.nx ? x - a.nx : x);
+    if (!a.walls) y = y < 0 ? y + a.ny : (y >= a.ny ? y - a.ny : y);
+    // covering disks of the cell, ascending id; the cell belongs to the first of them
+    int nc = 0, own = -1;
+    bool owner = true;
+    for (int k = 0; k < nd; ++k) {
+      T dx, dy;
+      lever_arm(a, s_de[k], x, y, &dx, &dy);
+      if (!covers_cell<T>(s_de[k].r, dx, dy)) continue;
+      if (s_de[k].pid != p && own < 0) owner = false;  // a lower id covers the cell
+      if (s_de[k].pid == p) own = nc;
+      if (nc >= MAXC) {
+        atomicOr(a.err, ERR_CELL);
+        continue;
+      }
+      s_cj[nc][tid] = k;
+      s_ce[nc][tid] = solid_fraction<T>(s_de[k].r, dx, dy);
+      ++nc;
+    }
+    if (own < 0) continue;  // p does not cover this cell
+    T f[NQ], fo[NQ];
+    pull_load<St>(a, src, x, y, f);
+    auto disk = [&](int k) {
+      Disk<T> d;
+      const PEntry<T>& e = s_de[s_cj[k][tid]];
+      d.eps = s_ce[k][tid];
+      lever_arm(a, e, x, y, &d.dx, &d.dy);
+      d.vx = e.vx;
+      d.vy = e.vy;
+      d.om = e.om;
+      return d;
+    };
+    auto emit = [&](int k, T fx, T fy, T tz) {
+      if (k != own) return;
+      afx.add(fx);
+      afy.add(fy);
+      atz.add(tz);
+    };
+    T rho;
+    if constexpr (St::deviation) {
+      rho = collide_dev(f, nc, disk, emit, rho0, tau0, csm, gx, gy, fo);
+    } else {
+      rho = collide_plain(f, nc, disk, emit, tau0, csm, gx, gy, fo);
+    }
+    if (!owner) continue;
+    if (!(rho > T(0)) || !isfinite(rho)) atomicOr(a.err, ERR_RHO);
+    const long long base = (long long)y * a.pitch + x;
+    if constexpr (St::stochastic) {
+      const unsigned r0 = pcg_hash(seed * 0x9E3779B9u + (unsigned)base);
+#pragma unroll
+      for (int i = 0; i < NQ; ++i)
+        St::store_sr(dst, (long long)i * a.plane + base, fo[i], pcg_hash(r0 + (unsigned)i));
+    } else {
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) St::store(dst, (long long)i * a.plane + base, fo[i], T(0));
+    }
+  }
+  // the disk's force and torque: wave sums, then the waves in a fixed order
+  const int lane = tid & 63, wave = tid >> 6;
+  const Acc<T> w0 = wave_sum(afx), w1 = wave_sum(afy), w2 = wave_sum(atz);
+  if (lane == 0) {
+    s_fr[wave][0] = w0;
+    s_fr[wave][1] = w1;
+    s_fr[wave][2] = w2;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double out[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      Acc<T> v = s_fr[0][c];
+#pragma unroll
+      for (int w = 1; w < WAVES; ++w) v.add(s_fr[w][c]);
+      out[c] = (double)v.hi + (double)v.lo;
+    }
+    a.force[p] = make_double4(out[0], out[1], out[2], 0.0);
+  }
+}
+
+}  // namespace imb

@@ -131,17 +131,22 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
     nn = s.nnbr[p];
 #pragma unroll
     for (int u = 0; u < NB_REG; ++u) nb[u] = s.nbr[p * NBMAX + u];
-    if (a.do_finalize) {
+    if (a.do_finalize && !a.direct) {
 #pragma unroll
       for (int u = 0; u < PF; ++u) pv[u] = a.partials[(long long)u * a.pstride + p];
     }
   }
-  const int rebuild_flag = a.do_dem || a.init_contacts ? *s.rebuild : 0;
+  const int rebuild_flag = a.do_dem || a.init_contacts || a.build_lists ? *s.rebuild : 0;
   const double x_start = x, y_start = y;
 
   // ---- 1. forces of the step that just ran: slots in order
   double Fx = 0.0, Fy = 0.0, Tz = 0.0;
-  if (have && a.do_finalize) {
+  if (have && a.do_finalize && a.direct) {
+    const double4 d = a.direct[p];
+    Fx = d.x;
+    Fy = d.y;
+    Tz = d.z;
+  } else if (have && a.do_finalize) {
     const int ns = box_slots(b);
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
@@ -249,18 +254,20 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
   bool rebuilt = false;
   // bit 1: some disk is free; bit 2: the neighbour list must be rebuilt
   int flags = 0;
-  if (a.do_dem || a.init_contacts) {
+  if (a.do_dem || a.init_contacts || a.build_lists) {
     int mine = own ? 1 : 0;
     if (have) {
+      // rebuild before any disk can have moved (by the next lattice step) far enough that a
+      // pair outside the list could touch, or cover a common cell
       const double ddx = nearest_image(x - xref, a.nx);
       const double ddy = a.walls ? y - yref : nearest_image(y - yref, a.ny);
-      const double lim = 0.5 * DEM_SKIN - MAX_MOVE;
+      const double lim = 0.5 * (DEM_SKIN - M_SQRT2) - MAX_MOVE;
       if (ddx * ddx + ddy * ddy > lim * lim) mine |= 2;
     }
     if (p == 0 && rebuild_flag) mine |= 2;
     flags = block_or(mine, &s_flag);
   }
-  if (flags & 1) {
+  if ((flags & 1) || a.build_lists) {
     // ---- neighbour list maintenance
     if (flags & 2) {
       rebuilt = true;
@@ -291,7 +298,8 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
         yref = y;
       }
     }
-
+  }
+  if ((flags & 1) && (a.do_dem || a.init_contacts)) {  // table-only calls never move a disk
     if (a.init_contacts) {
       if (own) contact(x, y, vx, vy, fcx, fcy);
       else {

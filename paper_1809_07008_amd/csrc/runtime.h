@@ -25,6 +25,7 @@ struct DeviceLayout {
   double* J;
   double* w;  // objective weights wfx, wfy, wtz (3 x capacity)
   unsigned* seed;  // [2] stochastic-rounding step counters
+  double4* force;  // [capacity] per-disk force and torque written by the lattice step
 };
 
 struct AdjointState;

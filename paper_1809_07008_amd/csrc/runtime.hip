@@ -78,6 +78,7 @@ size_t layout(const imb_config& c, char* base, DeviceLayout* L) {
   d.J = cv.take<double>(1);
   d.w = cv.take<double>(3 * mp);
   d.seed = cv.take<unsigned>(2);
+  d.force = cv.take<double4>(mp);
   if (L) *L = d;
   return align_up(cv.off, 256);
 }
@@ -187,6 +188,9 @@ LatticeArgs lattice_args(imb_sim* s, const void* src, void* dst) {
   a.pstride = std::max(s->cfg.max_particles, 1);
   a.seed = s->d.seed;
   a.seed_slot = src == s->d.f[1] ? 1 : 0;
+  a.nbr = s->d.ps.nbr;
+  a.nnbr = s->d.ps.nnbr;
+  a.force = s->d.force;
   return a;
 }
 
@@ -200,6 +204,8 @@ ParticleArgs particle_args(imb_sim* s) {
   a.s = s->d.ps; a.tab = s->d.tab; a.partials = s->d.partials; a.err = s->d.err;
   a.band_off = s->d.band_off; a.band_ids = s->d.band_ids;
   a.pstride = std::max(s->cfg.max_particles, 1);
+  a.direct = s->d.force;
+  a.build_lists = 1;
   return a;
 }
 

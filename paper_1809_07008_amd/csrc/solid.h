@@ -166,6 +166,17 @@ __host__ __device__ __noinline__ T cut_cell_fraction(T r, T x0, T x1, T y0, T y1
 // eps of the unit cell centred at (dx, dy) relative to the disk centre.  The cut-cell branch is
 // a separate (non-inlined) function: it runs only for cut cells and keeps the caller's register
 // budget small.
+// Whether the unit cell centred at (dx, dy) from the centre overlaps the disk of radius r: the
+// point of the cell nearest to the centre is strictly inside.  Every kernel decides "covered"
+// with exactly this test.
+template <class T>
+__host__ __device__ inline bool covers_cell(T r, T dx, T dy) {
+  const T x0 = dx - T(0.5), x1 = dx + T(0.5), y0 = dy - T(0.5), y1 = dy + T(0.5);
+  const T nx = x0 > T(0) ? x0 : (x1 < T(0) ? x1 : T(0));
+  const T ny = y0 > T(0) ? y0 : (y1 < T(0) ? y1 : T(0));
+  return nx * nx + ny * ny < r * r;
+}
+
 template <class T>
 __host__ __device__ inline T solid_fraction(T r, T dx, T dy) {
   const T x0 = dx - T(0.5), x1 = dx + T(0.5), y0 = dy - T(0.5), y1 = dy + T(0.5);

@@ -1,13 +1,21 @@
-// step.hip -- launchers of the fused lattice step (lattice_tile.h) and of the solid-ratio
-// diagnostic kernel.
+// step.hip -- the lattice step (disk_block.h: uncovered cells by tiles, covered cells by their
+// disks' workgroups) and the solid-ratio diagnostic kernel.
+#include "disk_block.h"
 #include "lattice_tile.h"
 #include "step.h"
 
 namespace imb {
 
+// Workgroups [0, np) are the disks' (covered cells, own force and torque), the rest the tiles'
+// (uncovered cells); the disks' longer work is dispatched first.
 template <class St>
 __global__ __launch_bounds__(BLOCK) void k_lattice_step(LatticeArgs a) {
-  lattice_tile<St>(a, xcd_remap(blockIdx.x, gridDim.x));
+  const int b = blockIdx.x;
+  if (b < a.np) {
+    disk_cells<St>(a, b);
+    return;
+  }
+  fluid_tile<St>(a, xcd_remap(b - a.np, a.tiles_x * a.tiles_y));
 }
 
 // eps_tot of every cell (diagnostic / parity of the solid-ratio stage alone).
@@ -37,7 +45,7 @@ __global__ __launch_bounds__(BLOCK) void k_solid_field(LatticeArgs a, double* ep
 template <class St>
 void launch_lattice_step_t(const LatticeArgs& a, hipStream_t s) {
   const int tiles = a.tiles_x * a.tiles_y;
-  hipLaunchKernelGGL(k_lattice_step<St>, dim3(tiles), dim3(BLOCK), 0, s, a);
+  hipLaunchKernelGGL(k_lattice_step<St>, dim3(tiles + a.np), dim3(BLOCK), 0, s, a);
 }
 
 void launch_lattice_step(int storage, const LatticeArgs& a, hipStream_t s) {
