@@ -1,0 +1,139 @@
+"""Cases run against the CPU emulation of libimb (test infrastructure; run by
+tests/test_cpu_emulation.py in a subprocess with AddressSanitizer preloaded).  Each case compares
+the emulated kernels with the FP64 oracle or with another path of the library and exits non-zero
+on a mismatch; AddressSanitizer aborts the process on any out-of-bounds access."""
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path[:0] = [ROOT, os.path.dirname(HERE)]
+
+import numpy as np  # noqa: E402
+
+from adjoint_fd import block_errors, fd_gradient  # noqa: E402
+from oracle import OracleConfig, OracleSim  # noqa: E402
+from paper_1809_07008_amd import imb  # noqa: E402
+from paper_1809_07008_amd import workloads as W  # noqa: E402
+
+imb.LIB_PATH = os.environ["EMU_LIB"]
+
+
+class HostStream:  # the emulated library ignores streams
+    cuda_stream = 0
+
+
+S = HostStream()
+
+
+def sim_of(case, storage, tile=(32, 2)):
+    s = imb.Simulation(imb.config_from_case(case, None, tile[0], tile[1], storage), S, device="cpu")
+    s.set_case_particles(case.particles)
+    return s
+
+
+def oracle_of(case):
+    r = OracleSim(OracleConfig(nx=case.nx, ny=case.ny, tau0=case.tau0, walls=case.walls, cs=case.cs,
+                               gx=case.gx, gy=case.gy, rho0=case.rho0, n_sub=case.n_sub))
+    p = case.particles
+    r.set_particles(p.x, p.y, p.r, p.vx, p.vy, p.om, p.mode)
+    return r
+
+
+def check(name, ok, detail):
+    print("%-48s %s  %s" % (name, "ok" if ok else "FAIL", detail), flush=True)
+    if not ok:
+        sys.exit(1)
+
+
+def moving_case():
+    rng = np.random.default_rng(5)
+    x, y, r = W.place_disks(rng, 64, 40, 3, 8.0, 11.0, gap=1.0, wall_gap=1.0)
+    p = W.Particles(x, y, r, rng.normal(0, 0.01, 3), rng.normal(0, 0.01, 3), np.zeros(3),
+                    np.zeros(3, np.int32))
+    return W.Case("emu_moving", 64, 40, tau0=0.6, steps=4, gx=1e-5, cs=0.1, particles=p)
+
+
+def overlap_case(walls):
+    p = W.Particles(np.array([20.2, 31.0, 25.6, 54.3]), np.array([16.1, 17.3, 25.4, 9.7]),
+                    np.array([6.2, 5.1, 5.4, 4.0]), np.array([0.01, -0.01, 0.0, 0.002]),
+                    np.zeros(4), np.array([0.0, 0.001, 0.0, 0.0]), np.array([1, 2, 1, 0], np.int32))
+    return W.Case("emu_overlap", 64, 36, tau0=0.7, steps=3, walls=walls, gx=1e-5, particles=p)
+
+
+def fp64_parity():
+    for case in (moving_case(), overlap_case(True), overlap_case(False)):
+        s = sim_of(case, "f64")
+        s.step(case.steps)
+        ref = oracle_of(case)
+        ref.step(case.steps)
+        fg, fo = np.array(s.forces()), np.array(ref.forces())
+        ferr = np.abs(fg - fo).max() / np.abs(fo).max()
+        perr = np.abs(s.populations() - ref.populations()).max()
+        check("fp64 parity %s walls=%s" % (case.name, case.walls), ferr < 1e-12 and perr < 1e-13,
+              "force %.2e populations %.2e" % (ferr, perr))
+
+
+def reduced_precision():
+    case = moving_case()
+    ref = oracle_of(case)
+    ref.step(case.steps)
+    fo = np.array(ref.forces())
+    for st, tol in (("f32", 1e-4), ("f16", 5e-2)):
+        s = sim_of(case, st)
+        s.step(case.steps)
+        err = np.abs(np.array(s.forces()) - fo).max() / np.abs(fo).max()
+        check("%s storage against the oracle" % st, err < tol, "force %.2e" % err)
+
+
+def roundtrip():
+    case = moving_case().with_(storage="f32")
+    a = sim_of(case, "f32")
+    a.step(2)
+    blob = a.save_state()
+    a.step(3)
+    b = sim_of(case, "f32")
+    b.load_state(blob)
+    b.step(3)
+    same = np.array_equal(a.populations(), b.populations()) and all(
+        np.array_equal(u, v) for u, v in zip(a.forces() + a.particles(), b.forces() + b.particles()))
+    check("checkpoint round trip continues bit for bit", same, "")
+
+
+def adjoint():
+    p = overlap_case(True).particles.copy()
+    p.mode[:] = 2
+    case = W.Case("emu_adjoint", 64, 36, tau0=0.7, steps=3, gx=1e-5, gy=2e-6,
+                  particles=W.Particles(p.x[[0, 3]], p.y[[0, 3]], p.r[[0, 3]], p.vx[[0, 3]],
+                                        p.vy[[0, 3]], p.om[[0, 3]], p.mode[[0, 3]]))
+    w = dict(wfx=np.array([1.0, 0.7]), wfy=np.array([0.3, -0.5]), wtz=np.array([0.05, 0.02]))
+    res = sim_of(case, "f64").adjoint(case.steps, 2, **w)
+    fd = fd_gradient(case, case.steps, **w)
+    errs = block_errors(res, fd)
+    check("fp64 adjoint against finite differences", max(errs.values()) < 1e-5,
+          " ".join("%s %.1e" % kv for kv in errs.items()))
+
+
+def batch():
+    cases = [moving_case(), overlap_case(False).with_(nx=48, ny=32,
+                                                      particles=W.Particles.empty())]
+    b = imb.Batch([imb.config_from_case(c, None, 32, 2, "f32") for c in cases], S, device="cpu")
+    for k, c in enumerate(cases):
+        b.set_case_particles(k, c.particles)
+    b.step(3)
+    b.sync()
+    for k, c in enumerate(cases):
+        s = sim_of(c, "f32")
+        s.step(3)
+        check("batch channel %d equals the channel alone" % k,
+              np.array_equal(b.populations(k), s.populations()), "")
+    b.autotune(trial_steps=1, max_trials=3)
+    b.step(1)
+    b.sync()
+    check("batch autotune", True, str(b.launch()))
+
+
+if __name__ == "__main__":
+    for fn in (fp64_parity, reduced_precision, roundtrip, adjoint, batch):
+        fn()
+    print("all emulated cases passed", flush=True)
