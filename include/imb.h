@@ -155,13 +155,17 @@ int imb_state_bytes(imb_sim* sim, size_t* bytes);
 int imb_save_state(imb_sim* sim, void* host_buf, size_t bytes);
 int imb_load_state(imb_sim* sim, const void* host_buf, size_t bytes);
 
-/* Per-kernel timing with HIP events on the simulation's stream.  When enabled, imb_step records
- * an event pair around every fused lattice-step launch and every particle-phase launch.
+/* Per-kernel timing with HIP events on the simulation's stream.  A step is three kernels: the
+ * fluid tiles (uncovered cells), the disk workgroups (covered cells, force and torque of each
+ * disk) and the particle phase (DEM, next step's disk tables).  imb_step normally runs the fluid
+ * tiles on a second stream, concurrently with the other two; when timing is enabled it runs the
+ * three one after the other on the simulation's stream with an event pair around each.
  * imb_get_kernel_timing synchronises and returns the summed milliseconds and launch counts since
  * the last reset (any pointer may be NULL). */
 int imb_set_kernel_timing(imb_sim* sim, int enable);
-int imb_get_kernel_timing(imb_sim* sim, double* lattice_ms, int64_t* lattice_launches,
-                          double* particle_ms, int64_t* particle_launches);
+int imb_get_kernel_timing(imb_sim* sim, double* fluid_ms, int64_t* fluid_launches,
+                          double* disk_ms, int64_t* disk_launches, double* particle_ms,
+                          int64_t* particle_launches);
 
 /* Streaming copy of n_bytes between two device buffers with the library's copy kernel, for
  * calibrating bandwidth counters.  Asynchronous on hip_stream. */

@@ -550,9 +550,11 @@ extern "C" int imb_adjoint(imb_sim* sim, int32_t nsteps, int32_t k, const double
   launch_fill_zero(A->lam[0], A->lam_bytes, st);
 
   // ---- forward pass: checkpoints every k steps, the table of every step
-  const ParticleTable live = d.tab;
-  int* const live_boff = d.band_off;
-  int* const live_bids = d.band_ids;
+  // the tables of the stored state, and those the state after the last step will use
+  const int c0 = *v.cur;
+  const ParticleTable live = d.tab[c0];
+  int* const live_boff = d.band_off[c0];
+  int* const live_bids = d.band_ids[c0];
   {
     TableSlot t0 = table_slot(v, A, 0);
     copy_table(v, t0.tab, t0.boff, t0.bids, live, live_boff, live_bids, st);
@@ -580,11 +582,10 @@ extern "C" int imb_adjoint(imb_sim* sim, int32_t nsteps, int32_t k, const double
     launch_lattice_step(cfg.storage, la, st);
     if (np > 0) {
       const TableSlot tn1 = table_slot(v, A, n + 1);
-      ParticleArgs pa = particle_args(sim);
+      ParticleArgs pa = particle_args(sim, 0);  // writes the history slot instead
       pa.do_finalize = 1;
       pa.do_dem = 1;
       pa.do_table = 1;
-      pa.box_in = tn.tab.box;
       pa.tab = tn1.tab;
       pa.band_off = tn1.boff;
       pa.band_ids = tn1.bids;
@@ -600,9 +601,9 @@ extern "C" int imb_adjoint(imb_sim* sim, int32_t nsteps, int32_t k, const double
   hipEventRecord(A->ev[1], st);
   *v.cur = last;
   *v.steps += nsteps;
-  {  // the live table is the one for the step after the last
+  {  // the stored state's tables are the ones of the step after the last
     TableSlot tN = table_slot(v, A, nsteps);
-    copy_table(v, live, live_boff, live_bids, tN.tab, tN.boff, tN.bids, st);
+    copy_table(v, d.tab[last], d.band_off[last], d.band_ids[last], tN.tab, tN.boff, tN.bids, st);
   }
 
   // ---- reverse sweep

@@ -37,9 +37,11 @@ constexpr int MAX_BATCH = 128;   // channels per batch
 constexpr int PP_LDS = 1280;     // doubles of particle-phase scratch: 256 disks x 5
 constexpr int SYNC_WORDS = 8;    // [0] arrivals [1] generation [2],[3] item counters [4] abort
 
+// Arguments of one channel for a step reading buffer k (la[k]: buffer k to buffer k ^ 1 with the
+// disk tables of slot k; pa[k]: that step's particle phase, writing the tables of slot k ^ 1).
 struct BatchChannel {
-  LatticeArgs la;  // src = buffer 0, dst = buffer 1 (swapped on odd steps)
-  ParticleArgs pa;
+  LatticeArgs la[2];
+  ParticleArgs pa[2];
 };
 
 struct BatchArgs {
@@ -148,22 +150,23 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs B) {
       __syncthreads();
       const int i = s_item;
       if (s_abort || i >= npart + ndisk + nlat) break;
-      if (i < npart) {
-        particle_phase<BLOCK>(B.ch[s_hch[ph][i]].pa, pp_lds);
+      if (i < npart) {  // the particle phase of step n (half B: of step n - 1)
+        const int m = h == 1 ? n : n - 1;
+        particle_phase<BLOCK>(B.ch[s_hch[ph][i]].pa[(B.parity0 + m) & 1], pp_lds);
         continue;
       }
       const bool is_disk = i < npart + ndisk;
       const int t = is_disk ? i - npart : i - npart - ndisk;
       const int k = find_slot(is_disk ? s_hdpref[h] : s_hpref[h], hn[h], t);
-      LatticeArgs la = B.ch[s_hch[h][k]].la;
-      if ((B.parity0 + n) & 1) {
-        const void* s = la.src;
-        la.src = la.dst;
-        la.dst = (void*)s;
-        la.seed_slot ^= 1;
+      const LatticeArgs la = B.ch[s_hch[h][k]].la[(B.parity0 + n) & 1];
+      if (is_disk) {
+        for (int part = 0; part < DISK_PARTS; ++part) {  // the bands of one disk in order
+          if (part > 0) __syncthreads();
+          disk_cells<StoreF32>(la, t - s_hdpref[h][k], part);
+        }
+      } else {
+        fluid_tile<StoreF32>(la, t - s_hpref[h][k]);
       }
-      if (is_disk) disk_cells<StoreF32>(la, t - s_hdpref[h][k]);
-      else fluid_tile<StoreF32>(la, t - s_hpref[h][k]);
     }
     if (p + 1 < nphase && !grid_barrier(B.sync, B.nblocks, 2 + (p & 1), B.spin_ticks)) return;
   }
@@ -263,13 +266,14 @@ int refresh(imb_batch* b) {
   for (int c = 0; c < b->nch; ++c) {
     imb_sim* s = b->sims[c];
     SimView v = sim_view(s);
-    LatticeArgs la = lattice_args(s, v.d->f[0], v.d->f[1]);
-    ParticleArgs pa = particle_args(s);
-    pa.do_finalize = 1;
-    pa.do_dem = 1;
-    pa.do_table = 1;
-    b->h_ch[c].la = la;
-    b->h_ch[c].pa = pa;
+    for (int k = 0; k < 2; ++k) {
+      ParticleArgs pa = particle_args(s, k ^ 1);
+      pa.do_finalize = 1;
+      pa.do_dem = 1;
+      pa.do_table = 1;
+      b->h_ch[c].la[k] = lattice_args(s, v.d->f[k], v.d->f[k ^ 1]);
+      b->h_ch[c].pa[k] = pa;
+    }
     tiles[c] = v.g->tiles_x * v.g->tiles_y;
     order[c] = c;
   }
@@ -293,7 +297,7 @@ int refresh(imb_batch* b) {
       hpref[h * (MAX_BATCH + 1) + k] = acc;
       hdpref[h * (MAX_BATCH + 1) + k] = dacc;
       acc += tiles[hc[h][k]];
-      dacc += b->h_ch[hc[h][k]].la.np;
+      dacc += b->h_ch[hc[h][k]].la[0].np;
     }
     for (size_t k = hc[h].size(); k <= (size_t)MAX_BATCH; ++k) {
       hpref[h * (MAX_BATCH + 1) + k] = acc;

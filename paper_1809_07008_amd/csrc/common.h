@@ -22,6 +22,7 @@ constexpr int MAX_BANDS = 6144;    // tile rows (bands) of one lattice
 constexpr int NBMAX = 32;          // DEM neighbour-list capacity per disk
 constexpr int MAX_PARTICLES = 512;
 constexpr int PBLOCK = 512;        // threads of the particle-phase workgroup (one per disk)
+constexpr int DISK_PARTS = 1;      // row bands of a disk's box, one workgroup each
 constexpr double DEM_SKIN = 5.0;   // neighbour-list skin (lattice units)
 constexpr double MAX_MOVE = 1.0;   // largest displacement of a disk in one lattice step
 constexpr float F16_SCALE = 16384.0f;  // power-of-two scale of FP16 deviations
@@ -74,14 +75,14 @@ struct LatticeArgs {
   ParticleTable tab;
   const int* band_off;   // [tiles_y + 1]: disks whose box touches tile row ty are
   const int* band_ids;   //   band_ids[band_off[ty] .. band_off[ty + 1])
-  double4* partials;     // [MAXSLOT][pstride] force / torque partial sums (Fx, Fy, Tz, 0),
-  int pstride;           //   slot-major so the particle phase reads them coalesced
+  int pstride;           // per-disk array stride (max_particles)
   int* err;
   unsigned* seed;        // [2] step counters of the stochastic rounding: this step reads
   int seed_slot;         //   seed[seed_slot], tile 0 writes seed[seed_slot ^ 1] = it + 1
   const int* nbr;        // [np][NBMAX] neighbour lists (ascending ids) and their lengths
   const int* nnbr;
-  double4* force;        // [np] force and torque of this step (Fx, Fy, Tz, 0)
+  double4* force;        // [np][DISK_PARTS] force and torque of this step (Fx, Fy, Tz, 0) per
+                         //   band of the disk's box
 };
 
 // Particle state on the device (structure of arrays, FP64).
@@ -102,12 +103,10 @@ struct ParticleArgs {
   int tiles_x, tiles_y, tw, th;
   ParticleState s;
   ParticleTable tab;
-  const int4* box_in;  // boxes of the step whose partials are finalised (null: tab.box)
-  const double4* direct;  // per-disk force of the step (null: sum the partial slots instead)
+  const double4* direct;  // [np][DISK_PARTS] per-band force of the step, summed in band order
   int build_lists;        // maintain the neighbour lists even when no disk is free
   int* band_off;   // written with the table: per tile row, the disks whose box touches it
   int* band_ids;   // capacity np * MAXSLOT
-  const double4* partials;  // [MAXSLOT][pstride]
   int pstride;
   int do_finalize, do_dem, do_table, init_contacts;
   const double *wfx, *wfy, *wtz;  // objective weights (adjoint forward); may be null

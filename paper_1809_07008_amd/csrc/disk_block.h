@@ -21,7 +21,8 @@
 
 namespace imb {
 
-// Plain update of the uncovered cells of one tile (one BLOCK-thread workgroup).
+// Plain update of the uncovered cells of one tile (one BLOCK-thread workgroup): only they are
+// loaded and stored.
 template <class St>
 __device__ void fluid_tile(const LatticeArgs& a, int tile) {
   using T = typename St::T;
@@ -41,23 +42,21 @@ __device__ void fluid_tile(const LatticeArgs& a, int tile) {
 
   unsigned seed = 0u;
   if constexpr (St::stochastic) seed = a.seed[a.seed_slot];
-  T f[NQ];
-  if (x < a.nx && ybase < a.ny) pull_load<St>(a, src, x, ybase, f);
   const int n = build_tile_list<T>(a, tx, ty, s_pl, s_cnt, s_pid, s_slot);
 
   const T tau0 = (T)a.tau0, csm = (T)a.cs, gx = (T)a.gx, gy = (T)a.gy, rho0 = (T)a.rho0;
   for (int rr = 0; rr < a.rows; ++rr) {
     const int y = ybase + rr * th;
     if (x >= a.nx || y >= a.ny) continue;
-    if (rr > 0) pull_load<St>(a, src, x, y, f);
     bool covered = false;
     for (int j = 0; j < n && !covered; ++j) {
       T dx, dy;
       lever_arm(a, s_pl[j], x, y, &dx, &dy);
       covered = covers_cell<T>(s_pl[j].r, dx, dy);
     }
-    if (covered) continue;  // stored by the workgroup of its lowest-id covering disk
-    T fo[NQ];
+    if (covered) continue;  // loaded and stored by the workgroup of its lowest-id covering disk
+    T f[NQ], fo[NQ];
+    pull_load<St>(a, src, x, y, f);
     auto none = [&](int) { return Disk<T>{}; };
     auto drop = [&](int, T, T, T) {};
     T rho;
@@ -83,10 +82,11 @@ __device__ void fluid_tile(const LatticeArgs& a, int tile) {
   }
 }
 
-// Covered cells of disk p's box (one BLOCK-thread workgroup): IMB collision of the cells p owns,
-// p's own force and torque over every cell it covers, written to a.force[p].
+// Covered cells of band `part` (of DISK_PARTS row bands) of disk p's box, one BLOCK-thread
+// workgroup: IMB collision of the cells p owns, p's own force and torque over every cell of the
+// band it covers, written to a.force[p * DISK_PARTS + part].
 template <class St>
-__device__ void disk_cells(const LatticeArgs& a, int p) {
+__device__ void disk_cells(const LatticeArgs& a, int p, int part) {
   using T = typename St::T;
   using S = typename St::S;
   __shared__ PEntry<T> s_de[NBMAX + 1];  // disk p and its neighbours, ascending id
@@ -139,12 +139,15 @@ __device__ void disk_cells(const LatticeArgs& a, int p) {
     if (iy1 > a.ny - 1) iy1 = a.ny - 1;
   }
   const int bw = ix1 - ix0 + 1, bh = iy1 - iy0 + 1;
-  const int ncell = (bw > 0 && bh > 0 && bw <= a.nx && bh <= a.ny) ? bw * bh : 0;
+  const bool box_ok = bw > 0 && bh > 0 && bw <= a.nx && bh <= a.ny;
+  const int r0 = box_ok ? part * bh / DISK_PARTS : 0;
+  const int r1 = box_ok ? (part + 1) * bh / DISK_PARTS : 0;
+  const int ncell = (r1 - r0) * bw;
 
   const T tau0 = (T)a.tau0, csm = (T)a.cs, gx = (T)a.gx, gy = (T)a.gy, rho0 = (T)a.rho0;
   Acc<T> afx{T(0), T(0)}, afy{T(0), T(0)}, atz{T(0), T(0)};
   for (int c = tid; c < ncell; c += BLOCK) {
-    int x = ix0 + c % bw, y = iy0 + c / bw;
+    int x = ix0 + c % bw, y = iy0 + r0 + c / bw;
     x = x < 0 ? x + a.nx : (x >= a.nx ? x - a.nx : x);
     if (!a.walls) y = y < 0 ? y + a.ny : (y >= a.ny ? y - a.ny : y);
     // covering disks of the cell, ascending id; the cell belongs to the first of them
@@ -220,7 +223,7 @@ __device__ void disk_cells(const LatticeArgs& a, int p) {
       for (int w = 1; w < WAVES; ++w) v.add(s_fr[w][c]);
       out[c] = (double)v.hi + (double)v.lo;
     }
-    a.force[p] = make_double4(out[0], out[1], out[2], 0.0);
+    a.force[(long long)p * DISK_PARTS + part] = make_double4(out[0], out[1], out[2], 0.0);
   }
 }
 

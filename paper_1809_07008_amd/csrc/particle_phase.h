@@ -105,7 +105,6 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
   __shared__ int s_nact, s_aid[64], s_ann[64], s_anb[64][8];
   __shared__ double s_ast[64][6];
   constexpr int NB_REG = 8;   // neighbour ids kept in registers; the rest are read from the list
-  constexpr int PF = 8;       // partial-sum slots loaded in the first batch
   const int np = a.np, p = threadIdx.x;
   const bool have = p < np;
   double* sx = lds;
@@ -116,60 +115,31 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
   const ParticleState& s = a.s;
 
   // ---- one batch of loads
-  int4 b = make_int4(0, 0, 0, 0);
   double x = 0, y = 0, vx = 0, vy = 0, om = 0, r = 1, fcx = 0, fcy = 0, xref = 0, yref = 0;
   int mode = 1, nn = 0;
   int nb[NB_REG];
-  double4 pv[PF];
 #pragma unroll
   for (int u = 0; u < NB_REG; ++u) nb[u] = 0;
   if (have) {
-    b = (a.box_in ? a.box_in : a.tab.box)[p];
     x = s.x[p]; y = s.y[p]; vx = s.vx[p]; vy = s.vy[p]; om = s.om[p]; r = s.r[p];
     mode = s.mode[p];
     fcx = s.fcx[p]; fcy = s.fcy[p]; xref = s.xref[p]; yref = s.yref[p];
     nn = s.nnbr[p];
 #pragma unroll
     for (int u = 0; u < NB_REG; ++u) nb[u] = s.nbr[p * NBMAX + u];
-    if (a.do_finalize && !a.direct) {
-#pragma unroll
-      for (int u = 0; u < PF; ++u) pv[u] = a.partials[(long long)u * a.pstride + p];
-    }
   }
   const int rebuild_flag = a.do_dem || a.init_contacts || a.build_lists ? *s.rebuild : 0;
   const double x_start = x, y_start = y;
 
-  // ---- 1. forces of the step that just ran: slots in order
+  // ---- 1. forces of the step that just ran: the disk's row bands in order
   double Fx = 0.0, Fy = 0.0, Tz = 0.0;
-  if (have && a.do_finalize && a.direct) {
-    const double4 d = a.direct[p];
-    Fx = d.x;
-    Fy = d.y;
-    Tz = d.z;
-  } else if (have && a.do_finalize) {
-    const int ns = box_slots(b);
+  if (have && a.do_finalize) {
 #pragma unroll
-    for (int u = 0; u < PF; ++u) {
-      if (u < ns) {
-        Fx += pv[u].x;
-        Fy += pv[u].y;
-        Tz += pv[u].z;
-      }
-    }
-    for (int k0 = PF; k0 < ns; k0 += PF) {  // further batches of PF loads, summed in order
-      double4 v[PF];
-#pragma unroll
-      for (int u = 0; u < PF; ++u)
-        v[u] = k0 + u < ns ? a.partials[(long long)(k0 + u) * a.pstride + p]
-                           : make_double4(0.0, 0.0, 0.0, 0.0);
-#pragma unroll
-      for (int u = 0; u < PF; ++u) {
-        if (k0 + u < ns) {
-          Fx += v[u].x;
-          Fy += v[u].y;
-          Tz += v[u].z;
-        }
-      }
+    for (int k = 0; k < DISK_PARTS; ++k) {
+      const double4 d = a.direct[(long long)p * DISK_PARTS + k];
+      Fx += d.x;
+      Fy += d.y;
+      Tz += d.z;
     }
   } else if (have) {
     Fx = s.Fx[p];

@@ -17,10 +17,12 @@ struct Geometry {
 struct DeviceLayout {
   void* f[2];
   ParticleState ps;
-  ParticleTable tab;
-  int* band_off;
-  int* band_ids;
-  double4* partials;
+  // disk tables, double-buffered: the lattice step whose source populations are f[k] reads
+  // tab[k], band_off[k], band_ids[k]; the particle phase after it writes the other copy, so it
+  // can run while the tiles of the same step still read theirs
+  ParticleTable tab[2];
+  int* band_off[2];
+  int* band_ids[2];
   int* err;
   double* J;
   double* w;  // objective weights wfx, wfy, wtz (3 x capacity)
@@ -42,6 +44,7 @@ struct SimView {
   std::string* err;
   AdjointState** adj;
   bool* timing;
+  hipStream_t side;
 };
 
 size_t align_up(size_t v, size_t a);
@@ -54,7 +57,8 @@ std::string describe_device_error(int bits);
 
 SimView sim_view(imb_sim* s);
 LatticeArgs lattice_args(imb_sim* s, const void* src, void* dst);
-ParticleArgs particle_args(imb_sim* s);
+// Particle-phase arguments writing the disk tables of slot out_slot.
+ParticleArgs particle_args(imb_sim* s, int out_slot);
 void enqueue_step(imb_sim* s, const double* wfx, const double* wfy, const double* wtz, double* J);
 int sync_and_check(imb_sim* s);
 int reset_device_error(imb_sim* s);

@@ -68,17 +68,18 @@ size_t layout(const imb_config& c, char* base, DeviceLayout* L) {
   s.nbr = cv.take<int>(mp * NBMAX);
   s.nnbr = cv.take<int>(mp);
   s.rebuild = cv.take<int>(1);
-  d.tab.box = cv.take<int4>(mp);
-  d.tab.pos = cv.take<double4>(mp);
-  d.tab.vel = cv.take<double4>(mp);
-  d.band_off = cv.take<int>((size_t)g.tiles_y + 1);
-  d.band_ids = cv.take<int>(mp * MAXSLOT);
-  d.partials = cv.take<double4>(mp * MAXSLOT);
+  for (int k = 0; k < 2; ++k) {  // tab[0] directly follows the particle state (see set_particles)
+    d.tab[k].box = cv.take<int4>(mp);
+    d.tab[k].pos = cv.take<double4>(mp);
+    d.tab[k].vel = cv.take<double4>(mp);
+    d.band_off[k] = cv.take<int>((size_t)g.tiles_y + 1);
+    d.band_ids[k] = cv.take<int>(mp * MAXSLOT);
+  }
   d.err = cv.take<int>(1);
   d.J = cv.take<double>(1);
   d.w = cv.take<double>(3 * mp);
   d.seed = cv.take<unsigned>(2);
-  d.force = cv.take<double4>(mp);
+  d.force = cv.take<double4>(mp * DISK_PARTS);
   if (L) *L = d;
   return align_up(cv.off, 256);
 }
@@ -159,10 +160,14 @@ struct imb_sim {
   std::string err;
   double* stage = nullptr;  // readback staging (library-owned)
   size_t stage_bytes = 0;
+  // the fluid tiles of a step run on `side` while the disk workgroups and the particle phase run
+  // on `stream`: fork and join events (timing disabled), created by the first imb_step
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool timing = false;
-  std::vector<hipEvent_t> ev_lat, ev_par;  // start/stop pairs
-  double lat_ms = 0, par_ms = 0;
-  int64_t lat_n = 0, par_n = 0;
+  std::vector<hipEvent_t> ev_k[3];  // start/stop pairs: fluid, disk, particle kernels
+  double k_ms[3] = {0, 0, 0};
+  int64_t k_n[3] = {0, 0, 0};
   std::vector<hipEvent_t> ev_pool;
   AdjointState* adj = nullptr;
   // captured step chains: graph[len][start buffer]; len index 0 = 2 steps, 1 = GRAPH_LONG steps
@@ -183,26 +188,28 @@ LatticeArgs lattice_args(imb_sim* s, const void* src, void* dst) {
   a.tau0 = s->cfg.tau0; a.cs = s->cfg.smag_cs; a.gx = s->cfg.gx; a.gy = s->cfg.gy;
   a.rho0 = s->cfg.rho0;
   a.src = src; a.dst = dst;
-  a.np = s->np; a.tab = s->d.tab; a.partials = s->d.partials; a.err = s->d.err;
-  a.band_off = s->d.band_off; a.band_ids = s->d.band_ids;
+  // the tables of the step reading this source (no source: those of the stored state)
+  const int t = src ? (src == s->d.f[1] ? 1 : 0) : s->cur;
+  a.np = s->np; a.tab = s->d.tab[t]; a.err = s->d.err;
+  a.band_off = s->d.band_off[t]; a.band_ids = s->d.band_ids[t];
   a.pstride = std::max(s->cfg.max_particles, 1);
   a.seed = s->d.seed;
-  a.seed_slot = src == s->d.f[1] ? 1 : 0;
+  a.seed_slot = t;
   a.nbr = s->d.ps.nbr;
   a.nnbr = s->d.ps.nnbr;
   a.force = s->d.force;
   return a;
 }
 
-ParticleArgs particle_args(imb_sim* s) {
+ParticleArgs particle_args(imb_sim* s, int out_slot) {
   ParticleArgs a{};
   a.np = s->np; a.nx = s->cfg.nx; a.ny = s->cfg.ny;
   a.walls = (s->cfg.flags & IMB_FLAG_WALLS) ? 1 : 0;
   a.n_sub = s->cfg.n_sub; a.kn = s->cfg.kn; a.zeta = s->cfg.damping_ratio;
   a.rho_s = s->cfg.rho_solid;
   a.tiles_x = s->g.tiles_x; a.tiles_y = s->g.tiles_y; a.tw = s->g.tw; a.th = s->g.th;
-  a.s = s->d.ps; a.tab = s->d.tab; a.partials = s->d.partials; a.err = s->d.err;
-  a.band_off = s->d.band_off; a.band_ids = s->d.band_ids;
+  a.s = s->d.ps; a.tab = s->d.tab[out_slot]; a.err = s->d.err;
+  a.band_off = s->d.band_off[out_slot]; a.band_ids = s->d.band_ids[out_slot];
   a.pstride = std::max(s->cfg.max_particles, 1);
   a.direct = s->d.force;
   a.build_lists = 1;
@@ -220,35 +227,42 @@ static hipEvent_t take_event(imb_sim* s) {
   return e;
 }
 
-// One coupled step: lattice step (eps, collision, streaming, force partials) then the
-// particle phase (forces, DEM, next tile boxes).
+// One coupled step.  The disks' workgroups (covered cells, forces) and then the particle phase
+// (DEM, the next step's tables) run on the simulation's stream while the fluid tiles of the same
+// step run on the side stream; the next step starts once both are done.  With kernel timing on,
+// the three kernels run one after the other on the simulation's stream, each between events.
 void enqueue_step(imb_sim* s, const double* wfx, const double* wfy, const double* wtz,
                   double* J) {
-  LatticeArgs la = lattice_args(s, s->d.f[s->cur], s->d.f[s->cur ^ 1]);
+  const int c = s->cur;
+  LatticeArgs la = lattice_args(s, s->d.f[c], s->d.f[c ^ 1]);
+  ParticleArgs pa = particle_args(s, c ^ 1);
+  pa.do_finalize = 1; pa.do_dem = 1; pa.do_table = 1;
+  pa.wfx = wfx; pa.wfy = wfy; pa.wtz = wtz; pa.J = J;
+  const int st = s->cfg.storage;
   if (s->timing) {
-    hipEvent_t e0 = take_event(s), e1 = take_event(s);
-    hipEventRecord(e0, s->stream);
-    launch_lattice_step(s->cfg.storage, la, s->stream);
-    hipEventRecord(e1, s->stream);
-    s->ev_lat.push_back(e0);
-    s->ev_lat.push_back(e1);
-  } else {
-    launch_lattice_step(s->cfg.storage, la, s->stream);
-  }
-  if (s->np > 0) {
-    ParticleArgs pa = particle_args(s);
-    pa.do_finalize = 1; pa.do_dem = 1; pa.do_table = 1;
-    pa.wfx = wfx; pa.wfy = wfy; pa.wtz = wtz; pa.J = J;
-    if (s->timing) {
+    auto timed = [&](int k, auto&& launch) {
       hipEvent_t e0 = take_event(s), e1 = take_event(s);
       hipEventRecord(e0, s->stream);
-      launch_particle_phase(pa, s->stream);
+      launch();
       hipEventRecord(e1, s->stream);
-      s->ev_par.push_back(e0);
-      s->ev_par.push_back(e1);
-    } else {
-      launch_particle_phase(pa, s->stream);
+      s->ev_k[k].push_back(e0);
+      s->ev_k[k].push_back(e1);
+    };
+    timed(0, [&] { launch_fluid_step(st, la, s->stream); });
+    if (s->np > 0) {
+      timed(1, [&] { launch_disk_step(st, la, s->stream); });
+      timed(2, [&] { launch_particle_phase(pa, s->stream); });
     }
+  } else if (s->np > 0) {
+    hipEventRecord(s->ev_fork, s->stream);
+    hipStreamWaitEvent(s->side, s->ev_fork, 0);
+    launch_fluid_step(st, la, s->side);
+    hipEventRecord(s->ev_join, s->side);
+    launch_disk_step(st, la, s->stream);
+    launch_particle_phase(pa, s->stream);
+    hipStreamWaitEvent(s->stream, s->ev_join, 0);
+  } else {
+    launch_fluid_step(st, la, s->stream);
   }
   s->cur ^= 1;
   s->steps++;
@@ -360,7 +374,7 @@ int create_sim(const imb_config* cfg, const imb_config* layout_cfg, void* hip_st
   if (dev_buf) {
     if (dev_bytes < need || ((uintptr_t)dev_buf & 255)) {
       g_create_error = "bound device buffer too small or not 256-byte aligned";
-      delete s;
+      imb_destroy(s);
       return IMB_ENOMEM;
     }
     s->mem = (char*)dev_buf;
@@ -369,7 +383,8 @@ int create_sim(const imb_config* cfg, const imb_config* layout_cfg, void* hip_st
     hipError_t e = hipMalloc((void**)&s->mem, need);
     if (e != hipSuccess) {
       g_create_error = std::string("hipMalloc: ") + hipGetErrorString(e);
-      delete s;
+      s->mem = nullptr;
+      imb_destroy(s);
       return IMB_ENOMEM;
     }
     s->owns = true;
@@ -414,7 +429,7 @@ int set_tile_shape(imb_sim* s, int tile_w, int tile_rows) {
   s->cfg = c;
   s->g = g;
   if (s->np > 0) {
-    ParticleArgs pa = particle_args(s);
+    ParticleArgs pa = particle_args(s, s->cur);
     pa.do_table = 1;
     launch_particle_phase(pa, s->stream);
   }
@@ -453,9 +468,12 @@ void imb_destroy(imb_sim* s) {
   hipStreamSynchronize(s->stream);
   drop_graphs(s);
   free_adjoint(s);
-  for (auto e : s->ev_lat) hipEventDestroy(e);
-  for (auto e : s->ev_par) hipEventDestroy(e);
+  for (auto& v : s->ev_k)
+    for (auto e : v) hipEventDestroy(e);
   for (auto e : s->ev_pool) hipEventDestroy(e);
+  if (s->ev_fork) hipEventDestroy(s->ev_fork);
+  if (s->ev_join) hipEventDestroy(s->ev_join);
+  if (s->side) hipStreamDestroy(s->side);
   if (s->stage) hipFree(s->stage);
   if (s->owns && s->mem) hipFree(s->mem);
   delete s;
@@ -585,7 +603,7 @@ int imb_set_particles(imb_sim* s, int32_t n, const double* x, const double* y, c
   ParticleState& ps = s->d.ps;
   const size_t mp = (size_t)std::max(s->cfg.max_particles, 1);
   // zero every per-particle array first (DEM caches, forces, lists)
-  launch_fill_zero(ps.x, (char*)(s->d.tab.box) - (char*)ps.x, s->stream);
+  launch_fill_zero(ps.x, (char*)(s->d.tab[0].box) - (char*)ps.x, s->stream);
   (void)mp;
   if (n > 0) {
     const double* src[6] = {x, y, r, vx, vy, om};
@@ -605,7 +623,7 @@ int imb_set_particles(imb_sim* s, int32_t n, const double* x, const double* y, c
     if (e == hipSuccess)
       e = hipMemcpyAsync(ps.rebuild, &one, sizeof(int), hipMemcpyHostToDevice, s->stream);
     if (e != hipSuccess) return hip_fail(&s->err, e, "hipMemcpyAsync");
-    ParticleArgs pa = particle_args(s);
+    ParticleArgs pa = particle_args(s, s->cur);
     pa.init_contacts = 1;
     pa.do_table = 1;
     launch_particle_phase(pa, s->stream);
@@ -620,6 +638,13 @@ int imb_set_particles(imb_sim* s, int32_t n, const double* x, const double* y, c
 
 int imb_step(imb_sim* s, int32_t nsteps) {
   if (!s || nsteps < 0) return IMB_EINVAL;
+  hipError_t e = hipSuccess;
+  if (!s->side) e = hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking);
+  if (e == hipSuccess && !s->ev_fork)
+    e = hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess && !s->ev_join)
+    e = hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming);
+  if (e != hipSuccess) return hip_fail(&s->err, e, "side stream");
   // per-kernel event timing needs the individual launches
   if (!s->use_graphs || s->timing) {
     for (int k = 0; k < nsteps; ++k) enqueue_step(s, nullptr, nullptr, nullptr, nullptr);
@@ -640,7 +665,7 @@ int imb_step(imb_sim* s, int32_t nsteps) {
       for (int k = 0; k < nsteps; ++k) enqueue_step(s, nullptr, nullptr, nullptr, nullptr);
       return launch_check(s, "step");
     }
-    hipError_t e = hipGraphLaunch(ge, s->stream);
+    e = hipGraphLaunch(ge, s->stream);
     if (e != hipSuccess) return hip_fail(&s->err, e, "hipGraphLaunch");
     s->steps += len;  // an even number of steps leaves the buffer parity unchanged
     nsteps -= len;
@@ -781,7 +806,7 @@ int imb_load_state(imb_sim* s, const void* host_buf, size_t bytes) {
   s->np = h.np;
   s->steps = h.steps;
   ParticleState& ps = s->d.ps;
-  launch_fill_zero(ps.x, (char*)(s->d.tab.box) - (char*)ps.x, s->stream);
+  launch_fill_zero(ps.x, (char*)(s->d.tab[0].box) - (char*)ps.x, s->stream);
   hipError_t e = hipMemcpyAsync(s->d.f[0], in, pop, hipMemcpyHostToDevice, s->stream);
   if (e == hipSuccess)
     e = hipMemcpy(s->d.seed, &h.seed, sizeof(unsigned), hipMemcpyHostToDevice);
@@ -805,7 +830,7 @@ int imb_load_state(imb_sim* s, const void* host_buf, size_t bytes) {
   }
   if (e != hipSuccess) return hip_fail(&s->err, e, "load_state copy");
   if (s->np) {
-    ParticleArgs pa = particle_args(s);
+    ParticleArgs pa = particle_args(s, s->cur);
     pa.do_table = 1;
     launch_particle_phase(pa, s->stream);
   }
@@ -819,38 +844,39 @@ int imb_load_state(imb_sim* s, const void* host_buf, size_t bytes) {
 int imb_set_kernel_timing(imb_sim* s, int enable) {
   if (!s) return IMB_EINVAL;
   hipStreamSynchronize(s->stream);
-  for (auto e : s->ev_lat) s->ev_pool.push_back(e);
-  for (auto e : s->ev_par) s->ev_pool.push_back(e);
-  s->ev_lat.clear();
-  s->ev_par.clear();
-  s->lat_ms = s->par_ms = 0;
-  s->lat_n = s->par_n = 0;
+  for (int k = 0; k < 3; ++k) {
+    for (auto e : s->ev_k[k]) s->ev_pool.push_back(e);
+    s->ev_k[k].clear();
+    s->k_ms[k] = 0;
+    s->k_n[k] = 0;
+  }
   s->timing = enable != 0;
   return IMB_OK;
 }
 
-int imb_get_kernel_timing(imb_sim* s, double* lat_ms, int64_t* lat_n, double* par_ms,
-                          int64_t* par_n) {
+int imb_get_kernel_timing(imb_sim* s, double* fluid_ms, int64_t* fluid_n, double* disk_ms,
+                          int64_t* disk_n, double* par_ms, int64_t* par_n) {
   if (!s) return IMB_EINVAL;
   hipError_t e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) return hip_fail(&s->err, e, "hipStreamSynchronize");
-  auto drain = [&](std::vector<hipEvent_t>& v, double& ms, int64_t& n) {
-    for (size_t k = 0; k + 1 < v.size(); k += 2) {
+  for (int k = 0; k < 3; ++k) {
+    std::vector<hipEvent_t>& v = s->ev_k[k];
+    for (size_t i = 0; i + 1 < v.size(); i += 2) {
       float t = 0;
-      hipEventElapsedTime(&t, v[k], v[k + 1]);
-      ms += t;
-      n += 1;
-      s->ev_pool.push_back(v[k]);
-      s->ev_pool.push_back(v[k + 1]);
+      hipEventElapsedTime(&t, v[i], v[i + 1]);
+      s->k_ms[k] += t;
+      s->k_n[k] += 1;
+      s->ev_pool.push_back(v[i]);
+      s->ev_pool.push_back(v[i + 1]);
     }
     v.clear();
-  };
-  drain(s->ev_lat, s->lat_ms, s->lat_n);
-  drain(s->ev_par, s->par_ms, s->par_n);
-  if (lat_ms) *lat_ms = s->lat_ms;
-  if (lat_n) *lat_n = s->lat_n;
-  if (par_ms) *par_ms = s->par_ms;
-  if (par_n) *par_n = s->par_n;
+  }
+  double* ms[3] = {fluid_ms, disk_ms, par_ms};
+  int64_t* n[3] = {fluid_n, disk_n, par_n};
+  for (int k = 0; k < 3; ++k) {
+    if (ms[k]) *ms[k] = s->k_ms[k];
+    if (n[k]) *n[k] = s->k_n[k];
+  }
   return IMB_OK;
 }
 

@@ -5,7 +5,10 @@
 
 namespace imb {
 
-// fused lattice step (step.hip)
+// lattice step (step.hip): the disks' covered cells and forces, the tiles' uncovered cells, and
+// both in that order on one stream
+void launch_disk_step(int storage, const LatticeArgs& a, hipStream_t s);
+void launch_fluid_step(int storage, const LatticeArgs& a, hipStream_t s);
 void launch_lattice_step(int storage, const LatticeArgs& a, hipStream_t s);
 void launch_solid_field(int storage, const LatticeArgs& a, double* eps_out, hipStream_t s);
 

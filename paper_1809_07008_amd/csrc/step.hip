@@ -1,21 +1,21 @@
-// step.hip -- the lattice step (disk_block.h: uncovered cells by tiles, covered cells by their
-// disks' workgroups) and the solid-ratio diagnostic kernel.
+// step.hip -- the lattice step as two kernels (disk_block.h): the covered cells and each disk's
+// force by the disks' workgroups, the uncovered cells by the tiles.  They write disjoint cells and
+// read only the source populations and the step's disk tables, so they may run concurrently.
 #include "disk_block.h"
-#include "lattice_tile.h"
 #include "step.h"
 
 namespace imb {
 
-// Workgroups [0, np) are the disks' (covered cells, own force and torque), the rest the tiles'
-// (uncovered cells); the disks' longer work is dispatched first.
+// One workgroup per disk: its covered cells and its own force and torque.
 template <class St>
-__global__ __launch_bounds__(BLOCK) void k_lattice_step(LatticeArgs a) {
-  const int b = blockIdx.x;
-  if (b < a.np) {
-    disk_cells<St>(a, b);
-    return;
-  }
-  fluid_tile<St>(a, xcd_remap(b - a.np, a.tiles_x * a.tiles_y));
+__global__ __launch_bounds__(BLOCK) void k_disk_step(LatticeArgs a) {
+  disk_cells<St>(a, blockIdx.x / DISK_PARTS, blockIdx.x % DISK_PARTS);
+}
+
+// One workgroup per tile: the cells no disk covers.
+template <class St>
+__global__ __launch_bounds__(BLOCK) void k_fluid_step(LatticeArgs a) {
+  fluid_tile<St>(a, xcd_remap(blockIdx.x, a.tiles_x * a.tiles_y));
 }
 
 // eps_tot of every cell (diagnostic / parity of the solid-ratio stage alone).
@@ -43,17 +43,34 @@ __global__ __launch_bounds__(BLOCK) void k_solid_field(LatticeArgs a, double* ep
 }
 
 template <class St>
-void launch_lattice_step_t(const LatticeArgs& a, hipStream_t s) {
-  const int tiles = a.tiles_x * a.tiles_y;
-  hipLaunchKernelGGL(k_lattice_step<St>, dim3(tiles + a.np), dim3(BLOCK), 0, s, a);
+void launch_disk_step_t(const LatticeArgs& a, hipStream_t s) {
+  if (a.np > 0) hipLaunchKernelGGL(k_disk_step<St>, dim3(a.np * DISK_PARTS), dim3(BLOCK), 0, s, a);
+}
+
+template <class St>
+void launch_fluid_step_t(const LatticeArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_fluid_step<St>, dim3(a.tiles_x * a.tiles_y), dim3(BLOCK), 0, s, a);
+}
+
+void launch_disk_step(int storage, const LatticeArgs& a, hipStream_t s) {
+  switch (storage) {
+    case IMB_STORAGE_F64: launch_disk_step_t<StoreF64>(a, s); break;
+    case IMB_STORAGE_F32: launch_disk_step_t<StoreF32>(a, s); break;
+    default: launch_disk_step_t<StoreF16>(a, s); break;
+  }
+}
+
+void launch_fluid_step(int storage, const LatticeArgs& a, hipStream_t s) {
+  switch (storage) {
+    case IMB_STORAGE_F64: launch_fluid_step_t<StoreF64>(a, s); break;
+    case IMB_STORAGE_F32: launch_fluid_step_t<StoreF32>(a, s); break;
+    default: launch_fluid_step_t<StoreF16>(a, s); break;
+  }
 }
 
 void launch_lattice_step(int storage, const LatticeArgs& a, hipStream_t s) {
-  switch (storage) {
-    case IMB_STORAGE_F64: launch_lattice_step_t<StoreF64>(a, s); break;
-    case IMB_STORAGE_F32: launch_lattice_step_t<StoreF32>(a, s); break;
-    default: launch_lattice_step_t<StoreF16>(a, s); break;
-  }
+  launch_disk_step(storage, a, s);
+  launch_fluid_step(storage, a, s);
 }
 
 void launch_solid_field(int storage, const LatticeArgs& a, double* eps_out, hipStream_t s) {

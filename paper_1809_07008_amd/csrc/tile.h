@@ -81,13 +81,11 @@ __device__ int build_tile_list(const LatticeArgs& a, int tx, int ty, PEntry<T>* 
 }
 
 // Per-thread scratch of a tile in LDS (indexed [k][thread] so a wave touches 64 distinct
-// banks): the disks covering the current cell and the thread's running force sums.
+// banks): the disks covering the current cell.
 template <class T>
 struct CellScratch {
   int cj[MAXC][BLOCK];     // list entries of the disks covering the current cell
   T ce[MAXC][BLOCK];       // their eps
-  int aj[MAXC][BLOCK];     // list entries owning the thread's accumulators (-1: free)
-  T af[3][MAXC][BLOCK];    // accumulated force x, y and torque
 };
 
 template <class T>
@@ -126,41 +124,6 @@ __device__ inline int covering_disks(const LatticeArgs& a, const PEntry<T>* pl, 
         atomicOr(a.err, ERR_CELL);
       }
     }
-  }
-  return nc;
-}
-
-// Disks whose image nearest to cell (x, y) reaches the cell, classified with the cheap tests of
-// solid_fraction: inside cells get eps = 1 now; cut cells are appended to the tile's queue
-// (owner thread, slot, disk) and get their exact area from the whole block afterwards, so the
-// expensive branch runs on densely packed lanes.  Returns the count.
-template <class T>
-__device__ inline int classify_cell(const LatticeArgs& a, const PEntry<T>* pl, int n, int x, int y,
-                                    CellScratch<T>& cs, int* s_qn, int* s_q) {
-  const int tid = threadIdx.x;
-  int nc = 0;
-  for (int j = 0; j < n; ++j) {
-    T dx, dy;
-    lever_arm(a, pl[j], x, y, &dx, &dy);
-    const T r = pl[j].r;
-    const T x0 = dx - T(0.5), x1 = dx + T(0.5), y0 = dy - T(0.5), y1 = dy + T(0.5);
-    const T nx = x0 > T(0) ? x0 : (x1 < T(0) ? x1 : T(0));
-    const T ny = y0 > T(0) ? y0 : (y1 < T(0) ? y1 : T(0));
-    if (nx * nx + ny * ny >= r * r) continue;
-    if (nc >= MAXC) {
-      atomicOr(a.err, ERR_CELL);
-      continue;
-    }
-    const T fx = fabs(x0) > fabs(x1) ? fabs(x0) : fabs(x1);
-    const T fy = fabs(y0) > fabs(y1) ? fabs(y0) : fabs(y1);
-    cs.cj[nc][tid] = j;
-    if (fx * fx + fy * fy <= r * r) {
-      cs.ce[nc][tid] = T(1);
-    } else {
-      const int q = atomicAdd(s_qn, 1);
-      s_q[q] = tid | (nc << 8) | (j << 10);
-    }
-    ++nc;
   }
   return nc;
 }

@@ -1,7 +1,9 @@
 // TEST INFRASTRUCTURE: runtime and launcher of the CPU emulation (see hip/hip_runtime.h).
 #include "hip/hip_runtime.h"
-#include <cstdio>
+
 #include <condition_variable>
+#include <cstdio>
+#include <deque>
 #include <memory>
 #include <mutex>
 
@@ -143,19 +145,60 @@ hipError_t hipMalloc(void** p, size_t n) {
 hipError_t hipFree(void* p) { std::free(p); return hipSuccess; }
 hipError_t hipMemcpy(void* d, const void* s, size_t n, hipMemcpyKind) { std::memmove(d, s, n); return hipSuccess; }
 hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind k, hipStream_t) { return hipMemcpy(d, s, n, k); }
-hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
-struct emu_stream { int x; };
-hipError_t hipStreamCreateWithFlags(hipStream_t* s, unsigned) { *s = new emu_stream{0}; return hipSuccess; }
-hipError_t hipStreamDestroy(hipStream_t s) { delete s; return hipSuccess; }
+struct emu_stream {
+  std::deque<std::function<void()>> pending;  // deferred launches, in order
+  long long queued = 0, done = 0;
+};
+static void emu_flush(hipStream_t s, long long upto) {
+  while (s && s->done < upto && !s->pending.empty()) {
+    std::function<void()> f = std::move(s->pending.front());
+    s->pending.pop_front();
+    ++s->done;
+    f();
+  }
+}
+void emu_launch_on(hipStream_t st, dim3 grid, dim3 block, size_t shmem,
+                   const std::function<void()>& body) {
+  if (!st) {
+    emu_launch(grid, block, shmem, body);
+    return;
+  }
+  st->pending.push_back([=]() { emu_launch(grid, block, shmem, body); });
+  ++st->queued;
+}
+hipError_t hipStreamSynchronize(hipStream_t s) {
+  if (s) emu_flush(s, s->queued);
+  return hipSuccess;
+}
+hipError_t hipStreamCreateWithFlags(hipStream_t* s, unsigned) { *s = new emu_stream{}; return hipSuccess; }
+hipError_t hipStreamDestroy(hipStream_t s) {
+  if (s) emu_flush(s, s->queued);
+  delete s;
+  return hipSuccess;
+}
 hipError_t hipStreamBeginCapture(hipStream_t, hipStreamCaptureMode) { return hipErrorNotSupported; }
 hipError_t hipStreamEndCapture(hipStream_t, hipGraph_t*) { return hipErrorNotSupported; }
 hipError_t hipGraphInstantiate(hipGraphExec_t*, hipGraph_t, void*, char*, size_t) { return hipErrorNotSupported; }
 hipError_t hipGraphDestroy(hipGraph_t) { return hipSuccess; }
 hipError_t hipGraphExecDestroy(hipGraphExec_t) { return hipSuccess; }
 hipError_t hipGraphLaunch(hipGraphExec_t, hipStream_t) { return hipErrorNotSupported; }
-struct emu_event { std::chrono::steady_clock::time_point t; };
+struct emu_event {
+  std::chrono::steady_clock::time_point t;
+  hipStream_t st = nullptr;  // deferring stream it was recorded on, and its launch count then
+  long long mark = 0;
+};
 hipError_t hipEventCreate(hipEvent_t* e) { *e = new emu_event{}; return hipSuccess; }
-hipError_t hipEventRecord(hipEvent_t e, hipStream_t) { e->t = std::chrono::steady_clock::now(); return hipSuccess; }
+hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned) { *e = new emu_event{}; return hipSuccess; }
+hipError_t hipEventRecord(hipEvent_t e, hipStream_t s) {
+  e->t = std::chrono::steady_clock::now();
+  e->st = s;
+  e->mark = s ? s->queued : 0;
+  return hipSuccess;
+}
+hipError_t hipStreamWaitEvent(hipStream_t, hipEvent_t e, unsigned) {
+  emu_flush(e->st, e->mark);
+  return hipSuccess;
+}
 hipError_t hipEventElapsedTime(float* ms, hipEvent_t a, hipEvent_t b) {
   *ms = std::chrono::duration<float, std::milli>(b->t - a->t).count(); return hipSuccess; }
 hipError_t hipEventDestroy(hipEvent_t e) { delete e; return hipSuccess; }

@@ -112,6 +112,7 @@ typedef struct emu_graph_exec* hipGraphExec_t;
 enum hipMemcpyKind { hipMemcpyHostToHost, hipMemcpyHostToDevice, hipMemcpyDeviceToHost,
                      hipMemcpyDeviceToDevice, hipMemcpyDefault };
 enum { hipStreamNonBlocking = 1 };
+enum { hipEventDisableTiming = 2 };
 enum hipStreamCaptureMode { hipStreamCaptureModeGlobal, hipStreamCaptureModeThreadLocal };
 enum hipDeviceAttribute_t { hipDeviceAttributeMultiprocessorCount, hipDeviceAttributeWallClockRate };
 hipError_t hipMalloc(void** p, size_t n);
@@ -129,6 +130,8 @@ hipError_t hipGraphDestroy(hipGraph_t);
 hipError_t hipGraphExecDestroy(hipGraphExec_t);
 hipError_t hipGraphLaunch(hipGraphExec_t, hipStream_t);
 hipError_t hipEventCreate(hipEvent_t*);
+hipError_t hipEventCreateWithFlags(hipEvent_t*, unsigned);
+hipError_t hipStreamWaitEvent(hipStream_t, hipEvent_t, unsigned);
 hipError_t hipEventRecord(hipEvent_t, hipStream_t);
 hipError_t hipEventElapsedTime(float*, hipEvent_t, hipEvent_t);
 hipError_t hipEventDestroy(hipEvent_t);
@@ -138,5 +141,12 @@ hipError_t hipDeviceGetAttribute(int*, hipDeviceAttribute_t, int);
 template <class K> inline hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int* n, K, int, size_t) { *n = 1; return hipSuccess; }
 
 void emu_launch(dim3 grid, dim3 block, size_t shmem, const std::function<void()>& body);
+// A launch on a stream the library created (hipStreamCreateWithFlags) is deferred: it runs only
+// when another stream waits for an event recorded after it, or that stream is synchronised or
+// destroyed.  Work such a stream overlaps with on the GPU thus runs after, not before, what the
+// other stream queued meanwhile -- the order the GPU is least likely to produce, which exposes a
+// missing dependency.  Launches on the caller's stream run at once.
+void emu_launch_on(hipStream_t st, dim3 grid, dim3 block, size_t shmem,
+                   const std::function<void()>& body);
 #define hipLaunchKernelGGL(kernel, grid, block, shmem, stream, ...) \
-  emu_launch(dim3(grid), dim3(block), (size_t)(shmem), [=]() { kernel(__VA_ARGS__); })
+  emu_launch_on(stream, dim3(grid), dim3(block), (size_t)(shmem), [=]() { kernel(__VA_ARGS__); })
