@@ -205,8 +205,8 @@ int imb_get_adjoint_timing(imb_sim* sim, double* forward_ms, double* reverse_ms,
  * captured once per (nsteps, buffer parity) in a hipGraph and replayed.  Inside the kernel the
  * channels are split into two halves of about equal tile counts; every step is two phases
  * separated by grid-wide barriers (lattice tiles of one half while the particle phases of the
- * other half run), with workgroups pulling work items (a channel's particle phase, or one
- * (channel, tile)) from an atomic counter.
+ * other half run), with workgroups pulling work items (a channel's particle phase, a chunk of
+ * (channel, disk) items or a chunk of (channel, tile) items) from an atomic counter.
  * The method per channel is the coupled step of imb_step (Sec. 2; Eqs. 1-2, 12-17), and a
  * channel evolves bit for bit as the same channel would alone with the same tile shape.
  * Limits: 1..128 channels, F32 storage, at most 256 disks and ny <= 2559 per channel

@@ -10,9 +10,10 @@
 // finalisation, DEM, disk tables) thus always runs while the other half streams its lattice, so
 // the one-workgroup DEM never idles the grid, and every dependency (tiles of a step -> that
 // step's particle phase -> the next step's tiles) crosses at least one barrier.  Inside a phase
-// the workgroups pull work items from an atomic counter: the half's particle phases first (the
-// long items), then its (channel, disk) items (a disk's covered cells and force), then its
-// (channel, tile) items (the uncovered cells), each in channel order.
+// the workgroups pull tickets from an atomic counter: the half's particle phases first (the
+// long items), then chunks of DISK_CHUNK (channel, disk) items (a disk's covered cells and
+// force), then chunks of TILE_CHUNK (channel, tile) items (the uncovered cells), each in channel
+// order; chunking keeps the number of increments of the one counter small.
 //
 // The persistent grid is sized to the number of co-resident workgroups; every wait is bounded
 // (a barrier that does not open within the time limit sets an abort flag that every workgroup
@@ -36,6 +37,8 @@ namespace imb {
 constexpr int MAX_BATCH = 128;   // channels per batch
 constexpr int PP_LDS = 1280;     // doubles of particle-phase scratch: 256 disks x 5
 constexpr int SYNC_WORDS = 8;    // [0] arrivals [1] generation [2],[3] item counters [4] abort
+constexpr int TILE_CHUNK = 8;    // consecutive tiles taken with one atomic increment
+constexpr int DISK_CHUNK = 2;    // consecutive disks taken with one atomic increment
 
 // Arguments of one channel for a step reading buffer k (la[k]: buffer k to buffer k ^ 1 with the
 // disk tables of slot k; pa[k]: that step's particle phase, writing the tables of slot k ^ 1).
@@ -140,6 +143,10 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs B) {
     const bool lat = p < 2 * B.nsteps;
     const int ndisk = lat ? hd[h] : 0;
     const int nlat = lat ? ht[h] : 0;
+    // tickets: one per particle phase, one per DISK_CHUNK disks, one per TILE_CHUNK tiles
+    const int ndc = (ndisk + DISK_CHUNK - 1) / DISK_CHUNK;
+    const int ntc = (nlat + TILE_CHUNK - 1) / TILE_CHUNK;
+    const int par = (B.parity0 + n) & 1;
     unsigned* ctr = &B.sync[2 + (p & 1)];
     for (;;) {
       __syncthreads();
@@ -149,23 +156,28 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs B) {
       }
       __syncthreads();
       const int i = s_item;
-      if (s_abort || i >= npart + ndisk + nlat) break;
+      if (s_abort || i >= npart + ndc + ntc) break;
       if (i < npart) {  // the particle phase of step n (half B: of step n - 1)
         const int m = h == 1 ? n : n - 1;
         particle_phase<BLOCK>(B.ch[s_hch[ph][i]].pa[(B.parity0 + m) & 1], pp_lds);
         continue;
       }
-      const bool is_disk = i < npart + ndisk;
-      const int t = is_disk ? i - npart : i - npart - ndisk;
-      const int k = find_slot(is_disk ? s_hdpref[h] : s_hpref[h], hn[h], t);
-      const LatticeArgs la = B.ch[s_hch[h][k]].la[(B.parity0 + n) & 1];
-      if (is_disk) {
-        for (int part = 0; part < DISK_PARTS; ++part) {  // the bands of one disk in order
-          if (part > 0) __syncthreads();
-          disk_cells<StoreF32>(la, t - s_hdpref[h][k], part);
+      const bool is_disk = i < npart + ndc;
+      const int chunk = is_disk ? DISK_CHUNK : TILE_CHUNK;
+      const int c0 = (is_disk ? i - npart : i - npart - ndc) * chunk;
+      const int c1 = min(c0 + chunk, is_disk ? ndisk : nlat);
+      for (int t = c0; t < c1; ++t) {  // the chunk's items in order (block-uniform bounds)
+        if (t > c0) __syncthreads();   // the previous item's LDS is no longer read
+        const int k = find_slot(is_disk ? s_hdpref[h] : s_hpref[h], hn[h], t);
+        const LatticeArgs la = B.ch[s_hch[h][k]].la[par];
+        if (is_disk) {
+          for (int part = 0; part < DISK_PARTS; ++part) {  // the bands of one disk in order
+            if (part > 0) __syncthreads();
+            disk_cells<StoreF32>(la, t - s_hdpref[h][k], part);
+          }
+        } else {
+          fluid_tile<StoreF32>(la, t - s_hpref[h][k]);
         }
-      } else {
-        fluid_tile<StoreF32>(la, t - s_hpref[h][k]);
       }
     }
     if (p + 1 < nphase && !grid_barrier(B.sync, B.nblocks, 2 + (p & 1), B.spin_ticks)) return;

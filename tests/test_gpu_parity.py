@@ -234,18 +234,24 @@ def test_fp32_full_size_against_oracle():
 
 
 def test_graph_replays_match_direct_launches():
-    """imb_step replays captured graphs (2- and 32-step chains); each replay, with readbacks and
-    syncs in between, must equal direct kernel launches bit for bit."""
+    """imb_step replays captured graphs (2- and 32-step chains) in which the fluid tiles run on a
+    second stream beside the disk and particle kernels; each replay, with readbacks and syncs in
+    between, must equal direct two-stream launches and the one-stream sequence of kernel timing
+    bit for bit."""
     case = W.moving_disks(seed=4, nx=320, ny=160, n=14, storage="f32")
-    g, d = gpu_for(case), gpu_for(case)
+    g, d, t = gpu_for(case), gpu_for(case), gpu_for(case)
     d.set_graphs(False)
+    t.set_kernel_timing(True)
     for n in (37, 2, 33, 1, 64):
-        g.step(n)
-        d.step(n)
-        assert np.array_equal(g.populations(), d.populations())
-        for a, b in zip(g.forces() + g.particles(), d.forces() + d.particles()):
-            assert np.array_equal(a, b)
-    assert g.counts() == d.counts() == (14, 137)
+        for s in (g, d, t):
+            s.step(n)
+        for o in (d, t):
+            assert np.array_equal(g.populations(), o.populations())
+            for a, b in zip(g.forces() + g.particles(), o.forces() + o.particles()):
+                assert np.array_equal(a, b)
+    assert g.counts() == d.counts() == t.counts() == (14, 137)
+    kt = t.kernel_timing()
+    assert kt["fluid_launches"] == kt["disk_launches"] == kt["particle_launches"] == 137
 
 
 def test_dense_channel_fp64_parity_and_determinism():
