@@ -3,8 +3,9 @@
 Workload: 2048x1024 channel, 500 moving disks (diameters U[16, 24]), Smagorinsky C_s = 0.1,
 tau 0.55, linear spring-dashpot DEM, FP32 deviation storage, seeded synthetic input (seed 0).
 One "step" is one full coupled step: solid ratio, IMB collision + streaming, force/torque sums,
-DEM update.  Prints one JSON line (throughput in MLUPS, HBM roofline of the fluid-tile kernel,
-the CPU oracle's throughput on the same workload).
+DEM update, all in one kernel launch.  Prints one JSON line (throughput in MLUPS, HBM roofline of
+the step kernel, the adjoint/forward time ratio, the CPU oracle's throughput on the same
+workload).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -22,12 +23,13 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 CSRC = os.path.join(ROOT, "paper_1809_07008_amd", "csrc")
-LATTICE_SOURCES = ("step.hip", "disk_block.h", "tile.h", "collide.h", "solid.h", "common.h")
-COUNTERS = os.path.join(ROOT, "profiles", "k_fluid_step_2048x1024_n500_counters.txt")
+LATTICE_SOURCES = ("step.hip", "disk_block.h", "particle_phase.h", "tile.h", "collide.h",
+                   "solid.h", "common.h")
+COUNTERS = os.path.join(ROOT, "profiles", "k_step_2048x1024_n500_counters.txt")
 
 
 def lattice_source_hash() -> str:
-    """sha256 over the sources the lattice-step kernels are compiled from."""
+    """sha256 over the sources the step kernel is compiled from."""
     import hashlib
     h = hashlib.sha256()
     for name in LATTICE_SOURCES:
@@ -37,7 +39,7 @@ def lattice_source_hash() -> str:
 
 
 def measured_traffic(storage: str, tile) -> float | None:
-    """HBM-side bytes per fluid-tile kernel launch from the committed rocprofv3 counter summary
+    """HBM-side bytes per step-kernel launch from the committed rocprofv3 counter summary
     (FETCH_SIZE + WRITE_SIZE, each scaled by what the counter reads for a copy kernel of known
     size), or None when the summary is missing, was taken for another storage format or tile,
     or the kernel's sources have changed since."""
@@ -98,10 +100,8 @@ def adjoint_ratio(tile, reps: int = 3):
                                        max(kk["adjoint_kernels"], 1), 2),
             "recompute_kernel_us": round(kk["recompute_kernel_ms"] * 1e3 /
                                          max(kk["recompute_kernels"], 1), 2),
-            "forward_lattice_kernels_us": round((kt["fluid_ms"] + kt["disk_ms"]) * 1e3 /
-                                                max(kt["fluid_launches"], 1), 2),
-            "forward_particle_kernel_us": round(kt["particle_ms"] * 1e3 /
-                                                max(kt["particle_launches"], 1), 2)}
+            "forward_step_kernel_us": round(kt["step_ms"] * 1e3 / max(kt["step_launches"], 1),
+                                            2)}
 
 
 def copy_calibration(nbytes: int, reps: int = 10) -> int:
@@ -157,9 +157,11 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storage", default="f32", choices=["f64", "f32", "f16"])
-    ap.add_argument("--tile-w", type=int, default=32)
-    ap.add_argument("--tile-rows", type=int, default=2)
+    ap.add_argument("--tile-w", type=int, default=64)
+    ap.add_argument("--tile-rows", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint/forward ratio (profiling the forward step alone)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch kernels directly instead of replaying captured graphs")
@@ -201,37 +203,23 @@ def main(argv=None):
     print("bench: %d steps %.3f ms/step %.1f MLUPS" % (args.steps, ms_per_step, mlups),
           file=sys.stderr, flush=True)
 
-    # per-kernel durations with HIP events on the simulation's stream (same K steps again, the
-    # three kernels of a step one after the other)
-    eps0 = sim.solid_field()
+    # step-kernel duration with HIP events on the simulation's stream (same K steps again)
     sim.set_kernel_timing(True)
     sim.step(args.steps)
     kt = sim.kernel_timing()
     sim.set_kernel_timing(False)
-    eps1 = sim.solid_field()
-    # cells the fluid-tile kernel updates: those no disk covers (eps > 0 marks a covered cell),
-    # averaged over the start and end of the timed steps
-    covered = 0.5 * (float((eps0 > 0).sum()) + float((eps1 > 0).sum()))
-    fluid_ms = kt["fluid_ms"] / max(kt["fluid_launches"], 1)
-    disk_ms = kt["disk_ms"] / max(kt["disk_launches"], 1)
-    par_ms = kt["particle_ms"] / max(kt["particle_launches"], 1)
+    step_kernel_ms = kt["step_ms"] / max(kt["step_launches"], 1)
     bpl = bytes_per_lup(args.storage)
-    fluid_bytes = int(round((case.cells - covered) * bpl))
-    achieved = fluid_bytes / (fluid_ms * 1e-3) / 1e9
+    step_bytes = case.cells * bpl
+    achieved = step_bytes / (step_kernel_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(args.storage, (args.tile_w, args.tile_rows)),
                 "kernel_source_sha256": lattice_source_hash(),
-                "kernel": "k_fluid_step<%s>" % {"f64": "StoreF64", "f32": "StoreF32",
-                                                "f16": "StoreF16"}[args.storage],
-                "kernel_avg_us": round(fluid_ms * 1e3, 2),
-                "bytes_per_launch": fluid_bytes,
-                "cells_per_launch": int(round(case.cells - covered)),
-                "disk_kernel_avg_us": round(disk_ms * 1e3, 2),
-                "covered_cells": int(round(covered)),
-                "particle_phase_avg_us": round(par_ms * 1e3, 2),
-                "lattice_kernels_frac": round(case.cells * bpl / ((fluid_ms + disk_ms) * 1e-3)
-                                              / 1e9 / HBM_PEAK_GBS, 4)}
+                "kernel": "k_step<%s>" % {"f64": "StoreF64", "f32": "StoreF32",
+                                          "f16": "StoreF16"}[args.storage],
+                "kernel_avg_us": round(step_kernel_ms * 1e3, 2),
+                "bytes_per_launch": step_bytes}
 
     out = {
         "metric": "MLUPS & % of HBM roofline, D2Q9 IMB 2048x1024; adjoint/forward time ratio",
@@ -253,8 +241,9 @@ def main(argv=None):
         "hbm_frac_whole_step": round(mlups * 1e6 * bpl / (HBM_PEAK_GBS * 1e9), 4),
         "roofline": roofline,
     }
-    out["adjoint"] = adjoint_ratio((args.tile_w, args.tile_rows))
-    print("bench: adjoint ratio %.3f" % out["adjoint"]["ratio"], file=sys.stderr, flush=True)
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_ratio((args.tile_w, args.tile_rows))
+        print("bench: adjoint ratio %.3f" % out["adjoint"]["ratio"], file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(out), flush=True)

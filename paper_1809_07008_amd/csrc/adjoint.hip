@@ -579,23 +579,20 @@ extern "C" int imb_adjoint(imb_sim* sim, int32_t nsteps, int32_t k, const double
     la.band_ids = tn.bids;
     la.nbr = tn.nbr;
     la.nnbr = tn.nnbr;
-    launch_lattice_step(cfg.storage, la, st);
-    if (np > 0) {
-      const TableSlot tn1 = table_slot(v, A, n + 1);
-      ParticleArgs pa = particle_args(sim, 0);  // writes the history slot instead
-      pa.do_finalize = 1;
-      pa.do_dem = 1;
-      pa.do_table = 1;
-      pa.tab = tn1.tab;
-      pa.band_off = tn1.boff;
-      pa.band_ids = tn1.bids;
-      pa.wfx = wd[0];
-      pa.wfy = wd[1];
-      pa.wtz = wd[2];
-      pa.J = d.J;
-      launch_particle_phase(pa, st);
-      copy_lists(v, tn1.nbr, tn1.nnbr, d.ps.nbr, d.ps.nnbr, st);
-    }
+    const TableSlot tn1 = table_slot(v, A, n + 1);
+    ParticleArgs pa = particle_args(sim, 0);  // writes the history slot instead
+    pa.do_finalize = 1;
+    pa.do_dem = 1;
+    pa.do_table = 1;
+    pa.tab = tn1.tab;
+    pa.band_off = tn1.boff;
+    pa.band_ids = tn1.bids;
+    pa.wfx = wd[0];
+    pa.wfy = wd[1];
+    pa.wtz = wd[2];
+    pa.J = d.J;
+    launch_step(cfg.storage, la, pa, true, st);
+    if (np > 0) copy_lists(v, tn1.nbr, tn1.nnbr, d.ps.nbr, d.ps.nnbr, st);
     src = dst;
   }
   hipEventRecord(A->ev[1], st);
@@ -640,7 +637,7 @@ extern "C" int imb_adjoint(imb_sim* sim, int32_t nsteps, int32_t k, const double
       la.band_ids = tn.bids;
       la.nbr = tn.nbr;
       la.nnbr = tn.nnbr;
-      timed(false, [&] { launch_lattice_step(cfg.storage, la, st); });
+      timed(false, [&] { launch_step(cfg.storage, la, ParticleArgs{}, false, st); });
       if (timing) kind.push_back(0);
       rs = dst;
     }

@@ -36,6 +36,7 @@ namespace imb {
 
 constexpr int MAX_BATCH = 128;   // channels per batch
 constexpr int PP_LDS = 1280;     // doubles of particle-phase scratch: 256 disks x 5
+constexpr int BATCH_MAX_DISKS = 256;
 constexpr int SYNC_WORDS = 8;    // [0] arrivals [1] generation [2],[3] item counters [4] abort
 constexpr int TILE_CHUNK = 8;    // consecutive tiles taken with one atomic increment
 constexpr int DISK_CHUNK = 2;    // consecutive disks taken with one atomic increment
@@ -171,10 +172,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs B) {
         const int k = find_slot(is_disk ? s_hdpref[h] : s_hpref[h], hn[h], t);
         const LatticeArgs la = B.ch[s_hch[h][k]].la[par];
         if (is_disk) {
-          for (int part = 0; part < DISK_PARTS; ++part) {  // the bands of one disk in order
-            if (part > 0) __syncthreads();
-            disk_cells<StoreF32>(la, t - s_hdpref[h][k], part);
-          }
+          disk_cells<StoreF32>(la, t - s_hdpref[h][k]);
         } else {
           fluid_tile<StoreF32>(la, t - s_hpref[h][k]);
         }
@@ -239,7 +237,7 @@ int validate_batch(int32_t nsim, const imb_config* cfgs, std::string* why) {
       *why = "channel " + std::to_string(c) + ": batched channels use F32 storage";
       return IMB_EUNSUPPORTED;
     }
-    if (cfgs[c].max_particles > BLOCK) {
+    if (cfgs[c].max_particles > BATCH_MAX_DISKS) {
       *why = "channel " + std::to_string(c) + ": at most 256 disks per batched channel";
       return IMB_EINVAL;
     }
@@ -676,8 +674,8 @@ int imb_batch_autotune(imb_batch* b, int32_t trial_steps, double* trial_ms, int3
       *v.steps = sim_steps0[c];
     }
   };
-  static const int shapes[][2] = {{32, 1}, {32, 2}, {32, 4}, {64, 1}, {64, 2}, {64, 4},
-                                  {128, 1}, {128, 2}, {16, 4}};
+  static const int shapes[][2] = {{32, 1}, {32, 2}, {64, 1}, {64, 2}, {64, 4}, {128, 1},
+                                  {128, 2}, {16, 1}, {16, 2}};
   const int nshapes = (int)(sizeof shapes / sizeof shapes[0]);
   double best = 1e300;
   int bw = b->tile_w, br = b->tile_rows, bg = b->grid_user;

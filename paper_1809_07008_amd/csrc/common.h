@@ -13,7 +13,7 @@
 namespace imb {
 
 constexpr int NQ = 9;              // D2Q9
-constexpr int BLOCK = 256;         // threads of a lattice-step workgroup (4 wave64)
+constexpr int BLOCK = 512;         // threads of a lattice-step workgroup (8 wave64)
 constexpr int WAVES = BLOCK / 64;
 constexpr int LMAX = 32;           // disks whose boxes may touch one tile
 constexpr int MAXC = 4;            // disks covering one cell (three cannot unless they overlap)
@@ -22,7 +22,6 @@ constexpr int MAX_BANDS = 6144;    // tile rows (bands) of one lattice
 constexpr int NBMAX = 32;          // DEM neighbour-list capacity per disk
 constexpr int MAX_PARTICLES = 512;
 constexpr int PBLOCK = 512;        // threads of the particle-phase workgroup (one per disk)
-constexpr int DISK_PARTS = 1;      // row bands of a disk's box, one workgroup each
 constexpr double DEM_SKIN = 5.0;   // neighbour-list skin (lattice units)
 constexpr double MAX_MOVE = 1.0;   // largest displacement of a disk in one lattice step
 constexpr float F16_SCALE = 16384.0f;  // power-of-two scale of FP16 deviations
@@ -81,8 +80,8 @@ struct LatticeArgs {
   int seed_slot;         //   seed[seed_slot], tile 0 writes seed[seed_slot ^ 1] = it + 1
   const int* nbr;        // [np][NBMAX] neighbour lists (ascending ids) and their lengths
   const int* nnbr;
-  double4* force;        // [np][DISK_PARTS] force and torque of this step (Fx, Fy, Tz, 0) per
-                         //   band of the disk's box
+  double4* force;        // [np] force and torque of this step (Fx, Fy, Tz, 0)
+  unsigned* done;        // disk workgroups finished in the running step kernel (0 between launches)
 };
 
 // Particle state on the device (structure of arrays, FP64).
@@ -103,7 +102,7 @@ struct ParticleArgs {
   int tiles_x, tiles_y, tw, th;
   ParticleState s;
   ParticleTable tab;
-  const double4* direct;  // [np][DISK_PARTS] per-band force of the step, summed in band order
+  const double4* direct;  // [np] force and torque of the step (Fx, Fy, Tz, 0)
   int build_lists;        // maintain the neighbour lists even when no disk is free
   int* band_off;   // written with the table: per tile row, the disks whose box touches it
   int* band_ids;   // capacity np * MAXSLOT

@@ -82,17 +82,18 @@ __device__ void fluid_tile(const LatticeArgs& a, int tile) {
   }
 }
 
-// Covered cells of band `part` (of DISK_PARTS row bands) of disk p's box, one BLOCK-thread
-// workgroup: IMB collision of the cells p owns, p's own force and torque over every cell of the
-// band it covers, written to a.force[p * DISK_PARTS + part].
+// Covered cells of disk p's box, one BLOCK-thread workgroup: IMB collision of the cells p owns,
+// p's own force and torque over every cell it covers, written to a.force[p].
 template <class St>
-__device__ void disk_cells(const LatticeArgs& a, int p, int part) {
+__device__ void disk_cells(const LatticeArgs& a, int p) {
   using T = typename St::T;
   using S = typename St::S;
   __shared__ PEntry<T> s_de[NBMAX + 1];  // disk p and its neighbours, ascending id
   __shared__ int s_cj[MAXC][BLOCK];       // covering entries of each thread's current cell
   __shared__ T s_ce[MAXC][BLOCK];         //   and their solid ratios
   __shared__ Acc<T> s_fr[WAVES][3];
+  __shared__ int s_q[BLOCK];  // queued cut-cell evaluations: thread | slot << 10 | entry << 12
+  __shared__ int s_qn;
 
   const int tid = threadIdx.x;
   const S* src = (const S*)a.src;
@@ -139,37 +140,66 @@ __device__ void disk_cells(const LatticeArgs& a, int p, int part) {
     if (iy1 > a.ny - 1) iy1 = a.ny - 1;
   }
   const int bw = ix1 - ix0 + 1, bh = iy1 - iy0 + 1;
-  const bool box_ok = bw > 0 && bh > 0 && bw <= a.nx && bh <= a.ny;
-  const int r0 = box_ok ? part * bh / DISK_PARTS : 0;
-  const int r1 = box_ok ? (part + 1) * bh / DISK_PARTS : 0;
-  const int ncell = (r1 - r0) * bw;
+  const int ncell = (bw > 0 && bh > 0 && bw <= a.nx && bh <= a.ny) ? bw * bh : 0;
 
   const T tau0 = (T)a.tau0, csm = (T)a.cs, gx = (T)a.gx, gy = (T)a.gy, rho0 = (T)a.rho0;
   Acc<T> afx{T(0), T(0)}, afy{T(0), T(0)}, atz{T(0), T(0)};
-  for (int c = tid; c < ncell; c += BLOCK) {
-    int x = ix0 + c % bw, y = iy0 + r0 + c / bw;
+  auto cell_of = [&](int c, int* cx, int* cy) {  // box cell c -> lattice node
+    int x = ix0 + c % bw, y = iy0 + c / bw;
     x = x < 0 ? x + a.nx : (x >= a.nx ? x - a.nx : x);
     if (!a.walls) y = y < 0 ? y + a.ny : (y >= a.ny ? y - a.ny : y);
-    // covering disks of the cell, ascending id; the cell belongs to the first of them
-    int nc = 0, own = -1;
+    *cx = x;
+    *cy = y;
+  };
+  // rounds of BLOCK cells (block-uniform count: every thread reaches every barrier)
+  for (int base = 0; base < ncell; base += BLOCK) {
+    const int c = base + tid;
+    if (tid == 0) s_qn = 0;
+    __syncthreads();  // the previous round's ratios are read, the queue is empty
+    int x = 0, y = 0, nc = 0, own = -1;
     bool owner = true;
-    for (int k = 0; k < nd; ++k) {
-      T dx, dy;
-      lever_arm(a, s_de[k], x, y, &dx, &dy);
-      if (!covers_cell<T>(s_de[k].r, dx, dy)) continue;
-      if (s_de[k].pid != p && own < 0) owner = false;  // a lower id covers the cell
-      if (s_de[k].pid == p) own = nc;
-      if (nc >= MAXC) {
-        atomicOr(a.err, ERR_CELL);
-        continue;
+    T f[NQ];
+    if (c < ncell) {
+      cell_of(c, &x, &y);
+      // covering disks of the cell, ascending id; the cell belongs to the first of them.  Whole
+      // cells get eps = 1 now; cut cells are queued and evaluated by the whole workgroup below,
+      // one entry per thread, so the long cut-cell branch runs on densely packed lanes.
+      for (int k = 0; k < nd; ++k) {
+        T dx, dy;
+        lever_arm(a, s_de[k], x, y, &dx, &dy);
+        if (!covers_cell<T>(s_de[k].r, dx, dy)) continue;
+        if (s_de[k].pid != p && own < 0) owner = false;  // a lower id covers the cell
+        if (s_de[k].pid == p) own = nc;
+        if (nc >= MAXC) {
+          atomicOr(a.err, ERR_CELL);
+          continue;
+        }
+        s_cj[nc][tid] = k;
+        if (covers_whole_cell<T>(s_de[k].r, dx, dy)) {
+          s_ce[nc][tid] = T(1);
+        } else {
+          const int q = atomicAdd(&s_qn, 1);
+          if (q < BLOCK) s_q[q] = tid | (nc << 10) | (k << 12);
+          else s_ce[nc][tid] = solid_fraction<T>(s_de[k].r, dx, dy);  // queue full
+        }
+        ++nc;
       }
-      s_cj[nc][tid] = k;
-      s_ce[nc][tid] = solid_fraction<T>(s_de[k].r, dx, dy);
-      ++nc;
+      if (own >= 0) pull_load<St>(a, src, x, y, f);  // in flight during the queue pass
     }
-    if (own < 0) continue;  // p does not cover this cell
-    T f[NQ], fo[NQ];
-    pull_load<St>(a, src, x, y, f);
+    __syncthreads();  // the queue is complete
+    const int qn = s_qn < BLOCK ? s_qn : BLOCK;
+    if (tid < qn) {
+      const int e = s_q[tid];
+      const int t = e & 1023, sl = (e >> 10) & 3, k = e >> 12;
+      int qx, qy;
+      cell_of(base + t, &qx, &qy);
+      T dx, dy;
+      lever_arm(a, s_de[k], qx, qy, &dx, &dy);
+      s_ce[sl][t] = solid_fraction<T>(s_de[k].r, dx, dy);
+    }
+    __syncthreads();  // every ratio of the round is in place
+    if (c >= ncell || own < 0) continue;  // p does not cover this cell
+    T fo[NQ];
     auto disk = [&](int k) {
       Disk<T> d;
       const PEntry<T>& e = s_de[s_cj[k][tid]];
@@ -194,15 +224,15 @@ __device__ void disk_cells(const LatticeArgs& a, int p, int part) {
     }
     if (!owner) continue;
     if (!(rho > T(0)) || !isfinite(rho)) atomicOr(a.err, ERR_RHO);
-    const long long base = (long long)y * a.pitch + x;
+    const long long off = (long long)y * a.pitch + x;
     if constexpr (St::stochastic) {
-      const unsigned r0 = pcg_hash(seed * 0x9E3779B9u + (unsigned)base);
+      const unsigned r0 = pcg_hash(seed * 0x9E3779B9u + (unsigned)off);
 #pragma unroll
       for (int i = 0; i < NQ; ++i)
-        St::store_sr(dst, (long long)i * a.plane + base, fo[i], pcg_hash(r0 + (unsigned)i));
+        St::store_sr(dst, (long long)i * a.plane + off, fo[i], pcg_hash(r0 + (unsigned)i));
     } else {
 #pragma unroll
-      for (int i = 0; i < NQ; ++i) St::store(dst, (long long)i * a.plane + base, fo[i], T(0));
+      for (int i = 0; i < NQ; ++i) St::store(dst, (long long)i * a.plane + off, fo[i], T(0));
     }
   }
   // the disk's force and torque: wave sums, then the waves in a fixed order
@@ -223,7 +253,7 @@ __device__ void disk_cells(const LatticeArgs& a, int p, int part) {
       for (int w = 1; w < WAVES; ++w) v.add(s_fr[w][c]);
       out[c] = (double)v.hi + (double)v.lo;
     }
-    a.force[(long long)p * DISK_PARTS + part] = make_double4(out[0], out[1], out[2], 0.0);
+    a.force[p] = make_double4(out[0], out[1], out[2], 0.0);
   }
 }
 

@@ -1,6 +1,6 @@
 // particle_phase.h -- the particle phase of a coupled step, one workgroup:
-//   1. hydrodynamic force and torque on each disk: sum of the disk's per-tile partial sums
-//      (Eqs. 15, 16), in slot order (deterministic);
+//   1. hydrodynamic force and torque on each disk (Eqs. 15, 16), as reduced by the disk's own
+//      workgroup of the lattice step;
 //   2. DEM (Sec. 2.1, 2.3): N_sub velocity-Verlet (kick-drift-kick) sub-cycles of dt = 1/N_sub
 //      (Eq. 17) with the hydrodynamic load held fixed; normal linear spring-dashpot contacts
 //      between disks and with the walls (Eqs. 7, 8); the contact force is evaluated after each
@@ -131,16 +131,13 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
   const int rebuild_flag = a.do_dem || a.init_contacts || a.build_lists ? *s.rebuild : 0;
   const double x_start = x, y_start = y;
 
-  // ---- 1. forces of the step that just ran: the disk's row bands in order
+  // ---- 1. forces of the step that just ran
   double Fx = 0.0, Fy = 0.0, Tz = 0.0;
   if (have && a.do_finalize) {
-#pragma unroll
-    for (int k = 0; k < DISK_PARTS; ++k) {
-      const double4 d = a.direct[(long long)p * DISK_PARTS + k];
-      Fx += d.x;
-      Fy += d.y;
-      Tz += d.z;
-    }
+    const double4 d = a.direct[p];
+    Fx = d.x;
+    Fy = d.y;
+    Tz = d.z;
   } else if (have) {
     Fx = s.Fx[p];
     Fy = s.Fy[p];
@@ -163,11 +160,11 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
   __syncthreads();
 
   const double kn = a.kn, zeta = a.zeta;
-  // contact force on disk p (Eqs. 7, 8): neighbours in ascending id, then the walls
-  auto contact_of = [&](int i, double ri, int cnn, const int* cnb, double px, double py,
-                        double pvx, double pvy, double& ox, double& oy) {
+  // contact force on disk i (Eqs. 7, 8): neighbours in ascending id, then the walls; mi is the
+  // disk's mass and cnw = 2 zeta sqrt(kn mi) its wall damping coefficient (fixed for the step)
+  auto contact_of = [&](int i, double ri, double mi, double cnw, int cnn, const int* cnb,
+                        double px, double py, double pvx, double pvy, double& ox, double& oy) {
     const double r = ri;
-    const double mi = a.rho_s * M_PI * r * r;
     double fx = 0.0, fy = 0.0;
     for (int q = 0; q < cnn; ++q) {
       int j = 0;
@@ -201,7 +198,7 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
       }
     }
     if (a.walls) {
-      const double cn = 2.0 * zeta * sqrt(kn * mi);
+      const double cn = cnw;
       const double db = r - (py + 0.5);
       if (db > 0.0) {
         const double vn = -pvy;
@@ -216,8 +213,10 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
     ox = fx;
     oy = fy;
   };
+  const double m_p = a.rho_s * M_PI * r * r;
+  const double cnw_p = 2.0 * zeta * sqrt(kn * m_p);
   auto contact = [&](double px, double py, double pvx, double pvy, double& ox, double& oy) {
-    contact_of(p, r, nn, nb, px, py, pvx, pvy, ox, oy);
+    contact_of(p, r, m_p, cnw_p, nn, nb, px, py, pvx, pvy, ox, oy);
   };
 
   const bool own = have && mode == 0;
@@ -299,7 +298,7 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
         if (a.walls && (y - r + 0.5 <= reach || (a.ny - 0.5) - y - r <= reach)) active = true;
       }
       const double dt = 1.0 / a.n_sub, h = 0.5 * dt;
-      const double m = a.rho_s * M_PI * r * r;
+      const double m = m_p;
       const double I = 0.5 * m * r * r;
       if (own && !active) {
         // quiet: no contact force during the whole step, so the accelerations are the same in
@@ -347,6 +346,7 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
           const double mi_ = a.rho_s * M_PI * ri * ri;
           const double Ii = 0.5 * mi_ * ri * ri;
           const double im = 1.0 / mi_;
+          const double cnw_i = 2.0 * zeta * sqrt(kn * mi_);
           double px = sx[i], py = sy[i], pvx = svx[i], pvy = svy[i];
           const double aFx = s_ast[t][0], aFy = s_ast[t][1], aTz = s_ast[t][2];
           double afx = s_ast[t][3], afy = s_ast[t][4], aom = s_ast[t][5];
@@ -367,7 +367,7 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
             sx[i] = px; sy[i] = py; svx[i] = pvx; svy[i] = pvy;
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            contact_of(i, ri, ann, anb, px, py, pvx, pvy, afx, afy);
+            contact_of(i, ri, mi_, cnw_i, ann, anb, px, py, pvx, pvy, afx, afy);
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
             const double bx = (afx + aFx) * im;

@@ -79,7 +79,8 @@ size_t layout(const imb_config& c, char* base, DeviceLayout* L) {
   d.J = cv.take<double>(1);
   d.w = cv.take<double>(3 * mp);
   d.seed = cv.take<unsigned>(2);
-  d.force = cv.take<double4>(mp * DISK_PARTS);
+  d.force = cv.take<double4>(mp);
+  d.done = cv.take<unsigned>(1);
   if (L) *L = d;
   return align_up(cv.off, 256);
 }
@@ -160,14 +161,10 @@ struct imb_sim {
   std::string err;
   double* stage = nullptr;  // readback staging (library-owned)
   size_t stage_bytes = 0;
-  // the fluid tiles of a step run on `side` while the disk workgroups and the particle phase run
-  // on `stream`: fork and join events (timing disabled), created by the first imb_step
-  hipStream_t side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool timing = false;
-  std::vector<hipEvent_t> ev_k[3];  // start/stop pairs: fluid, disk, particle kernels
-  double k_ms[3] = {0, 0, 0};
-  int64_t k_n[3] = {0, 0, 0};
+  std::vector<hipEvent_t> ev_step;  // start/stop pairs around step-kernel launches
+  double step_ms = 0;
+  int64_t step_n = 0;
   std::vector<hipEvent_t> ev_pool;
   AdjointState* adj = nullptr;
   // captured step chains: graph[len][start buffer]; len index 0 = 2 steps, 1 = GRAPH_LONG steps
@@ -198,6 +195,7 @@ LatticeArgs lattice_args(imb_sim* s, const void* src, void* dst) {
   a.nbr = s->d.ps.nbr;
   a.nnbr = s->d.ps.nnbr;
   a.force = s->d.force;
+  a.done = s->d.done;
   return a;
 }
 
@@ -227,10 +225,8 @@ static hipEvent_t take_event(imb_sim* s) {
   return e;
 }
 
-// One coupled step.  The disks' workgroups (covered cells, forces) and then the particle phase
-// (DEM, the next step's tables) run on the simulation's stream while the fluid tiles of the same
-// step run on the side stream; the next step starts once both are done.  With kernel timing on,
-// the three kernels run one after the other on the simulation's stream, each between events.
+// One coupled step: one launch of the step kernel (lattice, forces and, with disks, the particle
+// phase writing the other copy of the disk tables).
 void enqueue_step(imb_sim* s, const double* wfx, const double* wfy, const double* wtz,
                   double* J) {
   const int c = s->cur;
@@ -238,31 +234,15 @@ void enqueue_step(imb_sim* s, const double* wfx, const double* wfy, const double
   ParticleArgs pa = particle_args(s, c ^ 1);
   pa.do_finalize = 1; pa.do_dem = 1; pa.do_table = 1;
   pa.wfx = wfx; pa.wfy = wfy; pa.wtz = wtz; pa.J = J;
-  const int st = s->cfg.storage;
   if (s->timing) {
-    auto timed = [&](int k, auto&& launch) {
-      hipEvent_t e0 = take_event(s), e1 = take_event(s);
-      hipEventRecord(e0, s->stream);
-      launch();
-      hipEventRecord(e1, s->stream);
-      s->ev_k[k].push_back(e0);
-      s->ev_k[k].push_back(e1);
-    };
-    timed(0, [&] { launch_fluid_step(st, la, s->stream); });
-    if (s->np > 0) {
-      timed(1, [&] { launch_disk_step(st, la, s->stream); });
-      timed(2, [&] { launch_particle_phase(pa, s->stream); });
-    }
-  } else if (s->np > 0) {
-    hipEventRecord(s->ev_fork, s->stream);
-    hipStreamWaitEvent(s->side, s->ev_fork, 0);
-    launch_fluid_step(st, la, s->side);
-    hipEventRecord(s->ev_join, s->side);
-    launch_disk_step(st, la, s->stream);
-    launch_particle_phase(pa, s->stream);
-    hipStreamWaitEvent(s->stream, s->ev_join, 0);
+    hipEvent_t e0 = take_event(s), e1 = take_event(s);
+    hipEventRecord(e0, s->stream);
+    launch_step(s->cfg.storage, la, pa, true, s->stream);
+    hipEventRecord(e1, s->stream);
+    s->ev_step.push_back(e0);
+    s->ev_step.push_back(e1);
   } else {
-    launch_fluid_step(st, la, s->stream);
+    launch_step(s->cfg.storage, la, pa, true, s->stream);
   }
   s->cur ^= 1;
   s->steps++;
@@ -468,12 +448,8 @@ void imb_destroy(imb_sim* s) {
   hipStreamSynchronize(s->stream);
   drop_graphs(s);
   free_adjoint(s);
-  for (auto& v : s->ev_k)
-    for (auto e : v) hipEventDestroy(e);
+  for (auto e : s->ev_step) hipEventDestroy(e);
   for (auto e : s->ev_pool) hipEventDestroy(e);
-  if (s->ev_fork) hipEventDestroy(s->ev_fork);
-  if (s->ev_join) hipEventDestroy(s->ev_join);
-  if (s->side) hipStreamDestroy(s->side);
   if (s->stage) hipFree(s->stage);
   if (s->owns && s->mem) hipFree(s->mem);
   delete s;
@@ -638,13 +614,6 @@ int imb_set_particles(imb_sim* s, int32_t n, const double* x, const double* y, c
 
 int imb_step(imb_sim* s, int32_t nsteps) {
   if (!s || nsteps < 0) return IMB_EINVAL;
-  hipError_t e = hipSuccess;
-  if (!s->side) e = hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking);
-  if (e == hipSuccess && !s->ev_fork)
-    e = hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming);
-  if (e == hipSuccess && !s->ev_join)
-    e = hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming);
-  if (e != hipSuccess) return hip_fail(&s->err, e, "side stream");
   // per-kernel event timing needs the individual launches
   if (!s->use_graphs || s->timing) {
     for (int k = 0; k < nsteps; ++k) enqueue_step(s, nullptr, nullptr, nullptr, nullptr);
@@ -665,7 +634,7 @@ int imb_step(imb_sim* s, int32_t nsteps) {
       for (int k = 0; k < nsteps; ++k) enqueue_step(s, nullptr, nullptr, nullptr, nullptr);
       return launch_check(s, "step");
     }
-    e = hipGraphLaunch(ge, s->stream);
+    hipError_t e = hipGraphLaunch(ge, s->stream);
     if (e != hipSuccess) return hip_fail(&s->err, e, "hipGraphLaunch");
     s->steps += len;  // an even number of steps leaves the buffer parity unchanged
     nsteps -= len;
@@ -844,39 +813,29 @@ int imb_load_state(imb_sim* s, const void* host_buf, size_t bytes) {
 int imb_set_kernel_timing(imb_sim* s, int enable) {
   if (!s) return IMB_EINVAL;
   hipStreamSynchronize(s->stream);
-  for (int k = 0; k < 3; ++k) {
-    for (auto e : s->ev_k[k]) s->ev_pool.push_back(e);
-    s->ev_k[k].clear();
-    s->k_ms[k] = 0;
-    s->k_n[k] = 0;
-  }
+  for (auto e : s->ev_step) s->ev_pool.push_back(e);
+  s->ev_step.clear();
+  s->step_ms = 0;
+  s->step_n = 0;
   s->timing = enable != 0;
   return IMB_OK;
 }
 
-int imb_get_kernel_timing(imb_sim* s, double* fluid_ms, int64_t* fluid_n, double* disk_ms,
-                          int64_t* disk_n, double* par_ms, int64_t* par_n) {
+int imb_get_kernel_timing(imb_sim* s, double* step_ms, int64_t* step_launches) {
   if (!s) return IMB_EINVAL;
   hipError_t e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) return hip_fail(&s->err, e, "hipStreamSynchronize");
-  for (int k = 0; k < 3; ++k) {
-    std::vector<hipEvent_t>& v = s->ev_k[k];
-    for (size_t i = 0; i + 1 < v.size(); i += 2) {
-      float t = 0;
-      hipEventElapsedTime(&t, v[i], v[i + 1]);
-      s->k_ms[k] += t;
-      s->k_n[k] += 1;
-      s->ev_pool.push_back(v[i]);
-      s->ev_pool.push_back(v[i + 1]);
-    }
-    v.clear();
+  for (size_t i = 0; i + 1 < s->ev_step.size(); i += 2) {
+    float t = 0;
+    hipEventElapsedTime(&t, s->ev_step[i], s->ev_step[i + 1]);
+    s->step_ms += t;
+    s->step_n += 1;
+    s->ev_pool.push_back(s->ev_step[i]);
+    s->ev_pool.push_back(s->ev_step[i + 1]);
   }
-  double* ms[3] = {fluid_ms, disk_ms, par_ms};
-  int64_t* n[3] = {fluid_n, disk_n, par_n};
-  for (int k = 0; k < 3; ++k) {
-    if (ms[k]) *ms[k] = s->k_ms[k];
-    if (n[k]) *n[k] = s->k_n[k];
-  }
+  s->ev_step.clear();
+  if (step_ms) *step_ms = s->step_ms;
+  if (step_launches) *step_launches = s->step_n;
   return IMB_OK;
 }
 

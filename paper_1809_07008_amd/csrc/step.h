@@ -5,15 +5,15 @@
 
 namespace imb {
 
-// lattice step (step.hip): the disks' covered cells and forces, the tiles' uncovered cells, and
-// both in that order on one stream
-void launch_disk_step(int storage, const LatticeArgs& a, hipStream_t s);
-void launch_fluid_step(int storage, const LatticeArgs& a, hipStream_t s);
-void launch_lattice_step(int storage, const LatticeArgs& a, hipStream_t s);
+// the coupled step (step.hip): lattice update of every cell, each disk's force and torque and,
+// with with_dem, the particle phase `pa` (run by the last disk workgroup to finish)
+void launch_step(int storage, const LatticeArgs& a, const ParticleArgs& pa, bool with_dem,
+                 hipStream_t s);
 void launch_solid_field(int storage, const LatticeArgs& a, double* eps_out, hipStream_t s);
 
-// particle phase (particles.hip): force finalisation, DEM, tile boxes for the next step
+// particle phase alone (particles.hip): DEM and/or the disk tables, one workgroup
 void launch_particle_phase(const ParticleArgs& a, hipStream_t s);
+size_t particle_phase_lds(int np, int tiles_y);  // dynamic LDS bytes of the particle phase
 
 // population format conversion and moments (convert.hip)
 void launch_unstream(int storage, const LatticeArgs& a, const double* fq, const double* feq9,

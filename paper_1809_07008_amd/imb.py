@@ -96,8 +96,7 @@ def load_library():
         "imb_save_state": (C.c_int, [_VP, _VP, C.c_size_t]),
         "imb_load_state": (C.c_int, [_VP, _VP, C.c_size_t]),
         "imb_set_kernel_timing": (C.c_int, [_VP, C.c_int]),
-        "imb_get_kernel_timing": (C.c_int, [_VP, _D, P(C.c_int64), _D, P(C.c_int64), _D,
-                                            P(C.c_int64)]),
+        "imb_get_kernel_timing": (C.c_int, [_VP, _D, P(C.c_int64)]),
         "imb_copy_kernel": (C.c_int, [_VP, _VP, C.c_size_t, _VP]),
         "imb_adjoint": (C.c_int, [_VP, C.c_int32, C.c_int32, _D, _D, _D, _D, _D, _D, _D, _D,
                                   _D, _D, _D]),
@@ -305,16 +304,12 @@ class Simulation:
                     "imb_set_kernel_timing")
 
     def kernel_timing(self):
-        """Summed milliseconds and launch counts of the fluid, disk and particle kernels since
-        set_kernel_timing(True) (the three run one after the other while timing is on)."""
-        ms = [C.c_double() for _ in range(3)]
-        n = [C.c_int64() for _ in range(3)]
-        self._check(load_library().imb_get_kernel_timing(
-            self._h, C.byref(ms[0]), C.byref(n[0]), C.byref(ms[1]), C.byref(n[1]),
-            C.byref(ms[2]), C.byref(n[2])), "imb_get_kernel_timing")
-        return {"fluid_ms": ms[0].value, "fluid_launches": n[0].value,
-                "disk_ms": ms[1].value, "disk_launches": n[1].value,
-                "particle_ms": ms[2].value, "particle_launches": n[2].value}
+        """Summed milliseconds and launch count of the step kernel since set_kernel_timing(True)
+        (HIP events around every launch on the simulation's stream)."""
+        ms, n = C.c_double(), C.c_int64()
+        self._check(load_library().imb_get_kernel_timing(self._h, C.byref(ms), C.byref(n)),
+                    "imb_get_kernel_timing")
+        return {"step_ms": ms.value, "step_launches": n.value}
 
     def adjoint(self, nsteps: int, k_ckpt: int, wfx=None, wfy=None, wtz=None,
                 populations: bool = False):
