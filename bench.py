@@ -3,9 +3,9 @@
 Workload: 2048x1024 channel, 500 moving disks (diameters U[16, 24]), Smagorinsky C_s = 0.1,
 tau 0.55, linear spring-dashpot DEM, FP32 deviation storage, seeded synthetic input (seed 0).
 One "step" is one full coupled step: solid ratio, IMB collision + streaming, force/torque sums,
-DEM update, all in one kernel launch.  Prints one JSON line (throughput in MLUPS, HBM roofline of
-the step kernel, the adjoint/forward time ratio, the CPU oracle's throughput on the same
-workload).
+DEM update (two kernels: the lattice kernel, then the particle phase).  Prints one JSON line
+(throughput in MLUPS, HBM roofline of the lattice kernel, the adjoint/forward time ratio, the CPU
+oracle's throughput on the same workload).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -23,13 +23,12 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 CSRC = os.path.join(ROOT, "paper_1809_07008_amd", "csrc")
-LATTICE_SOURCES = ("step.hip", "disk_block.h", "particle_phase.h", "tile.h", "collide.h",
-                   "solid.h", "common.h")
+LATTICE_SOURCES = ("step.hip", "disk_block.h", "tile.h", "collide.h", "solid.h", "common.h")
 COUNTERS = os.path.join(ROOT, "profiles", "k_step_2048x1024_n500_counters.txt")
 
 
 def lattice_source_hash() -> str:
-    """sha256 over the sources the step kernel is compiled from."""
+    """sha256 over the sources the lattice kernel (k_step) is compiled from."""
     import hashlib
     h = hashlib.sha256()
     for name in LATTICE_SOURCES:
@@ -39,7 +38,7 @@ def lattice_source_hash() -> str:
 
 
 def measured_traffic(storage: str, tile) -> float | None:
-    """HBM-side bytes per step-kernel launch from the committed rocprofv3 counter summary
+    """HBM-side bytes per lattice-kernel launch from the committed rocprofv3 counter summary
     (FETCH_SIZE + WRITE_SIZE, each scaled by what the counter reads for a copy kernel of known
     size), or None when the summary is missing, was taken for another storage format or tile,
     or the kernel's sources have changed since."""
@@ -100,8 +99,10 @@ def adjoint_ratio(tile, reps: int = 3):
                                        max(kk["adjoint_kernels"], 1), 2),
             "recompute_kernel_us": round(kk["recompute_kernel_ms"] * 1e3 /
                                          max(kk["recompute_kernels"], 1), 2),
-            "forward_step_kernel_us": round(kt["step_ms"] * 1e3 / max(kt["step_launches"], 1),
-                                            2)}
+            "forward_lattice_kernel_us": round(kt["lattice_ms"] * 1e3 /
+                                               max(kt["lattice_launches"], 1), 2),
+            "forward_particle_kernel_us": round(kt["particle_ms"] * 1e3 /
+                                                max(kt["particle_launches"], 1), 2)}
 
 
 def copy_calibration(nbytes: int, reps: int = 10) -> int:
@@ -157,8 +158,8 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storage", default="f32", choices=["f64", "f32", "f16"])
-    ap.add_argument("--tile-w", type=int, default=64)
-    ap.add_argument("--tile-rows", type=int, default=1)
+    ap.add_argument("--tile-w", type=int, default=32)
+    ap.add_argument("--tile-rows", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint/forward ratio (profiling the forward step alone)")
@@ -203,23 +204,25 @@ def main(argv=None):
     print("bench: %d steps %.3f ms/step %.1f MLUPS" % (args.steps, ms_per_step, mlups),
           file=sys.stderr, flush=True)
 
-    # step-kernel duration with HIP events on the simulation's stream (same K steps again)
+    # per-kernel durations with HIP events on the simulation's stream (same K steps again)
     sim.set_kernel_timing(True)
     sim.step(args.steps)
     kt = sim.kernel_timing()
     sim.set_kernel_timing(False)
-    step_kernel_ms = kt["step_ms"] / max(kt["step_launches"], 1)
+    lat_ms = kt["lattice_ms"] / max(kt["lattice_launches"], 1)
+    par_ms = kt["particle_ms"] / max(kt["particle_launches"], 1)
     bpl = bytes_per_lup(args.storage)
     step_bytes = case.cells * bpl
-    achieved = step_bytes / (step_kernel_ms * 1e-3) / 1e9
+    achieved = step_bytes / (lat_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(args.storage, (args.tile_w, args.tile_rows)),
                 "kernel_source_sha256": lattice_source_hash(),
                 "kernel": "k_step<%s>" % {"f64": "StoreF64", "f32": "StoreF32",
                                           "f16": "StoreF16"}[args.storage],
-                "kernel_avg_us": round(step_kernel_ms * 1e3, 2),
-                "bytes_per_launch": step_bytes}
+                "kernel_avg_us": round(lat_ms * 1e3, 2),
+                "bytes_per_launch": step_bytes,
+                "particle_phase_avg_us": round(par_ms * 1e3, 2)}
 
     out = {
         "metric": "MLUPS & % of HBM roofline, D2Q9 IMB 2048x1024; adjoint/forward time ratio",

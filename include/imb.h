@@ -67,7 +67,7 @@ typedef struct imb_config {
   uint32_t flags;          /* IMB_FLAG_* */
   int32_t tile_w;          /* tile width in cells: 16, 32, 64, 128 or 256 (0 = 64) */
   int32_t tile_rows;       /* cell rows per thread: 1, 2 or 4 (0 = 1); a tile is
-                              tile_w x (512 / tile_w * tile_rows) cells */
+                              tile_w x (256 / tile_w * tile_rows) cells */
 } imb_config;
 
 typedef struct imb_sim imb_sim;
@@ -155,13 +155,14 @@ int imb_state_bytes(imb_sim* sim, size_t* bytes);
 int imb_save_state(imb_sim* sim, void* host_buf, size_t bytes);
 int imb_load_state(imb_sim* sim, const void* host_buf, size_t bytes);
 
-/* Per-kernel timing with HIP events on the simulation's stream.  A coupled step is one kernel
- * launch (lattice update of every cell, each disk's force and torque, and the DEM with the next
- * step's disk tables).  When enabled, imb_step records an event pair around every step-kernel
- * launch; imb_get_kernel_timing synchronises and returns the summed milliseconds and the launch
- * count since the last reset (either pointer may be NULL). */
+/* Per-kernel timing with HIP events on the simulation's stream.  A coupled step is two kernels:
+ * the lattice kernel (every cell's update, each disk's force and torque) and the particle phase
+ * (DEM, the next step's disk tables).  When enabled, imb_step records an event pair around every
+ * launch of each; imb_get_kernel_timing synchronises and returns the summed milliseconds and
+ * launch counts since the last reset (any pointer may be NULL). */
 int imb_set_kernel_timing(imb_sim* sim, int enable);
-int imb_get_kernel_timing(imb_sim* sim, double* step_ms, int64_t* step_launches);
+int imb_get_kernel_timing(imb_sim* sim, double* lattice_ms, int64_t* lattice_launches,
+                          double* particle_ms, int64_t* particle_launches);
 
 /* Streaming copy of n_bytes between two device buffers with the library's copy kernel, for
  * calibrating bandwidth counters.  Asynchronous on hip_stream. */

@@ -591,8 +591,11 @@ extern "C" int imb_adjoint(imb_sim* sim, int32_t nsteps, int32_t k, const double
     pa.wfy = wd[1];
     pa.wtz = wd[2];
     pa.J = d.J;
-    launch_step(cfg.storage, la, pa, true, st);
-    if (np > 0) copy_lists(v, tn1.nbr, tn1.nnbr, d.ps.nbr, d.ps.nnbr, st);
+    launch_lattice_step(cfg.storage, la, st);
+    if (np > 0) {
+      launch_particle_phase(pa, st);
+      copy_lists(v, tn1.nbr, tn1.nnbr, d.ps.nbr, d.ps.nnbr, st);
+    }
     src = dst;
   }
   hipEventRecord(A->ev[1], st);
@@ -637,7 +640,7 @@ extern "C" int imb_adjoint(imb_sim* sim, int32_t nsteps, int32_t k, const double
       la.band_ids = tn.bids;
       la.nbr = tn.nbr;
       la.nnbr = tn.nnbr;
-      timed(false, [&] { launch_step(cfg.storage, la, ParticleArgs{}, false, st); });
+      timed(false, [&] { launch_lattice_step(cfg.storage, la, st); });
       if (timing) kind.push_back(0);
       rs = dst;
     }

@@ -68,11 +68,14 @@ __device__ inline unsigned ld_agent(const unsigned* p) {
 // batch was aborted (a wait exceeded the limit here or elsewhere).
 __device__ bool grid_barrier(unsigned* sync, int nblocks, int reset_word, long long spin_ticks) {
   __shared__ int s_ok;
-  // every wave completes and releases its own stores (a fence orders only the issuing wave's
-  // memory operations), then the workgroup arrives once
-  __threadfence();
+  // Every wave waits until its own stores have reached the L2 (a workgroup barrier alone does
+  // not wait for global stores); thread 0 then releases them device-wide and arrives.  The
+  // agent-scope fence writes back the whole L2 of the compute die, so it is issued once per
+  // workgroup rather than once per wave.
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
+    __threadfence();
     int ok = 1;
     const unsigned gen = ld_agent(&sync[1]);
     const unsigned arrived = atomicAdd(&sync[0], 1u);
@@ -96,10 +99,10 @@ __device__ bool grid_barrier(unsigned* sync, int nblocks, int reset_word, long l
         __builtin_amdgcn_s_sleep(2);
       }
     }
+    __threadfence();  // acquire: what other workgroups released is visible to this workgroup
     s_ok = ok;
   }
   __syncthreads();
-  __threadfence();  // acquire: what other workgroups released before the barrier is visible
   return s_ok != 0;
 }
 
@@ -674,8 +677,8 @@ int imb_batch_autotune(imb_batch* b, int32_t trial_steps, double* trial_ms, int3
       *v.steps = sim_steps0[c];
     }
   };
-  static const int shapes[][2] = {{32, 1}, {32, 2}, {64, 1}, {64, 2}, {64, 4}, {128, 1},
-                                  {128, 2}, {16, 1}, {16, 2}};
+  static const int shapes[][2] = {{32, 1}, {32, 2}, {32, 4}, {64, 1}, {64, 2}, {64, 4},
+                                  {128, 1}, {128, 2}, {16, 4}};
   const int nshapes = (int)(sizeof shapes / sizeof shapes[0]);
   double best = 1e300;
   int bw = b->tile_w, br = b->tile_rows, bg = b->grid_user;

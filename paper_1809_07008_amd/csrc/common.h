@@ -13,7 +13,7 @@
 namespace imb {
 
 constexpr int NQ = 9;              // D2Q9
-constexpr int BLOCK = 512;         // threads of a lattice-step workgroup (8 wave64)
+constexpr int BLOCK = 256;         // threads of a lattice-step workgroup (4 wave64)
 constexpr int WAVES = BLOCK / 64;
 constexpr int LMAX = 32;           // disks whose boxes may touch one tile
 constexpr int MAXC = 4;            // disks covering one cell (three cannot unless they overlap)
@@ -81,7 +81,6 @@ struct LatticeArgs {
   const int* nbr;        // [np][NBMAX] neighbour lists (ascending ids) and their lengths
   const int* nnbr;
   double4* force;        // [np] force and torque of this step (Fx, Fy, Tz, 0)
-  unsigned* done;        // disk workgroups finished in the running step kernel (0 between launches)
 };
 
 // Particle state on the device (structure of arrays, FP64).

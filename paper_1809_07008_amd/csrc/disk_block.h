@@ -92,8 +92,6 @@ __device__ void disk_cells(const LatticeArgs& a, int p) {
   __shared__ int s_cj[MAXC][BLOCK];       // covering entries of each thread's current cell
   __shared__ T s_ce[MAXC][BLOCK];         //   and their solid ratios
   __shared__ Acc<T> s_fr[WAVES][3];
-  __shared__ int s_q[BLOCK];  // queued cut-cell evaluations: thread | slot << 10 | entry << 12
-  __shared__ int s_qn;
 
   const int tid = threadIdx.x;
   const S* src = (const S*)a.src;
@@ -144,62 +142,30 @@ __device__ void disk_cells(const LatticeArgs& a, int p) {
 
   const T tau0 = (T)a.tau0, csm = (T)a.cs, gx = (T)a.gx, gy = (T)a.gy, rho0 = (T)a.rho0;
   Acc<T> afx{T(0), T(0)}, afy{T(0), T(0)}, atz{T(0), T(0)};
-  auto cell_of = [&](int c, int* cx, int* cy) {  // box cell c -> lattice node
+  for (int c = tid; c < ncell; c += BLOCK) {
     int x = ix0 + c % bw, y = iy0 + c / bw;
     x = x < 0 ? x + a.nx : (x >= a.nx ? x - a.nx : x);
     if (!a.walls) y = y < 0 ? y + a.ny : (y >= a.ny ? y - a.ny : y);
-    *cx = x;
-    *cy = y;
-  };
-  // rounds of BLOCK cells (block-uniform count: every thread reaches every barrier)
-  for (int base = 0; base < ncell; base += BLOCK) {
-    const int c = base + tid;
-    if (tid == 0) s_qn = 0;
-    __syncthreads();  // the previous round's ratios are read, the queue is empty
-    int x = 0, y = 0, nc = 0, own = -1;
+    // covering disks of the cell, ascending id; the cell belongs to the first of them
+    int nc = 0, own = -1;
     bool owner = true;
-    T f[NQ];
-    if (c < ncell) {
-      cell_of(c, &x, &y);
-      // covering disks of the cell, ascending id; the cell belongs to the first of them.  Whole
-      // cells get eps = 1 now; cut cells are queued and evaluated by the whole workgroup below,
-      // one entry per thread, so the long cut-cell branch runs on densely packed lanes.
-      for (int k = 0; k < nd; ++k) {
-        T dx, dy;
-        lever_arm(a, s_de[k], x, y, &dx, &dy);
-        if (!covers_cell<T>(s_de[k].r, dx, dy)) continue;
-        if (s_de[k].pid != p && own < 0) owner = false;  // a lower id covers the cell
-        if (s_de[k].pid == p) own = nc;
-        if (nc >= MAXC) {
-          atomicOr(a.err, ERR_CELL);
-          continue;
-        }
-        s_cj[nc][tid] = k;
-        if (covers_whole_cell<T>(s_de[k].r, dx, dy)) {
-          s_ce[nc][tid] = T(1);
-        } else {
-          const int q = atomicAdd(&s_qn, 1);
-          if (q < BLOCK) s_q[q] = tid | (nc << 10) | (k << 12);
-          else s_ce[nc][tid] = solid_fraction<T>(s_de[k].r, dx, dy);  // queue full
-        }
-        ++nc;
-      }
-      if (own >= 0) pull_load<St>(a, src, x, y, f);  // in flight during the queue pass
-    }
-    __syncthreads();  // the queue is complete
-    const int qn = s_qn < BLOCK ? s_qn : BLOCK;
-    if (tid < qn) {
-      const int e = s_q[tid];
-      const int t = e & 1023, sl = (e >> 10) & 3, k = e >> 12;
-      int qx, qy;
-      cell_of(base + t, &qx, &qy);
+    for (int k = 0; k < nd; ++k) {
       T dx, dy;
-      lever_arm(a, s_de[k], qx, qy, &dx, &dy);
-      s_ce[sl][t] = solid_fraction<T>(s_de[k].r, dx, dy);
+      lever_arm(a, s_de[k], x, y, &dx, &dy);
+      if (!covers_cell<T>(s_de[k].r, dx, dy)) continue;
+      if (s_de[k].pid != p && own < 0) owner = false;  // a lower id covers the cell
+      if (s_de[k].pid == p) own = nc;
+      if (nc >= MAXC) {
+        atomicOr(a.err, ERR_CELL);
+        continue;
+      }
+      s_cj[nc][tid] = k;
+      s_ce[nc][tid] = solid_fraction<T>(s_de[k].r, dx, dy);
+      ++nc;
     }
-    __syncthreads();  // every ratio of the round is in place
-    if (c >= ncell || own < 0) continue;  // p does not cover this cell
-    T fo[NQ];
+    if (own < 0) continue;  // p does not cover this cell
+    T f[NQ], fo[NQ];
+    pull_load<St>(a, src, x, y, f);
     auto disk = [&](int k) {
       Disk<T> d;
       const PEntry<T>& e = s_de[s_cj[k][tid]];

@@ -23,7 +23,6 @@ struct DeviceLayout {
   ParticleTable tab[2];
   int* band_off[2];
   int* band_ids[2];
-  unsigned* done;  // disk workgroups finished in the running step kernel
   int* err;
   double* J;
   double* w;  // objective weights wfx, wfy, wtz (3 x capacity)

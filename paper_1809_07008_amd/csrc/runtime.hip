@@ -80,7 +80,6 @@ size_t layout(const imb_config& c, char* base, DeviceLayout* L) {
   d.w = cv.take<double>(3 * mp);
   d.seed = cv.take<unsigned>(2);
   d.force = cv.take<double4>(mp);
-  d.done = cv.take<unsigned>(1);
   if (L) *L = d;
   return align_up(cv.off, 256);
 }
@@ -162,9 +161,9 @@ struct imb_sim {
   double* stage = nullptr;  // readback staging (library-owned)
   size_t stage_bytes = 0;
   bool timing = false;
-  std::vector<hipEvent_t> ev_step;  // start/stop pairs around step-kernel launches
-  double step_ms = 0;
-  int64_t step_n = 0;
+  std::vector<hipEvent_t> ev_k[2];  // start/stop pairs: lattice kernel, particle phase
+  double k_ms[2] = {0, 0};
+  int64_t k_n[2] = {0, 0};
   std::vector<hipEvent_t> ev_pool;
   AdjointState* adj = nullptr;
   // captured step chains: graph[len][start buffer]; len index 0 = 2 steps, 1 = GRAPH_LONG steps
@@ -195,7 +194,6 @@ LatticeArgs lattice_args(imb_sim* s, const void* src, void* dst) {
   a.nbr = s->d.ps.nbr;
   a.nnbr = s->d.ps.nnbr;
   a.force = s->d.force;
-  a.done = s->d.done;
   return a;
 }
 
@@ -225,24 +223,30 @@ static hipEvent_t take_event(imb_sim* s) {
   return e;
 }
 
-// One coupled step: one launch of the step kernel (lattice, forces and, with disks, the particle
-// phase writing the other copy of the disk tables).
+// One coupled step: the lattice kernel (every cell, each disk's force and torque), then the
+// particle phase (DEM and the next step's disk tables, written to the other table copy).
 void enqueue_step(imb_sim* s, const double* wfx, const double* wfy, const double* wtz,
                   double* J) {
   const int c = s->cur;
   LatticeArgs la = lattice_args(s, s->d.f[c], s->d.f[c ^ 1]);
-  ParticleArgs pa = particle_args(s, c ^ 1);
-  pa.do_finalize = 1; pa.do_dem = 1; pa.do_table = 1;
-  pa.wfx = wfx; pa.wfy = wfy; pa.wtz = wtz; pa.J = J;
-  if (s->timing) {
+  auto timed = [&](int k, auto&& launch) {
+    if (!s->timing) {
+      launch();
+      return;
+    }
     hipEvent_t e0 = take_event(s), e1 = take_event(s);
     hipEventRecord(e0, s->stream);
-    launch_step(s->cfg.storage, la, pa, true, s->stream);
+    launch();
     hipEventRecord(e1, s->stream);
-    s->ev_step.push_back(e0);
-    s->ev_step.push_back(e1);
-  } else {
-    launch_step(s->cfg.storage, la, pa, true, s->stream);
+    s->ev_k[k].push_back(e0);
+    s->ev_k[k].push_back(e1);
+  };
+  timed(0, [&] { launch_lattice_step(s->cfg.storage, la, s->stream); });
+  if (s->np > 0) {
+    ParticleArgs pa = particle_args(s, c ^ 1);
+    pa.do_finalize = 1; pa.do_dem = 1; pa.do_table = 1;
+    pa.wfx = wfx; pa.wfy = wfy; pa.wtz = wtz; pa.J = J;
+    timed(1, [&] { launch_particle_phase(pa, s->stream); });
   }
   s->cur ^= 1;
   s->steps++;
@@ -448,7 +452,8 @@ void imb_destroy(imb_sim* s) {
   hipStreamSynchronize(s->stream);
   drop_graphs(s);
   free_adjoint(s);
-  for (auto e : s->ev_step) hipEventDestroy(e);
+  for (auto& v : s->ev_k)
+    for (auto e : v) hipEventDestroy(e);
   for (auto e : s->ev_pool) hipEventDestroy(e);
   if (s->stage) hipFree(s->stage);
   if (s->owns && s->mem) hipFree(s->mem);
@@ -813,29 +818,37 @@ int imb_load_state(imb_sim* s, const void* host_buf, size_t bytes) {
 int imb_set_kernel_timing(imb_sim* s, int enable) {
   if (!s) return IMB_EINVAL;
   hipStreamSynchronize(s->stream);
-  for (auto e : s->ev_step) s->ev_pool.push_back(e);
-  s->ev_step.clear();
-  s->step_ms = 0;
-  s->step_n = 0;
+  for (int k = 0; k < 2; ++k) {
+    for (auto e : s->ev_k[k]) s->ev_pool.push_back(e);
+    s->ev_k[k].clear();
+    s->k_ms[k] = 0;
+    s->k_n[k] = 0;
+  }
   s->timing = enable != 0;
   return IMB_OK;
 }
 
-int imb_get_kernel_timing(imb_sim* s, double* step_ms, int64_t* step_launches) {
+int imb_get_kernel_timing(imb_sim* s, double* lat_ms, int64_t* lat_n, double* par_ms,
+                          int64_t* par_n) {
   if (!s) return IMB_EINVAL;
   hipError_t e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) return hip_fail(&s->err, e, "hipStreamSynchronize");
-  for (size_t i = 0; i + 1 < s->ev_step.size(); i += 2) {
-    float t = 0;
-    hipEventElapsedTime(&t, s->ev_step[i], s->ev_step[i + 1]);
-    s->step_ms += t;
-    s->step_n += 1;
-    s->ev_pool.push_back(s->ev_step[i]);
-    s->ev_pool.push_back(s->ev_step[i + 1]);
+  for (int k = 0; k < 2; ++k) {
+    std::vector<hipEvent_t>& v = s->ev_k[k];
+    for (size_t i = 0; i + 1 < v.size(); i += 2) {
+      float t = 0;
+      hipEventElapsedTime(&t, v[i], v[i + 1]);
+      s->k_ms[k] += t;
+      s->k_n[k] += 1;
+      s->ev_pool.push_back(v[i]);
+      s->ev_pool.push_back(v[i + 1]);
+    }
+    v.clear();
   }
-  s->ev_step.clear();
-  if (step_ms) *step_ms = s->step_ms;
-  if (step_launches) *step_launches = s->step_n;
+  if (lat_ms) *lat_ms = s->k_ms[0];
+  if (lat_n) *lat_n = s->k_n[0];
+  if (par_ms) *par_ms = s->k_ms[1];
+  if (par_n) *par_n = s->k_n[1];
   return IMB_OK;
 }
 

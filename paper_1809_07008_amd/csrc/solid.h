@@ -177,15 +177,6 @@ __host__ __device__ inline bool covers_cell(T r, T dx, T dy) {
   return nx * nx + ny * ny < r * r;
 }
 
-// Whether that cell lies entirely inside the disk (its farthest corner is inside): eps = 1.
-template <class T>
-__host__ __device__ inline bool covers_whole_cell(T r, T dx, T dy) {
-  const T x0 = dx - T(0.5), x1 = dx + T(0.5), y0 = dy - T(0.5), y1 = dy + T(0.5);
-  const T fx = fabs(x0) > fabs(x1) ? fabs(x0) : fabs(x1);
-  const T fy = fabs(y0) > fabs(y1) ? fabs(y0) : fabs(y1);
-  return fx * fx + fy * fy <= r * r;
-}
-
 template <class T>
 __host__ __device__ inline T solid_fraction(T r, T dx, T dy) {
   const T x0 = dx - T(0.5), x1 = dx + T(0.5), y0 = dy - T(0.5), y1 = dy + T(0.5);

@@ -5,10 +5,8 @@
 
 namespace imb {
 
-// the coupled step (step.hip): lattice update of every cell, each disk's force and torque and,
-// with with_dem, the particle phase `pa` (run by the last disk workgroup to finish)
-void launch_step(int storage, const LatticeArgs& a, const ParticleArgs& pa, bool with_dem,
-                 hipStream_t s);
+// lattice part of the coupled step (step.hip): every cell's update, each disk's force and torque
+void launch_lattice_step(int storage, const LatticeArgs& a, hipStream_t s);
 void launch_solid_field(int storage, const LatticeArgs& a, double* eps_out, hipStream_t s);
 
 // particle phase alone (particles.hip): DEM and/or the disk tables, one workgroup

@@ -96,7 +96,7 @@ def load_library():
         "imb_save_state": (C.c_int, [_VP, _VP, C.c_size_t]),
         "imb_load_state": (C.c_int, [_VP, _VP, C.c_size_t]),
         "imb_set_kernel_timing": (C.c_int, [_VP, C.c_int]),
-        "imb_get_kernel_timing": (C.c_int, [_VP, _D, P(C.c_int64)]),
+        "imb_get_kernel_timing": (C.c_int, [_VP, _D, P(C.c_int64), _D, P(C.c_int64)]),
         "imb_copy_kernel": (C.c_int, [_VP, _VP, C.c_size_t, _VP]),
         "imb_adjoint": (C.c_int, [_VP, C.c_int32, C.c_int32, _D, _D, _D, _D, _D, _D, _D, _D,
                                   _D, _D, _D]),
@@ -304,12 +304,16 @@ class Simulation:
                     "imb_set_kernel_timing")
 
     def kernel_timing(self):
-        """Summed milliseconds and launch count of the step kernel since set_kernel_timing(True)
-        (HIP events around every launch on the simulation's stream)."""
-        ms, n = C.c_double(), C.c_int64()
-        self._check(load_library().imb_get_kernel_timing(self._h, C.byref(ms), C.byref(n)),
+        """Summed milliseconds and launch counts of the lattice kernel and the particle phase
+        since set_kernel_timing(True) (HIP events around every launch on the simulation's
+        stream)."""
+        lm, pm = C.c_double(), C.c_double()
+        ln, pn = C.c_int64(), C.c_int64()
+        self._check(load_library().imb_get_kernel_timing(self._h, C.byref(lm), C.byref(ln),
+                                                         C.byref(pm), C.byref(pn)),
                     "imb_get_kernel_timing")
-        return {"step_ms": ms.value, "step_launches": n.value}
+        return {"lattice_ms": lm.value, "lattice_launches": ln.value,
+                "particle_ms": pm.value, "particle_launches": pn.value}
 
     def adjoint(self, nsteps: int, k_ckpt: int, wfx=None, wfy=None, wtz=None,
                 populations: bool = False):

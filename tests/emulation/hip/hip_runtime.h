@@ -56,6 +56,7 @@ inline void __threadfence() { std::atomic_thread_fence(std::memory_order_seq_cst
 #define __builtin_amdgcn_fence(a, b) std::atomic_thread_fence(std::memory_order_seq_cst)
 #define __builtin_amdgcn_wave_barrier() ((void)0)
 #define __builtin_amdgcn_s_sleep(n) std::this_thread::yield()
+#define __builtin_amdgcn_s_waitcnt(n) std::atomic_thread_fence(std::memory_order_seq_cst)
 long long wall_clock64();
 inline int __popcll(unsigned long long v) { return __builtin_popcountll(v); }
 

@@ -234,9 +234,9 @@ def test_fp32_full_size_against_oracle():
 
 
 def test_graph_replays_match_direct_launches():
-    """imb_step replays captured graphs (2- and 32-step chains) of the step kernel; each replay,
-    with readbacks and syncs in between, must equal direct launches, and launches between timing
-    events, bit for bit."""
+    """imb_step replays captured graphs (2- and 32-step chains); each replay, with readbacks and
+    syncs in between, must equal direct launches, and launches between timing events, bit for
+    bit."""
     case = W.moving_disks(seed=4, nx=320, ny=160, n=14, storage="f32")
     g, d, t = gpu_for(case), gpu_for(case), gpu_for(case)
     d.set_graphs(False)
@@ -250,7 +250,7 @@ def test_graph_replays_match_direct_launches():
                 assert np.array_equal(a, b)
     assert g.counts() == d.counts() == t.counts() == (14, 137)
     kt = t.kernel_timing()
-    assert kt["step_launches"] == 137 and kt["step_ms"] > 0
+    assert kt["lattice_launches"] == kt["particle_launches"] == 137 and kt["lattice_ms"] > 0
 
 
 def test_dense_channel_fp64_parity_and_determinism():
