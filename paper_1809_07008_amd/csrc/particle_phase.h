@@ -50,13 +50,17 @@ __device__ inline double block_sum(double v, double* s_red) {
   return t;
 }
 
-__device__ inline int block_or(int v, int* s_flag) {
-  if (threadIdx.x == 0) *s_flag = 0;
+// Bitwise OR of v over the workgroup (one barrier); s_part holds NT / 64 ints and is free
+// again once every thread has returned.
+template <int NT>
+__device__ inline int block_or(int v, int* s_part) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v |= __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = v;
   __syncthreads();
-  if (v) atomicOr(s_flag, v);
-  __syncthreads();
-  const int r = *s_flag;
-  __syncthreads();
+  int r = 0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) r |= s_part[w];
   return r;
 }
 
@@ -101,7 +105,7 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
 #pragma clang fp contract(off)
   constexpr int PWAVES = NT / 64;
   __shared__ double s_red[PWAVES];
-  __shared__ int s_flag, s_wave[PWAVES];
+  __shared__ int s_wave[PWAVES], s_or[PWAVES];
   __shared__ int s_nact, s_aid[64], s_ann[64], s_anb[64][8];
   __shared__ double s_ast[64][6];
   constexpr int NB_REG = 8;   // neighbour ids kept in registers; the rest are read from the list
@@ -234,7 +238,7 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
       if (ddx * ddx + ddy * ddy > lim * lim) mine |= 2;
     }
     if (p == 0 && rebuild_flag) mine |= 2;
-    flags = block_or(mine, &s_flag);
+    flags = block_or<NT>(mine, s_or);
   }
   if ((flags & 1) || a.build_lists) {
     // ---- neighbour list maintenance
@@ -325,8 +329,9 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
       // block barriers
       if (threadIdx.x == 0) s_nact = 0;
       __syncthreads();
+      int idx = -1;  // this disk's slot among the active ones
       if (own && active) {
-        const int idx = atomicAdd(&s_nact, 1);
+        idx = atomicAdd(&s_nact, 1);
         if (idx < 64) {
           s_aid[idx] = p;
           s_ast[idx][0] = Fx; s_ast[idx][1] = Fy; s_ast[idx][2] = Tz;
@@ -381,11 +386,7 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
         }
         __syncthreads();
         if (own && active) {
-          for (int t2 = 0; t2 < nact; ++t2) {
-            if (s_aid[t2] == p) {
-              fcx = s_ast[t2][3]; fcy = s_ast[t2][4]; om = s_ast[t2][5];
-            }
-          }
+          fcx = s_ast[idx][3]; fcy = s_ast[idx][4]; om = s_ast[idx][5];
           x = sx[p]; y = sy[p]; vx = svx[p]; vy = svy[p];
         }
       } else if (nact > 64) {
