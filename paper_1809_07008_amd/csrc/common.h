@@ -105,7 +105,6 @@ struct ParticleArgs {
   int build_lists;        // maintain the neighbour lists even when no disk is free
   int* band_off;   // written with the table: per tile row, the disks whose box touches it
   int* band_ids;   // capacity np * MAXSLOT
-  int pstride;
   int do_finalize, do_dem, do_table, init_contacts;
   const double *wfx, *wfy, *wtz;  // objective weights (adjoint forward); may be null
   double* J;                      // objective accumulator; null = not accumulated

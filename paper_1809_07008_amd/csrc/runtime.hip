@@ -206,7 +206,6 @@ ParticleArgs particle_args(imb_sim* s, int out_slot) {
   a.tiles_x = s->g.tiles_x; a.tiles_y = s->g.tiles_y; a.tw = s->g.tw; a.th = s->g.th;
   a.s = s->d.ps; a.tab = s->d.tab[out_slot]; a.err = s->d.err;
   a.band_off = s->d.band_off[out_slot]; a.band_ids = s->d.band_ids[out_slot];
-  a.pstride = std::max(s->cfg.max_particles, 1);
   a.direct = s->d.force;
   a.build_lists = 1;
   return a;
