@@ -15,6 +15,17 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libimb.so")
+_HIP_LIB = LIB_PATH
+
+
+def _device_buffer(nbytes: int, device):
+    """The workspace tensor the library carves; the HIP library needs GPU memory (only a test
+    build of the library for the host may be given host memory)."""
+    import torch
+    dev = torch.device(device)
+    if dev.type != "cuda" and os.path.abspath(LIB_PATH) == os.path.abspath(_HIP_LIB):
+        raise ValueError("libimb.so runs on the GPU: its workspace must be a cuda device tensor")
+    return torch.empty(nbytes, dtype=torch.uint8, device=dev)
 
 STORAGE = {"f64": 0, "f32": 1, "f16": 2}
 FLAG_WALLS = 1
@@ -180,7 +191,7 @@ class Simulation:
         nbytes = C.c_size_t()
         self._check(lib.imb_required_bytes(C.byref(cfg), C.byref(nbytes)), "imb_required_bytes",
                     handle=False)
-        self._buf = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=device)
+        self._buf = _device_buffer(nbytes.value + 256, device)
         ptr = self._buf.data_ptr()
         off = (-ptr) % 256
         self._stream = stream
@@ -384,7 +395,7 @@ class Batch:
         self._h = None
         self._check(lib.imb_batch_required_bytes(len(self.cfgs), arr, C.byref(nbytes)),
                     "imb_batch_required_bytes", handle=False)
-        self._buf = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=device)
+        self._buf = _device_buffer(nbytes.value + 256, device)
         ptr = self._buf.data_ptr()
         off = (-ptr) % 256
         h = C.c_void_p()

@@ -91,3 +91,12 @@ def test_library_has_no_oracle_dependency():
     assert "o_step" not in out and "o_collide_cell" not in out
     src = open(os.path.join(ROOT, "paper_1809_07008_amd", "imb.py")).read()
     assert "oracle" not in src.replace("Oracle", "")
+
+
+def test_host_memory_is_refused_for_the_hip_library():
+    """The binding never hands host memory to the GPU library as its workspace (the check runs
+    before any device call, so it is a CPU test)."""
+    from paper_1809_07008_amd import workloads
+    case = workloads.single_disk_channel()
+    with pytest.raises(ValueError):
+        imb.Simulation(imb.config_from_case(case), device="cpu")
