@@ -105,6 +105,31 @@ def adjoint_ratio(tile, reps: int = 3):
                                                 max(kt["particle_launches"], 1), 2)}
 
 
+def batch_throughput(steps: int = 100):
+    """Batched form on the 64-channel workload (11.1 M cells, 4489 disks, FP32): GPU time per
+    step (HIP events around one graph replay) under each schedule at the default tile shape, then
+    after the autotuner."""
+    from paper_1809_07008_amd import imb, workloads
+    cases = workloads.batch_channels(seed=0)
+    cells = sum(c.cells for c in cases)
+    b = imb.batch_from_cases(cases)
+    out = {"workload": "batch_channels_n64", "channels": len(cases), "cells": cells,
+           "disks": int(sum(c.particles.n for c in cases)), "steps": steps}
+    for name, sched in (("persistent", imb.IMB_BATCH_PERSISTENT),
+                        ("per_step", imb.IMB_BATCH_PER_STEP)):
+        b.set_schedule(sched)
+        b.step(4)
+        ms = b.timed_steps(steps) / steps
+        out[name + "_ms_per_step"] = round(ms, 4)
+    b.autotune(trial_steps=10)
+    ms = b.timed_steps(steps) / steps
+    out["tuned"] = b.launch()
+    out["tuned_ms_per_step"] = round(ms, 4)
+    out["tuned_mlups"] = round(cells / (ms * 1e-3) / 1e6, 1)
+    b.close()
+    return out
+
+
 def copy_calibration(nbytes: int, reps: int = 10) -> int:
     """Runs only the plain copy kernel over nbytes (the counter calibration of the traffic
     figure) and prints its bandwidth."""
@@ -162,7 +187,8 @@ def main(argv=None):
     ap.add_argument("--tile-rows", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true",
-                    help="skip the adjoint/forward ratio (profiling the forward step alone)")
+                    help="skip the adjoint/forward ratio and the batched form (profiling the "
+                         "forward step alone)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch kernels directly instead of replaying captured graphs")
@@ -247,6 +273,9 @@ def main(argv=None):
     if not args.no_adjoint:
         out["adjoint"] = adjoint_ratio((args.tile_w, args.tile_rows))
         print("bench: adjoint ratio %.3f" % out["adjoint"]["ratio"], file=sys.stderr, flush=True)
+        out["batch"] = batch_throughput()
+        print("bench: batch %.3f ms per step" % out["batch"]["tuned_ms_per_step"],
+              file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(out), flush=True)

@@ -48,6 +48,10 @@ extern "C" {
 
 #define IMB_FLAG_WALLS 1u   /* resting half-way bounce-back walls in y (else periodic in y) */
 
+/* batch schedules (imb_batch_set_schedule) */
+#define IMB_BATCH_PERSISTENT 0
+#define IMB_BATCH_PER_STEP 1
+
 #define IMB_MODE_FREE 0      /* moved by the DEM (Eqs. 8, 10, 11, 17) */
 #define IMB_MODE_FIXED 1     /* never moved; its velocity/spin still act on the fluid */
 #define IMB_MODE_PRESCRIBED 2 /* moves by its velocity once per lattice step */
@@ -198,14 +202,18 @@ int imb_get_adjoint_timing(imb_sim* sim, double* forward_ms, double* reverse_ms,
 
 /* -------------------------------------------------------------- batched channels
  * Many independent simulations (channels), each with its own configuration (lattice size,
- * relaxation time, disks), advanced together by ONE persistent kernel per imb_batch_step call,
- * captured once per (nsteps, buffer parity) in a hipGraph and replayed.  Inside the kernel the
- * channels are split into two halves of about equal tile counts; every step is two phases
- * separated by grid-wide barriers (lattice tiles of one half while the particle phases of the
- * other half run), with workgroups pulling work items (a channel's particle phase, a chunk of
- * (channel, disk) items or a chunk of (channel, tile) items) from an atomic counter.
+ * relaxation time, disks), advanced together; the launches of one imb_batch_step call are
+ * captured once per (nsteps, buffer parity) in a hipGraph and replayed.  Two schedules:
+ *   IMB_BATCH_PERSISTENT: ONE persistent kernel per call.  The channels are split into two
+ *     halves of about equal tile counts; every step is two phases separated by grid-wide
+ *     barriers (lattice tiles of one half while the particle phases of the other half run),
+ *     with workgroups pulling work items (a channel's particle phase, a chunk of (channel, disk)
+ *     items or a chunk of (channel, tile) items) from an atomic counter.
+ *   IMB_BATCH_PER_STEP: two launches per step, the lattice part of every channel (disk items,
+ *     then tiles) and one particle-phase workgroup per channel.
  * The method per channel is the coupled step of imb_step (Sec. 2; Eqs. 1-2, 12-17), and a
- * channel evolves bit for bit as the same channel would alone with the same tile shape.
+ * channel evolves bit for bit as the same channel would alone with the same tile shape, under
+ * either schedule.
  * Limits: 1..128 channels, F32 storage, at most 256 disks and ny <= 2559 per channel
  * (IMB_EINVAL / IMB_EUNSUPPORTED otherwise).  A barrier that does not open within 2 s aborts
  * the kernel (every workgroup exits) and the next synchronising call returns IMB_EHIP. */
@@ -240,10 +248,15 @@ int imb_batch_set_launch(imb_batch* b, int32_t grid, int32_t tile_w, int32_t til
 /* Current grid, tile shape and the co-resident maximum (any pointer may be NULL). */
 int imb_batch_get_launch(imb_batch* b, int32_t* grid, int32_t* tile_w, int32_t* tile_rows,
                          int32_t* max_grid);
+/* Schedule of the batch (IMB_BATCH_PERSISTENT, the default, or IMB_BATCH_PER_STEP; other values
+ * IMB_EINVAL).  set synchronises. */
+int imb_batch_set_schedule(imb_batch* b, int32_t schedule);
+int imb_batch_get_schedule(imb_batch* b, int32_t* schedule);
 /* Autotuner: times trial_steps steps (after 2 warm-up steps) for each candidate tile shape
- * (16x4, 32x1/2/4, 64x1/2/4, 128x1/2: tile width x rows per thread) and grid size (every
- * co-resident workgroup, or one workgroup fewer per compute unit), rebuilding the disk tables
- * for the shape and restoring the channels' state after every trial, and keeps the fastest.
+ * (16x4, 32x1/2/4, 64x1/2/4, 128x1/2: tile width x rows per thread) under the per-step schedule
+ * and under the persistent schedule with two grid sizes (every co-resident workgroup, or one
+ * workgroup fewer per compute unit), rebuilding the disk tables for the shape and restoring the
+ * channels' state after every trial, and keeps the fastest (shape, schedule, grid).
  * max_trials > 0 caps the number of trials.  *trial_ms (may be NULL) receives the best time per
  * step.  Needs a temporary device copy of the channels' memory.  Synchronises; the simulation
  * state is unchanged. */

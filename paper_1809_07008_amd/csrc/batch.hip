@@ -49,7 +49,6 @@ struct BatchChannel {
 };
 
 struct BatchArgs {
-  const BatchChannel* ch;
   const int* half_ch;    // [2][MAX_BATCH] channels of each half
   const int* half_pref;  // [2][MAX_BATCH + 1] tile prefix sums of each half
   const int* half_dpref; // [2][MAX_BATCH + 1] disk prefix sums of each half
@@ -118,7 +117,9 @@ __device__ inline int find_slot(const int* pref, int n, int i) {
   return lo;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs B) {
+// ch: the channel table (read-only during the launch; the channel and item indices are uniform
+// over a workgroup, so a channel's arguments are read with scalar loads).
+__global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs B, const BatchChannel* __restrict__ ch) {
   __shared__ int s_item, s_abort;
   __shared__ int s_hch[2][MAX_BATCH];
   __shared__ int s_hpref[2][MAX_BATCH + 1];
@@ -159,11 +160,12 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs B) {
         s_abort = (int)ld_agent(&B.sync[4]);
       }
       __syncthreads();
-      const int i = s_item;
+      const int i = __builtin_amdgcn_readfirstlane(s_item);
       if (s_abort || i >= npart + ndc + ntc) break;
       if (i < npart) {  // the particle phase of step n (half B: of step n - 1)
         const int m = h == 1 ? n : n - 1;
-        particle_phase<BLOCK>(B.ch[s_hch[ph][i]].pa[(B.parity0 + m) & 1], pp_lds);
+        const int ci = __builtin_amdgcn_readfirstlane(s_hch[ph][i]);
+        particle_phase<BLOCK>(ch[ci].pa[(B.parity0 + m) & 1], pp_lds);
         continue;
       }
       const bool is_disk = i < npart + ndc;
@@ -173,7 +175,8 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs B) {
       for (int t = c0; t < c1; ++t) {  // the chunk's items in order (block-uniform bounds)
         if (t > c0) __syncthreads();   // the previous item's LDS is no longer read
         const int k = find_slot(is_disk ? s_hdpref[h] : s_hpref[h], hn[h], t);
-        const LatticeArgs la = B.ch[s_hch[h][k]].la[par];
+        const int ci = __builtin_amdgcn_readfirstlane(s_hch[h][k]);
+        const LatticeArgs la = ch[ci].la[par];
         if (is_disk) {
           disk_cells<StoreF32>(la, t - s_hdpref[h][k]);
         } else {
@@ -183,6 +186,36 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs B) {
     }
     if (p + 1 < nphase && !grid_barrier(B.sync, B.nblocks, 2 + (p & 1), B.spin_ticks)) return;
   }
+}
+
+// Per-step schedule: the lattice part of every channel as one ordinary launch (the disk items
+// of all channels first, then their tiles; the same device code as k_step), then one
+// particle-phase workgroup per channel.  No grid barrier and no device-wide fence: the kernel
+// boundaries order the steps.
+// The channel index is uniform over the workgroup and the tables are read-only during the
+// launch, so a channel's arguments are read with scalar loads instead of occupying vector
+// registers.
+__global__ __launch_bounds__(BLOCK) void k_batch_lattice(const BatchChannel* __restrict__ ch,
+                                                         const int* __restrict__ dpref,
+                                                         const int* __restrict__ tpref, int nch,
+                                                         int ndisk, int parity) {
+  const int b = blockIdx.x;
+  if (b < ndisk) {
+    const int k = __builtin_amdgcn_readfirstlane(find_slot(dpref, nch, b));
+    const LatticeArgs la = ch[k].la[parity];
+    disk_cells<StoreF32>(la, b - dpref[k]);
+    return;
+  }
+  const int t = b - ndisk;
+  const int k = __builtin_amdgcn_readfirstlane(find_slot(tpref, nch, t));
+  const LatticeArgs la = ch[k].la[parity];
+  fluid_tile<StoreF32>(la, t - tpref[k]);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_batch_particles(const BatchChannel* __restrict__ ch,
+                                                           int parity) {
+  __shared__ double pp_lds[PP_LDS];
+  particle_phase<BLOCK>(ch[blockIdx.x].pa[parity], pp_lds);
 }
 
 }  // namespace imb
@@ -199,10 +232,13 @@ struct imb_batch {
   bool owns = false;
   BatchChannel* d_ch = nullptr;
   int* d_half = nullptr;
+  int* d_all = nullptr;  // [2][MAX_BATCH + 1]: disk and tile prefix sums over all channels
   unsigned* d_sync = nullptr;
   std::vector<BatchChannel> h_ch;
   std::vector<int> h_half;
   int half_n[2] = {0, 0}, half_t[2] = {0, 0}, half_d[2] = {0, 0};
+  int all_d = 0, all_t = 0;    // disks and tiles of all channels
+  int schedule = IMB_BATCH_PERSISTENT;
   int grid = 0, grid_user = 0, occupancy = 0;
   int tile_w = 32, tile_rows = 2;
   int cur = 0;
@@ -260,6 +296,7 @@ int validate_batch(int32_t nsim, const imb_config* cfgs, std::string* why) {
 size_t table_bytes(int nsim) {
   return align_up(sizeof(BatchChannel) * nsim, 256) +
          align_up(sizeof(int) * 2 * (3 * MAX_BATCH + 2), 256) +
+         align_up(sizeof(int) * 2 * (MAX_BATCH + 1), 256) +
          align_up(sizeof(unsigned) * SYNC_WORDS, 256);
 }
 
@@ -320,11 +357,31 @@ int refresh(imb_batch* b) {
     b->half_t[h] = acc;
     b->half_d[h] = dacc;
   }
+  // all channels in order (per-step schedule)
+  std::vector<int> all(2 * (MAX_BATCH + 1), 0);
+  {
+    int dacc = 0, tacc = 0;
+    for (int c = 0; c < b->nch; ++c) {
+      all[c] = dacc;
+      all[MAX_BATCH + 1 + c] = tacc;
+      dacc += b->h_ch[c].la[0].np;
+      tacc += tiles[c];
+    }
+    for (int c = b->nch; c <= MAX_BATCH; ++c) {
+      all[c] = dacc;
+      all[MAX_BATCH + 1 + c] = tacc;
+    }
+    b->all_d = dacc;
+    b->all_t = tacc;
+  }
   hipError_t e = hipMemcpyAsync(b->d_ch, b->h_ch.data(), sizeof(BatchChannel) * b->nch,
                                 hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(b->d_half, b->h_half.data(), sizeof(int) * b->h_half.size(),
                        hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->d_all, all.data(), sizeof(int) * all.size(), hipMemcpyHostToDevice,
+                       b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) {
     b->err = std::string("batch table upload: ") + hipGetErrorString(e);
@@ -337,7 +394,6 @@ int refresh(imb_batch* b) {
 
 BatchArgs batch_args(imb_batch* b, int nsteps, int parity) {
   BatchArgs a{};
-  a.ch = b->d_ch;
   a.half_ch = b->d_half;
   a.half_pref = b->d_half + 2 * MAX_BATCH;
   a.half_dpref = b->d_half + 2 * MAX_BATCH + 2 * (MAX_BATCH + 1);
@@ -361,8 +417,19 @@ BatchArgs batch_args(imb_batch* b, int nsteps, int parity) {
 
 void enqueue_batch(imb_batch* b, int nsteps, int parity, hipStream_t s) {
   launch_fill_zero(b->d_sync, sizeof(unsigned) * SYNC_WORDS, s);
+  if (b->schedule == IMB_BATCH_PER_STEP) {
+    for (int n = 0; n < nsteps; ++n) {
+      const int par = (parity + n) & 1;
+      hipLaunchKernelGGL(k_batch_lattice, dim3(b->all_d + b->all_t), dim3(BLOCK), 0, s, b->d_ch,
+                         (const int*)b->d_all, (const int*)(b->d_all + MAX_BATCH + 1), b->nch,
+                         b->all_d, par);
+      hipLaunchKernelGGL(k_batch_particles, dim3(b->nch), dim3(BLOCK), 0, s, b->d_ch, par);
+    }
+    return;
+  }
   BatchArgs a = batch_args(b, nsteps, parity);
-  hipLaunchKernelGGL(k_batch, dim3(b->grid), dim3(BLOCK), 0, s, a);
+  hipLaunchKernelGGL(k_batch, dim3(b->grid), dim3(BLOCK), 0, s, a,
+                     (const BatchChannel*)b->d_ch);
 }
 
 hipGraphExec_t capture_batch(imb_batch* b, int nsteps, int parity) {
@@ -521,6 +588,8 @@ int imb_batch_create(int32_t nsim, const imb_config* cfgs, void* hip_stream, voi
   off += align_up(sizeof(BatchChannel) * nsim, 256);
   b->d_half = (int*)(b->mem + off);
   off += align_up(sizeof(int) * 2 * (3 * MAX_BATCH + 2), 256);
+  b->d_all = (int*)(b->mem + off);
+  off += align_up(sizeof(int) * 2 * (MAX_BATCH + 1), 256);
   b->d_sync = (unsigned*)(b->mem + off);
   off += align_up(sizeof(unsigned) * SYNC_WORDS, 256);
   launch_fill_zero(b->mem, off, b->stream);
@@ -648,6 +717,21 @@ int imb_batch_get_launch(imb_batch* b, int32_t* grid, int32_t* tile_w, int32_t* 
   return IMB_OK;
 }
 
+int imb_batch_set_schedule(imb_batch* b, int32_t schedule) {
+  if (!b || (schedule != IMB_BATCH_PERSISTENT && schedule != IMB_BATCH_PER_STEP))
+    return IMB_EINVAL;
+  hipStreamSynchronize(b->stream);
+  if (schedule != b->schedule) drop_batch_graphs(b);
+  b->schedule = schedule;
+  return IMB_OK;
+}
+
+int imb_batch_get_schedule(imb_batch* b, int32_t* schedule) {
+  if (!b || !schedule) return IMB_EINVAL;
+  *schedule = b->schedule;
+  return IMB_OK;
+}
+
 int imb_batch_autotune(imb_batch* b, int32_t trial_steps, double* trial_ms, int32_t max_trials) {
   if (!b || trial_steps < 1) return IMB_EINVAL;
   int rc = batch_sync(b);
@@ -681,23 +765,26 @@ int imb_batch_autotune(imb_batch* b, int32_t trial_steps, double* trial_ms, int3
                                   {128, 1}, {128, 2}, {16, 4}};
   const int nshapes = (int)(sizeof shapes / sizeof shapes[0]);
   double best = 1e300;
-  int bw = b->tile_w, br = b->tile_rows, bg = b->grid_user;
+  int bw = b->tile_w, br = b->tile_rows, bg = b->grid_user, bs = b->schedule;
   int done = 0;
   int cu_count = 0;
   hipDeviceGetAttribute(&cu_count, hipDeviceAttributeMultiprocessorCount, 0);
   cu_count = std::max(cu_count, 1);
   for (int k = 0; k < nshapes && rc == IMB_OK; ++k) {
-    for (int gsel = 0; gsel < 2 && rc == IMB_OK; ++gsel) {
+    for (int gsel = 0; gsel < 3 && rc == IMB_OK; ++gsel) {
       if (max_trials > 0 && done >= max_trials) break;
-      // grid: every co-resident workgroup, or one workgroup fewer per compute unit
-      const int g = gsel == 0 ? 0 : b->occupancy - cu_count;
-      if (gsel == 1 && g < cu_count) continue;
+      // per-step schedule; persistent with every co-resident workgroup, or with one workgroup
+      // fewer per compute unit
+      const int sched = gsel == 0 ? IMB_BATCH_PER_STEP : IMB_BATCH_PERSISTENT;
+      const int g = gsel == 2 ? b->occupancy - cu_count : 0;
+      if (gsel == 2 && g < cu_count) continue;
       // the disk tables were restored with the state: rebuild them for this trial's shape
       if (set_shape(b, shapes[k][0], shapes[k][1]) != IMB_OK) {  // shape not valid here
         restore();
         continue;
       }
       b->grid_user = g;
+      b->schedule = sched;
       b->dirty = true;
       rc = run_steps(b, 2, false);  // warm-up
       if (rc) break;
@@ -712,6 +799,7 @@ int imb_batch_autotune(imb_batch* b, int32_t trial_steps, double* trial_ms, int3
         bw = shapes[k][0];
         br = shapes[k][1];
         bg = g;
+        bs = sched;
       }
       restore();
       ++done;
@@ -719,6 +807,7 @@ int imb_batch_autotune(imb_batch* b, int32_t trial_steps, double* trial_ms, int3
   }
   if (!rc) rc = set_shape(b, bw, br);
   b->grid_user = bg;
+  b->schedule = bs;
   b->dirty = true;
   hipStreamSynchronize(b->stream);
   hipFree(save);

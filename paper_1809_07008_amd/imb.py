@@ -32,6 +32,8 @@ FLAG_WALLS = 1
 MODE_FREE, MODE_FIXED, MODE_PRESCRIBED = 0, 1, 2
 
 IMB_OK = 0
+IMB_BATCH_PERSISTENT = 0  # one persistent kernel per imb_batch_step call
+IMB_BATCH_PER_STEP = 1    # two launches per step (lattice of all channels, particle phases)
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EOVERFLOW", -5: "EUNSTABLE", -6: "EDEM",
           -7: "EUNSUPPORTED"}
 
@@ -47,7 +49,8 @@ EXPORTED = [
     "imb_batch_set_launch", "imb_strerror", "imb_last_error", "imb_version",
     "imb_get_solid_field", "imb_set_graphs", "imb_get_adjoint_timing",
     "imb_batch_get_populations", "imb_batch_get_launch", "imb_batch_autotune",
-    "imb_batch_get_timing", "imb_batch_last_error",
+    "imb_batch_get_timing", "imb_batch_last_error", "imb_batch_set_schedule",
+    "imb_batch_get_schedule",
 ]
 
 
@@ -129,6 +132,8 @@ def load_library():
         "imb_batch_autotune": (C.c_int, [_VP, C.c_int32, _D, C.c_int32]),
         "imb_batch_get_timing": (C.c_int, [_VP, C.c_int32, _D]),
         "imb_batch_last_error": (C.c_char_p, [_VP]),
+        "imb_batch_set_schedule": (C.c_int, [_VP, C.c_int32]),
+        "imb_batch_get_schedule": (C.c_int, [_VP, _I32]),
         "imb_strerror": (C.c_char_p, [C.c_int]),
         "imb_last_error": (C.c_char_p, [_VP]),
         "imb_version": (C.c_char_p, []),
@@ -480,12 +485,19 @@ class Batch:
         self._check(load_library().imb_batch_set_launch(self._h, int(grid), int(tile_w),
                                                         int(tile_rows)), "imb_batch_set_launch")
 
+    def set_schedule(self, schedule: int):
+        self._check(load_library().imb_batch_set_schedule(self._h, int(schedule)),
+                    "imb_batch_set_schedule")
+
     def launch(self):
-        v = [C.c_int32() for _ in range(4)]
-        self._check(load_library().imb_batch_get_launch(self._h, *(C.byref(x) for x in v)),
+        v = [C.c_int32() for _ in range(5)]
+        lib = load_library()
+        self._check(lib.imb_batch_get_launch(self._h, *(C.byref(x) for x in v[:4])),
                     "imb_batch_get_launch")
+        self._check(lib.imb_batch_get_schedule(self._h, C.byref(v[4])), "imb_batch_get_schedule")
         return {"grid": v[0].value, "tile_w": v[1].value, "tile_rows": v[2].value,
-                "max_grid": v[3].value}
+                "max_grid": v[3].value,
+                "schedule": "per_step" if v[4].value == IMB_BATCH_PER_STEP else "persistent"}
 
     def autotune(self, trial_steps: int = 5, max_trials: int = 0) -> float:
         """Runs the library's autotuner; returns the best time per step (ms)."""

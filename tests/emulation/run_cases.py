@@ -121,12 +121,14 @@ def batch():
     for k, c in enumerate(cases):
         b.set_case_particles(k, c.particles)
     b.step(3)
+    b.set_schedule(imb.IMB_BATCH_PER_STEP)
+    b.step(2)
     b.sync()
     for k, c in enumerate(cases):
         s = sim_of(c, "f32")
-        s.step(3)
+        s.step(5)
         check("batch channel %d equals the channel alone" % k,
-              np.array_equal(b.populations(k), s.populations()), "")
+              np.array_equal(b.populations(k), s.populations()), "both schedules")
     b.autotune(trial_steps=1, max_trials=3)
     b.step(1)
     b.sync()

@@ -42,10 +42,15 @@ def assert_same(b, k, sim):
             assert np.array_equal(u, v), k
 
 
-@pytest.mark.parametrize("tile", [(32, 2), (64, 1), (16, 4)])
-def test_batch_channels_match_single_simulations(tile):
+@pytest.mark.parametrize("tile,schedule", [((32, 2), imb.IMB_BATCH_PERSISTENT),
+                                           ((64, 1), imb.IMB_BATCH_PERSISTENT),
+                                           ((16, 4), imb.IMB_BATCH_PERSISTENT),
+                                           ((32, 2), imb.IMB_BATCH_PER_STEP),
+                                           ((16, 4), imb.IMB_BATCH_PER_STEP)])
+def test_batch_channels_match_single_simulations(tile, schedule):
     cases = mixed_cases()
     b = imb.batch_from_cases(cases, tile_w=tile[0], tile_rows=tile[1])
+    b.set_schedule(schedule)
     b.step(17)
     b.step(13)  # other buffer parity, other graph
     b.sync()
@@ -95,6 +100,8 @@ def test_autotune_leaves_state_and_picks_a_valid_shape():
     r = imb.batch_from_cases(cases)
     r.step(5)
     r.set_launch(grid=launch["grid"], tile_w=launch["tile_w"], tile_rows=launch["tile_rows"])
+    r.set_schedule(imb.IMB_BATCH_PER_STEP if launch["schedule"] == "per_step"
+                   else imb.IMB_BATCH_PERSISTENT)
     r.step(10)
     r.sync()
     for k in range(len(cases)):
@@ -104,11 +111,13 @@ def test_autotune_leaves_state_and_picks_a_valid_shape():
                 assert np.array_equal(u, v), k
 
 
-def test_batched_channel_workload_sampled_against_single():
+@pytest.mark.parametrize("schedule", [imb.IMB_BATCH_PERSISTENT, imb.IMB_BATCH_PER_STEP])
+def test_batched_channel_workload_sampled_against_single(schedule):
     """64 channels of 128x64 .. 1024x512 with 1-200 moving disks each (seeded), 8 steps; a
     sample of channels compared bit for bit with the same channels run alone."""
     cases = W.batch_channels(seed=0)
     b = imb.batch_from_cases(cases)
+    b.set_schedule(schedule)
     b.step(8)
     b.sync()
     for k in (0, 7, 31, 63):
@@ -138,6 +147,23 @@ def test_batch_rejects_invalid():
         imb.Batch([c])
     with pytest.raises(imb.ImbError):
         imb.Batch([])
+    b = imb.Batch([imb.make_config(64, 32, 0.6, storage="f32")])
+    with pytest.raises(imb.ImbError):
+        b.set_schedule(2)
+
+
+def test_schedules_can_alternate():
+    """Steps under the two schedules, alternated, equal the same steps under one."""
+    cases = mixed_cases()[:4]
+    a = imb.batch_from_cases(cases)
+    b = imb.batch_from_cases(cases)
+    for n, sched in ((3, imb.IMB_BATCH_PER_STEP), (4, imb.IMB_BATCH_PERSISTENT),
+                     (5, imb.IMB_BATCH_PER_STEP)):
+        b.set_schedule(sched)
+        b.step(n)
+    a.step(12)
+    for k in range(len(cases)):
+        assert np.array_equal(a.populations(k), b.populations(k)), k
     b = imb.Batch([imb.make_config(64, 32, 0.6, storage="f32")])
     z = np.zeros(1)
     assert imb.load_library().imb_batch_get_forces(b._h, 3, imb._dp(z), imb._dp(z),
