@@ -129,10 +129,10 @@ struct StoreF32 {
   __device__ static void store(S* p, long long i, T v, T) { p[i] = v; }
 };
 // FP16: h * 2^14 in binary16.  store() rounds to nearest even (used for set-up); store_sr()
-// rounds stochastically: up with probability equal to the fractional position between the two
-// neighbouring binary16 values, from a counter-based random word, so the rounding error of the
-// step-to-step updates has zero mean instead of the systematic bias of round-to-nearest on
-// increments of about one unit in the last place.
+// rounds stochastically: away from zero with probability equal to the fractional position
+// between the two neighbouring binary16 values, from a counter-based random word, so the
+// rounding error of the step-to-step updates has zero mean instead of the systematic bias of
+// round-to-nearest on increments of about one unit in the last place.
 struct StoreF16 {
   using T = float;
   using S = __half;
@@ -142,8 +142,25 @@ struct StoreF16 {
     return __half2float(p[i]) * (1.0f / F16_SCALE);
   }
   __device__ static void store(S* p, long long i, T v, T) { p[i] = __float2half_rn(v * F16_SCALE); }
+  // The value rounds away from zero when u < frac, u = (rnd >> 8) / 2^24 and frac the fractional
+  // position of s between its neighbours toward and away from zero.
   __device__ static void store_sr(S* p, long long i, T v, unsigned rnd) {
     const float s = v * F16_SCALE;
+    const float a = fabsf(s);
+    if (a >= 6.103515625e-05f && a < 65504.0f) {
+      // binary16 normal range: a half ulp is 2^13 float ulps, so frac = low / 2^13 with low the
+      // 13 float mantissa bits below the half mantissa, and u < frac exactly when
+      // (rnd >> 19) < low, i.e. when adding (~rnd >> 19) = 8191 - (rnd >> 19) to the float's bits
+      // carries into the half mantissa; the truncated value converts to binary16 exactly
+      const unsigned b = (__float_as_uint(s) + (~rnd >> 19)) & ~0x1FFFu;
+      p[i] = __float2half_rn(__uint_as_float(b));
+      return;
+    }
+    if (!(a < 6.103515625e-05f)) {  // beyond the binary16 range (saturates), or not finite
+      p[i] = __float2half_rz(s);
+      return;
+    }
+    // subnormal binary16 values (spacing 2^-24)
     const __half lo = __float2half_rz(s);  // neighbour toward zero
     const float flo = __half2float(lo);
     if (flo == s) {

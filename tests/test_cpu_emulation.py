@@ -30,3 +30,19 @@ def test_kernels_under_cpu_emulation_with_address_sanitizer():
     assert "AddressSanitizer" not in r.stderr, r.stderr[-6000:]
     assert r.returncode == 0, r.stdout[-3000:] + r.stderr[-3000:]
     assert "all emulated cases passed" in r.stdout
+
+
+def test_fp16_stochastic_rounding_matches_its_rule(tmp_path):
+    """The FP16 codec's stochastic-rounding store, compiled for the host, against the rounding
+    rule written out (tests/emulation/sr_check.cpp)."""
+    root = os.path.dirname(HERE)
+    exe = str(tmp_path / "sr_check")
+    subprocess.check_call(["g++", "-std=c++20", "-O1", "-ffp-contract=off", "-pthread",
+                           "-I" + os.path.join(HERE, "emulation"),
+                           "-I" + os.path.join(root, "paper_1809_07008_amd", "csrc"),
+                           "-I" + os.path.join(root, "include"),
+                           os.path.join(HERE, "emulation", "sr_check.cpp"),
+                           os.path.join(HERE, "emulation", "emu.cpp"), "-o", exe])
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=300)
+    print(r.stdout)
+    assert r.returncode == 0, r.stdout + r.stderr
