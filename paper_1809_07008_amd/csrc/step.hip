@@ -9,7 +9,7 @@
 namespace imb {
 
 template <class St>
-__global__ __launch_bounds__(BLOCK) void k_step(LatticeArgs a) {
+__device__ __forceinline__ void lattice_roles(const LatticeArgs& a) {
   const int b = blockIdx.x;
   if (b < a.np) {
     disk_cells<St>(a, b);
@@ -17,6 +17,16 @@ __global__ __launch_bounds__(BLOCK) void k_step(LatticeArgs a) {
   }
   fluid_tile<St>(a, xcd_remap(b - a.np, a.tiles_x * a.tiles_y));
 }
+
+// FP32 arithmetic (FP32 or FP16 storage): held to 80 VGPRs, six wavefronts per SIMD.
+template <class St>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void k_step(
+    LatticeArgs a) {
+  lattice_roles<St>(a);
+}
+
+// FP64 arithmetic needs more registers than that budget (it would spill).
+__global__ __launch_bounds__(BLOCK) void k_step_f64(LatticeArgs a) { lattice_roles<StoreF64>(a); }
 
 // eps_tot of every cell (diagnostic / parity of the solid-ratio stage alone).
 template <class T>
@@ -42,16 +52,12 @@ __global__ __launch_bounds__(BLOCK) void k_solid_field(LatticeArgs a, double* ep
   }
 }
 
-template <class St>
-void launch_lattice_step_t(const LatticeArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_step<St>, dim3(a.np + a.tiles_x * a.tiles_y), dim3(BLOCK), 0, s, a);
-}
-
 void launch_lattice_step(int storage, const LatticeArgs& a, hipStream_t s) {
+  const dim3 grid(a.np + a.tiles_x * a.tiles_y);
   switch (storage) {
-    case IMB_STORAGE_F64: launch_lattice_step_t<StoreF64>(a, s); break;
-    case IMB_STORAGE_F32: launch_lattice_step_t<StoreF32>(a, s); break;
-    default: launch_lattice_step_t<StoreF16>(a, s); break;
+    case IMB_STORAGE_F64: hipLaunchKernelGGL(k_step_f64, grid, dim3(BLOCK), 0, s, a); break;
+    case IMB_STORAGE_F32: hipLaunchKernelGGL(k_step<StoreF32>, grid, dim3(BLOCK), 0, s, a); break;
+    default: hipLaunchKernelGGL(k_step<StoreF16>, grid, dim3(BLOCK), 0, s, a); break;
   }
 }
 

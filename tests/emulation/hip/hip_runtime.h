@@ -25,6 +25,7 @@ using std::fmax; using std::floor; using std::ceil; using std::asin; using std::
 #define __device__
 #define __global__
 #define __noinline__ __attribute__((noinline))
+#define __forceinline__ inline __attribute__((always_inline))
 #define __restrict__ __restrict
 #define __shared__ static
 #define __launch_bounds__(...)
