@@ -117,6 +117,8 @@ struct StoreF64 {
   using S = double;
   static constexpr bool deviation = false;
   static constexpr bool stochastic = false;
+  __device__ static T decode(S s) { return s; }
+  __device__ static S encode(T v) { return v; }
   __device__ static T load(const S* p, long long i, T) { return p[i]; }
   __device__ static void store(S* p, long long i, T v, T) { p[i] = v; }
 };
@@ -125,6 +127,8 @@ struct StoreF32 {
   using S = float;
   static constexpr bool deviation = true;
   static constexpr bool stochastic = false;
+  __device__ static T decode(S s) { return s; }
+  __device__ static S encode(T v) { return v; }
   __device__ static T load(const S* p, long long i, T) { return p[i]; }
   __device__ static void store(S* p, long long i, T v, T) { p[i] = v; }
 };
@@ -138,13 +142,13 @@ struct StoreF16 {
   using S = __half;
   static constexpr bool deviation = true;
   static constexpr bool stochastic = true;
-  __device__ static T load(const S* p, long long i, T) {
-    return __half2float(p[i]) * (1.0f / F16_SCALE);
-  }
-  __device__ static void store(S* p, long long i, T v, T) { p[i] = __float2half_rn(v * F16_SCALE); }
+  __device__ static T decode(S s) { return __half2float(s) * (1.0f / F16_SCALE); }
+  __device__ static S encode(T v) { return __float2half_rn(v * F16_SCALE); }
+  __device__ static T load(const S* p, long long i, T) { return decode(p[i]); }
+  __device__ static void store(S* p, long long i, T v, T) { p[i] = encode(v); }
   // The value rounds away from zero when u < frac, u = (rnd >> 8) / 2^24 and frac the fractional
   // position of s between its neighbours toward and away from zero.
-  __device__ static void store_sr(S* p, long long i, T v, unsigned rnd) {
+  __device__ static S encode_sr(T v, unsigned rnd) {
     const float s = v * F16_SCALE;
     const float a = fabsf(s);
     if (a >= 6.103515625e-05f && a < 65504.0f) {
@@ -153,26 +157,20 @@ struct StoreF16 {
       // (rnd >> 19) < low, i.e. when adding (~rnd >> 19) = 8191 - (rnd >> 19) to the float's bits
       // carries into the half mantissa; the truncated value converts to binary16 exactly
       const unsigned b = (__float_as_uint(s) + (~rnd >> 19)) & ~0x1FFFu;
-      p[i] = __float2half_rn(__uint_as_float(b));
-      return;
+      return __float2half_rn(__uint_as_float(b));
     }
-    if (!(a < 6.103515625e-05f)) {  // beyond the binary16 range (saturates), or not finite
-      p[i] = __float2half_rz(s);
-      return;
-    }
+    if (!(a < 6.103515625e-05f)) return __float2half_rz(s);  // beyond the range (saturates)
     // subnormal binary16 values (spacing 2^-24)
     const __half lo = __float2half_rz(s);  // neighbour toward zero
     const float flo = __half2float(lo);
-    if (flo == s) {
-      p[i] = lo;
-      return;
-    }
+    if (flo == s) return lo;
     const __half hi = __ushort_as_half((unsigned short)(__half_as_ushort(lo) + 1u));  // away
     const float fhi = __half2float(hi);
     const float frac = (s - flo) / (fhi - flo);
     const float u = (float)(rnd >> 8) * (1.0f / 16777216.0f);
-    p[i] = u < frac ? hi : lo;
+    return u < frac ? hi : lo;
   }
+  __device__ static void store_sr(S* p, long long i, T v, unsigned rnd) { p[i] = encode_sr(v, rnd); }
 };
 
 // 32-bit integer hash "pcg_hash" (Jarzynski & Olano, Hash Functions for GPU Rendering, JCGT 9(3),

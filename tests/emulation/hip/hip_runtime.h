@@ -87,6 +87,12 @@ template <class T> inline T __shfl_up(T v, unsigned delta, int width = 64) {
   const int src = lw >= (int)delta ? l - (int)delta : l;
   return emu_from_bits<T>(emu_wave_exchange(emu_to_bits(v), src));
 }
+template <class T> inline T __shfl_down(T v, unsigned delta, int width = 64) {
+  const int l = emu_lane();
+  const int lw = l & (width - 1);
+  const int src = lw + (int)delta < width ? l + (int)delta : l;
+  return emu_from_bits<T>(emu_wave_exchange(emu_to_bits(v), src));
+}
 inline int __builtin_amdgcn_readfirstlane(int v) {  // every lane of the wave is active
   return (int)emu_wave_exchange(emu_to_bits(v), 0);
 }

@@ -74,6 +74,37 @@ def fp64_parity():
               "force %.2e populations %.2e" % (ferr, perr))
 
 
+def wide_tiles():
+    """Tiles 128 and 256 wide on ragged widths (odd, not a multiple of the tile), walls and
+    periodic y, random initial populations: FP64 parity, and FP16 equal bit for bit to 32x2."""
+    for nx, ny, tile, walls in ((131, 40, (128, 2), True), (259, 24, (256, 2), False),
+                                (130, 37, (128, 4), False), (97, 30, (128, 2), True)):
+        base = moving_case()
+        case = base.with_(nx=nx, ny=ny, walls=walls, particles=W.Particles(
+            np.array([20.3, 60.8, nx - 0.4]), np.array([12.2, ny / 2, ny - 9.7]),
+            np.array([5.5, 4.2, 3.9]), np.array([0.01, -0.01, 0.0]), np.zeros(3),
+            np.array([0.0, 0.001, 0.0]), np.array([0, 2, 1], np.int32)))
+        f0 = W.random_populations(np.random.default_rng(nx), nx, ny, amplitude=0.03)
+        s = sim_of(case, "f64", tile)
+        s.set_populations(f0)
+        s.step(case.steps)
+        ref = oracle_of(case)
+        ref.set_populations(f0)
+        ref.step(case.steps)
+        fg, fo = np.array(s.forces()), np.array(ref.forces())
+        ferr = np.abs(fg - fo).max() / np.abs(fo).max()
+        perr = np.abs(s.populations() - ref.populations()).max()
+        check("fp64 parity %dx%d tile %dx%d walls=%s" % (nx, ny, tile[0], tile[1], walls),
+              ferr < 1e-12 and perr < 1e-13, "force %.2e populations %.2e" % (ferr, perr))
+        a, b = sim_of(case, "f16", tile), sim_of(case, "f16", (32, 2))
+        a.set_populations(f0)
+        b.set_populations(f0)
+        a.step(case.steps)
+        b.step(case.steps)
+        check("f16 tile %dx%d equals tile 32x2 bit for bit" % tile,
+              np.array_equal(a.populations(), b.populations()), "")
+
+
 def reduced_precision():
     case = moving_case()
     ref = oracle_of(case)
@@ -136,6 +167,6 @@ def batch():
 
 
 if __name__ == "__main__":
-    for fn in (fp64_parity, reduced_precision, roundtrip, adjoint, batch):
+    for fn in (fp64_parity, wide_tiles, reduced_precision, roundtrip, adjoint, batch):
         fn()
     print("all emulated cases passed", flush=True)
