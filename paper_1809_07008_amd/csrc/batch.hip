@@ -35,7 +35,7 @@
 namespace imb {
 
 constexpr int MAX_BATCH = 128;   // channels per batch
-constexpr int PP_LDS = 1280;     // doubles of particle-phase scratch: 256 disks x 5
+constexpr int PP_LDS = 256 * PP_DOUBLES;  // doubles of particle-phase scratch: 256 disks
 constexpr int BATCH_MAX_DISKS = 256;
 constexpr int SYNC_WORDS = 8;    // [0] arrivals [1] generation [2],[3] item counters [4] abort
 constexpr int TILE_CHUNK = 8;    // consecutive tiles taken with one atomic increment

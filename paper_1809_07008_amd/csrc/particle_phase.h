@@ -12,10 +12,10 @@
 // Contacts are searched in a Verlet neighbour list (skin DEM_SKIN) rebuilt whenever a disk has
 // moved more than DEM_SKIN/2 - MAX_MOVE since the last build; a disk moving more than MAX_MOVE in
 // one step latches ERR_MOVE, so no contact can be missed silently.
-// Only disks with a neighbour or wall within 2 MAX_MOVE ("active") can touch anything during
-// the step; they run the sub-cycles together, synchronised per sub-step.  Every other free disk
-// feels no contact force for the whole step and runs the same sub-cycle arithmetic on its own,
-// without synchronisation.
+// A free disk that cannot reach a neighbour or a wall during the step ("quiet", the test bounds
+// each disk's displacement over the step) feels no contact force and runs its sub-cycles on its
+// own, without synchronisation; the others ("active") run them together, synchronised per
+// sub-step.
 // Readings: damping ratio zeta with c_n = 2 zeta sqrt(k_n m_eff); m = rho_s pi r^2, I = m r^2/2;
 // no tangential force and no gravity.
 #pragma once
@@ -23,6 +23,8 @@
 #include "step.h"
 
 namespace imb {
+
+constexpr int PP_DOUBLES = 6;  // LDS doubles per disk: x, y, vx, vy, r and the step's reach
 
 __device__ inline double nearest_image(double d, int n) {
   if (d > 0.5 * n) d -= n;
@@ -99,14 +101,14 @@ __device__ inline int block_exclusive_scan(int* cnt, int n, int* s_wave) {
 // every global store is issued after the last barrier, so barriers never wait on memory; each
 // disk's state lives in its own thread's registers and only positions and velocities that other
 // disks' contact tests read are mirrored in LDS.
-// One disk per thread: NT >= np.  `lds` holds max(5 np doubles, tiles_y + 1 ints).
+// One disk per thread: NT >= np.  `lds` holds max(PP_DOUBLES np doubles, tiles_y + 1 ints).
 template <int NT>
 __device__ void particle_phase(const ParticleArgs& a, double* lds) {
 #pragma clang fp contract(off)
   constexpr int PWAVES = NT / 64;
   __shared__ double s_red[PWAVES];
   __shared__ int s_wave[PWAVES], s_or[PWAVES];
-  __shared__ int s_nact, s_aid[64], s_ann[64], s_anb[64][8];
+  __shared__ int s_nact, s_aid[64], s_ann[64], s_awall[64], s_anb[64][8];
   __shared__ double s_ast[64][6];
   constexpr int NB_REG = 8;   // neighbour ids kept in registers; the rest are read from the list
   const int np = a.np, p = threadIdx.x;
@@ -165,9 +167,13 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
 
   const double kn = a.kn, zeta = a.zeta;
   // contact force on disk i (Eqs. 7, 8): neighbours in ascending id, then the walls; mi is the
-  // disk's mass and cnw = 2 zeta sqrt(kn mi) its wall damping coefficient (fixed for the step)
+  // disk's mass and cnw = 2 zeta sqrt(kn mi) its wall damping coefficient (fixed for the step).
+  // cnb may be any ascending sub-list of the neighbours that holds every disk able to touch i,
+  // and near_wall may be false when no wall can: the terms left out are zero, so the sum is
+  // the same bit for bit.
   auto contact_of = [&](int i, double ri, double mi, double cnw, int cnn, const int* cnb,
-                        double px, double py, double pvx, double pvy, double& ox, double& oy) {
+                        bool near_wall, double px, double py, double pvx, double pvy, double& ox,
+                        double& oy) {
     const double r = ri;
     double fx = 0.0, fy = 0.0;
     for (int q = 0; q < cnn; ++q) {
@@ -201,7 +207,7 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
         fy += -fn * nyu;
       }
     }
-    if (a.walls) {
+    if (a.walls && near_wall) {
       const double cn = cnw;
       const double db = r - (py + 0.5);
       if (db > 0.0) {
@@ -220,7 +226,7 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
   const double m_p = a.rho_s * M_PI * r * r;
   const double cnw_p = 2.0 * zeta * sqrt(kn * m_p);
   auto contact = [&](double px, double py, double pvx, double pvy, double& ox, double& oy) {
-    contact_of(p, r, m_p, cnw_p, nn, nb, px, py, pvx, pvy, ox, oy);
+    contact_of(p, r, m_p, cnw_p, nn, nb, true, px, py, pvx, pvy, ox, oy);
   };
 
   const bool own = have && mode == 0;
@@ -246,12 +252,12 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
       rebuilt = true;
       if (have) {
         int cnt = 0;
-        for (int j = 0; j < np; ++j) {
-          if (j == p) continue;
-          double dx = nearest_image(sx[j] - x, a.nx);
-          double dy = sy[j] - y;
+        auto consider = [&](int j, double ox, double oy, double orad) {
+          if (j == p) return;
+          const double dx = nearest_image(ox - x, a.nx);
+          double dy = oy - y;
           if (!a.walls) dy = nearest_image(dy, a.ny);
-          const double reach = r + sr[j] + DEM_SKIN;
+          const double reach = r + orad + DEM_SKIN;
           if (dx * dx + dy * dy < reach * reach) {
             if (cnt < NB_REG) {
 #pragma unroll
@@ -261,7 +267,22 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
             if (cnt < NBMAX) s.nbr[p * NBMAX + cnt] = j;  // read back only by this thread
             ++cnt;
           }
+        };
+        // candidates in ascending id, eight at a time so their loads issue together
+        constexpr int RB = 8;
+        int j0 = 0;
+        for (; j0 + RB <= np; j0 += RB) {
+          double ox[RB], oy[RB], orad[RB];
+#pragma unroll
+          for (int u = 0; u < RB; ++u) {
+            ox[u] = sx[j0 + u];
+            oy[u] = sy[j0 + u];
+            orad[u] = sr[j0 + u];
+          }
+#pragma unroll
+          for (int u = 0; u < RB; ++u) consider(j0 + u, ox[u], oy[u], orad[u]);
         }
+        for (; j0 < np; ++j0) consider(j0, sx[j0], sy[j0], sr[j0]);
         if (cnt > NBMAX) {
           atomicOr(a.err, ERR_NBR);
           cnt = NBMAX;
@@ -280,30 +301,74 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
         fcy = 0.0;
       }
     } else {
-      // ---- classify: active if a neighbour's or a wall's gap is within 2 MAX_MOVE
-      bool active = false;
-      if (own) {
-        const double reach = 2.0 * MAX_MOVE;
-        for (int q = 0; q < nn; ++q) {
-          int j = 0;
-          if (q < NB_REG) {
-#pragma unroll
-            for (int u = 0; u < NB_REG; ++u)
-              if (u == q) j = nb[u];
-          } else {
-            j = s.nbr[p * NBMAX + q];
-          }
-          const double dx = nearest_image(sx[j] - x, a.nx);
-          double dy = sy[j] - y;
-          if (!a.walls) dy = nearest_image(dy, a.ny);
-          const double g = r + sr[j] + reach;
-          active |= dx * dx + dy * dy <= g * g;
-        }
-        if (a.walls && (y - r + 0.5 <= reach || (a.ny - 0.5) - y - r <= reach)) active = true;
-      }
+      // ---- classify.  During the sub-steps a disk stays within B of its start: a quiet disk
+      // (no contact force all step) moves on the parabola of its fixed hydrodynamic load, so
+      // B = |V| + |a| / 2 plus a rounding margin; an active disk B = MAX_MOVE (moving further
+      // latches ERR_MOVE); fixed and prescribed disks keep their place until the sub-steps end,
+      // B = 0.  A free disk is active when its stored contact force is not zero, when the gap
+      // to a neighbour is within the sum of both reaches, or the gap to a wall within its own.
+      // Starting from every free disk quiet, the test is repeated until no disk changes; then
+      // no quiet disk can touch anything in any sub-step (by induction over the sub-steps).
+      // An active disk searches only its "close" neighbours, those within 2 MAX_MOVE: bit u of
+      // cmask marks list slot u < NB_REG, cfar a close one further down the list.
+      double* sB = sr + np;
       const double dt = 1.0 / a.n_sub, h = 0.5 * dt;
       const double m = m_p;
       const double I = 0.5 * m * r * r;
+      auto neighbour = [&](int q) {
+        int j = 0;
+        if (q < NB_REG) {
+#pragma unroll
+          for (int u = 0; u < NB_REG; ++u)
+            if (u == q) j = nb[u];
+        } else {
+          j = s.nbr[p * NBMAX + q];
+        }
+        return j;
+      };
+      auto within = [&](int j, double reach) {
+        const double dx = nearest_image(sx[j] - x, a.nx);
+        double dy = sy[j] - y;
+        if (!a.walls) dy = nearest_image(dy, a.ny);
+        const double g = r + sr[j] + reach;
+        return dx * dx + dy * dy <= g * g;
+      };
+      double Bq = 0.0;
+      if (own) {
+        const double qax = (0.0 + Fx) / m, qay = (0.0 + Fy) / m;
+        Bq = sqrt(vx * vx + vy * vy) + 0.5 * sqrt(qax * qax + qay * qay) + 1e-9;
+      }
+      bool active = own && (fcx != 0.0 || fcy != 0.0);
+      if (have) sB[p] = active ? (Bq > MAX_MOVE ? Bq : MAX_MOVE) : (own ? Bq : 0.0);
+      __syncthreads();
+      for (;;) {
+        bool turned = false;
+        if (own && !active) {
+          for (int q = 0; q < nn && !turned; ++q) {
+            const int j = neighbour(q);
+            turned = within(j, Bq + sB[j]);
+          }
+          if (a.walls && (y - r + 0.5 <= Bq || (a.ny - 0.5) - y - r <= Bq)) turned = true;
+        }
+        __syncthreads();  // every reach of this round has been read
+        if (turned) {
+          active = true;
+          sB[p] = Bq > MAX_MOVE ? Bq : MAX_MOVE;
+        }
+        if (!block_or<NT>(turned ? 1 : 0, s_or)) break;
+      }
+      bool cfar = false, nearw = false;
+      unsigned cmask = 0u;
+      if (active) {
+        const double reach = 2.0 * MAX_MOVE;
+        for (int q = 0; q < nn; ++q) {
+          if (within(neighbour(q), reach)) {
+            if (q < NB_REG) cmask |= 1u << q;
+            else cfar = true;
+          }
+        }
+        nearw = a.walls && (y - r + 0.5 <= reach || (a.ny - 0.5) - y - r <= reach);
+      }
       if (own && !active) {
         // quiet: no contact force during the whole step, so the accelerations are the same in
         // every sub-step (computed once; the sub-step arithmetic is otherwise unchanged)
@@ -336,29 +401,43 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
           s_aid[idx] = p;
           s_ast[idx][0] = Fx; s_ast[idx][1] = Fy; s_ast[idx][2] = Tz;
           s_ast[idx][3] = fcx; s_ast[idx][4] = fcy; s_ast[idx][5] = om;
-          s_ann[idx] = nn;
+          s_awall[idx] = nearw ? 1 : 0;
+          if (cfar) {  // search the whole list
+            s_ann[idx] = nn;
 #pragma unroll
-          for (int u = 0; u < NB_REG; ++u) s_anb[idx][u] = nb[u];
+            for (int u = 0; u < NB_REG; ++u) s_anb[idx][u] = nb[u];
+          } else {     // only the close slots, in list order
+            int c = 0;
+#pragma unroll
+            for (int u = 0; u < NB_REG; ++u)
+              if ((cmask >> u) & 1u) s_anb[idx][c++] = nb[u];
+            s_ann[idx] = c;
+          }
         }
       }
       __syncthreads();
       const int nact = s_nact;
       if (nact > 0 && nact <= 64) {
+        // every lane of wavefront 0 runs the loop (lanes past nact on slot 0's data, storing
+        // nothing), so each wavefront barrier below is reached by the whole wavefront
         const int t = threadIdx.x;
-        if (t < nact) {
-          const int i = s_aid[t];
+        if (t < 64) {
+          const bool act = t < nact;
+          const int ts = act ? t : 0;
+          const int i = s_aid[ts];
           const double ri = sr[i];
           const double mi_ = a.rho_s * M_PI * ri * ri;
           const double Ii = 0.5 * mi_ * ri * ri;
           const double im = 1.0 / mi_;
           const double cnw_i = 2.0 * zeta * sqrt(kn * mi_);
           double px = sx[i], py = sy[i], pvx = svx[i], pvy = svy[i];
-          const double aFx = s_ast[t][0], aFy = s_ast[t][1], aTz = s_ast[t][2];
-          double afx = s_ast[t][3], afy = s_ast[t][4], aom = s_ast[t][5];
-          const int ann = s_ann[t];
+          const double aFx = s_ast[ts][0], aFy = s_ast[ts][1], aTz = s_ast[ts][2];
+          double afx = s_ast[ts][3], afy = s_ast[ts][4], aom = s_ast[ts][5];
+          const int ann = s_ann[ts];
+          const bool awall = s_awall[ts] != 0;
           int anb[NB_REG];
 #pragma unroll
-          for (int u = 0; u < NB_REG; ++u) anb[u] = s_anb[t][u];
+          for (int u = 0; u < NB_REG; ++u) anb[u] = s_anb[ts][u];
           const double hal = h * (aTz / Ii);
           for (int k = 0; k < a.n_sub; ++k) {
             const double ax = (afx + aFx) * im;
@@ -369,10 +448,12 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
             py = py + dt * pvy;
             if (!a.walls) py = wrap_coord(py, a.ny);
             aom = aom + hal;
-            sx[i] = px; sy[i] = py; svx[i] = pvx; svy[i] = pvy;
+            if (act) {
+              sx[i] = px; sy[i] = py; svx[i] = pvx; svy[i] = pvy;
+            }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            contact_of(i, ri, mi_, cnw_i, ann, anb, px, py, pvx, pvy, afx, afy);
+            if (act) contact_of(i, ri, mi_, cnw_i, ann, anb, awall, px, py, pvx, pvy, afx, afy);
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
             const double bx = (afx + aFx) * im;
@@ -381,8 +462,10 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
             pvy = pvy + h * by;
             aom = aom + hal;
           }
-          svx[i] = pvx; svy[i] = pvy;
-          s_ast[t][3] = afx; s_ast[t][4] = afy; s_ast[t][5] = aom;
+          if (act) {
+            svx[i] = pvx; svy[i] = pvy;
+            s_ast[t][3] = afx; s_ast[t][4] = afy; s_ast[t][5] = aom;
+          }
         }
         __syncthreads();
         if (own && active) {

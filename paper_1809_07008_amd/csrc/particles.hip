@@ -9,7 +9,7 @@ __global__ __launch_bounds__(PBLOCK) void k_particle_phase(ParticleArgs a) {
 }
 
 size_t particle_phase_lds(int np, int tiles_y) {
-  const size_t dem = (size_t)np * 5 * sizeof(double);
+  const size_t dem = (size_t)np * PP_DOUBLES * sizeof(double);
   const size_t band = (size_t)(tiles_y + 1) * sizeof(int);
   return dem > band ? dem : band;
 }

@@ -135,6 +135,36 @@ def moving_disks(seed: int = 0, nx: int = 2048, ny: int = 1024, n: int = 500,
                 storage=storage, cs=0.1, gx=1.0e-6, kn=1.0e3, zeta=0.1, n_sub=10, particles=p)
 
 
+def touching_disks(rows: int = 6, walls: bool = True, steps: int = 4, seed: int = 0) -> Case:
+    """Free disks of radius U[2.9, 3.01] on a triangular lattice of spacing 6 (ten per row,
+    positions jittered by 0.05), so each touches or nearly touches its six nearest neighbours and
+    has twelve within the DEM list reach; velocities N(0, 0.02).  60x48 with walls, 60x42
+    periodic; k_n = 20 keeps the overlaps' accelerations small."""
+    rng = np.random.default_rng(11 + rows + 100 * seed)
+    xs, ys = [], []
+    for k in range(rows):
+        for c in range(10):
+            xs.append((6.0 * c + 3.0 * (k % 2) + rng.uniform(-0.05, 0.05)) % 60.0)
+            ys.append(4.0 + 5.196 * k + rng.uniform(-0.05, 0.05))
+    n = len(xs)
+    r = rng.uniform(2.9, 3.01, n)
+    p = _particles(xs, ys, r, rng.normal(0.0, 0.02, n), rng.normal(0.0, 0.02, n))
+    return Case("touching_disks_%d" % n, 60, 48 if walls else 42, tau0=0.7, steps=steps,
+                walls=walls, gx=1.0e-5, kn=20.0, particles=p)
+
+
+def approaching_disks(steps: int = 300) -> Case:
+    """128x48 channel with walls, free disks of radius 5 on the line y = 24: a touching pair, then
+    disks at gaps 0.9 and 0.95 (each within one cell of the previous) drifting towards it, a
+    disk 3 cells further on, and a pair 3 cells apart closing at 0.4 cells per step; k_n = 50."""
+    x = [20.0, 29.99, 40.89, 51.84, 64.84, 90.0, 103.0]
+    vx = [0.005, 0.0, -0.004, -0.003, -0.01, 0.2, -0.2]
+    n = len(x)
+    p = _particles(x, [24.0] * n, [5.0] * n, vx, [0.0] * n)
+    return Case("approaching_disks", 128, 48, tau0=0.7, steps=steps, gx=1.0e-5, kn=50.0,
+                particles=p)
+
+
 def adjoint_channel(seed: int = 0, storage: str = "f32", v_std: float = 0.0) -> Case:
     """512x256 channel, 20 disks of diameter 20 at seeded positions (gap >= 2), tau = 0.6,
     g_x = 1e-6, 200 steps; disks move with prescribed constant velocity (zero by default)."""

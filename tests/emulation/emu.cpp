@@ -28,6 +28,7 @@ long long wall_clock64() {
 }
 void __syncthreads() { g_ctx.block->arrive_and_wait(); }
 int emu_lane() { return t_lane; }
+void __builtin_amdgcn_wave_barrier() { g_ctx.waves[t_wave]->arrive_and_wait(); }
 unsigned long long emu_wave_exchange(unsigned long long mine, int src) {
   auto& b = *g_ctx.waves[t_wave];
   unsigned long long* buf = &g_ctx.xbuf[(size_t)t_wave * 64];

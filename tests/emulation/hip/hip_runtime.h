@@ -55,7 +55,7 @@ inline long long min(long long a, long long b) { return a < b ? a : b; }
 #define __hip_atomic_store(p, v, o, s) __atomic_store_n((p), (v), __ATOMIC_SEQ_CST)
 inline void __threadfence() { std::atomic_thread_fence(std::memory_order_seq_cst); }
 #define __builtin_amdgcn_fence(a, b) std::atomic_thread_fence(std::memory_order_seq_cst)
-#define __builtin_amdgcn_wave_barrier() ((void)0)
+void __builtin_amdgcn_wave_barrier();  // every lane of the wavefront must reach it
 #define __builtin_amdgcn_s_sleep(n) std::this_thread::yield()
 #define __builtin_amdgcn_s_waitcnt(n) std::atomic_thread_fence(std::memory_order_seq_cst)
 long long wall_clock64();

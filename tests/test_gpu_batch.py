@@ -168,3 +168,19 @@ def test_schedules_can_alternate():
     z = np.zeros(1)
     assert imb.load_library().imb_batch_get_forces(b._h, 3, imb._dp(z), imb._dp(z),
                                                    imb._dp(z)) == -1
+
+
+@pytest.mark.parametrize("schedule", [imb.IMB_BATCH_PERSISTENT, imb.IMB_BATCH_PER_STEP])
+def test_touching_disks_in_a_batch_match_single(schedule):
+    """The DEM with every disk in contact (one wavefront of active disks, and more than one) in
+    the batch's 256-thread particle phase, bit for bit like the channels alone."""
+    cases = [W.touching_disks(6, True, steps=0).with_(storage="f32"),
+             W.touching_disks(8, False, steps=0).with_(storage="f32")]
+    b = imb.batch_from_cases(cases, tile_w=32, tile_rows=2)
+    b.set_schedule(schedule)
+    b.step(12)
+    b.sync()
+    for k, c in enumerate(cases):
+        s = single(c, (32, 2))
+        s.step(12)
+        assert_same(b, k, s)

@@ -266,3 +266,26 @@ def test_dense_channel_fp64_parity_and_determinism():
     again = gpu_for(case, tile_w=32, tile_rows=2)
     again.step(10)
     assert np.array_equal(sim.populations(), again.populations())
+
+
+@pytest.mark.parametrize("rows,walls", [(6, True), (8, False)])
+def test_touching_disks_dem_fp64_parity(rows, walls):
+    """Free disks in contact with their neighbours from the first step, every one of them active
+    in the DEM: 60 fit one wavefront (walls), 80 do not (periodic); lists of twelve neighbours
+    with close ones past the eighth slot.  FP64 parity with the oracle after 20 steps."""
+    case = W.touching_disks(rows, walls, steps=20).with_(storage="f64")
+    sim, ref = gpu_for(case, tile_w=32, tile_rows=2), oracle_for(case)
+    sim.step(case.steps)
+    ref.step(case.steps)
+    assert_parity(sim, ref)
+
+
+def test_approaching_disks_dem_fp64_parity():
+    """Disks that turn active one after another (a touching pair, then disks within one cell of
+    an active neighbour) and a pair closing at 0.4 cells per step, 300 steps: every contact the
+    oracle sees happens on the GPU too (a missed one would change the trajectories)."""
+    case = W.approaching_disks(steps=300).with_(storage="f64")
+    sim, ref = gpu_for(case, tile_w=32, tile_rows=2), oracle_for(case)
+    sim.step(case.steps)
+    ref.step(case.steps)
+    assert_parity(sim, ref, pos_tol=1e-9)
