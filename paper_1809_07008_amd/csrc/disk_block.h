@@ -45,8 +45,16 @@ __device__ void fluid_tile(const LatticeArgs& a, int tile) {
   const int n = build_tile_list<T>(a, tx, ty, s_pl, s_cnt, s_pid, s_slot);
 
   const T tau0 = (T)a.tau0, csm = (T)a.cs, gx = (T)a.gx, gy = (T)a.gy, rho0 = (T)a.rho0;
+  // byte offsets within one plane fit 32 bits: stores (and the inner loads) take the
+  // scalar-base form
+  const bool off32 = (unsigned long long)a.plane * sizeof(S) <= 0xFFFFFFFFull;
+  // the tile's columns have both x neighbours inside the lattice
+  const bool xin = tx * tw >= 1 && tx * tw + tw <= a.nx - 1;
   for (int rr = 0; rr < a.rows; ++rr) {
     const int y = ybase + rr * th;
+    // every cell of this pass has its eight neighbours inside the lattice (uniform)
+    const int ylo = ybase - ly + rr * th;
+    const bool inner = off32 && xin && ylo >= 1 && ylo + th <= a.ny - 1;
     if (x >= a.nx || y >= a.ny) continue;
     bool covered = false;
     for (int j = 0; j < n && !covered; ++j) {
@@ -56,7 +64,9 @@ __device__ void fluid_tile(const LatticeArgs& a, int tile) {
     }
     if (covered) continue;  // loaded and stored by the workgroup of its lowest-id covering disk
     T f[NQ], fo[NQ];
-    pull_load<St>(a, src, x, y, f);
+    const unsigned cell = (unsigned)(y * a.pitch + x);
+    if (inner) pull_load_inner<St>(a, src, cell * (unsigned)sizeof(S), f);
+    else pull_load<St>(a, src, x, y, f);
     auto none = [&](int) { return Disk<T>{}; };
     auto drop = [&](int, T, T, T) {};
     T rho;
@@ -67,14 +77,22 @@ __device__ void fluid_tile(const LatticeArgs& a, int tile) {
     }
     if (!(rho > T(0)) || !isfinite(rho)) atomicOr(a.err, ERR_RHO);
     const long long base = (long long)y * a.pitch + x;
+    S out[NQ];
     if constexpr (St::stochastic) {
       const unsigned r0 = pcg_hash(seed * 0x9E3779B9u + (unsigned)base);
 #pragma unroll
-      for (int i = 0; i < NQ; ++i)
-        St::store_sr(dst, (long long)i * a.plane + base, fo[i], pcg_hash(r0 + (unsigned)i));
+      for (int i = 0; i < NQ; ++i) out[i] = St::encode_sr(fo[i], pcg_hash(r0 + (unsigned)i));
     } else {
 #pragma unroll
-      for (int i = 0; i < NQ; ++i) St::store(dst, (long long)i * a.plane + base, fo[i], T(0));
+      for (int i = 0; i < NQ; ++i) out[i] = St::encode(fo[i]);
+    }
+    if (off32) {
+      const unsigned boff = cell * (unsigned)sizeof(S);
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) *at_bytes(dst + (long long)i * a.plane, boff) = out[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) dst[(long long)i * a.plane + base] = out[i];
     }
   }
   if constexpr (St::stochastic) {

@@ -151,6 +151,31 @@ __device__ inline void pull_load(const LatticeArgs& a, const typename St::S* src
   }
 }
 
+// Element at byte offset boff of p: a uniform base plus one 32-bit offset per lane, the form of
+// the global memory instructions that take a scalar base.
+template <class S>
+__device__ __forceinline__ const S* at_bytes(const S* p, unsigned boff) {
+  return (const S*)((const char*)p + boff);
+}
+template <class S>
+__device__ __forceinline__ S* at_bytes(S* p, unsigned boff) {
+  return (S*)((char*)p + boff);
+}
+
+// Pull-stream loads of a cell whose eight neighbours all lie inside the lattice (no periodic
+// wrap, no wall link): population i comes from the fixed shift (-cx_i, -cy_i) of the cell, so its
+// load is plane i's base moved by that shift (uniform) plus the cell's own byte offset.
+template <class St>
+__device__ inline void pull_load_inner(const LatticeArgs& a, const typename St::S* src,
+                                       unsigned boff, typename St::T f[NQ]) {
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    const typename St::S* p =
+        src + ((long long)i * a.plane - (long long)cy_of(i) * a.pitch - cx_of(i));
+    f[i] = St::decode(*at_bytes(p, boff));
+  }
+}
+
 // Compensated (hi, lo) pair used for the force sums in FP32; plain sum in FP64.
 template <class T>
 struct Acc {

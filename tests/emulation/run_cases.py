@@ -88,9 +88,13 @@ def fp64_parity():
 
 def wide_tiles():
     """Tiles 128 and 256 wide on ragged widths (odd, not a multiple of the tile), walls and
-    periodic y, random initial populations: FP64 parity, and FP16 equal bit for bit to 32x2."""
+    periodic y, random initial populations: FP64 parity, and FP16 equal bit for bit to 32x2.
+    The 200x72 grids also hold tile passes away from every edge, which load through the
+    shifted-plane form; 32x2 tiles cut the grid differently, so the FP16 comparison sets that
+    form against the general one."""
     for nx, ny, tile, walls in ((131, 40, (128, 2), True), (259, 24, (256, 2), False),
-                                (130, 37, (128, 4), False), (97, 30, (128, 2), True)):
+                                (130, 37, (128, 4), False), (97, 30, (128, 2), True),
+                                (200, 72, (64, 2), True), (200, 72, (16, 4), False)):
         base = moving_case()
         case = base.with_(nx=nx, ny=ny, walls=walls, particles=W.Particles(
             np.array([20.3, 60.8, nx - 0.4]), np.array([12.2, ny / 2, ny - 9.7]),
