@@ -107,53 +107,63 @@ __device__ inline double collide_plain(const double f[NQ], int nc, GetDisk disk,
 // --------------------------------------------------------------- FP32 (deviation form)
 // h_i = f_i - w_i rho0; the equilibrium deviation is w_i (drho + rho (3cu + 4.5cu^2 - 1.5uu))
 // with drho = rho - rho0 = sum h_i; the momentum is sum c_i h_i (the w_i rho0 parts cancel).
+// Opposite directions share their even part (cu_opp = -cu_i), and with
+// gw_i = w_i (c_i . g) the update of a cell is
+//   h*_i = h_i - (1 - B_tot)/tau neq_i + 3 rho (1 - B_tot) gw_i + sum_p B_p Omega^s_{p,i}.
+// A cell no disk covers (nc == 0) has B_tot = 0.
 template <class GetDisk, class Emit>
 __device__ inline float collide_dev(const float h[NQ], int nc, GetDisk disk, Emit emit,
                                     float rho0, float tau0, float cs, float gx, float gy,
                                     float hout[NQ]) {
 #pragma clang fp contract(fast)
-  float dr = 0.f, mx = 0.f, my = 0.f;
-#pragma unroll
-  for (int i = 0; i < NQ; ++i) {
-    dr += h[i];
-    mx += (float)cx_of(i) * h[i];
-    my += (float)cy_of(i) * h[i];
-  }
+  // moments (Eqs. 3, 4); D2Q9 order: rest, E, N, W, S, NE, NW, SW, SE
+  const float d57 = h[5] - h[7], d86 = h[8] - h[6];
+  const float dr = ((h[0] + (h[1] + h[3])) + (h[2] + h[4])) + ((h[5] + h[7]) + (h[6] + h[8]));
+  const float mx = (h[1] - h[3]) + (d57 + d86);
+  const float my = (h[2] - h[4]) + (d57 - d86);
   const float rho = rho0 + dr;
   const float irho = 1.0f / rho;
   const float ux = mx * irho, uy = my * irho;
   const float uu = ux * ux + uy * uy;
+  const float even0 = dr - 1.5f * rho * uu;  // (drho + rho (-1.5 uu)): the part common to all i
+  const float rho45 = 4.5f * rho, rho3 = 3.f * rho;
   float neq[NQ];
+  neq[0] = h[0] - (float)w_of(0) * even0;
+  constexpr int PAIR[4] = {1, 2, 5, 6};  // and their opposites 3, 4, 7, 8
 #pragma unroll
-  for (int i = 0; i < NQ; ++i) {
+  for (int k = 0; k < 4; ++k) {
+    const int i = PAIR[k], o = opp_of(i);
     const float cu = (float)cx_of(i) * ux + (float)cy_of(i) * uy;
-    const float heq = (float)w_of(i) * (dr + rho * (3.f * cu + 4.5f * cu * cu - 1.5f * uu));
-    neq[i] = h[i] - heq;
+    const float ev = (rho45 * cu) * cu + even0;
+    const float od = rho3 * cu;
+    neq[i] = h[i] - (float)w_of(i) * (ev + od);
+    neq[o] = h[o] - (float)w_of(o) * (ev - od);
   }
   float tau = tau0;
   if (cs > 0.f) {
-    float pxx = 0.f, pxy = 0.f, pyy = 0.f;
-#pragma unroll
-    for (int i = 0; i < NQ; ++i) {
-      pxx += (float)(cx_of(i) * cx_of(i)) * neq[i];
-      pxy += (float)(cx_of(i) * cy_of(i)) * neq[i];
-      pyy += (float)(cy_of(i) * cy_of(i)) * neq[i];
-    }
+    // Pi = sum c_i c_i neq_i
+    const float s57 = neq[5] + neq[7], s68 = neq[6] + neq[8];
+    const float dd = s57 + s68;
+    const float pxx = (neq[1] + neq[3]) + dd;
+    const float pyy = (neq[2] + neq[4]) + dd;
+    const float pxy = s57 - s68;
     const float pn = sqrtf(pxx * pxx + 2.f * pxy * pxy + pyy * pyy);
     tau = 0.5f * (tau0 + sqrtf(tau0 * tau0 + 25.455844122715710f * cs * cs * pn * irho));
   }
-  float S = 0.f;
-  for (int k = 0; k < nc; ++k) S += disk(k).eps;
-  const float et = S < 1.f ? S : 1.f;
-  const float a = tau - 0.5f;
-  const float Bt = et * a / ((1.f - et) + a);
   const float itau = 1.0f / tau;
+  float S = 0.f, Bt = 0.f;
+  if (nc > 0) {
+    for (int k = 0; k < nc; ++k) S += disk(k).eps;
+    const float et = S < 1.f ? S : 1.f;
+    const float a = tau - 0.5f;
+    Bt = et * a / ((1.f - et) + a);
+  }
   const float fl = 1.f - Bt;
-  const float rg = 3.f * rho;
+  const float k1 = fl * itau, k2 = fl * rho3;
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
-    const float G = (float)w_of(i) * rg * ((float)cx_of(i) * gx + (float)cy_of(i) * gy);
-    hout[i] = h[i] + fl * (G - neq[i] * itau);
+    const float gw = (float)w_of(i) * ((float)cx_of(i) * gx + (float)cy_of(i) * gy);
+    hout[i] = (h[i] - k1 * neq[i]) + k2 * gw;
   }
   for (int k = 0; k < nc; ++k) {
     const Disk<float> d = disk(k);

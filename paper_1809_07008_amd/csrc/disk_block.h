@@ -50,23 +50,26 @@ __device__ void fluid_tile(const LatticeArgs& a, int tile) {
   const bool off32 = (unsigned long long)a.plane * sizeof(S) <= 0xFFFFFFFFull;
   // the tile's columns have both x neighbours inside the lattice
   const bool xin = tx * tw >= 1 && tx * tw + tw <= a.nx - 1;
-  for (int rr = 0; rr < a.rows; ++rr) {
-    const int y = ybase + rr * th;
-    // every cell of this pass has its eight neighbours inside the lattice (uniform)
-    const int ylo = ybase - ly + rr * th;
-    const bool inner = off32 && xin && ylo >= 1 && ylo + th <= a.ny - 1;
-    if (x >= a.nx || y >= a.ny) continue;
-    bool covered = false;
-    for (int j = 0; j < n && !covered; ++j) {
+  // this thread's cell of pass rr exists and no disk covers it (a covered cell is loaded and
+  // stored by the workgroup of its lowest-id covering disk)
+  auto live = [&](int y) {
+    if (x >= a.nx || y >= a.ny) return false;
+    for (int j = 0; j < n; ++j) {
       T dx, dy;
       lever_arm(a, s_pl[j], x, y, &dx, &dy);
-      covered = covers_cell<T>(s_pl[j].r, dx, dy);
+      if (covers_cell<T>(s_pl[j].r, dx, dy)) return false;
     }
-    if (covered) continue;  // loaded and stored by the workgroup of its lowest-id covering disk
-    T f[NQ], fo[NQ];
-    const unsigned cell = (unsigned)(y * a.pitch + x);
-    if (inner) pull_load_inner<St>(a, src, cell * (unsigned)sizeof(S), f);
+    return true;
+  };
+  auto load = [&](int rr, int y, T f[NQ]) {
+    // every cell of pass rr has its eight neighbours inside the lattice (uniform)
+    const int ylo = ybase - ly + rr * th;
+    const bool inner = off32 && xin && ylo >= 1 && ylo + th <= a.ny - 1;
+    if (inner) pull_load_inner<St>(a, src, (unsigned)(y * a.pitch + x) * (unsigned)sizeof(S), f);
     else pull_load<St>(a, src, x, y, f);
+  };
+  auto update = [&](int y, const T f[NQ]) {
+    T fo[NQ];
     auto none = [&](int) { return Disk<T>{}; };
     auto drop = [&](int, T, T, T) {};
     T rho;
@@ -87,13 +90,23 @@ __device__ void fluid_tile(const LatticeArgs& a, int tile) {
       for (int i = 0; i < NQ; ++i) out[i] = St::encode(fo[i]);
     }
     if (off32) {
-      const unsigned boff = cell * (unsigned)sizeof(S);
+      const unsigned boff = (unsigned)base * (unsigned)sizeof(S);
 #pragma unroll
       for (int i = 0; i < NQ; ++i) *at_bytes(dst + (long long)i * a.plane, boff) = out[i];
     } else {
 #pragma unroll
       for (int i = 0; i < NQ; ++i) dst[(long long)i * a.plane + base] = out[i];
     }
+  };
+  // passes in pairs: both passes' loads are in flight before either is updated
+  for (int rr = 0; rr < a.rows; rr += 2) {
+    const int y0 = ybase + rr * th, y1 = y0 + th;
+    const bool l0 = live(y0), l1 = rr + 1 < a.rows && live(y1);
+    T f0[NQ], f1[NQ];
+    if (l0) load(rr, y0, f0);
+    if (l1) load(rr + 1, y1, f1);
+    if (l0) update(y0, f0);
+    if (l1) update(y1, f1);
   }
   if constexpr (St::stochastic) {
     if (tile == 0 && tid == 0) a.seed[a.seed_slot ^ 1] = seed + 1u;

@@ -160,8 +160,19 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
     jsum = block_sum<NT>(jl, s_red);
   }
 
+  const bool own = have && mode == 0;
+  const double m_p = a.rho_s * M_PI * r * r;
+  // the step's reach of each disk (the classification below), published with the mirror
+  double* sB = sr + np;
+  double Bq = 0.0;
+  if (own && a.do_dem) {
+    const double qax = (0.0 + Fx) / m_p, qay = (0.0 + Fy) / m_p;
+    Bq = sqrt(vx * vx + vy * vy) + 0.5 * sqrt(qax * qax + qay * qay) + 1e-9;
+  }
   if (have) {
     sx[p] = x; sy[p] = y; svx[p] = vx; svy[p] = vy; sr[p] = r;
+    const bool touching = own && (fcx != 0.0 || fcy != 0.0);
+    sB[p] = touching ? (Bq > MAX_MOVE ? Bq : MAX_MOVE) : Bq;
   }
   __syncthreads();
 
@@ -223,13 +234,11 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
     ox = fx;
     oy = fy;
   };
-  const double m_p = a.rho_s * M_PI * r * r;
   const double cnw_p = 2.0 * zeta * sqrt(kn * m_p);
   auto contact = [&](double px, double py, double pvx, double pvy, double& ox, double& oy) {
     contact_of(p, r, m_p, cnw_p, nn, nb, true, px, py, pvx, pvy, ox, oy);
   };
 
-  const bool own = have && mode == 0;
   bool rebuilt = false;
   // bit 1: some disk is free; bit 2: the neighbour list must be rebuilt
   int flags = 0;
@@ -311,7 +320,6 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
       // no quiet disk can touch anything in any sub-step (by induction over the sub-steps).
       // An active disk searches only its "close" neighbours, those within 2 MAX_MOVE: bit u of
       // cmask marks list slot u < NB_REG, cfar a close one further down the list.
-      double* sB = sr + np;
       const double dt = 1.0 / a.n_sub, h = 0.5 * dt;
       const double m = m_p;
       const double I = 0.5 * m * r * r;
@@ -333,14 +341,8 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
         const double g = r + sr[j] + reach;
         return dx * dx + dy * dy <= g * g;
       };
-      double Bq = 0.0;
-      if (own) {
-        const double qax = (0.0 + Fx) / m, qay = (0.0 + Fy) / m;
-        Bq = sqrt(vx * vx + vy * vy) + 0.5 * sqrt(qax * qax + qay * qay) + 1e-9;
-      }
       bool active = own && (fcx != 0.0 || fcy != 0.0);
-      if (have) sB[p] = active ? (Bq > MAX_MOVE ? Bq : MAX_MOVE) : (own ? Bq : 0.0);
-      __syncthreads();
+      bool any_active = false;
       for (;;) {
         bool turned = false;
         if (own && !active) {
@@ -355,7 +357,9 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
           active = true;
           sB[p] = Bq > MAX_MOVE ? Bq : MAX_MOVE;
         }
-        if (!block_or<NT>(turned ? 1 : 0, s_or)) break;
+        const int ro = block_or<NT>((turned ? 1 : 0) | (active ? 2 : 0), s_or);
+        any_active = (ro & 2) != 0;
+        if (!(ro & 1)) break;
       }
       bool cfar = false, nearw = false;
       unsigned cmask = 0u;
@@ -389,114 +393,116 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
         fcx = 0.0;
         fcy = 0.0;
       }
-      // active disks: up to 64 are packed into the first wavefront and run their sub-steps
-      // there with wavefront-level ordering only; more than 64 use every owner thread and
-      // block barriers
-      if (threadIdx.x == 0) s_nact = 0;
-      __syncthreads();
-      int idx = -1;  // this disk's slot among the active ones
-      if (own && active) {
-        idx = atomicAdd(&s_nact, 1);
-        if (idx < 64) {
-          s_aid[idx] = p;
-          s_ast[idx][0] = Fx; s_ast[idx][1] = Fy; s_ast[idx][2] = Tz;
-          s_ast[idx][3] = fcx; s_ast[idx][4] = fcy; s_ast[idx][5] = om;
-          s_awall[idx] = nearw ? 1 : 0;
-          if (cfar) {  // search the whole list
-            s_ann[idx] = nn;
+      if (any_active) {
+        // active disks: up to 64 are packed into the first wavefront and run their sub-steps
+        // there with wavefront-level ordering only; more than 64 use every owner thread and
+        // block barriers
+        if (threadIdx.x == 0) s_nact = 0;
+        __syncthreads();
+        int idx = -1;  // this disk's slot among the active ones
+        if (own && active) {
+          idx = atomicAdd(&s_nact, 1);
+          if (idx < 64) {
+            s_aid[idx] = p;
+            s_ast[idx][0] = Fx; s_ast[idx][1] = Fy; s_ast[idx][2] = Tz;
+            s_ast[idx][3] = fcx; s_ast[idx][4] = fcy; s_ast[idx][5] = om;
+            s_awall[idx] = nearw ? 1 : 0;
+            if (cfar) {  // search the whole list
+              s_ann[idx] = nn;
 #pragma unroll
-            for (int u = 0; u < NB_REG; ++u) s_anb[idx][u] = nb[u];
-          } else {     // only the close slots, in list order
-            int c = 0;
+              for (int u = 0; u < NB_REG; ++u) s_anb[idx][u] = nb[u];
+            } else {     // only the close slots, in list order
+              int c = 0;
 #pragma unroll
-            for (int u = 0; u < NB_REG; ++u)
-              if ((cmask >> u) & 1u) s_anb[idx][c++] = nb[u];
-            s_ann[idx] = c;
-          }
-        }
-      }
-      __syncthreads();
-      const int nact = s_nact;
-      if (nact > 0 && nact <= 64) {
-        // every lane of wavefront 0 runs the loop (lanes past nact on slot 0's data, storing
-        // nothing), so each wavefront barrier below is reached by the whole wavefront
-        const int t = threadIdx.x;
-        if (t < 64) {
-          const bool act = t < nact;
-          const int ts = act ? t : 0;
-          const int i = s_aid[ts];
-          const double ri = sr[i];
-          const double mi_ = a.rho_s * M_PI * ri * ri;
-          const double Ii = 0.5 * mi_ * ri * ri;
-          const double im = 1.0 / mi_;
-          const double cnw_i = 2.0 * zeta * sqrt(kn * mi_);
-          double px = sx[i], py = sy[i], pvx = svx[i], pvy = svy[i];
-          const double aFx = s_ast[ts][0], aFy = s_ast[ts][1], aTz = s_ast[ts][2];
-          double afx = s_ast[ts][3], afy = s_ast[ts][4], aom = s_ast[ts][5];
-          const int ann = s_ann[ts];
-          const bool awall = s_awall[ts] != 0;
-          int anb[NB_REG];
-#pragma unroll
-          for (int u = 0; u < NB_REG; ++u) anb[u] = s_anb[ts][u];
-          const double hal = h * (aTz / Ii);
-          for (int k = 0; k < a.n_sub; ++k) {
-            const double ax = (afx + aFx) * im;
-            const double ay = (afy + aFy) * im;
-            pvx = pvx + h * ax;
-            pvy = pvy + h * ay;
-            px = wrap_coord(px + dt * pvx, a.nx);
-            py = py + dt * pvy;
-            if (!a.walls) py = wrap_coord(py, a.ny);
-            aom = aom + hal;
-            if (act) {
-              sx[i] = px; sy[i] = py; svx[i] = pvx; svy[i] = pvy;
+              for (int u = 0; u < NB_REG; ++u)
+                if ((cmask >> u) & 1u) s_anb[idx][c++] = nb[u];
+              s_ann[idx] = c;
             }
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            if (act) contact_of(i, ri, mi_, cnw_i, ann, anb, awall, px, py, pvx, pvy, afx, afy);
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            const double bx = (afx + aFx) * im;
-            const double by = (afy + aFy) * im;
-            pvx = pvx + h * bx;
-            pvy = pvy + h * by;
-            aom = aom + hal;
-          }
-          if (act) {
-            svx[i] = pvx; svy[i] = pvy;
-            s_ast[t][3] = afx; s_ast[t][4] = afy; s_ast[t][5] = aom;
           }
         }
         __syncthreads();
-        if (own && active) {
-          fcx = s_ast[idx][3]; fcy = s_ast[idx][4]; om = s_ast[idx][5];
-          x = sx[p]; y = sy[p]; vx = svx[p]; vy = svy[p];
-        }
-      } else if (nact > 64) {
-        // active disks: sub-steps synchronised across the block through LDS
-        const double hal = h * (Tz / I);
-        const double im = 1.0 / m;
-        for (int k = 0; k < a.n_sub; ++k) {
-          if (own && active) {
-            const double ax = (fcx + Fx) * im;
-            const double ay = (fcy + Fy) * im;
-            vx = vx + h * ax;
-            vy = vy + h * ay;
-            x = wrap_coord(x + dt * vx, a.nx);
-            y = y + dt * vy;
-            if (!a.walls) y = wrap_coord(y, a.ny);
-            om = om + hal;
-            sx[p] = x; sy[p] = y; svx[p] = vx; svy[p] = vy;
+        const int nact = s_nact;
+        if (nact > 0 && nact <= 64) {
+          // every lane of wavefront 0 runs the loop (lanes past nact on slot 0's data, storing
+          // nothing), so each wavefront barrier below is reached by the whole wavefront
+          const int t = threadIdx.x;
+          if (t < 64) {
+            const bool act = t < nact;
+            const int ts = act ? t : 0;
+            const int i = s_aid[ts];
+            const double ri = sr[i];
+            const double mi_ = a.rho_s * M_PI * ri * ri;
+            const double Ii = 0.5 * mi_ * ri * ri;
+            const double im = 1.0 / mi_;
+            const double cnw_i = 2.0 * zeta * sqrt(kn * mi_);
+            double px = sx[i], py = sy[i], pvx = svx[i], pvy = svy[i];
+            const double aFx = s_ast[ts][0], aFy = s_ast[ts][1], aTz = s_ast[ts][2];
+            double afx = s_ast[ts][3], afy = s_ast[ts][4], aom = s_ast[ts][5];
+            const int ann = s_ann[ts];
+            const bool awall = s_awall[ts] != 0;
+            int anb[NB_REG];
+#pragma unroll
+            for (int u = 0; u < NB_REG; ++u) anb[u] = s_anb[ts][u];
+            const double hal = h * (aTz / Ii);
+            for (int k = 0; k < a.n_sub; ++k) {
+              const double ax = (afx + aFx) * im;
+              const double ay = (afy + aFy) * im;
+              pvx = pvx + h * ax;
+              pvy = pvy + h * ay;
+              px = wrap_coord(px + dt * pvx, a.nx);
+              py = py + dt * pvy;
+              if (!a.walls) py = wrap_coord(py, a.ny);
+              aom = aom + hal;
+              if (act) {
+                sx[i] = px; sy[i] = py; svx[i] = pvx; svy[i] = pvy;
+              }
+              __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+              __builtin_amdgcn_wave_barrier();
+              if (act) contact_of(i, ri, mi_, cnw_i, ann, anb, awall, px, py, pvx, pvy, afx, afy);
+              __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+              __builtin_amdgcn_wave_barrier();
+              const double bx = (afx + aFx) * im;
+              const double by = (afy + aFy) * im;
+              pvx = pvx + h * bx;
+              pvy = pvy + h * by;
+              aom = aom + hal;
+            }
+            if (act) {
+              svx[i] = pvx; svy[i] = pvy;
+              s_ast[t][3] = afx; s_ast[t][4] = afy; s_ast[t][5] = aom;
+            }
           }
           __syncthreads();
-          if (own && active) contact(x, y, vx, vy, fcx, fcy);
-          __syncthreads();
           if (own && active) {
-            const double ax = (fcx + Fx) * im;
-            const double ay = (fcy + Fy) * im;
-            vx = vx + h * ax;
-            vy = vy + h * ay;
-            om = om + hal;
+            fcx = s_ast[idx][3]; fcy = s_ast[idx][4]; om = s_ast[idx][5];
+            x = sx[p]; y = sy[p]; vx = svx[p]; vy = svy[p];
+          }
+        } else if (nact > 64) {
+          // active disks: sub-steps synchronised across the block through LDS
+          const double hal = h * (Tz / I);
+          const double im = 1.0 / m;
+          for (int k = 0; k < a.n_sub; ++k) {
+            if (own && active) {
+              const double ax = (fcx + Fx) * im;
+              const double ay = (fcy + Fy) * im;
+              vx = vx + h * ax;
+              vy = vy + h * ay;
+              x = wrap_coord(x + dt * vx, a.nx);
+              y = y + dt * vy;
+              if (!a.walls) y = wrap_coord(y, a.ny);
+              om = om + hal;
+              sx[p] = x; sy[p] = y; svx[p] = vx; svy[p] = vy;
+            }
+            __syncthreads();
+            if (own && active) contact(x, y, vx, vy, fcx, fcy);
+            __syncthreads();
+            if (own && active) {
+              const double ax = (fcx + Fx) * im;
+              const double ay = (fcy + Fy) * im;
+              vx = vx + h * ax;
+              vy = vy + h * ay;
+              om = om + hal;
+            }
           }
         }
       }
