@@ -195,10 +195,10 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs B, const BatchChannel
 // The channel index is uniform over the workgroup and the tables are read-only during the
 // launch, so a channel's arguments are read with scalar loads instead of occupying vector
 // registers.
-__global__ __launch_bounds__(BLOCK) void k_batch_lattice(const BatchChannel* __restrict__ ch,
-                                                         const int* __restrict__ dpref,
-                                                         const int* __restrict__ tpref, int nch,
-                                                         int ndisk, int parity) {
+// Held to six wavefronts per SIMD (80 VGPRs) like the single-simulation lattice kernel.
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void k_batch_lattice(
+    const BatchChannel* __restrict__ ch, const int* __restrict__ dpref,
+    const int* __restrict__ tpref, int nch, int ndisk, int parity) {
   const int b = blockIdx.x;
   if (b < ndisk) {
     const int k = __builtin_amdgcn_readfirstlane(find_slot(dpref, nch, b));

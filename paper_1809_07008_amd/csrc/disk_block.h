@@ -98,15 +98,27 @@ __device__ void fluid_tile(const LatticeArgs& a, int tile) {
       for (int i = 0; i < NQ; ++i) dst[(long long)i * a.plane + base] = out[i];
     }
   };
-  // passes in pairs: both passes' loads are in flight before either is updated
-  for (int rr = 0; rr < a.rows; rr += 2) {
-    const int y0 = ybase + rr * th, y1 = y0 + th;
-    const bool l0 = live(y0), l1 = rr + 1 < a.rows && live(y1);
-    T f0[NQ], f1[NQ];
-    if (l0) load(rr, y0, f0);
-    if (l1) load(rr + 1, y1, f1);
-    if (l0) update(y0, f0);
-    if (l1) update(y1, f1);
+  if constexpr (sizeof(T) == 8) {
+    // FP64: one pass at a time (two passes' populations in flight cost more registers than
+    // the overlap gains)
+    for (int rr = 0; rr < a.rows; ++rr) {
+      const int y = ybase + rr * th;
+      if (!live(y)) continue;
+      T f[NQ];
+      load(rr, y, f);
+      update(y, f);
+    }
+  } else {
+    // passes in pairs: both passes' loads are in flight before either is updated
+    for (int rr = 0; rr < a.rows; rr += 2) {
+      const int y0 = ybase + rr * th, y1 = y0 + th;
+      const bool l0 = live(y0), l1 = rr + 1 < a.rows && live(y1);
+      T f0[NQ], f1[NQ];
+      if (l0) load(rr, y0, f0);
+      if (l1) load(rr + 1, y1, f1);
+      if (l0) update(y0, f0);
+      if (l1) update(y1, f1);
+    }
   }
   if constexpr (St::stochastic) {
     if (tile == 0 && tid == 0) a.seed[a.seed_slot ^ 1] = seed + 1u;

@@ -107,7 +107,7 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
 #pragma clang fp contract(off)
   constexpr int PWAVES = NT / 64;
   __shared__ double s_red[PWAVES];
-  __shared__ int s_wave[PWAVES], s_or[PWAVES];
+  __shared__ int s_wave[PWAVES], s_or[PWAVES], s_flag[PWAVES];
   __shared__ int s_nact, s_aid[64], s_ann[64], s_awall[64], s_anb[64][8];
   __shared__ double s_ast[64][6];
   constexpr int NB_REG = 8;   // neighbour ids kept in registers; the rest are read from the list
@@ -169,12 +169,36 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
     const double qax = (0.0 + Fx) / m_p, qay = (0.0 + Fy) / m_p;
     Bq = sqrt(vx * vx + vy * vy) + 0.5 * sqrt(qax * qax + qay * qay) + 1e-9;
   }
+  // bit 1: some disk is free; bit 2: the neighbour list must be rebuilt (ORed over the
+  // workgroup through the mirror's barrier)
+  const bool lists = a.do_dem || a.init_contacts || a.build_lists;
+  int mine = 0;
+  if (lists) {
+    mine = own ? 1 : 0;
+    if (have) {
+      // rebuild before any disk can have moved (by the next lattice step) far enough that a
+      // pair outside the list could touch, or cover a common cell
+      const double ddx = nearest_image(x - xref, a.nx);
+      const double ddy = a.walls ? y - yref : nearest_image(y - yref, a.ny);
+      const double lim = 0.5 * (DEM_SKIN - M_SQRT2) - MAX_MOVE;
+      if (ddx * ddx + ddy * ddy > lim * lim) mine |= 2;
+    }
+    if (p == 0 && rebuild_flag) mine |= 2;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mine |= __shfl_xor(mine, off, 64);
+    if ((threadIdx.x & 63) == 0) s_flag[threadIdx.x >> 6] = mine;
+  }
   if (have) {
     sx[p] = x; sy[p] = y; svx[p] = vx; svy[p] = vy; sr[p] = r;
     const bool touching = own && (fcx != 0.0 || fcy != 0.0);
     sB[p] = touching ? (Bq > MAX_MOVE ? Bq : MAX_MOVE) : Bq;
   }
   __syncthreads();
+  int flags = 0;
+  if (lists) {
+#pragma unroll
+    for (int w = 0; w < PWAVES; ++w) flags |= s_flag[w];
+  }
 
   const double kn = a.kn, zeta = a.zeta;
   // contact force on disk i (Eqs. 7, 8): neighbours in ascending id, then the walls; mi is the
@@ -240,21 +264,6 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
   };
 
   bool rebuilt = false;
-  // bit 1: some disk is free; bit 2: the neighbour list must be rebuilt
-  int flags = 0;
-  if (a.do_dem || a.init_contacts || a.build_lists) {
-    int mine = own ? 1 : 0;
-    if (have) {
-      // rebuild before any disk can have moved (by the next lattice step) far enough that a
-      // pair outside the list could touch, or cover a common cell
-      const double ddx = nearest_image(x - xref, a.nx);
-      const double ddy = a.walls ? y - yref : nearest_image(y - yref, a.ny);
-      const double lim = 0.5 * (DEM_SKIN - M_SQRT2) - MAX_MOVE;
-      if (ddx * ddx + ddy * ddy > lim * lim) mine |= 2;
-    }
-    if (p == 0 && rebuild_flag) mine |= 2;
-    flags = block_or<NT>(mine, s_or);
-  }
   if ((flags & 1) || a.build_lists) {
     // ---- neighbour list maintenance
     if (flags & 2) {
@@ -352,14 +361,15 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
           }
           if (a.walls && (y - r + 0.5 <= Bq || (a.ny - 0.5) - y - r <= Bq)) turned = true;
         }
-        __syncthreads();  // every reach of this round has been read
+        // the OR's barrier also ends this round's reads of the reaches
+        const int ro = block_or<NT>((turned ? 1 : 0) | (active || turned ? 2 : 0), s_or);
+        any_active = (ro & 2) != 0;
+        if (!(ro & 1)) break;
         if (turned) {
           active = true;
           sB[p] = Bq > MAX_MOVE ? Bq : MAX_MOVE;
         }
-        const int ro = block_or<NT>((turned ? 1 : 0) | (active ? 2 : 0), s_or);
-        any_active = (ro & 2) != 0;
-        if (!(ro & 1)) break;
+        __syncthreads();  // the new reaches are visible to the next round
       }
       bool cfar = false, nearw = false;
       unsigned cmask = 0u;
