@@ -135,6 +135,7 @@ __device__ void disk_cells(const LatticeArgs& a, int p) {
   __shared__ int s_cj[MAXC][BLOCK];       // covering entries of each thread's current cell
   __shared__ T s_ce[MAXC][BLOCK];         //   and their solid ratios
   __shared__ Acc<T> s_fr[WAVES][3];
+  __shared__ int s_rx0[64], s_rpre[65];   // row-wise cell enumeration (rows of the box <= 64)
 
   const int tid = threadIdx.x;
   const S* src = (const S*)a.src;
@@ -181,12 +182,65 @@ __device__ void disk_cells(const LatticeArgs& a, int p) {
     if (iy1 > a.ny - 1) iy1 = a.ny - 1;
   }
   const int bw = ix1 - ix0 + 1, bh = iy1 - iy0 + 1;
-  const int ncell = (bw > 0 && bh > 0 && bw <= a.nx && bh <= a.ny) ? bw * bh : 0;
+  const bool boxed = bw > 0 && bh > 0 && bw <= a.nx && bh <= a.ny;
+  // Row by row, only the cells whose nearest point to the centre can lie within r: in the row at
+  // y-distance ny from the centre (to the row's nearest edge) those with |x - X| < s + 1/2,
+  // s = sqrt(r^2 - ny^2), widened by 1e-3 so that no rounding of the exact test drops a cell.
+  // Rows start at s_rx0[k]; s_rpre holds the prefix counts.  Boxes taller than a wavefront
+  // walk the whole box.
+  const bool rowwise = boxed && bh <= 64;
+  int ncell = boxed ? bw * bh : 0;
+  if (rowwise) {
+    if (tid < 64) {
+      int x0 = 0, len = 0;
+      if (tid < bh) {
+        const double dy = (double)(iy0 + tid) - pp.y;
+        const double ny = dy - 0.5 > 0.0 ? dy - 0.5 : (dy + 0.5 < 0.0 ? dy + 0.5 : 0.0);
+        const double q = pp.z * pp.z - ny * ny;
+        if (q > 0.0) {
+          const double sw = sqrt(q) + 1e-3;
+          int lo = (int)floor(pp.x - sw - 0.5) + 1, hi = (int)ceil(pp.x + sw + 0.5) - 1;
+          lo = lo > ix0 ? lo : ix0;
+          hi = hi < ix1 ? hi : ix1;
+          if (hi >= lo) {
+            x0 = lo;
+            len = hi - lo + 1;
+          }
+        }
+      }
+      int incl = len;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int v = __shfl_up(incl, off, 64);
+        if (tid >= off) incl += v;
+      }
+      if (tid < bh) {
+        s_rx0[tid] = x0;
+        s_rpre[tid + 1] = incl;
+      }
+      if (tid == 0) s_rpre[0] = 0;
+    }
+    __syncthreads();
+    ncell = s_rpre[bh];
+  }
 
   const T tau0 = (T)a.tau0, csm = (T)a.cs, gx = (T)a.gx, gy = (T)a.gy, rho0 = (T)a.rho0;
   Acc<T> afx{T(0), T(0)}, afy{T(0), T(0)}, atz{T(0), T(0)};
   for (int c = tid; c < ncell; c += BLOCK) {
-    int x = ix0 + c % bw, y = iy0 + c / bw;
+    int x, y;
+    if (rowwise) {  // the row holding cell c: s_rpre[k] <= c < s_rpre[k + 1]
+      int lo = 0, hi = bh;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (s_rpre[mid] <= c) lo = mid;
+        else hi = mid;
+      }
+      x = s_rx0[lo] + (c - s_rpre[lo]);
+      y = iy0 + lo;
+    } else {
+      x = ix0 + c % bw;
+      y = iy0 + c / bw;
+    }
     x = x < 0 ? x + a.nx : (x >= a.nx ? x - a.nx : x);
     if (!a.walls) y = y < 0 ? y + a.ny : (y >= a.ny ? y - a.ny : y);
     // covering disks of the cell, ascending id; the cell belongs to the first of them
