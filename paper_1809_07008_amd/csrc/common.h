@@ -191,6 +191,17 @@ __device__ inline int xcd_remap(int b, int n) {
 
 __host__ __device__ inline int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 __host__ __device__ inline int wrap_int(int a, int n) { int m = a % n; return m < 0 ? m + n : m; }
+// wrap_int for a within one period of [0, n) without a division (the general form otherwise)
+__host__ __device__ inline int wrap_near(int a, int n) {
+  if (a >= 0 && a < n) return a;
+  if (a < 0 && a >= -n) return a + n;
+  if (a >= n && a < 2 * n) return a - n;
+  return wrap_int(a, n);
+}
+// a / d for a >= 0; a shift when d is a power of two (tile widths and heights are)
+__host__ __device__ inline int div_tile(int a, int d) {
+  return (d & (d - 1)) == 0 ? a >> __builtin_ctz((unsigned)d) : a / d;
+}
 
 // Tile box of a disk: the cyclic range of tiles that contain a cell of its bounding box
 // [floor(X - r - 1/2), ceil(X + r + 1/2)] (only those cells can be covered).  Returns false if
@@ -203,9 +214,9 @@ __host__ __device__ inline bool tile_box(double X, double Y, double r, int nx, i
     tx0 = 0;
     ntx = tiles_x;
   } else {
-    tx0 = wrap_int(ix0, nx) / tw;
-    const int txe = wrap_int(ix1, nx) / tw;
-    ntx = wrap_int(txe - tx0, tiles_x) + 1;
+    tx0 = div_tile(wrap_near(ix0, nx), tw);
+    const int txe = div_tile(wrap_near(ix1, nx), tw);
+    ntx = wrap_near(txe - tx0, tiles_x) + 1;
   }
   int iy0 = (int)floor(Y - r - 0.5), iy1 = (int)ceil(Y + r + 0.5);
   int ty0, nty;
@@ -216,16 +227,16 @@ __host__ __device__ inline bool tile_box(double X, double Y, double r, int nx, i
       ty0 = 0;
       nty = 0;
     } else {
-      ty0 = iy0 / th;
-      nty = iy1 / th - ty0 + 1;
+      ty0 = div_tile(iy0, th);
+      nty = div_tile(iy1, th) - ty0 + 1;
     }
   } else if (iy1 - iy0 + 1 > ny - th) {
     ty0 = 0;
     nty = tiles_y;
   } else {
-    ty0 = wrap_int(iy0, ny) / th;
-    const int tye = wrap_int(iy1, ny) / th;
-    nty = wrap_int(tye - ty0, tiles_y) + 1;
+    ty0 = div_tile(wrap_near(iy0, ny), th);
+    const int tye = div_tile(wrap_near(iy1, ny), th);
+    nty = wrap_near(tye - ty0, tiles_y) + 1;
   }
   *out = make_int4(tx0, ntx, ty0, nty);
   return ntx * nty <= MAXSLOT;
