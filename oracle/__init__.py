@@ -4,7 +4,7 @@ Test infrastructure only: used by the test suite, the smoke check and the benchm
 CPU-baseline leg, never by the product package.
 """
 from .oracle import (OracleConfig, OracleSim, build, collide_cell, get_threads, set_threads,
-                     solid_fraction, weight)
+                     solid_fraction, subcell_fraction, weight)
 
 __all__ = ["OracleConfig", "OracleSim", "build", "collide_cell", "get_threads", "set_threads",
-           "solid_fraction", "weight"]
+           "solid_fraction", "subcell_fraction", "weight"]

@@ -16,7 +16,8 @@
  *                         The paper's lattice is D3Q19 (Table 1); this oracle is two-dimensional and
  *                         uses the D2Q9 set with weights 4/9, 1/9, 1/36 and c_s^2 = 1/3.
  *   Sec. 2.2             solid ratio of a cell = covered area / cell area (Fig. 3a), computed
- *                         exactly for a disk (the paper estimates it by cell decomposition).
+ *                         exactly for a disk; optionally the paper's own estimate by cell
+ *                         decomposition (fraction of n x n sub-cell centres inside the disk).
  *   Eq. (12)             Noble-Torczynski solid collision operator.
  *   Eq. (13), Eq. (14)   blended collision and its weight B(eps, tau).
  *   Eqs. (15), (16)      hydrodynamic force and torque; the printed sum is the momentum the fluid
@@ -74,6 +75,7 @@ typedef struct {
   double kn;      /* normal contact stiffness */
   double zeta;    /* normal damping ratio */
   double rho_s;   /* particle density (mass per unit area) */
+  int32_t eps_subcells; /* 0: exact solid ratio; n > 0: the n x n sub-cell estimate */
 } ocfg;
 
 typedef struct {
@@ -100,6 +102,22 @@ static void equilibrium(double rho, double ux, double uy, double feq[NQ]) {
     double cu = CX[i] * ux + CY[i] * uy;
     feq[i] = WQ[i] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
   }
+}
+
+/* The paper's estimate of the solid ratio (Sec. 2.2): the unit cell centred at (dx, dy) from the
+ * disk centre is split into n x n equal sub-cells, and eps is the fraction of sub-cell centres
+ * lying inside the disk (strictly: a centre on the circle counts as outside). */
+double o_subcell_fraction(double r, double dx, double dy, int n) {
+  if (n < 1) return 0.0;
+  int inside = 0;
+  for (int j = 0; j < n; ++j) {
+    const double yc = dy + ((j + 0.5) / n - 0.5);
+    for (int i = 0; i < n; ++i) {
+      const double xc = dx + ((i + 0.5) / n - 0.5);
+      if (xc * xc + yc * yc < r * r) ++inside;
+    }
+  }
+  return (double)inside / ((double)n * (double)n);
 }
 
 /* Weight of Eq. (14): B(eps, tau) = eps (tau - 1/2) / ((1 - eps) + (tau - 1/2)). */
@@ -285,7 +303,9 @@ static void *xcalloc(size_t n, size_t sz) { return n ? calloc(n, sz) : calloc(1,
 void o_destroy(osim *s);
 
 osim *o_create(const ocfg *c) {
-  if (!c || c->nx < 2 || c->ny < 2 || !(c->tau0 > 0.5) || c->cs < 0.0 || c->n_sub < 1) return NULL;
+  if (!c || c->nx < 2 || c->ny < 2 || !(c->tau0 > 0.5) || c->cs < 0.0 || c->n_sub < 1 ||
+      c->eps_subcells < 0)
+    return NULL;
   osim *s = (osim *)calloc(1, sizeof(osim));
   if (!s) return NULL;
   s->c = *c;
@@ -565,7 +585,8 @@ static int map_particles(osim *s) {
         if (di > nx / 2) di -= nx;
         else if (di < -(nx / 2)) di += nx;
         double dx = (double)di - fx;
-        double e = o_solid_fraction(r, dx, dy);
+        double e = s->c.eps_subcells > 0 ? o_subcell_fraction(r, dx, dy, s->c.eps_subcells)
+                                         : o_solid_fraction(r, dx, dy);
         if (e > 0.0) {
           size_t k = (size_t)yw * nx + xw;
           int ns = s->nslot[k];

@@ -35,7 +35,8 @@ class _Cfg(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("walls", C.c_int32),
                 ("n_sub", C.c_int32), ("tau0", C.c_double), ("cs", C.c_double),
                 ("gx", C.c_double), ("gy", C.c_double), ("rho0", C.c_double),
-                ("kn", C.c_double), ("zeta", C.c_double), ("rho_s", C.c_double)]
+                ("kn", C.c_double), ("zeta", C.c_double), ("rho_s", C.c_double),
+                ("eps_subcells", C.c_int32)]
 
 
 _lib = None
@@ -65,6 +66,8 @@ def _load():
         lib.o_solid_field.argtypes = [C.c_void_p, _D]
         lib.o_solid_fraction.restype = C.c_double
         lib.o_solid_fraction.argtypes = [C.c_double, C.c_double, C.c_double]
+        lib.o_subcell_fraction.restype = C.c_double
+        lib.o_subcell_fraction.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int]
         lib.o_weight.restype = C.c_double
         lib.o_weight.argtypes = [C.c_double, C.c_double]
         lib.o_collide_cell.argtypes = [_D, C.c_int, _D, _D, _D, _D, _D, _D, C.c_double,
@@ -96,6 +99,12 @@ def solid_fraction(r: float, dx: float, dy: float) -> float:
     """Exact covered fraction of the unit cell centred at (dx, dy) relative to a disk of radius r
     centred at the origin."""
     return float(_load().o_solid_fraction(r, dx, dy))
+
+
+def subcell_fraction(r: float, dx: float, dy: float, n: int) -> float:
+    """The paper's sub-cell estimate of the same fraction: the share of the n x n sub-cell centres
+    of the unit cell centred at (dx, dy) that lie strictly inside the disk."""
+    return float(_load().o_subcell_fraction(r, dx, dy, n))
 
 
 def weight(eps: float, tau: float) -> float:
@@ -138,6 +147,7 @@ class OracleConfig:
     kn: float = 1.0e3
     zeta: float = 0.1
     rho_s: float = 1.0
+    eps_subcells: int = 0       # 0: exact solid ratio; n > 0: the paper's n x n sub-cell estimate
 
 
 class OracleSim:
@@ -147,7 +157,7 @@ class OracleSim:
         lib = _load()
         self.cfg = cfg
         c = _Cfg(cfg.nx, cfg.ny, 1 if cfg.walls else 0, cfg.n_sub, cfg.tau0, cfg.cs, cfg.gx,
-                 cfg.gy, cfg.rho0, cfg.kn, cfg.zeta, cfg.rho_s)
+                 cfg.gy, cfg.rho0, cfg.kn, cfg.zeta, cfg.rho_s, cfg.eps_subcells)
         self._h = lib.o_create(C.byref(c))
         if not self._h:
             raise ValueError("oracle: invalid configuration %r" % (cfg,))

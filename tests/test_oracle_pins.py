@@ -90,6 +90,113 @@ def test_solid_fraction_symmetries_and_range():
             assert abs(ex - e) < 1e-15
 
 
+# ---- the paper's own estimate of the solid ratio: cell decomposition into n x n sub-cells whose
+# centres are tested against the disk (Sec. 2.2)
+
+def test_subcell_one_point_is_the_centre_inside_indicator():
+    """n = 1: the single sub-cell centre is the cell centre; a centre on the circle is outside."""
+    rng = np.random.default_rng(21)
+    for _ in range(2000):
+        r = rng.uniform(0.2, 6.0)
+        dx, dy = rng.uniform(-7, 7, 2)
+        assert oracle.subcell_fraction(r, dx, dy, 1) == (1.0 if dx * dx + dy * dy < r * r else 0.0)
+    assert oracle.subcell_fraction(2.0, 2.0, 0.0, 1) == 0.0
+    assert oracle.subcell_fraction(2.0, 0.0, -2.0, 1) == 0.0
+
+
+@pytest.mark.parametrize("n", [2, 3, 5, 8])
+def test_subcell_full_and_empty_cells(n):
+    """A cell whose farthest corner is inside the disk counts every sub-cell centre, one whose
+    nearest point is outside counts none (the exact ratio is then 1 or 0 as well)."""
+    rng = np.random.default_rng(22 + n)
+    seen = {0.0: 0, 1.0: 0}
+    for _ in range(3000):
+        r = rng.uniform(0.5, 8.0)
+        dx, dy = rng.uniform(-r - 2, r + 2, 2)
+        e = oracle.solid_fraction(r, dx, dy)
+        if e in (0.0, 1.0):
+            assert oracle.subcell_fraction(r, dx, dy, n) == e
+            seen[e] += 1
+    assert seen[0.0] > 100 and seen[1.0] > 100
+
+
+@pytest.mark.parametrize("n", [2, 5, 6, 11])
+def test_subcell_reflection_symmetry(n):
+    """The sub-cell centres are placed symmetrically in the cell, so the count is unchanged by
+    the reflections x -> -x, y -> -y and x <-> y of the cell about the disk centre (a shifted
+    sub-grid breaks this)."""
+    rng = np.random.default_rng(30 + n)
+    cut = 0
+    for _ in range(1500):
+        r = rng.uniform(0.5, 6.0)
+        dx, dy = rng.uniform(-r - 1, r + 1, 2)
+        e = oracle.subcell_fraction(r, dx, dy, n)
+        cut += 0.0 < e < 1.0
+        for ex in (oracle.subcell_fraction(r, -dx, dy, n), oracle.subcell_fraction(r, dx, -dy, n),
+                   oracle.subcell_fraction(r, dy, dx, n)):
+            assert ex == e
+    assert cut > 200
+
+
+@pytest.mark.parametrize("n", [1, 4, 5, 9])
+def test_subcell_counts_agree_with_row_interval_counts(n):
+    """Independent count: in sub-row j (centre ordinate yc) the inside centres are those with
+    |xc| < s, s = sqrt(r^2 - yc^2); the abscissae form the progression dx - 1/2 + (i + 1/2)/n, so
+    their number is the count of integers i in an open interval, taken with floor and ceil."""
+    rng = np.random.default_rng(40 + n)
+    for _ in range(1500):
+        r = rng.uniform(0.3, 5.0)
+        dx, dy = rng.uniform(-r - 1, r + 1, 2)
+        cnt = 0
+        for j in range(n):
+            yc = dy - 0.5 + (j + 0.5) / n
+            if yc * yc >= r * r:
+                continue
+            s = math.sqrt(r * r - yc * yc)
+            lo = (-s - dx + 0.5) * n - 0.5   # i > lo
+            hi = (s - dx + 0.5) * n - 0.5    # i < hi
+            i0, i1 = max(0, math.floor(lo) + 1), min(n - 1, math.ceil(hi) - 1)
+            cnt += max(0, i1 - i0 + 1)
+        assert oracle.subcell_fraction(r, dx, dy, n) * n * n == pytest.approx(cnt, abs=1e-9)
+
+
+@pytest.mark.parametrize("n", [2, 5, 10, 25])
+def test_subcell_total_within_lattice_point_bound(n):
+    """Over every cell of a disk the sub-cell centres form one square grid of spacing h = 1/n;
+    squares of side h around the centres inside lie in the disk of radius r + h/sqrt2 and cover
+    the disk of radius r - h/sqrt2, so |sum eps_n - pi r^2| <= sqrt2 pi r / n + pi / (2 n^2)."""
+    rng = np.random.default_rng(50 + n)
+    for _ in range(6):
+        r = rng.uniform(1.0, 9.0)
+        cx, cy = rng.uniform(0, 1, 2)
+        R = int(r) + 2
+        tot = sum(oracle.subcell_fraction(r, i - cx, j - cy, n) for i in range(-R, R + 1)
+                  for j in range(-R, R + 1))
+        assert abs(tot - math.pi * r * r) <= math.sqrt(2) * math.pi * r / n + math.pi / (2 * n * n)
+
+
+def test_subcell_converges_to_the_exact_ratio():
+    """On cut cells the mean error against the exact area falls as n grows, and at n = 64 every
+    cell is within 4 (l n + 1) / n^2 of it, l <= 2 being a bound on the arc length inside the
+    cell for r >= 1 (only the sub-cells the circle crosses can be miscounted)."""
+    rng = np.random.default_rng(60)
+    cells = []
+    while len(cells) < 300:
+        r = rng.uniform(1.0, 8.0)
+        dx, dy = rng.uniform(-r - 1, r + 1, 2)
+        e = oracle.solid_fraction(r, dx, dy)
+        if 0.0 < e < 1.0:
+            cells.append((r, dx, dy, e))
+    means = []
+    for n in (2, 5, 16, 64):
+        errs = [abs(oracle.subcell_fraction(r, dx, dy, n) - e) for r, dx, dy, e in cells]
+        means.append(float(np.mean(errs)))
+        if n == 64:
+            assert max(errs) <= 4 * (2 * n + 1) / n ** 2
+    assert means[0] > means[1] > means[2] > means[3]
+    assert means[3] < 2e-3
+
+
 def test_solid_fraction_small_disk_inside_one_cell():
     # a disk entirely inside the cell covers pi r^2 of it
     for r in (0.05, 0.2, 0.35):
