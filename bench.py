@@ -130,6 +130,27 @@ def batch_throughput(steps: int = 100):
     return out
 
 
+def subcell_estimate(storage: str, tile, n: int = 5, steps: int = 300):
+    """The same workload with the paper's n x n sub-cell solid ratio instead of the exact one:
+    whole-step time (graph replay) and lattice-kernel time (HIP events)."""
+    from paper_1809_07008_amd import imb, workloads
+    case = workloads.moving_disks(seed=0, storage=storage).with_(eps_subcells=n)
+    sim = imb.simulation_from_case(case, storage=storage, tile_w=tile[0], tile_rows=tile[1])
+    sim.step(20)
+    sim.sync()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    step_us = (time.perf_counter() - t0) * 1e6 / steps
+    sim.set_kernel_timing(True)
+    sim.step(steps)
+    kt = sim.kernel_timing()
+    sim.close()
+    return {"eps_subcells": n, "ms_per_step": round(step_us * 1e-3, 5),
+            "mlups": round(case.cells / step_us, 1),
+            "lattice_kernel_us": round(kt["lattice_ms"] * 1e3 / max(kt["lattice_launches"], 1), 2)}
+
+
 def copy_calibration(nbytes: int, reps: int = 10) -> int:
     """Runs only the plain copy kernel over nbytes (the counter calibration of the traffic
     figure) and prints its bandwidth."""
@@ -271,6 +292,7 @@ def main(argv=None):
         "roofline": roofline,
     }
     if not args.no_adjoint:
+        out["subcell"] = subcell_estimate(args.storage, (args.tile_w, args.tile_rows))
         out["adjoint"] = adjoint_ratio((args.tile_w, args.tile_rows))
         print("bench: adjoint ratio %.3f" % out["adjoint"]["ratio"], file=sys.stderr, flush=True)
         out["batch"] = batch_throughput()

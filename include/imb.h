@@ -72,6 +72,11 @@ typedef struct imb_config {
   int32_t tile_w;          /* tile width in cells: 16, 32, 64, 128 or 256 (0 = 64) */
   int32_t tile_rows;       /* cell rows per thread: 1, 2 or 4 (0 = 1); a tile is
                               tile_w x (256 / tile_w * tile_rows) cells */
+  int32_t eps_subcells;    /* solid ratio of a cell (Sec. 2.2): 0 = the exact covered area;
+                              n = 1..64: the paper's cell decomposition, the fraction of the
+                              n x n sub-cell centres strictly inside the disk (imb_adjoint
+                              rejects n > 0: that estimate is piecewise constant in the position) */
+  int32_t reserved;        /* must be 0 */
 } imb_config;
 
 typedef struct imb_sim imb_sim;

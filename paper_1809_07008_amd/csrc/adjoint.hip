@@ -508,6 +508,11 @@ extern "C" int imb_adjoint(imb_sim* sim, int32_t nsteps, int32_t k, const double
     *v.err = "adjoint: the Smagorinsky term is not differentiated (smag_cs must be 0)";
     return IMB_EINVAL;
   }
+  if (cfg.eps_subcells != 0) {
+    *v.err = "adjoint: the sub-cell solid ratio is piecewise constant in the position and has no "
+             "useful derivative (eps_subcells must be 0)";
+    return IMB_EINVAL;
+  }
   if (cfg.storage != IMB_STORAGE_F32 && cfg.storage != IMB_STORAGE_F64) {
     *v.err = "adjoint: needs F32 or F64 storage";
     return IMB_EUNSUPPORTED;

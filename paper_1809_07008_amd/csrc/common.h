@@ -66,6 +66,7 @@ struct LatticeArgs {
   int nx, ny, pitch, walls;
   int tiles_x, tiles_y;  // tile grid
   int tw_log, rows;      // tile = (1 << tw_log) x ((BLOCK >> tw_log) * rows) cells
+  int eps_sub;           // 0: exact solid ratio; n > 0: fraction of n x n sub-cell centres
   long long plane;       // elements per population plane (pitch * ny)
   double tau0, cs, gx, gy, rho0;
   const void* src;       // stored post-collision populations of the previous step

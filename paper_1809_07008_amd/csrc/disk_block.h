@@ -257,7 +257,7 @@ __device__ void disk_cells(const LatticeArgs& a, int p) {
         continue;
       }
       s_cj[nc][tid] = k;
-      s_ce[nc][tid] = solid_fraction<T>(s_de[k].r, dx, dy);
+      s_ce[nc][tid] = cell_solid_ratio<T>(s_de[k].r, dx, dy, a.eps_sub);
       ++nc;
     }
     if (own < 0) continue;  // p does not cover this cell

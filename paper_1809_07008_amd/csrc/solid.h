@@ -191,6 +191,58 @@ __host__ __device__ inline T solid_fraction(T r, T dx, T dy) {
   return cut_cell_fraction(r, x0, x1, y0, y1);
 }
 
+// Fraction of the n x n sub-cell centres of the cell centred at (dx, dy) strictly inside the
+// disk; out of line, like cut_cell_fraction, so that it does not enlarge the caller's registers.
+template <class T>
+__host__ __device__ __noinline__ T subcell_count(T r, T dx, T dy, int n) {
+  int inside = 0;
+  for (int j = 0; j < n; ++j) {
+    const T yc = dy + (T)((j + 0.5) / n - 0.5);
+    for (int i = 0; i < n; ++i) {
+      const T xc = dx + (T)((i + 0.5) / n - 0.5);
+      inside += xc * xc + yc * yc < r * r ? 1 : 0;
+    }
+  }
+  return (T)inside / ((T)n * (T)n);
+}
+
+// The paper's estimate of the same ratio (Sec. 2.2, cell decomposition): the cell is split into
+// n x n equal sub-cells and eps is the fraction of their centres strictly inside the disk.  A
+// cell whose nearest point is not inside counts none, one whose farthest corner is inside (or on
+// the circle) counts all: every sub-cell centre is then at least 1/(2n) further in or out.
+template <class T>
+__host__ __device__ inline T subcell_fraction(T r, T dx, T dy, int n) {
+  const T x0 = dx - T(0.5), x1 = dx + T(0.5), y0 = dy - T(0.5), y1 = dy + T(0.5);
+  const T nx = x0 > T(0) ? x0 : (x1 < T(0) ? x1 : T(0));
+  const T ny = y0 > T(0) ? y0 : (y1 < T(0) ? y1 : T(0));
+  if (nx * nx + ny * ny >= r * r) return T(0);
+  const T fx = fabs(x0) > fabs(x1) ? fabs(x0) : fabs(x1);
+  const T fy = fabs(y0) > fabs(y1) ? fabs(y0) : fabs(y1);
+  if (fx * fx + fy * fy <= r * r) return T(1);
+  return subcell_count(r, dx, dy, n);
+}
+
+// A cut cell's ratio under the selected estimate (out of line: one call site in the caller).
+template <class T>
+__host__ __device__ __noinline__ T cut_ratio(T r, T dx, T dy, int n) {
+  if (n > 0) return subcell_count(r, dx, dy, n);
+  return cut_cell_fraction(r, dx - T(0.5), dx + T(0.5), dy - T(0.5), dy + T(0.5));
+}
+
+// The solid ratio the configuration selects: exact area (n = 0) or the n x n sub-cell estimate.
+// Both share the test for cells wholly outside or inside.
+template <class T>
+__host__ __device__ inline T cell_solid_ratio(T r, T dx, T dy, int n) {
+  const T x0 = dx - T(0.5), x1 = dx + T(0.5), y0 = dy - T(0.5), y1 = dy + T(0.5);
+  const T nx = x0 > T(0) ? x0 : (x1 < T(0) ? x1 : T(0));
+  const T ny = y0 > T(0) ? y0 : (y1 < T(0) ? y1 : T(0));
+  if (nx * nx + ny * ny >= r * r) return T(0);
+  const T fx = fabs(x0) > fabs(x1) ? fabs(x0) : fabs(x1);
+  const T fy = fabs(y0) > fabs(y1) ? fabs(y0) : fabs(y1);
+  if (fx * fx + fy * fy <= r * r) return T(1);
+  return cut_ratio(r, dx, dy, n);
+}
+
 template <class T>
 __host__ __device__ inline T chord_in(T r, T c, T lo, T hi) {  // chord at coordinate c clipped to [lo, hi]
   const T s = half_chord(r, c);

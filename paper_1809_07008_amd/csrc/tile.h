@@ -114,7 +114,7 @@ __device__ inline int covering_disks(const LatticeArgs& a, const PEntry<T>* pl, 
   for (int j = 0; j < n; ++j) {
     T dx, dy;
     lever_arm(a, pl[j], x, y, &dx, &dy);
-    const T eps = solid_fraction<T>(pl[j].r, dx, dy);
+    const T eps = cell_solid_ratio<T>(pl[j].r, dx, dy, a.eps_sub);
     if (eps > T(0)) {
       if (nc < MAXC) {
         cs.cj[nc][tid] = j;

@@ -60,6 +60,7 @@ class Case:
     kn: float = 1.0e3
     zeta: float = 0.1
     rho_s: float = 1.0
+    eps_subcells: int = 0       # solid ratio: 0 exact area, n > 0 the n x n sub-cell estimate
     particles: Particles = field(default_factory=Particles.empty)
 
     @property

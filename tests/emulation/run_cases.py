@@ -35,7 +35,8 @@ def sim_of(case, storage, tile=(32, 2)):
 def oracle_of(case):
     r = OracleSim(OracleConfig(nx=case.nx, ny=case.ny, tau0=case.tau0, walls=case.walls, cs=case.cs,
                                gx=case.gx, gy=case.gy, rho0=case.rho0, n_sub=case.n_sub,
-                               kn=case.kn, zeta=case.zeta, rho_s=case.rho_s))
+                               kn=case.kn, zeta=case.zeta, rho_s=case.rho_s,
+                               eps_subcells=case.eps_subcells))
     p = case.particles
     r.set_particles(p.x, p.y, p.r, p.vx, p.vy, p.om, p.mode)
     return r
@@ -65,7 +66,8 @@ def overlap_case(walls):
 def fp64_parity():
     for case in (moving_case(), overlap_case(True), overlap_case(False),
                  W.touching_disks(6, True, steps=2), W.touching_disks(8, False, steps=2),
-                 W.approaching_disks(steps=12)):
+                 W.approaching_disks(steps=12), moving_case().with_(eps_subcells=4),
+                 overlap_case(True).with_(eps_subcells=5)):
         s = sim_of(case, "f64")
         s.step(case.steps)
         ref = oracle_of(case)
@@ -81,7 +83,8 @@ def fp64_parity():
             if not case.walls:
                 d[1] -= case.ny * np.round(d[1] / case.ny)
             kerr = np.abs(d).max()
-        check("fp64 parity %s walls=%s" % (case.name, case.walls),
+        check("fp64 parity %s walls=%s eps_subcells=%d" % (case.name, case.walls,
+                                                            case.eps_subcells),
               ferr < 1e-12 and perr < 1e-13 and kerr < 1e-12,
               "force %.2e populations %.2e disks %.2e" % (ferr, perr, kerr))
 

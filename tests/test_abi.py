@@ -39,6 +39,7 @@ int main(void) {
   printf("size %zu\n", sizeof(imb_config));
   O(nx) O(ny) O(storage) O(n_sub) O(tau0) O(smag_cs) O(gx) O(gy) O(rho0) O(kn)
   O(damping_ratio) O(rho_solid) O(max_particles) O(flags) O(tile_w) O(tile_rows)
+  O(eps_subcells) O(reserved)
   return 0;
 }
 ''')
@@ -71,10 +72,20 @@ def test_required_bytes_scales_with_storage():
 @pytest.mark.parametrize("kw", [dict(tau0=0.5), dict(tau0=0.3), dict(nx=1), dict(ny=0),
                                 dict(storage=7), dict(cs=-0.1), dict(n_sub=0),
                                 dict(max_particles=5000), dict(tile_w=48), dict(tile_rows=3),
-                                dict(rho0=0.0), dict(rho_s=0.0)])
+                                dict(rho0=0.0), dict(rho_s=0.0), dict(eps_subcells=-1),
+                                dict(eps_subcells=65)])
 def test_invalid_configs_rejected(kw):
     rc, _ = required(**kw)
     assert rc == -1
+
+
+def test_reserved_config_word_must_be_zero():
+    lib = imb.load_library()
+    c = imb.make_config(nx=64, ny=32, tau0=0.6, eps_subcells=5)
+    n = C.c_size_t()
+    assert lib.imb_required_bytes(C.byref(c), C.byref(n)) == 0
+    c.reserved = 1
+    assert lib.imb_required_bytes(C.byref(c), C.byref(n)) == -1
 
 
 def test_strerror_and_version():

@@ -145,6 +145,8 @@ def test_adjoint_rejects_unsupported():
         gpu_adjoint(case.with_(particles=p), k=2)
     with pytest.raises(imb.ImbError):
         gpu_adjoint(case, k=0)
+    with pytest.raises(imb.ImbError):  # the sub-cell solid ratio has no useful derivative
+        gpu_adjoint(case.with_(eps_subcells=5), k=2)
 
 
 def test_adjoint_no_disks_body_force_only():
