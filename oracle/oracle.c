@@ -76,6 +76,7 @@ typedef struct {
   double zeta;    /* normal damping ratio */
   double rho_s;   /* particle density (mass per unit area) */
   int32_t eps_subcells; /* 0: exact solid ratio; n > 0: the n x n sub-cell estimate */
+  double uw_bot, uw_top; /* x-velocity of the wall at y = -1/2 and of the wall at y = ny - 1/2 */
 } ocfg;
 
 typedef struct {
@@ -304,7 +305,7 @@ void o_destroy(osim *s);
 
 osim *o_create(const ocfg *c) {
   if (!c || c->nx < 2 || c->ny < 2 || !(c->tau0 > 0.5) || c->cs < 0.0 || c->n_sub < 1 ||
-      c->eps_subcells < 0)
+      c->eps_subcells < 0 || (!c->walls && (c->uw_bot != 0.0 || c->uw_top != 0.0)))
     return NULL;
   osim *s = (osim *)calloc(1, sizeof(osim));
   if (!s) return NULL;
@@ -626,7 +627,9 @@ static void collide_all(osim *s) {
 }
 
 /* Streaming, left-hand side of Eq. (1): f_i(x + c_i) <- f*_i(x); a link leaving through a wall
- * returns to its own node in the opposite direction (half-way bounce-back, resting wall). */
+ * returns to its own node in the opposite direction (half-way bounce-back).  A wall moving with
+ * velocity u_w along x hands back f*_i - 6 w_i rho0 (c_i . u_w): the momentum exchange of a
+ * moving bounce-back wall (Ladd), with the reference density rho0 at the wall. */
 static void stream_all(osim *s) {
   int nx = s->c.nx, ny = s->c.ny;
 #pragma omp parallel for schedule(static)
@@ -638,7 +641,9 @@ static void stream_all(osim *s) {
         int yn = y + CY[i];
         if (yn < 0 || yn >= ny) {
           if (s->c.walls) {
-            s->f[((size_t)y * nx + x) * NQ + OPP[i]] = fp[i];
+            const double uw = yn >= ny ? s->c.uw_top : s->c.uw_bot;
+            const double corr = 6.0 * WQ[i] * s->c.rho0 * ((double)CX[i] * uw);
+            s->f[((size_t)y * nx + x) * NQ + OPP[i]] = fp[i] - corr;
             continue;
           }
           yn = (yn + ny) % ny;

@@ -36,7 +36,7 @@ class _Cfg(C.Structure):
                 ("n_sub", C.c_int32), ("tau0", C.c_double), ("cs", C.c_double),
                 ("gx", C.c_double), ("gy", C.c_double), ("rho0", C.c_double),
                 ("kn", C.c_double), ("zeta", C.c_double), ("rho_s", C.c_double),
-                ("eps_subcells", C.c_int32)]
+                ("eps_subcells", C.c_int32), ("uw_bot", C.c_double), ("uw_top", C.c_double)]
 
 
 _lib = None
@@ -148,6 +148,8 @@ class OracleConfig:
     zeta: float = 0.1
     rho_s: float = 1.0
     eps_subcells: int = 0       # 0: exact solid ratio; n > 0: the paper's n x n sub-cell estimate
+    uw_bot: float = 0.0         # x-velocity of the bottom wall (y = -1/2), walls only
+    uw_top: float = 0.0         # x-velocity of the top wall (y = ny - 1/2), walls only
 
 
 class OracleSim:
@@ -157,7 +159,8 @@ class OracleSim:
         lib = _load()
         self.cfg = cfg
         c = _Cfg(cfg.nx, cfg.ny, 1 if cfg.walls else 0, cfg.n_sub, cfg.tau0, cfg.cs, cfg.gx,
-                 cfg.gy, cfg.rho0, cfg.kn, cfg.zeta, cfg.rho_s, cfg.eps_subcells)
+                 cfg.gy, cfg.rho0, cfg.kn, cfg.zeta, cfg.rho_s, cfg.eps_subcells,
+                 cfg.uw_bot, cfg.uw_top)
         self._h = lib.o_create(C.byref(c))
         if not self._h:
             raise ValueError("oracle: invalid configuration %r" % (cfg,))

@@ -197,6 +197,58 @@ def test_subcell_converges_to_the_exact_ratio():
     assert means[3] < 2e-3
 
 
+# ---- moving walls: half-way bounce-back with the wall's momentum (Ladd), plane Couette flow
+
+@pytest.mark.parametrize("ny,tau,ub,ut", [(8, 0.6, 0.0, 0.04), (16, 0.8, -0.03, 0.02),
+                                          (12, 1.0, 0.05, 0.05), (10, 0.7, 0.01, -0.02)])
+def test_couette_flow_closed_form(ny, tau, ub, ut):
+    """Walls at y = -1/2 and y = ny - 1/2 moving along x at ub and ut, no body force: the steady
+    state is the linear profile u(y) = ub + (ut - ub)(y + 1/2)/ny, uniform density, no cross
+    flow (an exact steady solution of the lattice equations with half-way bounce-back).  Run for
+    40 e-folds of the slowest shear mode (rate nu pi^2 / ny^2); the tolerance is the round-off
+    the mode's conditioning (about ny^2 / nu) allows, and the density's, the drift of the total
+    mass (a neutral mode) under the two wall corrections of a cell, which cancel exactly only
+    in real arithmetic (below 1e-16 per step)."""
+    nu = (tau - 0.5) / 3.0
+    steps = int(math.ceil(40.0 * ny * ny / (nu * math.pi ** 2)))
+    r = OracleSim(OracleConfig(nx=2, ny=ny, tau0=tau, uw_bot=ub, uw_top=ut))
+    r.step(steps)
+    rho, ux, uy = r.fields()
+    exact = ub + (ut - ub) * (np.arange(ny) + 0.5) / ny
+    scale = max(abs(ub), abs(ut))
+    assert np.abs(ux - exact[:, None]).max() <= 1e-11 * scale
+    assert np.abs(uy).max() <= 1e-11 * scale
+    assert np.abs(rho - 1.0).max() <= 1e-16 * steps
+
+
+def test_walls_moving_with_the_fluid_keep_its_equilibrium():
+    """Both walls at U and f = f^eq(rho0, U): the bounce-back correction maps f^eq_i(U) onto
+    f^eq_opp(i)(U) exactly, so the uniform flow is a fixed point of the step (up to round-off,
+    which drifts by about 1e-17 per step)."""
+    U = 0.04
+    r = OracleSim(OracleConfig(nx=6, ny=10, tau0=0.7, uw_bot=U, uw_top=U))
+    r.init_equilibrium(1.0, U, 0.0)
+    f0 = r.populations()
+    r.step(300)
+    assert np.abs(r.populations() - f0).max() <= 1e-13
+
+
+def test_resting_walls_are_unchanged_by_a_zero_wall_velocity():
+    p = W.Particles(np.array([10.3]), np.array([6.2]), np.array([3.1]), np.zeros(1), np.zeros(1),
+                    np.zeros(1), np.array([1], np.int32))
+    a = OracleSim(OracleConfig(nx=24, ny=14, tau0=0.7, gx=1e-5))
+    b = OracleSim(OracleConfig(nx=24, ny=14, tau0=0.7, gx=1e-5, uw_bot=0.0, uw_top=-0.0))
+    for r in (a, b):
+        r.set_particles(p.x, p.y, p.r, p.vx, p.vy, p.om, p.mode)
+        r.step(30)
+    assert np.array_equal(a.populations(), b.populations())
+
+
+def test_moving_walls_need_walls():
+    with pytest.raises(ValueError):
+        OracleSim(OracleConfig(nx=8, ny=8, tau0=0.7, walls=False, uw_top=0.01))
+
+
 def test_solid_fraction_small_disk_inside_one_cell():
     # a disk entirely inside the cell covers pi r^2 of it
     for r in (0.05, 0.2, 0.35):
