@@ -77,6 +77,10 @@ typedef struct imb_config {
                               n x n sub-cell centres strictly inside the disk (imb_adjoint
                               rejects n > 0: that estimate is piecewise constant in the position) */
   int32_t reserved;        /* must be 0 */
+  double wall_ux_bottom;   /* x-velocity of the wall at y = -1/2 (walls only; |u| <= 0.3) */
+  double wall_ux_top;      /* x-velocity of the wall at y = ny - 1/2: a link crossing a wall
+                              that moves at u_w returns f*_i - 6 w_i rho0 (c_i . u_w), the
+                              moving bounce-back (plane Couette flow between the two) */
 } imb_config;
 
 typedef struct imb_sim imb_sim;

@@ -67,6 +67,11 @@ struct LatticeArgs {
   int tiles_x, tiles_y;  // tile grid
   int tw_log, rows;      // tile = (1 << tw_log) x ((BLOCK >> tw_log) * rows) cells
   int eps_sub;           // 0: exact solid ratio; n > 0: fraction of n x n sub-cell centres
+  // moving walls: 6 w_j rho0 (c_j . u_w) for a population j sent into the wall at y = -1/2
+  // (wall_bot) or y = ny - 1/2 (wall_top), u_w along x; it comes back as opp(j) lowered by it
+  int walls_move;
+  double wall_bot[NQ], wall_top[NQ];
+  float wall_bot_f[NQ], wall_top_f[NQ];  // the same rounded to FP32 (the FP32 arithmetic forms)
   long long plane;       // elements per population plane (pitch * ny)
   double tau0, cs, gx, gy, rho0;
   const void* src;       // stored post-collision populations of the previous step
@@ -83,6 +88,32 @@ struct LatticeArgs {
   const int* nnbr;
   double4* force;        // [np] force and torque of this step (Fx, Fy, Tz, 0)
 };
+
+// The momentum a moving wall takes from population j sent into it (through y = -1/2 when
+// `bottom`): the returning opp(j) is lowered by this.
+template <class T>
+__device__ inline T wall_momentum(const LatticeArgs& a, int j, bool bottom) {
+  if constexpr (sizeof(T) == 4) return bottom ? a.wall_bot_f[j] : a.wall_top_f[j];
+  else return bottom ? a.wall_bot[j] : a.wall_top[j];
+}
+
+// A population that a wall-row cell sends into a moving wall is read back only by that cell's
+// own bounce-back pull, so it is stored already lowered by the wall's momentum: the pull then
+// returns f*_j - 6 w_j rho0 (c_j . u_w) unchanged.  No-op unless a wall moves (uniform).
+template <class T>
+__device__ inline void wall_adjust(const LatticeArgs& a, int y, T fo[NQ]) {
+  if (!a.walls_move) return;
+  if (y == 0) {
+#pragma unroll
+    for (int j = 0; j < NQ; ++j)
+      if (cy_of(j) < 0) fo[j] = fo[j] - wall_momentum<T>(a, j, true);
+  }
+  if (y == a.ny - 1) {
+#pragma unroll
+    for (int j = 0; j < NQ; ++j)
+      if (cy_of(j) > 0) fo[j] = fo[j] - wall_momentum<T>(a, j, false);
+  }
+}
 
 // Particle state on the device (structure of arrays, FP64).
 struct ParticleState {

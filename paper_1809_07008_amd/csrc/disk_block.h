@@ -79,6 +79,7 @@ __device__ void fluid_tile(const LatticeArgs& a, int tile) {
       rho = collide_plain(f, 0, none, drop, tau0, csm, gx, gy, fo);
     }
     if (!(rho > T(0)) || !isfinite(rho)) atomicOr(a.err, ERR_RHO);
+    wall_adjust<T>(a, y, fo);
     const long long base = (long long)y * a.pitch + x;
     S out[NQ];
     if constexpr (St::stochastic) {
@@ -287,6 +288,7 @@ __device__ void disk_cells(const LatticeArgs& a, int p) {
     }
     if (!owner) continue;
     if (!(rho > T(0)) || !isfinite(rho)) atomicOr(a.err, ERR_RHO);
+    wall_adjust<T>(a, y, fo);
     const long long off = (long long)y * a.pitch + x;
     if constexpr (St::stochastic) {
       const unsigned r0 = pcg_hash(seed * 0x9E3779B9u + (unsigned)off);

@@ -98,6 +98,10 @@ int validate_config(const imb_config* c, std::string* why) {
   if (!(c->smag_cs >= 0.0)) return bad("Smagorinsky constant must be >= 0");
   if (c->eps_subcells < 0 || c->eps_subcells > 64) return bad("eps_subcells must be 0..64");
   if (c->reserved != 0) return bad("reserved must be 0");
+  if (!(std::fabs(c->wall_ux_bottom) <= 0.3) || !(std::fabs(c->wall_ux_top) <= 0.3))
+    return bad("wall velocities must be finite and at most 0.3 in magnitude");
+  if (!(c->flags & IMB_FLAG_WALLS) && (c->wall_ux_bottom != 0.0 || c->wall_ux_top != 0.0))
+    return bad("moving walls need walls");
   if (c->n_sub < 1 || c->n_sub > 100000) return bad("n_sub must be in 1..100000");
   if (!(c->rho0 > 0.0)) return bad("rho0 must be positive");
   if (!(c->kn >= 0.0) || !(c->damping_ratio >= 0.0) || !(c->rho_solid > 0.0))
@@ -185,6 +189,13 @@ LatticeArgs lattice_args(imb_sim* s, const void* src, void* dst) {
   a.tw_log = s->g.tw_log; a.rows = s->g.rows; a.plane = s->g.plane;
   a.tau0 = s->cfg.tau0; a.cs = s->cfg.smag_cs; a.gx = s->cfg.gx; a.gy = s->cfg.gy;
   a.eps_sub = s->cfg.eps_subcells;
+  a.walls_move = a.walls && (s->cfg.wall_ux_bottom != 0.0 || s->cfg.wall_ux_top != 0.0);
+  for (int j = 0; j < NQ; ++j) {  // 6 w_j rho0 (c_j . u_w), evaluated as the oracle does
+    a.wall_bot[j] = 6.0 * w_of(j) * s->cfg.rho0 * ((double)cx_of(j) * s->cfg.wall_ux_bottom);
+    a.wall_top[j] = 6.0 * w_of(j) * s->cfg.rho0 * ((double)cx_of(j) * s->cfg.wall_ux_top);
+    a.wall_bot_f[j] = (float)a.wall_bot[j];
+    a.wall_top_f[j] = (float)a.wall_top[j];
+  }
   a.rho0 = s->cfg.rho0;
   a.src = src; a.dst = dst;
   // the tables of the step reading this source (no source: those of the stored state)
@@ -434,7 +445,7 @@ void imb_config_default(imb_config* c) {
   c->tau0 = 0.6; c->smag_cs = 0.0; c->gx = 0.0; c->gy = 0.0; c->rho0 = 1.0;
   c->kn = 1.0e3; c->damping_ratio = 0.1; c->rho_solid = 1.0; c->max_particles = 64;
   c->flags = IMB_FLAG_WALLS; c->tile_w = 64; c->tile_rows = 1;
-  c->eps_subcells = 0; c->reserved = 0;
+  c->eps_subcells = 0; c->reserved = 0; c->wall_ux_bottom = 0.0; c->wall_ux_top = 0.0;
 }
 
 int imb_required_bytes(const imb_config* cfg, size_t* bytes) {

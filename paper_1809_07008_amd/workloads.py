@@ -61,6 +61,8 @@ class Case:
     zeta: float = 0.1
     rho_s: float = 1.0
     eps_subcells: int = 0       # solid ratio: 0 exact area, n > 0 the n x n sub-cell estimate
+    uw_bot: float = 0.0         # x-velocity of the bottom wall (walls only)
+    uw_top: float = 0.0         # x-velocity of the top wall (walls only)
     particles: Particles = field(default_factory=Particles.empty)
 
     @property
@@ -164,6 +166,14 @@ def approaching_disks(steps: int = 300) -> Case:
     p = _particles(x, [24.0] * n, [5.0] * n, vx, [0.0] * n)
     return Case("approaching_disks", 128, 48, tau0=0.7, steps=steps, gx=1.0e-5, kn=50.0,
                 particles=p)
+
+
+def couette_channel(storage: str = "f64", disk: bool = True, steps: int = 400) -> Case:
+    """128x48 channel between walls moving along x at -0.02 (bottom) and +0.03 (top), tau 0.8,
+    no body force; optionally a fixed disk of radius 6 at (52.3, 23.6) in the shear flow."""
+    p = (_particles([52.3], [23.6], [6.0], mode=MODE_FIXED) if disk else Particles.empty())
+    return Case("couette_128x48", 128, 48, tau0=0.8, steps=steps, storage=storage, gx=0.0,
+                uw_bot=-0.02, uw_top=0.03, particles=p)
 
 
 def adjoint_channel(seed: int = 0, storage: str = "f32", v_std: float = 0.0) -> Case:

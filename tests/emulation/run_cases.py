@@ -36,7 +36,8 @@ def oracle_of(case):
     r = OracleSim(OracleConfig(nx=case.nx, ny=case.ny, tau0=case.tau0, walls=case.walls, cs=case.cs,
                                gx=case.gx, gy=case.gy, rho0=case.rho0, n_sub=case.n_sub,
                                kn=case.kn, zeta=case.zeta, rho_s=case.rho_s,
-                               eps_subcells=case.eps_subcells))
+                               eps_subcells=case.eps_subcells, uw_bot=case.uw_bot,
+                               uw_top=case.uw_top))
     p = case.particles
     r.set_particles(p.x, p.y, p.r, p.vx, p.vy, p.om, p.mode)
     return r
@@ -67,7 +68,8 @@ def fp64_parity():
     for case in (moving_case(), overlap_case(True), overlap_case(False),
                  W.touching_disks(6, True, steps=2), W.touching_disks(8, False, steps=2),
                  W.approaching_disks(steps=12), moving_case().with_(eps_subcells=4),
-                 overlap_case(True).with_(eps_subcells=5)):
+                 overlap_case(True).with_(eps_subcells=5), W.couette_channel("f64", steps=6),
+                 moving_case().with_(uw_bot=0.02, uw_top=-0.01)):
         s = sim_of(case, "f64")
         s.step(case.steps)
         ref = oracle_of(case)

@@ -39,7 +39,7 @@ int main(void) {
   printf("size %zu\n", sizeof(imb_config));
   O(nx) O(ny) O(storage) O(n_sub) O(tau0) O(smag_cs) O(gx) O(gy) O(rho0) O(kn)
   O(damping_ratio) O(rho_solid) O(max_particles) O(flags) O(tile_w) O(tile_rows)
-  O(eps_subcells) O(reserved)
+  O(eps_subcells) O(reserved) O(wall_ux_bottom) O(wall_ux_top)
   return 0;
 }
 ''')
@@ -73,7 +73,8 @@ def test_required_bytes_scales_with_storage():
                                 dict(storage=7), dict(cs=-0.1), dict(n_sub=0),
                                 dict(max_particles=5000), dict(tile_w=48), dict(tile_rows=3),
                                 dict(rho0=0.0), dict(rho_s=0.0), dict(eps_subcells=-1),
-                                dict(eps_subcells=65)])
+                                dict(eps_subcells=65), dict(uw_top=0.4), dict(uw_bot=-0.31),
+                                dict(walls=False, uw_top=0.01)])
 def test_invalid_configs_rejected(kw):
     rc, _ = required(**kw)
     assert rc == -1
