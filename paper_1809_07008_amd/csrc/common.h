@@ -67,11 +67,12 @@ struct LatticeArgs {
   int tiles_x, tiles_y;  // tile grid
   int tw_log, rows;      // tile = (1 << tw_log) x ((BLOCK >> tw_log) * rows) cells
   int eps_sub;           // 0: exact solid ratio; n > 0: fraction of n x n sub-cell centres
-  // moving walls: 6 w_j rho0 (c_j . u_w) for a population j sent into the wall at y = -1/2
-  // (wall_bot) or y = ny - 1/2 (wall_top), u_w along x; it comes back as opp(j) lowered by it
+  // moving walls: 6 w_j rho0 (c_j . u_w) for a population j sent into a wall moving along x
+  // at u_w; it comes back as opp(j) lowered by it.  Only the diagonal directions carry it:
+  // [0], [1] for j = 7, 8 into the wall at y = -1/2, [2], [3] for j = 5, 6 into y = ny - 1/2
   int walls_move;
-  double wall_bot[NQ], wall_top[NQ];
-  float wall_bot_f[NQ], wall_top_f[NQ];  // the same rounded to FP32 (the FP32 arithmetic forms)
+  double wall_c[4];
+  float wall_cf[4];  // the same rounded to FP32 (the FP32 arithmetic forms)
   long long plane;       // elements per population plane (pitch * ny)
   double tau0, cs, gx, gy, rho0;
   const void* src;       // stored post-collision populations of the previous step
@@ -91,11 +92,6 @@ struct LatticeArgs {
 
 // The momentum a moving wall takes from population j sent into it (through y = -1/2 when
 // `bottom`): the returning opp(j) is lowered by this.
-template <class T>
-__device__ inline T wall_momentum(const LatticeArgs& a, int j, bool bottom) {
-  if constexpr (sizeof(T) == 4) return bottom ? a.wall_bot_f[j] : a.wall_top_f[j];
-  else return bottom ? a.wall_bot[j] : a.wall_top[j];
-}
 
 // A population that a wall-row cell sends into a moving wall is read back only by that cell's
 // own bounce-back pull, so it is stored already lowered by the wall's momentum: the pull then
@@ -103,15 +99,24 @@ __device__ inline T wall_momentum(const LatticeArgs& a, int j, bool bottom) {
 template <class T>
 __device__ inline void wall_adjust(const LatticeArgs& a, int y, T fo[NQ]) {
   if (!a.walls_move) return;
+  static_assert(cy_of(7) < 0 && cy_of(8) < 0 && cy_of(5) > 0 && cy_of(6) > 0, "diagonals");
   if (y == 0) {
-#pragma unroll
-    for (int j = 0; j < NQ; ++j)
-      if (cy_of(j) < 0) fo[j] = fo[j] - wall_momentum<T>(a, j, true);
+    if constexpr (sizeof(T) == 4) {
+      fo[7] = fo[7] - a.wall_cf[0];
+      fo[8] = fo[8] - a.wall_cf[1];
+    } else {
+      fo[7] = fo[7] - a.wall_c[0];
+      fo[8] = fo[8] - a.wall_c[1];
+    }
   }
   if (y == a.ny - 1) {
-#pragma unroll
-    for (int j = 0; j < NQ; ++j)
-      if (cy_of(j) > 0) fo[j] = fo[j] - wall_momentum<T>(a, j, false);
+    if constexpr (sizeof(T) == 4) {
+      fo[5] = fo[5] - a.wall_cf[2];
+      fo[6] = fo[6] - a.wall_cf[3];
+    } else {
+      fo[5] = fo[5] - a.wall_c[2];
+      fo[6] = fo[6] - a.wall_c[3];
+    }
   }
 }
 

@@ -190,11 +190,11 @@ LatticeArgs lattice_args(imb_sim* s, const void* src, void* dst) {
   a.tau0 = s->cfg.tau0; a.cs = s->cfg.smag_cs; a.gx = s->cfg.gx; a.gy = s->cfg.gy;
   a.eps_sub = s->cfg.eps_subcells;
   a.walls_move = a.walls && (s->cfg.wall_ux_bottom != 0.0 || s->cfg.wall_ux_top != 0.0);
-  for (int j = 0; j < NQ; ++j) {  // 6 w_j rho0 (c_j . u_w), evaluated as the oracle does
-    a.wall_bot[j] = 6.0 * w_of(j) * s->cfg.rho0 * ((double)cx_of(j) * s->cfg.wall_ux_bottom);
-    a.wall_top[j] = 6.0 * w_of(j) * s->cfg.rho0 * ((double)cx_of(j) * s->cfg.wall_ux_top);
-    a.wall_bot_f[j] = (float)a.wall_bot[j];
-    a.wall_top_f[j] = (float)a.wall_top[j];
+  const int wj[4] = {7, 8, 5, 6};  // diagonals into the bottom wall, then into the top wall
+  for (int k = 0; k < 4; ++k) {  // 6 w_j rho0 (c_j . u_w), evaluated as the oracle does
+    const double uw = k < 2 ? s->cfg.wall_ux_bottom : s->cfg.wall_ux_top;
+    a.wall_c[k] = 6.0 * w_of(wj[k]) * s->cfg.rho0 * ((double)cx_of(wj[k]) * uw);
+    a.wall_cf[k] = (float)a.wall_c[k];
   }
   a.rho0 = s->cfg.rho0;
   a.src = src; a.dst = dst;
