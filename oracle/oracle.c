@@ -39,6 +39,8 @@
  *   - cycle order: map disks -> collide -> stream -> forces -> DEM sub-cycles (Fig. 4 entered at the
  *     mapping stage).
  *   - DEM damping ratio zeta: c_n = 2 zeta sqrt(k_n m_eff); m = rho_s pi r^2, I = m r^2 / 2.
+ *   - walls moving along x (plane Couette flow): bounce-back with the wall's momentum,
+ *     f*_i - 6 w_i rho0 (c_i . u_w) (Ladd), the reference density taken at the wall.
  *
  * Compile with -ffp-contract=off (no fused multiply-add) and without -ffast-math.
  */
