@@ -1,4 +1,6 @@
 // particles.hip -- the particle phase as its own one-workgroup kernel (particle_phase.h).
+#include <hip/hip_ext.h>
+
 #include "particle_phase.h"
 
 namespace imb {
@@ -14,9 +16,12 @@ size_t particle_phase_lds(int np, int tiles_y) {
   return dem > band ? dem : band;
 }
 
-void launch_particle_phase(const ParticleArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_particle_phase, dim3(1), dim3(PBLOCK),
-                     particle_phase_lds(a.np, a.tiles_y), s, a);
+void launch_particle_phase(const ParticleArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  const size_t lds = particle_phase_lds(a.np, a.tiles_y);
+  if (e0 || e1)
+    hipExtLaunchKernelGGL(k_particle_phase, dim3(1), dim3(PBLOCK), (uint32_t)lds, s, e0, e1, 0, a);
+  else
+    hipLaunchKernelGGL(k_particle_phase, dim3(1), dim3(PBLOCK), lds, s, a);
 }
 
 }  // namespace imb

@@ -242,24 +242,25 @@ void enqueue_step(imb_sim* s, const double* wfx, const double* wfy, const double
                   double* J) {
   const int c = s->cur;
   LatticeArgs la = lattice_args(s, s->d.f[c], s->d.f[c ^ 1]);
+  // timing: events recorded by the launch itself at the kernel's start and end
   auto timed = [&](int k, auto&& launch) {
     if (!s->timing) {
-      launch();
+      launch(nullptr, nullptr);
       return;
     }
     hipEvent_t e0 = take_event(s), e1 = take_event(s);
-    hipEventRecord(e0, s->stream);
-    launch();
-    hipEventRecord(e1, s->stream);
+    launch(e0, e1);
     s->ev_k[k].push_back(e0);
     s->ev_k[k].push_back(e1);
   };
-  timed(0, [&] { launch_lattice_step(s->cfg.storage, la, s->stream); });
+  timed(0, [&](hipEvent_t e0, hipEvent_t e1) {
+    launch_lattice_step(s->cfg.storage, la, s->stream, e0, e1);
+  });
   if (s->np > 0) {
     ParticleArgs pa = particle_args(s, c ^ 1);
     pa.do_finalize = 1; pa.do_dem = 1; pa.do_table = 1;
     pa.wfx = wfx; pa.wfy = wfy; pa.wtz = wtz; pa.J = J;
-    timed(1, [&] { launch_particle_phase(pa, s->stream); });
+    timed(1, [&](hipEvent_t e0, hipEvent_t e1) { launch_particle_phase(pa, s->stream, e0, e1); });
   }
   s->cur ^= 1;
   s->steps++;

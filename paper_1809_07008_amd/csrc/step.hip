@@ -3,6 +3,8 @@
 // (fluid_tile: the cells no disk covers).  The disks' longer, latency-bound work is dispatched
 // first and overlaps the tiles' streaming.  The particle phase follows as its own one-workgroup
 // kernel (particles.hip) on the same stream.
+#include <hip/hip_ext.h>
+
 #include "disk_block.h"
 #include "step.h"
 
@@ -52,12 +54,17 @@ __global__ __launch_bounds__(BLOCK) void k_solid_field(LatticeArgs a, double* ep
   }
 }
 
-void launch_lattice_step(int storage, const LatticeArgs& a, hipStream_t s) {
+void launch_lattice_step(int storage, const LatticeArgs& a, hipStream_t s, hipEvent_t e0,
+                         hipEvent_t e1) {
   const dim3 grid(a.np + a.tiles_x * a.tiles_y);
+  auto go = [&](auto kernel) {
+    if (e0 || e1) hipExtLaunchKernelGGL(kernel, grid, dim3(BLOCK), 0, s, e0, e1, 0, a);
+    else hipLaunchKernelGGL(kernel, grid, dim3(BLOCK), 0, s, a);
+  };
   switch (storage) {
-    case IMB_STORAGE_F64: hipLaunchKernelGGL(k_step_f64, grid, dim3(BLOCK), 0, s, a); break;
-    case IMB_STORAGE_F32: hipLaunchKernelGGL(k_step<StoreF32>, grid, dim3(BLOCK), 0, s, a); break;
-    default: hipLaunchKernelGGL(k_step<StoreF16>, grid, dim3(BLOCK), 0, s, a); break;
+    case IMB_STORAGE_F64: go(k_step_f64); break;
+    case IMB_STORAGE_F32: go(k_step<StoreF32>); break;
+    default: go(k_step<StoreF16>); break;
   }
 }
 
