@@ -170,9 +170,10 @@ int imb_load_state(imb_sim* sim, const void* host_buf, size_t bytes);
 
 /* Per-kernel timing with HIP events on the simulation's stream.  A coupled step is two kernels:
  * the lattice kernel (every cell's update, each disk's force and torque) and the particle phase
- * (DEM, the next step's disk tables).  When enabled, imb_step records an event pair around every
- * launch of each; imb_get_kernel_timing synchronises and returns the summed milliseconds and
- * launch counts since the last reset (any pointer may be NULL). */
+ * (DEM, the next step's disk tables).  When enabled, every launch of each records an event pair
+ * at the kernel's own start and end (so the gap after the previous kernel is not counted);
+ * imb_get_kernel_timing synchronises and returns the summed milliseconds and launch counts since
+ * the last reset (any pointer may be NULL). */
 int imb_set_kernel_timing(imb_sim* sim, int enable);
 int imb_get_kernel_timing(imb_sim* sim, double* lattice_ms, int64_t* lattice_launches,
                           double* particle_ms, int64_t* particle_launches);

@@ -226,7 +226,6 @@ __device__ inline int xcd_remap(int b, int n) {
   return xcd * q + (xcd < r ? xcd : r) + j;
 }
 
-__host__ __device__ inline int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 __host__ __device__ inline int wrap_int(int a, int n) { int m = a % n; return m < 0 ? m + n : m; }
 // wrap_int for a within one period of [0, n) without a division (the general form otherwise)
 __host__ __device__ inline int wrap_near(int a, int n) {

@@ -206,22 +206,6 @@ __host__ __device__ __noinline__ T subcell_count(T r, T dx, T dy, int n) {
   return (T)inside / ((T)n * (T)n);
 }
 
-// The paper's estimate of the same ratio (Sec. 2.2, cell decomposition): the cell is split into
-// n x n equal sub-cells and eps is the fraction of their centres strictly inside the disk.  A
-// cell whose nearest point is not inside counts none, one whose farthest corner is inside (or on
-// the circle) counts all: every sub-cell centre is then at least 1/(2n) further in or out.
-template <class T>
-__host__ __device__ inline T subcell_fraction(T r, T dx, T dy, int n) {
-  const T x0 = dx - T(0.5), x1 = dx + T(0.5), y0 = dy - T(0.5), y1 = dy + T(0.5);
-  const T nx = x0 > T(0) ? x0 : (x1 < T(0) ? x1 : T(0));
-  const T ny = y0 > T(0) ? y0 : (y1 < T(0) ? y1 : T(0));
-  if (nx * nx + ny * ny >= r * r) return T(0);
-  const T fx = fabs(x0) > fabs(x1) ? fabs(x0) : fabs(x1);
-  const T fy = fabs(y0) > fabs(y1) ? fabs(y0) : fabs(y1);
-  if (fx * fx + fy * fy <= r * r) return T(1);
-  return subcell_count(r, dx, dy, n);
-}
-
 // A cut cell's ratio under the selected estimate (out of line: one call site in the caller).
 template <class T>
 __host__ __device__ __noinline__ T cut_ratio(T r, T dx, T dy, int n) {
@@ -229,8 +213,11 @@ __host__ __device__ __noinline__ T cut_ratio(T r, T dx, T dy, int n) {
   return cut_cell_fraction(r, dx - T(0.5), dx + T(0.5), dy - T(0.5), dy + T(0.5));
 }
 
-// The solid ratio the configuration selects: exact area (n = 0) or the n x n sub-cell estimate.
-// Both share the test for cells wholly outside or inside.
+// The solid ratio the configuration selects: the exact area (n = 0) or the paper's estimate
+// (Sec. 2.2, cell decomposition), the fraction of the cell's n x n sub-cell centres strictly
+// inside the disk.  Both share the test for cells wholly outside (nearest point not inside: 0)
+// or inside (farthest corner inside or on the circle: 1; every sub-cell centre is then at least
+// 1/(2n) further in or out), so only cut cells reach the out-of-line part.
 template <class T>
 __host__ __device__ inline T cell_solid_ratio(T r, T dx, T dy, int n) {
   const T x0 = dx - T(0.5), x1 = dx + T(0.5), y0 = dy - T(0.5), y1 = dy + T(0.5);
