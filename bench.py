@@ -177,7 +177,8 @@ def bytes_per_lup(storage: str) -> int:
 
 
 def cpu_baseline(case, target_s: float = 15.0):
-    """The FP64 CPU oracle on the same workload, a bounded number of steps (host cores)."""
+    """The FP64 CPU oracle on the same workload, a bounded number of steps, on the host's cores
+    and (as `single_core`) on one core."""
     import oracle
     ref = oracle.OracleSim(oracle.OracleConfig(nx=case.nx, ny=case.ny, tau0=case.tau0,
                                                walls=case.walls, cs=case.cs, gx=case.gx,
@@ -192,10 +193,26 @@ def cpu_baseline(case, target_s: float = 15.0):
     t0 = time.perf_counter()
     ref.step(n)
     dt = time.perf_counter() - t0
-    return {"value": round(case.cells * n / dt / 1e6, 3), "unit": "MLUPS",
-            "cores": oracle.get_threads(), "kind": "oracle",
-            "sample": "%d coupled steps of the %dx%d / %d-disk workload in FP64 (after 1 warm-up "
-                      "step), %.1f s" % (n, case.nx, case.ny, p.n, dt)}
+    out = {"value": round(case.cells * n / dt / 1e6, 3), "unit": "MLUPS",
+           "cores": oracle.get_threads(), "kind": "oracle",
+           "sample": "%d coupled steps of the %dx%d / %d-disk workload in FP64 (after 1 warm-up "
+                     "step), %.1f s" % (n, case.nx, case.ny, p.n, dt)}
+    # the same on one core (a few steps, about 5 s)
+    threads = oracle.get_threads()
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        ref.step(1)
+        t1 = time.perf_counter() - t0
+        n1 = max(1, min(100, int(5.0 / max(t1, 1e-6))))
+        t0 = time.perf_counter()
+        ref.step(n1)
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(threads)
+    out["single_core"] = {"value": round(case.cells * n1 / dt1 / 1e6, 3), "unit": "MLUPS",
+                          "cores": 1, "sample": "%d coupled steps, %.1f s" % (n1, dt1)}
+    return out
 
 
 def main(argv=None):
