@@ -79,6 +79,8 @@ typedef struct {
   double rho_s;   /* particle density (mass per unit area) */
   int32_t eps_subcells; /* 0: exact solid ratio; n > 0: the n x n sub-cell estimate */
   double uw_bot, uw_top; /* x-velocity of the wall at y = -1/2 and of the wall at y = ny - 1/2 */
+  double kt;      /* tangential contact stiffness (0 with mu = 0: normal force only) */
+  double mu;      /* Coulomb friction coefficient of the tangential contact force */
 } ocfg;
 
 typedef struct {
@@ -94,6 +96,9 @@ typedef struct {
   double *x, *y, *r, *vx, *vy, *om;
   int32_t *mode;                /* 0 free (DEM), 1 fixed, 2 prescribed velocity */
   double *fcx, *fcy;            /* contact force at the last DEM evaluation */
+  double *tcz;                  /* contact torque at the last DEM evaluation */
+  double *ht;                   /* [np][np] tangential spring of pair (i, j), seen from i */
+  double *hwb, *hwt;            /* tangential spring against the bottom / top wall */
   double *Fx, *Fy, *Tz;         /* hydrodynamic force / torque of the last step */
   long step;
 } osim;
@@ -307,6 +312,7 @@ void o_destroy(osim *s);
 
 osim *o_create(const ocfg *c) {
   if (!c || c->nx < 2 || c->ny < 2 || !(c->tau0 > 0.5) || c->cs < 0.0 || c->n_sub < 1 ||
+      !(c->kt >= 0.0) || !(c->mu >= 0.0) ||
       c->eps_subcells < 0 || (!c->walls && (c->uw_bot != 0.0 || c->uw_top != 0.0)))
     return NULL;
   osim *s = (osim *)calloc(1, sizeof(osim));
@@ -334,7 +340,9 @@ osim *o_create(const ocfg *c) {
 static void free_particles(osim *s) {
   free(s->x); free(s->y); free(s->r); free(s->vx); free(s->vy); free(s->om); free(s->mode);
   free(s->fcx); free(s->fcy); free(s->Fx); free(s->Fy); free(s->Tz);
+  free(s->tcz); free(s->ht); free(s->hwb); free(s->hwt);
   s->x = s->y = s->r = s->vx = s->vy = s->om = s->fcx = s->fcy = s->Fx = s->Fy = s->Tz = NULL;
+  s->tcz = s->ht = s->hwb = s->hwt = NULL;
   s->mode = NULL;
   s->np = 0;
 }
@@ -425,15 +433,40 @@ static double nearest_image(double d, int n) {
   return d;
 }
 
-/* Normal spring-dashpot contact forces (Eqs. 7, 8) on every free disk, from all other disks
- * (ascending id) and then the two walls.  Force on i:  -(k_n delta + c_n v_n) n, with n the unit
- * vector from i towards its partner, delta the overlap, v_n = (V_i - V_partner) . n the approach
- * speed and c_n = 2 zeta sqrt(k_n m_eff). */
-static void contact_forces(osim *s) {
+/* Contact forces and torques (Eqs. 7, 8) on every free disk, from all other disks (ascending id)
+ * and then the two walls.  Normal: -(k_n delta + c_n v_n) n, with n the unit vector from i
+ * towards its partner, delta the overlap, v_n = (V_i - V_partner) . n the approach speed and
+ * c_n = 2 zeta sqrt(k_n m_eff).  Tangential (only when k_t or mu is set; linear spring-dashpot
+ * with a Coulomb limit): t = (-n_y, n_x); the contact point sits in the middle of the overlap,
+ * at l_i = r_i - delta/2 from each centre (so l_i + l_j = |X_i - X_j| and the pair's torques
+ * conserve angular momentum); the slip of i against its partner there is
+ * v_t = (V_i - V_j) . t + omega_i l_i + omega_j l_j; the spring s grows by v_t dt at each
+ * evaluation (`advance`); F_t = -k_t s - c_t v_t with c_t = 2 zeta sqrt(k_t m_eff), limited to
+ * |F_t| <= mu max(F_n, 0), where sliding resets s = -F_t / k_t; the force F_t t acts on i with
+ * torque l_i F_t.  A wall is a partner at rest in y moving along x at its wall velocity.  A
+ * contact that has ended leaves s = 0. */
+static double tangential(const osim *s, double *spring, double vt, double fn, double meff,
+                         int advance) {
+  double kt = s->c.kt, mu = s->c.mu;
+  double dt = 1.0 / s->c.n_sub;
+  double sp = advance ? *spring + vt * dt : *spring;
+  double ct = 2.0 * s->c.zeta * sqrt(kt * meff);
+  double ft = -kt * sp - ct * vt;
+  double cap = mu * (fn > 0.0 ? fn : 0.0);
+  if (fabs(ft) > cap) {
+    ft = ft > 0.0 ? cap : -cap;
+    sp = kt > 0.0 ? -ft / kt : 0.0;
+  }
+  *spring = sp;
+  return ft;
+}
+
+static void contact_forces(osim *s, int advance) {
   int np = s->np;
   double kn = s->c.kn, zeta = s->c.zeta;
+  int tang = s->c.kt > 0.0 || s->c.mu > 0.0;
   for (int i = 0; i < np; ++i) {
-    double fx = 0.0, fy = 0.0;
+    double fx = 0.0, fy = 0.0, tz = 0.0;
     if (s->mode[i] == 0) {
       double mi = disk_mass(s, i);
       for (int j = 0; j < np; ++j) {
@@ -453,24 +486,57 @@ static void contact_forces(osim *s) {
           double fn = kn * delta + cn * vn;
           fx += -fn * nxu;
           fy += -fn * nyu;
+          if (tang) {
+            double tx = -nyu, ty = nxu;
+            double li = s->r[i] - 0.5 * delta, lj = s->r[j] - 0.5 * delta;
+            double vt = (s->vx[i] - s->vx[j]) * tx + (s->vy[i] - s->vy[j]) * ty +
+                        s->om[i] * li + s->om[j] * lj;
+            double ft = tangential(s, &s->ht[(size_t)i * np + j], vt, fn, meff, advance);
+            fx += ft * tx;
+            fy += ft * ty;
+            tz += li * ft;
+          }
+        } else if (tang) {
+          s->ht[(size_t)i * np + j] = 0.0;
         }
       }
       if (s->c.walls) {
         double cn = 2.0 * zeta * sqrt(kn * mi);
-        double db = s->r[i] - (s->y[i] + 0.5); /* wall at y = -1/2, n = (0,-1) */
+        double db = s->r[i] - (s->y[i] + 0.5); /* wall at y = -1/2, n = (0,-1), t = (1,0) */
         if (db > 0.0) {
           double vn = -s->vy[i];
-          fy += kn * db + cn * vn;
+          double fn = kn * db + cn * vn;
+          fy += fn;
+          if (tang) {
+            double l = s->r[i] - 0.5 * db;
+            double vt = (s->vx[i] - s->c.uw_bot) + s->om[i] * l;
+            double ft = tangential(s, &s->hwb[i], vt, fn, mi, advance);
+            fx += ft;
+            tz += l * ft;
+          }
+        } else if (tang) {
+          s->hwb[i] = 0.0;
         }
         double dt = s->r[i] - ((s->c.ny - 0.5) - s->y[i]); /* wall at y = ny-1/2, n = (0,1) */
         if (dt > 0.0) {
           double vn = s->vy[i];
-          fy += -(kn * dt + cn * vn);
+          double fn = kn * dt + cn * vn;
+          fy += -fn;
+          if (tang) { /* t = (-1, 0) */
+            double l = s->r[i] - 0.5 * dt;
+            double vt = -(s->vx[i] - s->c.uw_top) + s->om[i] * l;
+            double ft = tangential(s, &s->hwt[i], vt, fn, mi, advance);
+            fx += -ft;
+            tz += l * ft;
+          }
+        } else if (tang) {
+          s->hwt[i] = 0.0;
         }
       }
     }
     s->fcx[i] = fx;
     s->fcy[i] = fy;
+    s->tcz[i] = tz;
   }
 }
 
@@ -497,9 +563,9 @@ static void dem_phase(osim *s) {
         s->x[i] = wrap_coord(s->x[i] + dt * s->vx[i], s->c.nx);
         s->y[i] = s->y[i] + dt * s->vy[i];
         if (!s->c.walls) s->y[i] = wrap_coord(s->y[i], s->c.ny);
-        s->om[i] = s->om[i] + h * (s->Tz[i] / I);
+        s->om[i] = s->om[i] + h * ((s->Tz[i] + s->tcz[i]) / I);
       }
-      contact_forces(s);
+      contact_forces(s, 1);
       for (int i = 0; i < np; ++i) {
         if (s->mode[i] != 0) continue;
         double m = disk_mass(s, i);
@@ -508,7 +574,7 @@ static void dem_phase(osim *s) {
         double ay = (s->fcy[i] + s->Fy[i]) / m;
         s->vx[i] = s->vx[i] + h * ax;
         s->vy[i] = s->vy[i] + h * ay;
-        s->om[i] = s->om[i] + h * (s->Tz[i] / I);
+        s->om[i] = s->om[i] + h * ((s->Tz[i] + s->tcz[i]) / I);
       }
     }
   }
@@ -543,15 +609,19 @@ int o_set_particles(osim *s, int n, const double *x, const double *y, const doub
   s->Fx = (double *)xcalloc(nn, sizeof(double));
   s->Fy = (double *)xcalloc(nn, sizeof(double));
   s->Tz = (double *)xcalloc(nn, sizeof(double));
+  s->tcz = (double *)xcalloc(nn, sizeof(double));
+  s->ht = (double *)xcalloc(nn * nn + 1, sizeof(double));
+  s->hwb = (double *)xcalloc(nn + 1, sizeof(double));
+  s->hwt = (double *)xcalloc(nn + 1, sizeof(double));
   if (!s->x || !s->y || !s->r || !s->vx || !s->vy || !s->om || !s->mode || !s->fcx || !s->fcy ||
-      !s->Fx || !s->Fy || !s->Tz)
+      !s->Fx || !s->Fy || !s->Tz || !s->tcz || !s->ht || !s->hwb || !s->hwt)
     return O_ENOMEM;
   s->np = n;
   for (int p = 0; p < n; ++p) {
     s->x[p] = x[p]; s->y[p] = y[p]; s->r[p] = r[p];
     s->vx[p] = vx[p]; s->vy[p] = vy[p]; s->om[p] = om[p]; s->mode[p] = mode[p];
   }
-  contact_forces(s);
+  contact_forces(s, 0);  /* the force of the initial overlaps; no spring has stretched yet */
   return O_OK;
 }
 
@@ -698,6 +768,27 @@ int o_step_accumulate(osim *s, int nsteps, const double *wfx, const double *wfy,
     }
   }
   *J = acc;
+  return O_OK;
+}
+
+/* Contact force and torque of every disk at the last DEM evaluation (tests). */
+int o_get_contacts(const osim *s, double *fcx, double *fcy, double *tcz) {
+  for (int p = 0; p < s->np; ++p) {
+    fcx[p] = s->fcx[p];
+    fcy[p] = s->fcy[p];
+    tcz[p] = s->tcz[p];
+  }
+  return O_OK;
+}
+
+/* Sets the stored hydrodynamic force and torque that DEM-alone steps hold fixed (for tests of
+ * the contact law without fluid). */
+int o_set_loads(osim *s, const double *fx, const double *fy, const double *tz) {
+  for (int p = 0; p < s->np; ++p) {
+    s->Fx[p] = fx[p];
+    s->Fy[p] = fy[p];
+    s->Tz[p] = tz[p];
+  }
   return O_OK;
 }
 

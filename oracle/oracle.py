@@ -36,7 +36,8 @@ class _Cfg(C.Structure):
                 ("n_sub", C.c_int32), ("tau0", C.c_double), ("cs", C.c_double),
                 ("gx", C.c_double), ("gy", C.c_double), ("rho0", C.c_double),
                 ("kn", C.c_double), ("zeta", C.c_double), ("rho_s", C.c_double),
-                ("eps_subcells", C.c_int32), ("uw_bot", C.c_double), ("uw_top", C.c_double)]
+                ("eps_subcells", C.c_int32), ("uw_bot", C.c_double), ("uw_top", C.c_double),
+                ("kt", C.c_double), ("mu", C.c_double)]
 
 
 _lib = None
@@ -61,6 +62,8 @@ def _load():
         lib.o_step.argtypes = [C.c_void_p, C.c_int]
         lib.o_step_accumulate.argtypes = [C.c_void_p, C.c_int, _D, _D, _D, _D]
         lib.o_dem_steps.argtypes = [C.c_void_p, C.c_int]
+        lib.o_set_loads.argtypes = [C.c_void_p, _D, _D, _D]
+        lib.o_get_contacts.argtypes = [C.c_void_p, _D, _D, _D]
         lib.o_get_forces.argtypes = [C.c_void_p, _D, _D, _D]
         lib.o_get_particles.argtypes = [C.c_void_p, _D, _D, _D, _D, _D]
         lib.o_solid_field.argtypes = [C.c_void_p, _D]
@@ -150,6 +153,8 @@ class OracleConfig:
     eps_subcells: int = 0       # 0: exact solid ratio; n > 0: the paper's n x n sub-cell estimate
     uw_bot: float = 0.0         # x-velocity of the bottom wall (y = -1/2), walls only
     uw_top: float = 0.0         # x-velocity of the top wall (y = ny - 1/2), walls only
+    kt: float = 0.0             # tangential contact stiffness
+    mu: float = 0.0             # Coulomb friction coefficient
 
 
 class OracleSim:
@@ -160,7 +165,7 @@ class OracleSim:
         self.cfg = cfg
         c = _Cfg(cfg.nx, cfg.ny, 1 if cfg.walls else 0, cfg.n_sub, cfg.tau0, cfg.cs, cfg.gx,
                  cfg.gy, cfg.rho0, cfg.kn, cfg.zeta, cfg.rho_s, cfg.eps_subcells,
-                 cfg.uw_bot, cfg.uw_top)
+                 cfg.uw_bot, cfg.uw_top, cfg.kt, cfg.mu)
         self._h = lib.o_create(C.byref(c))
         if not self._h:
             raise ValueError("oracle: invalid configuration %r" % (cfg,))
@@ -224,6 +229,18 @@ class OracleSim:
         if rc:
             raise RuntimeError("oracle: step failed (code %d)" % rc)
         return Jc.value
+
+    def set_loads(self, fx, fy, tz):
+        """Hydrodynamic force and torque held fixed by dem_steps (tests of the contact law)."""
+        fx, fy, tz = _f64(fx), _f64(fy), _f64(tz)
+        _load().o_set_loads(self._h, _dp(fx), _dp(fy), _dp(tz))
+
+    def contacts(self):
+        """Contact force (x, y) and torque of every disk at the last DEM evaluation."""
+        n = max(self.np, 1)
+        a = [np.zeros(n) for _ in range(3)]
+        _load().o_get_contacts(self._h, *(_dp(v) for v in a))
+        return tuple(v[: self.np] for v in a)
 
     def dem_steps(self, n: int = 1):
         _load().o_dem_steps(self._h, int(n))

@@ -614,6 +614,82 @@ def test_dem_constant_hydrodynamic_load_integrates_exactly():
         assert abs((y1 - y0) - (vy0 + fy / (2 * m))) < 1e-13
 
 
+# ---- tangential contact force with a Coulomb limit (the full contact law of the paper's DEM)
+
+def _dem_pair(kt, mu, n_sub=10):
+    """Two free disks on an oblique collision course, away from walls and the periodic seam."""
+    s = OracleSim(OracleConfig(nx=200, ny=120, tau0=0.7, kn=1e3, zeta=0.1, n_sub=n_sub, kt=kt,
+                               mu=mu))
+    s.set_particles([60.0, 80.5], [60.0, 63.0], [8.0, 11.0], [0.02, -0.03], [0.004, -0.002],
+                    [0.001, -0.002], [W.MODE_FREE, W.MODE_FREE])
+    return s
+
+
+def test_frictionless_contact_is_the_normal_law_bit_for_bit():
+    """mu = 0 caps the tangential force at zero whatever k_t is: the trajectories equal those of
+    the normal-only law exactly."""
+    a, b = _dem_pair(0.0, 0.0), _dem_pair(800.0, 0.0)
+    a.dem_steps(400)
+    b.dem_steps(400)
+    for u, v in zip(a.particles(), b.particles()):
+        assert np.array_equal(u, v)
+
+
+def test_oblique_collision_conserves_momentum_and_angular_momentum():
+    """The pair's tangential forces are equal and opposite and act at the middle of the overlap
+    (lever arms r - delta/2 summing to the centre distance), so linear momentum and the angular
+    momentum sum m (x v_y - y v_x) + I omega are conserved through a frictional collision."""
+    s = _dem_pair(800.0, 0.3)
+    m = np.pi * np.array([64.0, 121.0])
+    I = 0.5 * m * np.array([64.0, 121.0])
+
+    def invariants():
+        x, y, vx, vy, om = s.particles()
+        return (np.sum(m * vx), np.sum(m * vy), np.sum(m * (x * vy - y * vx) + I * om))
+
+    p0 = invariants()
+    touched = False
+    for _ in range(400):
+        s.dem_steps(1)
+        touched |= np.abs(s.contacts()[2]).max() > 0.0
+    p1 = invariants()
+    assert touched
+    assert abs(p1[0] - p0[0]) <= 1e-12 * np.sum(m) * 0.03
+    assert abs(p1[1] - p0[1]) <= 1e-12 * np.sum(m) * 0.03
+    assert abs(p1[2] - p0[2]) <= 1e-10 * abs(p0[2])
+    x, y, vx, vy, om = s.particles()
+    assert np.abs(om - np.array([0.001, -0.002])).max() > 1e-4  # friction spun the disks
+
+
+def test_sliding_disk_obeys_coulomb_then_rolls():
+    """A disk pressed on the bottom wall by a constant load F and launched at v0 without spin:
+    while it slides the friction force is exactly mu times the normal force, and it ends up
+    rolling, v + omega l = 0, at v = v0 / (1 + I / (m l^2)), 2 v0 / 3 for a disk (the angular
+    momentum about the contact point, m v l + I omega, is kept while it slides)."""
+    r, F, v0, mu = 5.0, 1.0, 0.05, 0.2
+    s = OracleSim(OracleConfig(nx=400, ny=40, tau0=0.7, kn=1e3, zeta=0.1, n_sub=20, kt=1e3,
+                               mu=mu))
+    delta0 = F / 1e3
+    s.set_particles([50.0], [r - 0.5 - delta0], [r], [v0], [0.0], [0.0], [W.MODE_FREE])
+    s.set_loads([0.0], [-F], [0.0])
+    sliding = 0
+    for _ in range(6):
+        s.dem_steps(1)
+        fcx, fcy, tcz = (a[0] for a in s.contacts())
+        x, y, vx, vy, om = (a[0] for a in s.particles())
+        if vx + om * r > 1e-3:  # clearly slipping
+            assert abs(fcx) == pytest.approx(mu * fcy, rel=1e-14, abs=0.0) and fcx < 0.0
+            sliding += 1
+    assert sliding >= 4
+    s.dem_steps(400)
+    x, y, vx, vy, om = (a[0] for a in s.particles())
+    m = np.pi * r * r
+    I = 0.5 * m * r * r
+    l = r - 0.5 * delta0
+    assert vx == pytest.approx(v0 / (1.0 + I / (m * l * l)), rel=2e-3)
+    assert abs(vx + om * l) <= 1e-3 * v0
+
+
 def test_collision_overlapping_cover_saturates():
     """Two disks covering more than the whole cell: eps_tot = 1, so B_tot = 1 and the cell's
     momentum is set to the eps-weighted mix of the two solid velocities."""
