@@ -81,6 +81,19 @@ typedef struct imb_config {
   double wall_ux_top;      /* x-velocity of the wall at y = ny - 1/2: a link crossing a wall
                               that moves at u_w returns f*_i - 6 w_i rho0 (c_i . u_w), the
                               moving bounce-back (plane Couette flow between the two) */
+  double kt;               /* tangential contact stiffness (Sec. 2.1 names the tangential law;
+                              0 with mu = 0: normal force only, bit for bit).  With kt, mu > 0
+                              each contact (disk-disk, disk-wall) adds F_t along
+                              t = (-n_y, n_x): the slip at the middle of the overlap
+                              v_t = (V_i - V_j).t + w_i l_i + w_j l_j (l = r - overlap/2; a wall
+                              moves at its wall_ux) stretches a spring s by v_t dt per DEM
+                              sub-step, F_t = -kt s - c_t v_t with c_t = 2 zeta sqrt(kt m_eff),
+                              and the torque l F_t enters the spin.  A disk holds at most 6
+                              disk-disk springs at once: a seventh simultaneous contact latches
+                              a device error (IMB_EDEVICE).  The springs are part of a saved
+                              state.  imb_adjoint rejects kt or mu > 0.  Finite, >= 0. */
+  double mu;               /* Coulomb limit |F_t| <= mu max(F_n, 0); a sliding contact resets
+                              s = -F_t / kt.  Finite, >= 0. */
 } imb_config;
 
 typedef struct imb_sim imb_sim;

@@ -22,7 +22,8 @@
  *   Eq. (13), Eq. (14)   blended collision and its weight B(eps, tau).
  *   Eqs. (15), (16)      hydrodynamic force and torque; the printed sum is the momentum the fluid
  *                         gains, so the force on the particle is its negative.
- *   Eqs. (7), (8)        DEM overlap and normal spring-dashpot force (no tangential force).
+ *   Eqs. (7), (8)        DEM overlap and normal spring-dashpot force; with kt, mu a tangential
+ *                        spring-dashpot with a Coulomb limit (contact_forces, tangential).
  *   Eqs. (10), (11), (17) Newton's equations integrated by velocity Verlet with N_sub sub-cycles per
  *                         lattice step, the hydrodynamic force and torque held fixed (Sec. 2.3).
  *   Sec. 3.3.2           Smagorinsky sub-grid model (closed form of the Hou et al. model, see

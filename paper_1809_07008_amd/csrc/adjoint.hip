@@ -513,6 +513,10 @@ extern "C" int imb_adjoint(imb_sim* sim, int32_t nsteps, int32_t k, const double
              "useful derivative (eps_subcells must be 0)";
     return IMB_EINVAL;
   }
+  if (cfg.kt != 0.0 || cfg.mu != 0.0) {
+    *v.err = "adjoint: the tangential contact force is not differentiated (kt and mu must be 0)";
+    return IMB_EINVAL;
+  }
   if (cfg.storage != IMB_STORAGE_F32 && cfg.storage != IMB_STORAGE_F64) {
     *v.err = "adjoint: needs F32 or F64 storage";
     return IMB_EUNSUPPORTED;

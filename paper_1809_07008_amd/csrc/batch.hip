@@ -119,6 +119,12 @@ __device__ inline int find_slot(const int* pref, int n, int i) {
 
 // ch: the channel table (read-only during the launch; the channel and item indices are uniform
 // over a workgroup, so a channel's arguments are read with scalar loads).
+// The persistent kernel calls the particle phase out of line: in-line, its registers would add to
+// those of the lattice roles and spill.
+__device__ __attribute__((noinline)) void particle_phase_call(const ParticleArgs& a, double* lds) {
+  particle_phase<BLOCK>(a, lds);
+}
+
 __global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs B, const BatchChannel* __restrict__ ch) {
   __shared__ int s_item, s_abort;
   __shared__ int s_hch[2][MAX_BATCH];
@@ -165,7 +171,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs B, const BatchChannel
       if (i < npart) {  // the particle phase of step n (half B: of step n - 1)
         const int m = h == 1 ? n : n - 1;
         const int ci = __builtin_amdgcn_readfirstlane(s_hch[ph][i]);
-        particle_phase<BLOCK>(ch[ci].pa[(B.parity0 + m) & 1], pp_lds);
+        particle_phase_call(ch[ci].pa[(B.parity0 + m) & 1], pp_lds);
         continue;
       }
       const bool is_disk = i < npart + ndc;

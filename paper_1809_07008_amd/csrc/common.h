@@ -22,6 +22,7 @@ constexpr int MAX_BANDS = 6144;    // tile rows (bands) of one lattice
 constexpr int NBMAX = 32;          // DEM neighbour-list capacity per disk
 constexpr int MAX_PARTICLES = 512;
 constexpr int PBLOCK = 512;        // threads of the particle-phase workgroup (one per disk)
+constexpr int HK = 6;         // tangential springs per disk (disks touching it at once)
 constexpr double DEM_SKIN = 5.0;   // neighbour-list skin (lattice units)
 constexpr double MAX_MOVE = 1.0;   // largest displacement of a disk in one lattice step
 constexpr float F16_SCALE = 16384.0f;  // power-of-two scale of FP16 deviations
@@ -36,6 +37,7 @@ enum : int {
   ERR_MOVE = 32,       // a disk moved more than MAX_MOVE in one step
   ERR_LEFT = 64,       // a disk centre left the channel between the walls
   ERR_BAND = 128,      // band list capacity exceeded
+  ERR_CONTACTS = 256,  // a disk touches more than HK other disks at once (tangential springs)
 };
 
 // D2Q9 velocity set (the paper's Table 1 gives the 3D D3Q19 set; its 2D analogue here).
@@ -125,6 +127,10 @@ struct ParticleState {
   double *x, *y, *r, *vx, *vy, *om;
   int* mode;
   double *fcx, *fcy;      // contact force of the last DEM evaluation
+  double* tcz;            // contact torque of the last DEM evaluation
+  int* hid;               // [np][HK] partners with a tangential spring, id + 1 (0: free entry)
+  double* hsp;            // [np][HK] their springs (tangential displacement, from this disk)
+  double* hw;             // [np][2] springs against the bottom and the top wall
   double *Fx, *Fy, *Tz;   // hydrodynamic force / torque of the last step
   double *xref, *yref;    // positions at the last neighbour-list build
   int* nbr;               // [np][NBMAX] neighbour ids, ascending
@@ -135,6 +141,8 @@ struct ParticleState {
 struct ParticleArgs {
   int np, nx, ny, walls, n_sub;
   double kn, zeta, rho_s;
+  double kt, mu;          // tangential stiffness and friction (both 0: normal force only)
+  double uw_bot, uw_top;  // wall velocities along x (the walls' tangential slip)
   int tiles_x, tiles_y, tw, th;
   ParticleState s;
   ParticleTable tab;

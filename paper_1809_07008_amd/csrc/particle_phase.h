@@ -17,14 +17,35 @@
 // own, without synchronisation; the others ("active") run them together, synchronised per
 // sub-step.
 // Readings: damping ratio zeta with c_n = 2 zeta sqrt(k_n m_eff); m = rho_s pi r^2, I = m r^2/2;
-// no tangential force and no gravity.
+// no gravity; a tangential force only when k_t or mu is set (a widening beyond the paper's normal
+// contact law).
 #pragma once
 
 #include "step.h"
 
 namespace imb {
 
-constexpr int PP_DOUBLES = 6;  // LDS doubles per disk: x, y, vx, vy, r and the step's reach
+constexpr int PP_DOUBLES = 7;  // LDS doubles per disk: x, y, vx, vy, r, the step's reach, spin
+
+// Tangential contact force (2D Cundall-Strack, with a Coulomb limit): the spring s of the contact
+// grows by the slip v_t over one sub-step when `advance`; F_t = -k_t s - c_t v_t with
+// c_t = 2 zeta sqrt(k_t m_eff), limited to mu max(F_n, 0), a sliding contact resetting the spring
+// to -F_t / k_t.  Returns F_t (along t = (-n_y, n_x) of the disk's own normal n).
+__device__ inline double tangential_force(const ParticleArgs& a, double* spring, double vt,
+                                          double fn, double meff, bool advance) {
+#pragma clang fp contract(off)
+  const double dt = 1.0 / a.n_sub;
+  double sp = advance ? *spring + vt * dt : *spring;
+  const double ct = 2.0 * a.zeta * sqrt(a.kt * meff);
+  double ft = -a.kt * sp - ct * vt;
+  const double cap = a.mu * (fn > 0.0 ? fn : 0.0);
+  if (fabs(ft) > cap) {
+    ft = ft > 0.0 ? cap : -cap;
+    sp = a.kt > 0.0 ? -ft / a.kt : 0.0;
+  }
+  *spring = sp;
+  return ft;
+}
 
 __device__ inline double nearest_image(double d, int n) {
   if (d > 0.5 * n) d -= n;
@@ -103,13 +124,13 @@ __device__ inline int block_exclusive_scan(int* cnt, int n, int* s_wave) {
 // disks' contact tests read are mirrored in LDS.
 // One disk per thread: NT >= np.  `lds` holds max(PP_DOUBLES np doubles, tiles_y + 1 ints).
 template <int NT>
-__device__ void particle_phase(const ParticleArgs& a, double* lds) {
+__device__ __attribute__((always_inline)) void particle_phase(const ParticleArgs& a, double* lds) {
 #pragma clang fp contract(off)
   constexpr int PWAVES = NT / 64;
   __shared__ double s_red[PWAVES];
   __shared__ int s_wave[PWAVES], s_or[PWAVES], s_flag[PWAVES];
   __shared__ int s_nact, s_aid[64], s_ann[64], s_awall[64], s_anb[64][8];
-  __shared__ double s_ast[64][6];
+  __shared__ double s_ast[64][7];
   constexpr int NB_REG = 8;   // neighbour ids kept in registers; the rest are read from the list
   const int np = a.np, p = threadIdx.x;
   const bool have = p < np;
@@ -122,6 +143,7 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
 
   // ---- one batch of loads
   double x = 0, y = 0, vx = 0, vy = 0, om = 0, r = 1, fcx = 0, fcy = 0, xref = 0, yref = 0;
+  double tc = 0;  // contact torque of the last evaluation
   int mode = 1, nn = 0;
   int nb[NB_REG];
 #pragma unroll
@@ -130,6 +152,7 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
     x = s.x[p]; y = s.y[p]; vx = s.vx[p]; vy = s.vy[p]; om = s.om[p]; r = s.r[p];
     mode = s.mode[p];
     fcx = s.fcx[p]; fcy = s.fcy[p]; xref = s.xref[p]; yref = s.yref[p];
+    tc = s.tcz[p];
     nn = s.nnbr[p];
 #pragma unroll
     for (int u = 0; u < NB_REG; ++u) nb[u] = s.nbr[p * NBMAX + u];
@@ -164,6 +187,8 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
   const double m_p = a.rho_s * M_PI * r * r;
   // the step's reach of each disk (the classification below), published with the mirror
   double* sB = sr + np;
+  double* som = sB + np;  // spins, for the partners' slip in tangential contacts
+  const bool tang = a.kt > 0.0 || a.mu > 0.0;
   double Bq = 0.0;
   if (own && a.do_dem) {
     const double qax = (0.0 + Fx) / m_p, qay = (0.0 + Fy) / m_p;
@@ -190,7 +215,8 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
   }
   if (have) {
     sx[p] = x; sy[p] = y; svx[p] = vx; svy[p] = vy; sr[p] = r;
-    const bool touching = own && (fcx != 0.0 || fcy != 0.0);
+    som[p] = om;
+    const bool touching = own && (fcx != 0.0 || fcy != 0.0 || tc != 0.0);
     sB[p] = touching ? (Bq > MAX_MOVE ? Bq : MAX_MOVE) : Bq;
   }
   __syncthreads();
@@ -206,11 +232,21 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
   // cnb may be any ascending sub-list of the neighbours that holds every disk able to touch i,
   // and near_wall may be false when no wall can: the terms left out are zero, so the sum is
   // the same bit for bit.
+  // Tangential springs (when k_t or mu is set): a disk's table (hid, hsp: HK entries, partner
+  // id + 1 and its spring) and its two wall springs; an entry exists only while the contact
+  // does, and is freed when it ends.  `advance`: the springs grow by this evaluation's slip.
   auto contact_of = [&](int i, double ri, double mi, double cnw, int cnn, const int* cnb,
-                        bool near_wall, double px, double py, double pvx, double pvy, double& ox,
-                        double& oy) {
+                        bool near_wall, double px, double py, double pvx, double pvy, double pom,
+                        int* hid, double* hsp, double* hw, bool advance, double& ox, double& oy,
+                        double& otz) {
     const double r = ri;
-    double fx = 0.0, fy = 0.0;
+    double fx = 0.0, fy = 0.0, tz = 0.0;
+    auto find = [&](int key) {
+      int k = -1;
+      for (int e = 0; e < HK; ++e)
+        if (hid[e] == key) k = e;
+      return k;
+    };
     for (int q = 0; q < cnn; ++q) {
       int j = 0;
       if (q < NB_REG) {
@@ -227,40 +263,92 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
       const double d2 = dx * dx + dy * dy;
       const double rs = r + sr[j];
       // pairs clearly apart skip the square root (the margin keeps rounding cases exact)
-      if (d2 > rs * rs * (1.0 + 1e-12)) continue;
-      const double dist = sqrt(d2);
-      const double delta = rs - dist;
-      if (delta > 0.0 && dist > 0.0) {
-        const double idist = 1.0 / dist;
-        const double nxu = dx * idist, nyu = dy * idist;
-        const double vn = (pvx - svx[j]) * nxu + (pvy - svy[j]) * nyu;
-        const double mj = a.rho_s * M_PI * sr[j] * sr[j];
-        const double meff = mi * mj / (mi + mj);
-        const double cn = 2.0 * zeta * sqrt(kn * meff);
-        const double fn = kn * delta + cn * vn;
-        fx += -fn * nxu;
-        fy += -fn * nyu;
+      bool touch = false;
+      if (d2 <= rs * rs * (1.0 + 1e-12)) {
+        const double dist = sqrt(d2);
+        const double delta = rs - dist;
+        if (delta > 0.0 && dist > 0.0) {
+          touch = true;
+          const double idist = 1.0 / dist;
+          const double nxu = dx * idist, nyu = dy * idist;
+          const double vn = (pvx - svx[j]) * nxu + (pvy - svy[j]) * nyu;
+          const double mj = a.rho_s * M_PI * sr[j] * sr[j];
+          const double meff = mi * mj / (mi + mj);
+          const double cn = 2.0 * zeta * sqrt(kn * meff);
+          const double fn = kn * delta + cn * vn;
+          fx += -fn * nxu;
+          fy += -fn * nyu;
+          if (tang) {
+            const double tx = -nyu, ty = nxu;
+            const double li = r - 0.5 * delta, lj = sr[j] - 0.5 * delta;
+            const double vt = (pvx - svx[j]) * tx + (pvy - svy[j]) * ty + pom * li + som[j] * lj;
+            int k = find(j + 1);
+            double sp = k >= 0 ? hsp[k] : 0.0;
+            const double ft = tangential_force(a, &sp, vt, fn, meff, advance);
+            fx += ft * tx;
+            fy += ft * ty;
+            tz += li * ft;
+            if (k < 0) k = find(0);
+            if (k >= 0) {
+              hid[k] = j + 1;
+              hsp[k] = sp;
+            } else {
+              atomicOr(a.err, ERR_CONTACTS);
+            }
+          }
+        }
+      }
+      if (tang && !touch) {
+        const int k = find(j + 1);
+        if (k >= 0) {
+          hid[k] = 0;
+          hsp[k] = 0.0;
+        }
       }
     }
     if (a.walls && near_wall) {
       const double cn = cnw;
-      const double db = r - (py + 0.5);
+      const double db = r - (py + 0.5);  // wall at y = -1/2: n = (0, -1), t = (1, 0)
       if (db > 0.0) {
         const double vn = -pvy;
-        fy += kn * db + cn * vn;
+        const double fn = kn * db + cn * vn;
+        fy += fn;
+        if (tang) {
+          const double l = r - 0.5 * db;
+          const double vt = (pvx - a.uw_bot) + pom * l;
+          const double ft = tangential_force(a, &hw[0], vt, fn, mi, advance);
+          fx += ft;
+          tz += l * ft;
+        }
+      } else if (tang) {
+        hw[0] = 0.0;
       }
-      const double dt = r - ((a.ny - 0.5) - py);
+      const double dt = r - ((a.ny - 0.5) - py);  // wall at y = ny - 1/2: n = (0, 1), t = (-1, 0)
       if (dt > 0.0) {
         const double vn = pvy;
-        fy += -(kn * dt + cn * vn);
+        const double fn = kn * dt + cn * vn;
+        fy += -fn;
+        if (tang) {
+          const double l = r - 0.5 * dt;
+          const double vt = -(pvx - a.uw_top) + pom * l;
+          const double ft = tangential_force(a, &hw[1], vt, fn, mi, advance);
+          fx += -ft;
+          tz += l * ft;
+        }
+      } else if (tang) {
+        hw[1] = 0.0;
       }
     }
     ox = fx;
     oy = fy;
+    otz = tz;
   };
   const double cnw_p = 2.0 * zeta * sqrt(kn * m_p);
-  auto contact = [&](double px, double py, double pvx, double pvy, double& ox, double& oy) {
-    contact_of(p, r, m_p, cnw_p, nn, nb, true, px, py, pvx, pvy, ox, oy);
+  // the springs stay in global memory, each disk's read and written by its own thread only
+  auto contact = [&](double px, double py, double pvx, double pvy, double pom, bool advance,
+                     double& ox, double& oy, double& otz) {
+    contact_of(p, r, m_p, cnw_p, nn, nb, true, px, py, pvx, pvy, pom, s.hid + p * HK,
+               s.hsp + p * HK, s.hw + p * 2, advance, ox, oy, otz);
   };
 
   bool rebuilt = false;
@@ -313,10 +401,12 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
   }
   if ((flags & 1) && (a.do_dem || a.init_contacts)) {  // table-only calls never move a disk
     if (a.init_contacts) {
-      if (own) contact(x, y, vx, vy, fcx, fcy);
+      // the force of the present overlaps; no spring stretches here
+      if (own) contact(x, y, vx, vy, om, false, fcx, fcy, tc);
       else {
         fcx = 0.0;
         fcy = 0.0;
+        tc = 0.0;
       }
     } else {
       // ---- classify.  During the sub-steps a disk stays within B of its start: a quiet disk
@@ -350,7 +440,7 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
         const double g = r + sr[j] + reach;
         return dx * dx + dy * dy <= g * g;
       };
-      bool active = own && (fcx != 0.0 || fcy != 0.0);
+      bool active = own && (fcx != 0.0 || fcy != 0.0 || tc != 0.0);
       bool any_active = false;
       for (;;) {
         bool turned = false;
@@ -402,6 +492,7 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
         }
         fcx = 0.0;
         fcy = 0.0;
+        tc = 0.0;
       }
       if (any_active) {
         // active disks: up to 64 are packed into the first wavefront and run their sub-steps
@@ -416,6 +507,7 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
             s_aid[idx] = p;
             s_ast[idx][0] = Fx; s_ast[idx][1] = Fy; s_ast[idx][2] = Tz;
             s_ast[idx][3] = fcx; s_ast[idx][4] = fcy; s_ast[idx][5] = om;
+            s_ast[idx][6] = tc;
             s_awall[idx] = nearw ? 1 : 0;
             if (cfar) {  // search the whole list
               s_ann[idx] = nn;
@@ -448,6 +540,7 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
             double px = sx[i], py = sy[i], pvx = svx[i], pvy = svy[i];
             const double aFx = s_ast[ts][0], aFy = s_ast[ts][1], aTz = s_ast[ts][2];
             double afx = s_ast[ts][3], afy = s_ast[ts][4], aom = s_ast[ts][5];
+            double atc = s_ast[ts][6];
             const int ann = s_ann[ts];
             const bool awall = s_awall[ts] != 0;
             int anb[NB_REG];
@@ -462,29 +555,34 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
               px = wrap_coord(px + dt * pvx, a.nx);
               py = py + dt * pvy;
               if (!a.walls) py = wrap_coord(py, a.ny);
-              aom = aom + hal;
+              aom = aom + (tang ? h * ((aTz + atc) / Ii) : hal);
               if (act) {
                 sx[i] = px; sy[i] = py; svx[i] = pvx; svy[i] = pvy;
+                som[i] = aom;
               }
               __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
               __builtin_amdgcn_wave_barrier();
-              if (act) contact_of(i, ri, mi_, cnw_i, ann, anb, awall, px, py, pvx, pvy, afx, afy);
+              if (act)
+                contact_of(i, ri, mi_, cnw_i, ann, anb, awall, px, py, pvx, pvy, aom,
+                           s.hid + i * HK, s.hsp + i * HK, s.hw + i * 2, true, afx, afy, atc);
               __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
               __builtin_amdgcn_wave_barrier();
               const double bx = (afx + aFx) * im;
               const double by = (afy + aFy) * im;
               pvx = pvx + h * bx;
               pvy = pvy + h * by;
-              aom = aom + hal;
+              aom = aom + (tang ? h * ((aTz + atc) / Ii) : hal);
             }
             if (act) {
               svx[i] = pvx; svy[i] = pvy;
               s_ast[t][3] = afx; s_ast[t][4] = afy; s_ast[t][5] = aom;
+              s_ast[t][6] = atc;
             }
           }
           __syncthreads();
           if (own && active) {
             fcx = s_ast[idx][3]; fcy = s_ast[idx][4]; om = s_ast[idx][5];
+            tc = s_ast[idx][6];
             x = sx[p]; y = sy[p]; vx = svx[p]; vy = svy[p];
           }
         } else if (nact > 64) {
@@ -500,18 +598,19 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
               x = wrap_coord(x + dt * vx, a.nx);
               y = y + dt * vy;
               if (!a.walls) y = wrap_coord(y, a.ny);
-              om = om + hal;
+              om = om + (tang ? h * ((Tz + tc) / I) : hal);
               sx[p] = x; sy[p] = y; svx[p] = vx; svy[p] = vy;
+              som[p] = om;
             }
             __syncthreads();
-            if (own && active) contact(x, y, vx, vy, fcx, fcy);
+            if (own && active) contact(x, y, vx, vy, om, true, fcx, fcy, tc);
             __syncthreads();
             if (own && active) {
               const double ax = (fcx + Fx) * im;
               const double ay = (fcy + Fy) * im;
               vx = vx + h * ax;
               vy = vy + h * ay;
-              om = om + hal;
+              om = om + (tang ? h * ((Tz + tc) / I) : hal);
             }
           }
         }
@@ -586,6 +685,7 @@ __device__ void particle_phase(const ParticleArgs& a, double* lds) {
     if (a.do_dem || a.init_contacts) {
       s.fcx[p] = fcx;
       s.fcy[p] = fcy;
+      s.tcz[p] = tc;
     }
     if (rebuilt) {
       s.nnbr[p] = nn;

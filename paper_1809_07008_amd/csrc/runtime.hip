@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "runtime.h"
@@ -63,6 +64,9 @@ size_t layout(const imb_config& c, char* base, DeviceLayout* L) {
   s.vx = cv.take<double>(mp); s.vy = cv.take<double>(mp); s.om = cv.take<double>(mp);
   s.mode = cv.take<int>(mp);
   s.fcx = cv.take<double>(mp); s.fcy = cv.take<double>(mp);
+  s.tcz = cv.take<double>(mp);
+  s.hid = cv.take<int>(mp * HK); s.hsp = cv.take<double>(mp * HK);
+  s.hw = cv.take<double>(mp * 2);
   s.Fx = cv.take<double>(mp); s.Fy = cv.take<double>(mp); s.Tz = cv.take<double>(mp);
   s.xref = cv.take<double>(mp); s.yref = cv.take<double>(mp);
   s.nbr = cv.take<int>(mp * NBMAX);
@@ -102,6 +106,8 @@ int validate_config(const imb_config* c, std::string* why) {
     return bad("wall velocities must be finite and at most 0.3 in magnitude");
   if (!(c->flags & IMB_FLAG_WALLS) && (c->wall_ux_bottom != 0.0 || c->wall_ux_top != 0.0))
     return bad("moving walls need walls");
+  if (!(c->kt >= 0.0 && c->kt < 1e300) || !(c->mu >= 0.0 && c->mu < 1e300))
+    return bad("kt and mu must be finite and >= 0");
   if (c->n_sub < 1 || c->n_sub > 100000) return bad("n_sub must be in 1..100000");
   if (!(c->rho0 > 0.0)) return bad("rho0 must be positive");
   if (!(c->kn >= 0.0) || !(c->damping_ratio >= 0.0) || !(c->rho_solid > 0.0))
@@ -145,6 +151,7 @@ std::string describe_device_error(int bits) {
   if (bits & ERR_NBR) s += "DEM neighbour list overflow; ";
   if (bits & ERR_MOVE) s += "a disk moved more than one cell in one step; ";
   if (bits & ERR_LEFT) s += "a disk centre left the channel; ";
+  if (bits & ERR_CONTACTS) s += "a disk touches more than 6 others at once; ";
   return s;
 }
 
@@ -217,6 +224,8 @@ ParticleArgs particle_args(imb_sim* s, int out_slot) {
   a.walls = (s->cfg.flags & IMB_FLAG_WALLS) ? 1 : 0;
   a.n_sub = s->cfg.n_sub; a.kn = s->cfg.kn; a.zeta = s->cfg.damping_ratio;
   a.rho_s = s->cfg.rho_solid;
+  a.kt = s->cfg.kt; a.mu = s->cfg.mu;
+  a.uw_bot = s->cfg.wall_ux_bottom; a.uw_top = s->cfg.wall_ux_top;
   a.tiles_x = s->g.tiles_x; a.tiles_y = s->g.tiles_y; a.tw = s->g.tw; a.th = s->g.th;
   a.s = s->d.ps; a.tab = s->d.tab[out_slot]; a.err = s->d.err;
   a.band_off = s->d.band_off[out_slot]; a.band_ids = s->d.band_ids[out_slot];
@@ -447,6 +456,7 @@ void imb_config_default(imb_config* c) {
   c->kn = 1.0e3; c->damping_ratio = 0.1; c->rho_solid = 1.0; c->max_particles = 64;
   c->flags = IMB_FLAG_WALLS; c->tile_w = 64; c->tile_rows = 1;
   c->eps_subcells = 0; c->reserved = 0; c->wall_ux_bottom = 0.0; c->wall_ux_top = 0.0;
+  c->kt = 0.0; c->mu = 0.0;
 }
 
 int imb_required_bytes(const imb_config* cfg, size_t* bytes) {
@@ -722,10 +732,15 @@ struct StateHeader {
 };
 }  // namespace
 
+// per disk in a checkpoint: 11 FP64 values and the mode, the contact torque, the two wall
+// springs, and the HK tangential springs with their partners
+constexpr size_t PARTICLE_STATE_BYTES =
+    11 * sizeof(double) + sizeof(int) + (3 + HK) * sizeof(double) + HK * sizeof(int);
+
 static size_t state_bytes(imb_sim* s) {
   const size_t pop = NQ * (size_t)s->g.plane * storage_bytes(s->cfg.storage);
   const size_t npb = (size_t)s->np;
-  return sizeof(StateHeader) + pop + npb * (11 * sizeof(double) + sizeof(int));
+  return sizeof(StateHeader) + pop + npb * PARTICLE_STATE_BYTES;
 }
 
 int imb_state_bytes(imb_sim* s, size_t* bytes) {
@@ -763,8 +778,18 @@ int imb_save_state(imb_sim* s, void* host_buf, size_t bytes) {
     e = hipMemcpyAsync(out, arrs[k], s->np * sizeof(double), hipMemcpyDeviceToHost, s->stream);
     out += s->np * sizeof(double);
   }
-  if (e == hipSuccess && s->np)
+  if (e == hipSuccess && s->np) {
     e = hipMemcpyAsync(out, ps.mode, s->np * sizeof(int), hipMemcpyDeviceToHost, s->stream);
+    out += s->np * sizeof(int);
+  }
+  // the contact torque and the tangential springs
+  const std::pair<const void*, size_t> extra[4] = {
+      {ps.tcz, s->np * sizeof(double)}, {ps.hw, 2 * s->np * sizeof(double)},
+      {ps.hsp, HK * s->np * sizeof(double)}, {ps.hid, HK * s->np * sizeof(int)}};
+  for (int k = 0; k < 4 && e == hipSuccess && s->np; ++k) {
+    e = hipMemcpyAsync(out, extra[k].first, extra[k].second, hipMemcpyDeviceToHost, s->stream);
+    out += extra[k].second;
+  }
   if (e != hipSuccess) return hip_fail(&s->err, e, "save_state copy");
   return sync_and_check(s);
 }
@@ -783,7 +808,7 @@ int imb_load_state(imb_sim* s, const void* host_buf, size_t bytes) {
     return IMB_EINVAL;
   }
   const size_t pop = NQ * (size_t)s->g.plane * storage_bytes(s->cfg.storage);
-  const size_t need = sizeof h + pop + (size_t)h.np * (11 * sizeof(double) + sizeof(int));
+  const size_t need = sizeof h + pop + (size_t)h.np * PARTICLE_STATE_BYTES;
   if (bytes < need || h.pop_bytes != pop) {
     s->err = "checkpoint truncated";
     return IMB_EINVAL;
@@ -807,6 +832,14 @@ int imb_load_state(imb_sim* s, const void* host_buf, size_t bytes) {
   }
   if (e == hipSuccess && s->np) {
     e = hipMemcpyAsync(ps.mode, in, s->np * sizeof(int), hipMemcpyHostToDevice, s->stream);
+    in += s->np * sizeof(int);
+    const std::pair<void*, size_t> extra[4] = {
+        {ps.tcz, s->np * sizeof(double)}, {ps.hw, 2 * s->np * sizeof(double)},
+        {ps.hsp, HK * s->np * sizeof(double)}, {ps.hid, HK * s->np * sizeof(int)}};
+    for (int k = 0; k < 4 && e == hipSuccess; ++k) {
+      e = hipMemcpyAsync(extra[k].first, in, extra[k].second, hipMemcpyHostToDevice, s->stream);
+      in += extra[k].second;
+    }
     if (e == hipSuccess)
       e = hipMemcpyAsync(ps.xref, ps.x, s->np * sizeof(double), hipMemcpyDeviceToDevice,
                          s->stream);

@@ -63,6 +63,8 @@ class Case:
     eps_subcells: int = 0       # solid ratio: 0 exact area, n > 0 the n x n sub-cell estimate
     uw_bot: float = 0.0         # x-velocity of the bottom wall (walls only)
     uw_top: float = 0.0         # x-velocity of the top wall (walls only)
+    kt: float = 0.0             # tangential contact stiffness (with mu: the tangential force)
+    mu: float = 0.0             # Coulomb friction coefficient of the tangential contact force
     particles: Particles = field(default_factory=Particles.empty)
 
     @property
@@ -154,6 +156,21 @@ def touching_disks(rows: int = 6, walls: bool = True, steps: int = 4, seed: int 
     p = _particles(xs, ys, r, rng.normal(0.0, 0.02, n), rng.normal(0.0, 0.02, n))
     return Case("touching_disks_%d" % n, 60, 48 if walls else 42, tau0=0.7, steps=steps,
                 walls=walls, gx=1.0e-5, kn=20.0, particles=p)
+
+
+def frictional_disks(rows: int = 6, walls: bool = True, steps: int = 4, kt: float = 10.0,
+                     mu: float = 0.3, seed: int = 0) -> Case:
+    """The packing of :func:`touching_disks` with the tangential contact force (k_t, mu) and
+    spins N(0, 0.005).  With walls the packing sits 1.6 cells lower, so its bottom row presses
+    on the bottom wall, and the walls move along x at +0.01 (bottom) and -0.01 (top)."""
+    base = touching_disks(rows, walls, steps, seed)
+    p = base.particles.copy()
+    rng = np.random.default_rng(31 + rows + 100 * seed)
+    p.om[:] = rng.normal(0.0, 0.005, p.n)
+    if walls:
+        p.y[:] -= 1.6
+    return base.with_(name="frictional_disks_%d" % p.n, particles=p, kt=kt, mu=mu,
+                      uw_bot=0.01 if walls else 0.0, uw_top=-0.01 if walls else 0.0)
 
 
 def approaching_disks(steps: int = 300) -> Case:

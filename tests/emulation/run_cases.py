@@ -37,7 +37,7 @@ def oracle_of(case):
                                gx=case.gx, gy=case.gy, rho0=case.rho0, n_sub=case.n_sub,
                                kn=case.kn, zeta=case.zeta, rho_s=case.rho_s,
                                eps_subcells=case.eps_subcells, uw_bot=case.uw_bot,
-                               uw_top=case.uw_top))
+                               uw_top=case.uw_top, kt=case.kt, mu=case.mu))
     p = case.particles
     r.set_particles(p.x, p.y, p.r, p.vx, p.vy, p.om, p.mode)
     return r
@@ -69,7 +69,9 @@ def fp64_parity():
                  W.touching_disks(6, True, steps=2), W.touching_disks(8, False, steps=2),
                  W.approaching_disks(steps=12), moving_case().with_(eps_subcells=4),
                  overlap_case(True).with_(eps_subcells=5), W.couette_channel("f64", steps=6),
-                 moving_case().with_(uw_bot=0.02, uw_top=-0.01)):
+                 moving_case().with_(uw_bot=0.02, uw_top=-0.01),
+                 W.frictional_disks(6, True, steps=3), W.frictional_disks(8, False, steps=3),
+                 W.frictional_disks(6, True, steps=3, mu=0.05)):
         s = sim_of(case, "f64")
         s.step(case.steps)
         ref = oracle_of(case)
@@ -85,8 +87,8 @@ def fp64_parity():
             if not case.walls:
                 d[1] -= case.ny * np.round(d[1] / case.ny)
             kerr = np.abs(d).max()
-        check("fp64 parity %s walls=%s eps_subcells=%d" % (case.name, case.walls,
-                                                            case.eps_subcells),
+        check("fp64 parity %s walls=%s eps_subcells=%d mu=%g" % (case.name, case.walls,
+                                                                  case.eps_subcells, case.mu),
               ferr < 1e-12 and perr < 1e-13 and kerr < 1e-12,
               "force %.2e populations %.2e disks %.2e" % (ferr, perr, kerr))
 

@@ -39,7 +39,7 @@ int main(void) {
   printf("size %zu\n", sizeof(imb_config));
   O(nx) O(ny) O(storage) O(n_sub) O(tau0) O(smag_cs) O(gx) O(gy) O(rho0) O(kn)
   O(damping_ratio) O(rho_solid) O(max_particles) O(flags) O(tile_w) O(tile_rows)
-  O(eps_subcells) O(reserved) O(wall_ux_bottom) O(wall_ux_top)
+  O(eps_subcells) O(reserved) O(wall_ux_bottom) O(wall_ux_top) O(kt) O(mu)
   return 0;
 }
 ''')

@@ -147,6 +147,8 @@ def test_adjoint_rejects_unsupported():
         gpu_adjoint(case, k=0)
     with pytest.raises(imb.ImbError):  # the sub-cell solid ratio has no useful derivative
         gpu_adjoint(case.with_(eps_subcells=5), k=2)
+    with pytest.raises(imb.ImbError):  # the tangential contact force is not differentiated
+        gpu_adjoint(case.with_(kt=10.0, mu=0.3), k=2)
 
 
 def test_adjoint_no_disks_body_force_only():

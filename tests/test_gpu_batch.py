@@ -186,6 +186,18 @@ def test_touching_disks_in_a_batch_match_single(schedule):
         assert_same(b, k, s)
 
 
+def test_frictional_disks_in_a_batch_match_single():
+    cases = [W.frictional_disks(6, True, steps=0).with_(storage="f32"),
+             W.frictional_disks(8, False, steps=0).with_(storage="f32")]
+    b = imb.batch_from_cases(cases, tile_w=32, tile_rows=2)
+    b.step(12)
+    b.sync()
+    for k, c in enumerate(cases):
+        s = single(c, (32, 2))
+        s.step(12)
+        assert_same(b, k, s)
+
+
 def test_moving_walls_in_a_batch_match_single():
     cases = [W.couette_channel("f32", steps=0), W.couette_channel("f32", disk=False, steps=0)]
     b = imb.batch_from_cases(cases, tile_w=32, tile_rows=2)

@@ -19,7 +19,7 @@ def oracle_for(case, f0=None):
                                  cs=case.cs, gx=case.gx, gy=case.gy, rho0=case.rho0,
                                  n_sub=case.n_sub, kn=case.kn, zeta=case.zeta, rho_s=case.rho_s,
                                  eps_subcells=case.eps_subcells, uw_bot=case.uw_bot,
-                                 uw_top=case.uw_top))
+                                 uw_top=case.uw_top, kt=case.kt, mu=case.mu))
     if f0 is not None:
         ref.set_populations(f0)
     p = case.particles
@@ -282,6 +282,41 @@ def test_touching_disks_dem_fp64_parity(rows, walls):
     sim.step(case.steps)
     ref.step(case.steps)
     assert_parity(sim, ref)
+
+
+@pytest.mark.parametrize("rows,walls,mu", [(6, True, 0.3), (8, False, 0.3), (6, True, 0.05)])
+def test_frictional_disks_dem_fp64_parity(rows, walls, mu):
+    """The touching packing with the tangential contact force: springs kept per contact across
+    sub-steps and steps, sticking and (mu = 0.05: mostly) sliding contacts, the bottom row on a
+    moving wall (walls), one wavefront of active disks (60) and more (80).  FP64 parity with the
+    oracle after 20 steps; the spins must differ from the frictionless run's, so the tangential
+    force is really exercised."""
+    case = W.frictional_disks(rows, walls, steps=20, mu=mu).with_(storage="f64")
+    sim, ref = gpu_for(case, tile_w=32, tile_rows=2), oracle_for(case)
+    sim.step(case.steps)
+    ref.step(case.steps)
+    assert_parity(sim, ref)
+    plain = oracle_for(case.with_(kt=0.0, mu=0.0))
+    plain.step(case.steps)
+    om, om0 = np.array(ref.particles()[4]), np.array(plain.particles()[4])
+    assert np.abs(om - om0).max() > 1e-4
+    assert np.abs(np.array(ref.contacts()[2])).max() > 0.0
+
+
+def test_frictional_state_roundtrip_continues_identically():
+    """A checkpoint holds the contact springs: a run resumed from it continues bit for bit."""
+    case = W.frictional_disks(6, True, steps=0).with_(storage="f32")
+    sim = gpu_for(case, tile_w=32, tile_rows=2)
+    sim.step(5)
+    blob = sim.save_state()
+    sim.step(7)
+    sim2 = gpu_for(case, tile_w=32, tile_rows=2)
+    sim2.load_state(blob)
+    assert sim2.save_state() == blob
+    sim2.step(7)
+    assert np.array_equal(sim.populations(), sim2.populations())
+    for a, b in zip(sim.forces() + sim.particles(), sim2.forces() + sim2.particles()):
+        assert np.array_equal(a, b)
 
 
 def test_approaching_disks_dem_fp64_parity():
