@@ -74,7 +74,8 @@ def test_required_bytes_scales_with_storage():
                                 dict(max_particles=5000), dict(tile_w=48), dict(tile_rows=3),
                                 dict(rho0=0.0), dict(rho_s=0.0), dict(eps_subcells=-1),
                                 dict(eps_subcells=65), dict(uw_top=0.4), dict(uw_bot=-0.31),
-                                dict(walls=False, uw_top=0.01)])
+                                dict(walls=False, uw_top=0.01), dict(kt=-1.0),
+                                dict(mu=float("nan")), dict(kt=float("inf"), mu=0.3)])
 def test_invalid_configs_rejected(kw):
     rc, _ = required(**kw)
     assert rc == -1
