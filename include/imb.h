@@ -90,7 +90,7 @@ typedef struct imb_config {
                               sub-step, F_t = -kt s - c_t v_t with c_t = 2 zeta sqrt(kt m_eff),
                               and the torque l F_t enters the spin.  A disk holds at most 6
                               disk-disk springs at once: a seventh simultaneous contact latches
-                              a device error (IMB_EDEVICE).  The springs are part of a saved
+                              IMB_EOVERFLOW at the next sync.  The springs are part of a saved
                               state.  imb_adjoint rejects kt or mu > 0.  Finite, >= 0. */
   double mu;               /* Coulomb limit |F_t| <= mu max(F_n, 0); a sliding contact resets
                               s = -F_t / kt.  Finite, >= 0. */

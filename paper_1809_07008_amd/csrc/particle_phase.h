@@ -289,6 +289,22 @@ __device__ __attribute__((always_inline)) void particle_phase(const ParticleArgs
             fy += ft * ty;
             tz += li * ft;
             if (k < 0) k = find(0);
+            if (k < 0) {
+              // a full table can still hold a contact that has ended and whose partner comes
+              // later in the list: free those entries now (the same spring, 0, they get below)
+              for (int e = 0; e < HK; ++e) {
+                const int o = hid[e] - 1;
+                double ex = nearest_image(sx[o] - px, a.nx);
+                double ey = sy[o] - py;
+                if (!a.walls) ey = nearest_image(ey, a.ny);
+                const double ed = sqrt(ex * ex + ey * ey);
+                if (!(r + sr[o] - ed > 0.0 && ed > 0.0)) {
+                  hid[e] = 0;
+                  hsp[e] = 0.0;
+                  if (k < 0) k = e;
+                }
+              }
+            }
             if (k >= 0) {
               hid[k] = j + 1;
               hsp[k] = sp;

@@ -173,6 +173,19 @@ def frictional_disks(rows: int = 6, walls: bool = True, steps: int = 4, kt: floa
                       uw_bot=0.01 if walls else 0.0, uw_top=-0.01 if walls else 0.0)
 
 
+def crowded_disk(n_small: int = 7, kt: float = 10.0, mu: float = 0.3) -> Case:
+    """64x48 channel with walls: a free disk of radius 6 at (32, 24) and n_small free disks of
+    radius 2 around it, centres 7.95 away at equal angles, each overlapping it by 0.05 (and
+    apart from one another); with seven or more the large disk has more simultaneous contacts
+    than its tangential spring table holds."""
+    a = 2.0 * np.pi * np.arange(n_small) / n_small
+    x = [32.0] + list(32.0 + 7.95 * np.cos(a))
+    y = [24.0] + list(24.0 + 7.95 * np.sin(a))
+    p = _particles(x, y, [6.0] + [2.0] * n_small)
+    return Case("crowded_disk_%d" % n_small, 64, 48, tau0=0.7, steps=2, gx=1.0e-5, kn=20.0,
+                kt=kt, mu=mu, particles=p)
+
+
 def approaching_disks(steps: int = 300) -> Case:
     """128x48 channel with walls, free disks of radius 5 on the line y = 24: a touching pair, then
     disks at gaps 0.9 and 0.95 (each within one cell of the previous) drifting towards it, a

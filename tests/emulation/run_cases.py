@@ -93,6 +93,28 @@ def fp64_parity():
               "force %.2e populations %.2e disks %.2e" % (ferr, perr, kerr))
 
 
+def spring_table_limit():
+    """Six simultaneous tangential contacts fit a disk's spring table; a seventh latches the
+    device error."""
+    case = W.crowded_disk(6)
+    s = sim_of(case, "f64")
+    s.step(case.steps)
+    ref = oracle_of(case)
+    ref.step(case.steps)
+    kerr = np.abs(np.array(s.particles()) - np.array(ref.particles())).max()
+    check("six tangential contacts on one disk", kerr < 1e-12, "disks %.2e" % kerr)
+    seven = W.crowded_disk(7)
+    try:
+        s = sim_of(seven, "f64")
+        s.step(1)
+        s.sync()
+        msg = None
+    except imb.ImbError as e:
+        msg = "%d %s" % (e.code, e)
+    check("a seventh latches the device error", msg is not None and "more than 6" in msg,
+          str(msg))
+
+
 def wide_tiles():
     """Tiles 128 and 256 wide on ragged widths (odd, not a multiple of the tile), walls and
     periodic y, random initial populations: FP64 parity, and FP16 equal bit for bit to 32x2.
@@ -190,6 +212,6 @@ def batch():
 
 
 if __name__ == "__main__":
-    for fn in (fp64_parity, wide_tiles, reduced_precision, roundtrip, adjoint, batch):
+    for fn in (spring_table_limit, fp64_parity, wide_tiles, reduced_precision, roundtrip, adjoint, batch):
         fn()
     print("all emulated cases passed", flush=True)

@@ -204,6 +204,28 @@ def test_error_paths():
     assert e.value.code == -5
 
 
+def test_tangential_spring_table_limit():
+    """Six simultaneous tangential contacts per disk fit its spring table (parity with the
+    oracle); a seventh is reported as a device error, and without friction there is no limit."""
+    six = W.crowded_disk(6).with_(storage="f64")
+    sim, ref = gpu_for(six), oracle_for(six)
+    sim.step(six.steps)
+    ref.step(six.steps)
+    assert_parity(sim, ref)
+    seven = W.crowded_disk(7).with_(storage="f64")
+    sim = imb.simulation_from_case(seven.with_(particles=W.Particles.empty()), max_particles=8)
+    with pytest.raises(imb.ImbError) as e:
+        sim.set_case_particles(seven.particles)
+        sim.step(1)
+        sim.sync()
+    assert e.value.code == -4 and "more than 6" in str(e.value)
+    plain = seven.with_(kt=0.0, mu=0.0)
+    sim, ref = gpu_for(plain), oracle_for(plain)
+    sim.step(plain.steps)
+    ref.step(plain.steps)
+    assert_parity(sim, ref)
+
+
 @pytest.mark.parametrize("storage,tol", [("f32", 1e-4), ("f16", 1e-3)])
 def test_reduced_precision_drag_against_fp64_oracle(storage, tol):
     """FP32 / FP16-deviation populations (FP32 arithmetic, compensated force sums), 1000 steps of
