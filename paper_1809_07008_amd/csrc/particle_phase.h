@@ -131,6 +131,9 @@ __device__ __attribute__((always_inline)) void particle_phase(const ParticleArgs
   __shared__ int s_wave[PWAVES], s_or[PWAVES], s_flag[PWAVES];
   __shared__ int s_nact, s_aid[64], s_ann[64], s_awall[64], s_anb[64][8];
   __shared__ double s_ast[64][7];
+  // the tangential springs of the one-wavefront path's active disks (LDS copies of their tables)
+  __shared__ int s_hid[64][HK];
+  __shared__ double s_hsp[64][HK], s_hw[64][2];
   constexpr int NB_REG = 8;   // neighbour ids kept in registers; the rest are read from the list
   const int np = a.np, p = threadIdx.x;
   const bool have = p < np;
@@ -360,7 +363,8 @@ __device__ __attribute__((always_inline)) void particle_phase(const ParticleArgs
     otz = tz;
   };
   const double cnw_p = 2.0 * zeta * sqrt(kn * m_p);
-  // the springs stay in global memory, each disk's read and written by its own thread only
+  // the springs stay in global memory, each disk's read and written by its own thread only (the
+  // one-wavefront path works on LDS copies)
   auto contact = [&](double px, double py, double pvx, double pvy, double pom, bool advance,
                      double& ox, double& oy, double& otz) {
     contact_of(p, r, m_p, cnw_p, nn, nb, true, px, py, pvx, pvy, pom, s.hid + p * HK,
@@ -524,6 +528,14 @@ __device__ __attribute__((always_inline)) void particle_phase(const ParticleArgs
             s_ast[idx][0] = Fx; s_ast[idx][1] = Fy; s_ast[idx][2] = Tz;
             s_ast[idx][3] = fcx; s_ast[idx][4] = fcy; s_ast[idx][5] = om;
             s_ast[idx][6] = tc;
+            if (tang) {
+              for (int e = 0; e < HK; ++e) {
+                s_hid[idx][e] = s.hid[p * HK + e];
+                s_hsp[idx][e] = s.hsp[p * HK + e];
+              }
+              s_hw[idx][0] = s.hw[p * 2];
+              s_hw[idx][1] = s.hw[p * 2 + 1];
+            }
             s_awall[idx] = nearw ? 1 : 0;
             if (cfar) {  // search the whole list
               s_ann[idx] = nn;
@@ -579,8 +591,8 @@ __device__ __attribute__((always_inline)) void particle_phase(const ParticleArgs
               __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
               __builtin_amdgcn_wave_barrier();
               if (act)
-                contact_of(i, ri, mi_, cnw_i, ann, anb, awall, px, py, pvx, pvy, aom,
-                           s.hid + i * HK, s.hsp + i * HK, s.hw + i * 2, true, afx, afy, atc);
+                contact_of(i, ri, mi_, cnw_i, ann, anb, awall, px, py, pvx, pvy, aom, s_hid[t],
+                           s_hsp[t], s_hw[t], true, afx, afy, atc);
               __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
               __builtin_amdgcn_wave_barrier();
               const double bx = (afx + aFx) * im;
@@ -599,6 +611,14 @@ __device__ __attribute__((always_inline)) void particle_phase(const ParticleArgs
           if (own && active) {
             fcx = s_ast[idx][3]; fcy = s_ast[idx][4]; om = s_ast[idx][5];
             tc = s_ast[idx][6];
+            if (tang) {
+              for (int e = 0; e < HK; ++e) {
+                s.hid[p * HK + e] = s_hid[idx][e];
+                s.hsp[p * HK + e] = s_hsp[idx][e];
+              }
+              s.hw[p * 2] = s_hw[idx][0];
+              s.hw[p * 2 + 1] = s_hw[idx][1];
+            }
             x = sx[p]; y = sy[p]; vx = svx[p]; vy = svy[p];
           }
         } else if (nact > 64) {
