@@ -3,7 +3,8 @@
 //      workgroup of the lattice step;
 //   2. DEM (Sec. 2.1, 2.3): N_sub velocity-Verlet (kick-drift-kick) sub-cycles of dt = 1/N_sub
 //      (Eq. 17) with the hydrodynamic load held fixed; normal linear spring-dashpot contacts
-//      between disks and with the walls (Eqs. 7, 8); the contact force is evaluated after each
+//      between disks and with the walls (Eqs. 7, 8), with k_t and mu also a tangential
+//      spring-dashpot with a Coulomb limit; the contact force is evaluated after each
 //      drift from the new positions and half-step velocities and reused by the next kick;
 //      prescribed disks move by V once per step, fixed disks stay;
 //   3. the disk table (tile box, position, velocity) and the per-tile-row (band) candidate lists
@@ -17,8 +18,8 @@
 // own, without synchronisation; the others ("active") run them together, synchronised per
 // sub-step.
 // Readings: damping ratio zeta with c_n = 2 zeta sqrt(k_n m_eff); m = rho_s pi r^2, I = m r^2/2;
-// no gravity; a tangential force only when k_t or mu is set (a widening beyond the paper's normal
-// contact law).
+// no gravity; a tangential force (Sec. 2.1 names it without giving a discrete form) only when k_t
+// or mu is set.
 #pragma once
 
 #include "step.h"
