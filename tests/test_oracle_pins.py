@@ -6,6 +6,8 @@ counting, the paper's own cell-decomposition idea of Sec. 2.2 taken to 1000x1000
 conservation laws that follow from Eqs. (12)-(16), special cases (eps = 0, eps = 1) and symmetry.
 """
 import math
+import os
+from fractions import Fraction
 
 import numpy as np
 import pytest
@@ -282,10 +284,113 @@ def test_weight_limits_and_monotonicity():
         assert all(b1 < b2 for b1, b2 in zip(bs, bs[1:]))
 
 
+def _weight_golden():
+    path = os.path.join(os.path.dirname(__file__), "golden", "weight_eq14.txt")
+    rows = []
+    for line in open(path):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            e, t, num, den = line.split()
+            rows.append((float(e), float(t), Fraction(int(num), int(den))))
+    return rows
+
+
+def test_weight_interior_values_by_hand():
+    """Eq. (14) at interior points, against exact rationals worked out by hand
+    (tests/golden/weight_eq14.txt): a weight with a term dropped or misplaced (for example
+    tau in place of tau - 1/2) passes the limits and monotonicity but not these."""
+    rows = _weight_golden()
+    assert len(rows) >= 6
+    for eps, tau, b in rows:
+        got = oracle.weight(eps, tau)
+        assert abs(got - float(b)) <= 4 * np.finfo(float).eps * float(b), (eps, tau, got, b)
+
+
 # ------------------------------------------------------------------ one-cell collision
 def rand_cell(rng):
     return (1.0 / 9.0) * (1.0 + 0.2 * rng.uniform(-1, 1, 9)) * np.array(
         [4, 1, 1, 1, 1, 0.25, 0.25, 0.25, 0.25]) * 9 / 4.0 * 0.9
+
+
+def relax_to_equilibrium(f):
+    """f^eq(rho, u) of the oracle, obtained without retyping Eq. (2): with tau = 1, no solid, no
+    body force and no sub-grid model, Eq. (1) replaces f by its equilibrium."""
+    return oracle.collide_cell(f, tau0=1.0)[0]
+
+
+def second_moments(f):
+    f = np.asarray(f)
+    return (CX * CX * f).sum(), (CX * CY * f).sum(), (CY * CY * f).sum()
+
+
+def test_equilibrium_has_the_defining_moments():
+    """Eq. (2) is fixed by its moments: sum f^eq = rho, sum c f^eq = rho u and
+    sum c c f^eq = rho (I / 3 + u u) (c_s^2 = 1/3).  Checked at random (rho, u), with rho and
+    u taken from the input populations by plain sums; the second moment is what fails for a
+    wrong factor on the O(u^2) terms (e.g. 9 (c.u)^2 - 3 u.u keeps the zeroth and first
+    moments but doubles u u)."""
+    rng = np.random.default_rng(31)
+    for _ in range(200):
+        f = rand_cell(rng)
+        # push the mean velocity to Mach ~0.1-0.3 in a random direction so u u matters
+        ang = rng.uniform(0, 2 * math.pi)
+        amp = rng.uniform(0.01, 0.03)
+        f = f + amp * (CX * math.cos(ang) + CY * math.sin(ang)) * f
+        rho, mx, my = moments(f)
+        ux, uy = mx / rho, my / rho
+        feq = relax_to_equilibrium(f)
+        r2, mx2, my2 = moments(feq)
+        tol = 16 * np.finfo(float).eps
+        assert abs(r2 - rho) <= tol * rho
+        assert abs(mx2 - rho * ux) <= tol * rho and abs(my2 - rho * uy) <= tol * rho
+        pxx, pxy, pyy = second_moments(feq)
+        assert abs(pxx - rho * (1 / 3 + ux * ux)) <= tol * rho
+        assert abs(pxy - rho * ux * uy) <= tol * rho
+        assert abs(pyy - rho * (1 / 3 + uy * uy)) <= tol * rho
+        assert max(abs(ux), abs(uy)) > 1e-3
+
+
+def test_solid_equilibrium_has_the_moments_of_the_solid_velocity():
+    """Eq. (12) with eps = 1 (B = 1, Eq. 14): an equilibrium cell leaves with f^eq(rho, u_s),
+    u_s = V + omega x d the solid velocity at the node; its moments are rho, rho u_s and
+    rho (I/3 + u_s u_s), which pins the O(u^2) terms of the solid-side equilibrium too."""
+    rng = np.random.default_rng(32)
+    for _ in range(50):
+        f = relax_to_equilibrium(rand_cell(rng))
+        rho, _, _ = moments(f)
+        V = rng.normal(0, 0.03, 2)
+        om = rng.normal(0, 0.01)
+        d = rng.uniform(-3, 3, 2)
+        fo = oracle.collide_cell(f, [1.0], [d[0]], [d[1]], [V[0]], [V[1]], [om], tau0=0.7)[0]
+        usx, usy = V[0] - om * d[1], V[1] + om * d[0]
+        r2, mx2, my2 = moments(fo)
+        tol = 32 * np.finfo(float).eps
+        assert abs(r2 - rho) <= tol * rho
+        assert abs(mx2 - rho * usx) <= tol and abs(my2 - rho * usy) <= tol
+        pxx, pxy, pyy = second_moments(fo)
+        assert abs(pxx - rho * (1 / 3 + usx * usx)) <= tol
+        assert abs(pxy - rho * usx * usy) <= tol
+        assert abs(pyy - rho * (1 / 3 + usy * usy)) <= tol
+
+
+def test_partially_covered_equilibrium_cell_keeps_one_minus_b_of_its_momentum():
+    """Eqs. (12)-(15) at interior solid ratios: an equilibrium cell (Omega^f = 0) covered by a
+    resting disk leaves with (1 - B) f^eq(rho, u) + B f^eq(rho, 0), so it keeps (1 - B) of its
+    momentum and hands B m to the disk, with B the hand-worked value of Eq. (14)."""
+    rng = np.random.default_rng(33)
+    for eps, tau, b in _weight_golden():
+        B = float(b)
+        f = relax_to_equilibrium(rand_cell(rng))
+        rho, mx, my = moments(f)
+        fo, dF, dT, tau_eff, Bt = oracle.collide_cell(f, [eps], [0.4], [-0.2], [0.0], [0.0],
+                                                      [0.0], tau0=tau)
+        assert tau_eff == tau
+        assert abs(Bt - B) <= 4 * np.finfo(float).eps
+        _, mx2, my2 = moments(fo)
+        assert abs(mx2 - (1 - B) * mx) < 1e-16 + 1e-14 * abs(mx)
+        assert abs(my2 - (1 - B) * my) < 1e-16 + 1e-14 * abs(my)
+        assert abs(dF[0, 0] - B * mx) < 1e-16 + 1e-14 * abs(mx)
+        assert abs(dF[0, 1] - B * my) < 1e-16 + 1e-14 * abs(my)
 
 
 @pytest.mark.parametrize("np_", [0, 1, 2])
@@ -369,19 +474,14 @@ def test_smagorinsky_relaxation_identities():
         cs = rng.uniform(0.05, 0.4)
         tau = oracle.collide_cell(f, tau0=0.55, cs=cs)[3]
         rho, mx, my = moments(f)
-        ux, uy = mx / rho, my / rho
-        cu = CX * ux + CY * uy
-        feq = w * rho * (1 + 3 * cu + 4.5 * cu ** 2 - 1.5 * (ux * ux + uy * uy))
-        neq = f - feq
+        neq = f - relax_to_equilibrium(f)
         pxx, pxy, pyy = (CX * CX * neq).sum(), (CX * CY * neq).sum(), (CY * CY * neq).sum()
         pn = math.sqrt(pxx ** 2 + 2 * pxy ** 2 + pyy ** 2)
         S = 3 * math.sqrt(2) * pn / (2 * rho * tau)
         assert abs((tau - 0.55) - 3 * cs * cs * S) < 1e-13
         assert tau > 0.55
     # equilibrium input: no strain, no eddy viscosity
-    rho, ux, uy = 1.01, 0.03, -0.02
-    cu = CX * ux + CY * uy
-    feq = w * rho * (1 + 3 * cu + 4.5 * cu ** 2 - 1.5 * (ux * ux + uy * uy))
+    feq = relax_to_equilibrium(1.01 * w * (1 + 0.1 * (CX - 0.5 * CY)))
     assert abs(oracle.collide_cell(feq, tau0=0.55, cs=0.3)[3] - 0.55) < 1e-7
 
 
