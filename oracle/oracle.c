@@ -772,6 +772,26 @@ int o_step_accumulate(osim *s, int nsteps, const double *wfx, const double *wfy,
   return O_OK;
 }
 
+/* Conditioning scales of each disk's force and torque of the last step (tests): sF, the sum over
+ * its covered cells of the magnitudes |dF| of the per-cell force contributions (Eq. 15), and sT,
+ * the sum of |d| |dF| (the largest moment each contribution can exert, Eq. 16).  A sum evaluated
+ * in another order, from contributions each correct to a few units in the last place of their
+ * magnitude, differs from this oracle's by a small multiple of the unit roundoff times these. */
+int o_force_scales(const osim *s, double *sF, double *sT) {
+  for (int p = 0; p < s->np; ++p) sF[p] = sT[p] = 0.0;
+  size_t nc = (size_t)s->c.nx * s->c.ny;
+  for (size_t k = 0; k < nc; ++k) {
+    for (int q = 0; q < s->nslot[k]; ++q) {
+      size_t j = k * MAX_SLOTS + q;
+      int p = s->spid[j];
+      double f = sqrt(s->sfx[j] * s->sfx[j] + s->sfy[j] * s->sfy[j]);
+      sF[p] += f;
+      sT[p] += sqrt(s->sdx[j] * s->sdx[j] + s->sdy[j] * s->sdy[j]) * f;
+    }
+  }
+  return O_OK;
+}
+
 /* Contact force and torque of every disk at the last DEM evaluation (tests). */
 int o_get_contacts(const osim *s, double *fcx, double *fcy, double *tcz) {
   for (int p = 0; p < s->np; ++p) {

@@ -65,6 +65,7 @@ def _load():
         lib.o_set_loads.argtypes = [C.c_void_p, _D, _D, _D]
         lib.o_get_contacts.argtypes = [C.c_void_p, _D, _D, _D]
         lib.o_get_forces.argtypes = [C.c_void_p, _D, _D, _D]
+        lib.o_force_scales.argtypes = [C.c_void_p, _D, _D]
         lib.o_get_particles.argtypes = [C.c_void_p, _D, _D, _D, _D, _D]
         lib.o_solid_field.argtypes = [C.c_void_p, _D]
         lib.o_solid_fraction.restype = C.c_double
@@ -250,6 +251,15 @@ class OracleSim:
         fx, fy, tz = np.zeros(n), np.zeros(n), np.zeros(n)
         _load().o_get_forces(self._h, _dp(fx), _dp(fy), _dp(tz))
         return fx[: self.np], fy[: self.np], tz[: self.np]
+
+    def force_scales(self):
+        """Per disk, the conditioning scales of its force and torque sums in the last step:
+        (sum over covered cells of |dF|, sum of |d| |dF|), dF the per-cell force contribution
+        and d its lever arm."""
+        n = max(self.np, 1)
+        a = [np.zeros(n) for _ in range(2)]
+        _load().o_force_scales(self._h, *(_dp(v) for v in a))
+        return tuple(v[: self.np] for v in a)
 
     def particles(self):
         n = max(self.np, 1)

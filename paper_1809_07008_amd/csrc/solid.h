@@ -54,14 +54,29 @@ __host__ __device__ inline T segment_excess(T x) {
 // power r^2 - x^2 - y^2, computed with error-free products, so crossings near a corner keep
 // full relative precision.
 
+// Power r^2 - (dx + sx/2)^2 - (dy + sy/2)^2 of the cell corner (sx, sy = -1 or +1) of the unit
+// cell centred at (dx, dy): expanded as r^2 - dx^2 - dy^2 - sx dx - sy dy - 1/2, every term exact
+// (error-free squares) and summed with error-free additions, so the corner is exactly
+// (dx + sx/2, dy + sy/2) even where that coordinate has no representation in T, and the power
+// has full relative precision near the circle.
 template <class T>
-__host__ __device__ inline T exact_power(T r, T x, T y) {  // r^2 - x^2 - y^2
+__host__ __device__ inline void sum_exact(T& s, T& c, T v) {  // s + c += v (TwoSum)
+  const T t = s + v, bp = t - s;
+  c += (s - (t - bp)) + (v - bp);
+  s = t;
+}
+template <class T>
+__host__ __device__ inline T corner_power(T r, T dx, T dy, T sx, T sy) {
   const T hr = r * r, lr = fma(r, r, -hr);
-  const T hx = x * x, lx = fma(x, x, -hx);
-  const T hy = y * y, ly = fma(y, y, -hy);
-  const T s1 = hr - hx, b1 = s1 - hr, e1 = (hr - (s1 - b1)) + (-hx - b1);
-  const T s2 = s1 - hy, b2 = s2 - s1, e2 = (s1 - (s2 - b2)) + (-hy - b2);
-  return s2 + (((e1 + e2) + lr) - lx - ly);
+  const T hx = dx * dx, lx = fma(dx, dx, -hx);
+  const T hy = dy * dy, ly = fma(dy, dy, -hy);
+  T s = hr, c = T(0);
+  sum_exact(s, c, -hx);
+  sum_exact(s, c, -hy);
+  sum_exact(s, c, -(sx * dx));
+  sum_exact(s, c, -(sy * dy));
+  sum_exact(s, c, T(-0.5));
+  return s + (((c + lr) - lx) - ly);
 }
 
 // Offset, from edge end e0, of the crossing at coordinate cc (cc = +-h) on an edge running from
@@ -117,10 +132,12 @@ struct AreaWalk {
 };
 
 template <class T>
-__host__ __device__ __noinline__ T cut_cell_fraction(T r, T x0, T x1, T y0, T y1) {
-  // corner powers, counter-clockwise from (x0, y0)
-  const T p00 = exact_power(r, x0, y0), p10 = exact_power(r, x1, y0);
-  const T p11 = exact_power(r, x1, y1), p01 = exact_power(r, x0, y1);
+__host__ __device__ __noinline__ T cut_cell_fraction(T r, T dx, T dy) {
+  // edges (rounded; they only locate the crossings, whose offsets come from the exact corner
+  // powers) and corner powers, counter-clockwise from (x0, y0)
+  const T x0 = dx - T(0.5), x1 = dx + T(0.5), y0 = dy - T(0.5), y1 = dy + T(0.5);
+  const T p00 = corner_power(r, dx, dy, T(-1), T(-1)), p10 = corner_power(r, dx, dy, T(1), T(-1));
+  const T p11 = corner_power(r, dx, dy, T(1), T(1)), p01 = corner_power(r, dx, dy, T(-1), T(1));
   AreaWalk<T> w;
   w.r = r; w.prev_kind = -1; w.first_kind = -1; w.twice_area = T(0); w.seg = T(0);
   w.u0 = w.v0 = w.pu = w.pv = T(0);
@@ -188,7 +205,7 @@ __host__ __device__ inline T solid_fraction(T r, T dx, T dy) {
   const T fx = fabs(x0) > fabs(x1) ? fabs(x0) : fabs(x1);
   const T fy = fabs(y0) > fabs(y1) ? fabs(y0) : fabs(y1);
   if (fx * fx + fy * fy <= r * r) return T(1);
-  return cut_cell_fraction(r, x0, x1, y0, y1);
+  return cut_cell_fraction(r, dx, dy);
 }
 
 // Fraction of the n x n sub-cell centres of the cell centred at (dx, dy) strictly inside the
@@ -210,7 +227,7 @@ __host__ __device__ __noinline__ T subcell_count(T r, T dx, T dy, int n) {
 template <class T>
 __host__ __device__ __noinline__ T cut_ratio(T r, T dx, T dy, int n) {
   if (n > 0) return subcell_count(r, dx, dy, n);
-  return cut_cell_fraction(r, dx - T(0.5), dx + T(0.5), dy - T(0.5), dy + T(0.5));
+  return cut_cell_fraction(r, dx, dy);
 }
 
 // The solid ratio the configuration selects: the exact area (n = 0) or the paper's estimate
