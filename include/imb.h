@@ -161,6 +161,13 @@ int imb_step(imb_sim* sim, int32_t nsteps);
  * Per-kernel timing (imb_set_kernel_timing) always launches directly.  Synchronises. */
 int imb_set_graphs(imb_sim* sim, int enable);
 
+/* Captures (if not yet captured) and uploads every step graph imb_step can replay: 2 and 32
+ * steps, from either population buffer, so that a later imb_step only replays graphs (no
+ * capture or instantiation inside a timed region).  A graph's first replay may still carry a
+ * one-time cost; timing code replays each once beforehand.  No effect with graphs disabled.
+ * Synchronises. */
+int imb_prepare_graphs(imb_sim* sim);
+
 /* Force (fx, fy) and torque tz on each disk from the last completed step, FP64, host arrays of
  * length n (particle count).  Zero before the first step.  Synchronises. */
 int imb_get_forces(imb_sim* sim, double* fx, double* fy, double* tz);
@@ -215,7 +222,21 @@ int imb_adjoint(imb_sim* sim, int32_t nsteps, int32_t k_ckpt, const double* wfx,
                 const double* wfy, const double* wtz, double* gx0, double* gy0, double* gvx,
                 double* gvy, double* gom, double* gg, double* J, double* gf0);
 
-/* GPU time of the last imb_adjoint call (HIP events): the forward pass and the reverse sweep
+/* The same run split in two, for reverse-mode automatic differentiation: imb_adjoint_forward
+ * validates as imb_adjoint, runs the forward pass keeping its checkpoints and per-step disk
+ * tables, advances the simulation by nsteps and returns J (host, may be NULL); it arms one
+ * reverse sweep.  imb_adjoint_backward runs that sweep (recomputation from the checkpoints and
+ * the adjoint steps) and returns the gradients as imb_adjoint does.  IMB_EINVAL if no forward
+ * pass is armed: imb_set_particles, imb_load_state and a completed backward call disarm it.
+ * Between the two calls the simulation may be read or stepped (the sweep uses its own copies of
+ * the states and tables), but its disks must not be replaced.  imb_adjoint is forward then
+ * backward.  Both synchronise. */
+int imb_adjoint_forward(imb_sim* sim, int32_t nsteps, int32_t k_ckpt, const double* wfx,
+                        const double* wfy, const double* wtz, double* J);
+int imb_adjoint_backward(imb_sim* sim, double* gx0, double* gy0, double* gvx, double* gvy,
+                         double* gom, double* gg, double* gf0);
+
+/* GPU time of the last forward pass and reverse sweep (HIP events): the forward pass and the reverse sweep
  * (recomputation + adjoint steps + finalisation), in milliseconds.  With kernel timing on
  * (imb_set_kernel_timing), also the summed time and count of the adjoint-step and recompute
  * launches since the last call of this function (which resets them).  Any pointer may be NULL. */

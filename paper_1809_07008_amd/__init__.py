@@ -6,4 +6,4 @@ The compute path is a C-ABI library of hand-written HIP kernels (``libimb.so``, 
 package does not load the library; the binding does, and fails loudly if it is missing.
 """
 
-__all__ = ["imb", "workloads", "adjoint", "autotune"]
+__all__ = ["imb", "workloads", "adjoint"]

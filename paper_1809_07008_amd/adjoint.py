@@ -4,10 +4,11 @@
     J = sum over the unrolled steps n and disks p of wfx_p Fx_p^n + wfy_p Fy_p^n + wtz_p Tz_p^n
 (hydrodynamic force and torque on the disks, Eqs. 15-16) of a channel whose disks move with
 prescribed constant velocity (X^n = X^0 + n V, spin omega), and differentiates it with respect to
-the disk positions, velocities, spins and the body force g.  The forward call runs the forward
-pass with checkpoints and the reverse sweep in one library call; backward only scales the stored
-gradients by the incoming gradient.  All arithmetic runs in the HIP kernels; the tensors here are
-FP64 host tensors that carry the inputs and results across the C-ABI.
+the disk positions, velocities, spins and the body force g.  forward runs the forward pass with
+its checkpoints (imb_adjoint_forward) and keeps the simulation; backward runs the recomputation
+and the adjoint sweep (imb_adjoint_backward), releases the simulation and scales the gradients by
+the incoming gradient.  All arithmetic runs in the HIP kernels; the tensors here are FP64 host
+tensors that carry the inputs and results across the C-ABI.
 """
 from __future__ import annotations
 
@@ -60,21 +61,35 @@ class DragObjective(torch.autograd.Function):
             sim.set_particles(_np(x), _np(y), np.asarray(setup.radii, float), _np(vx), _np(vy),
                               _np(om), mode)
             wfx = np.ones(n) if setup.wfx is None else setup.wfx
-            res = sim.adjoint(setup.steps, setup.k_ckpt, wfx=wfx, wfy=setup.wfy, wtz=setup.wtz)
-            setup.last = sim.adjoint_timing()
-        finally:
+            J = sim.adjoint_forward(setup.steps, setup.k_ckpt, wfx=wfx, wfy=setup.wfy,
+                                    wtz=setup.wtz)
+        except BaseException:
             sim.close()
-        dev = x.device
-        grads = [torch.as_tensor(res[k], dtype=x.dtype, device=dev)
-                 for k in ("x0", "y0", "vx", "vy", "om")]
-        grads.append(torch.as_tensor(res["g"], dtype=g.dtype, device=g.device).reshape(g.shape))
-        ctx.save_for_backward(*grads)
-        return torch.tensor(res["J"], dtype=torch.float64, device=dev)
+            raise
+        ctx.sim = sim  # holds the checkpoints until backward
+        ctx.setup = setup
+        ctx.meta = (x.dtype, x.device, g.dtype, g.device, g.shape)
+        return torch.tensor(J, dtype=torch.float64, device=x.device)
 
     @staticmethod
     def backward(ctx, gJ):
-        gs = ctx.saved_tensors
-        return tuple(gJ.to(t.dtype) * t for t in gs) + (None,)
+        # the reverse sweep runs once; a second backward through the same graph
+        # (retain_graph) reuses its gradients
+        res = getattr(ctx, "grads", None)
+        if res is None:
+            sim = ctx.sim
+            try:
+                res = sim.adjoint_backward()
+                ctx.setup.last = sim.adjoint_timing()
+            finally:
+                sim.close()
+                ctx.sim = None
+            ctx.grads = res
+        xd, xdev, gd, gdev, gshape = ctx.meta
+        grads = [torch.as_tensor(res[k], dtype=xd, device=xdev)
+                 for k in ("x0", "y0", "vx", "vy", "om")]
+        grads.append(torch.as_tensor(res["g"], dtype=gd, device=gdev).reshape(gshape))
+        return tuple(gJ.to(t.dtype) * t for t in grads) + (None,)
 
 
 def drag_objective(x, y, vx, vy, om, g, setup: AdjointSetup) -> torch.Tensor:

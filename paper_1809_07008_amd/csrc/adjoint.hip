@@ -355,14 +355,24 @@ struct AdjointState {
   double adj_ms = 0.0, rec_ms = 0.0;
   int64_t adj_n = 0, rec_n = 0;
   std::vector<hipEvent_t> kev;  // per-kernel event pairs when timing
+  // a forward pass whose reverse sweep has not run yet (imb_adjoint_forward)
+  bool armed = false;
+  int run_nsteps = 0;
+  bool has_w[3] = {false, false, false};
 };
 
 static void release(AdjointState* A) {
+  A->armed = false;
   for (void* p : A->owned) hipFree(p);
   A->owned.clear();
   A->ckpt.clear();
   A->ring.clear();
   A->nseg = A->k = A->nsteps = A->np_cap = 0;
+}
+
+void disarm_adjoint(imb_sim* s) {
+  SimView v = sim_view(s);
+  if (*v.adj) (*v.adj)->armed = false;
 }
 
 void free_adjoint(imb_sim* s) {
@@ -493,10 +503,11 @@ static void launch_adjoint_step(const AdjointArgs& A, hipStream_t s) {
 
 using namespace imb;
 
-extern "C" int imb_adjoint(imb_sim* sim, int32_t nsteps, int32_t k, const double* wfx,
-                           const double* wfy, const double* wtz, double* gx0, double* gy0,
-                           double* gvx, double* gvy, double* gom, double* gg, double* J,
-                           double* gf0) {
+// Forward pass of the differentiated run: nsteps coupled steps from the current state keeping a
+// checkpoint every k steps and the disk tables of every step; J on the host.  Arms the reverse
+// sweep (adjoint_reverse).
+static int adjoint_forward(imb_sim* sim, int32_t nsteps, int32_t k, const double* wfx,
+                           const double* wfy, const double* wtz, double* J) {
   if (!sim) return IMB_EINVAL;
   SimView v = sim_view(sim);
   const imb_config& cfg = *v.cfg;
@@ -614,6 +625,42 @@ extern "C" int imb_adjoint(imb_sim* sim, int32_t nsteps, int32_t k, const double
     TableSlot tN = table_slot(v, A, nsteps);
     copy_table(v, d.tab[last], d.band_off[last], d.band_ids[last], tN.tab, tN.boff, tN.bids, st);
   }
+  const hipError_t fe = hipGetLastError();
+  if (fe != hipSuccess) return hip_fail(v.err, fe, "adjoint forward launch");
+  rc = sync_and_check(sim);
+  if (rc) return rc;
+  hipEventElapsedTime(&A->fwd_ms, A->ev[0], A->ev[1]);
+  if (J && hipMemcpy(J, d.J, sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+    return hip_fail(v.err, hipGetLastError(), "hipMemcpy(J)");
+  A->armed = true;
+  A->run_nsteps = nsteps;
+  for (int c = 0; c < 3; ++c) A->has_w[c] = wd[c] != nullptr;
+  return IMB_OK;
+}
+
+// Reverse sweep of the armed forward pass: recomputation from the checkpoints and the adjoint
+// steps, then the gradients on the host.  Disarms.
+static int adjoint_reverse(imb_sim* sim, double* gx0, double* gy0, double* gvx, double* gvy,
+                           double* gom, double* gg, double* gf0) {
+  if (!sim) return IMB_EINVAL;
+  SimView v = sim_view(sim);
+  AdjointState* A = *v.adj;
+  if (!A || !A->armed) {
+    *v.err = "adjoint: no forward pass to reverse (call imb_adjoint_forward first; "
+             "imb_set_particles, imb_load_state and a second reverse sweep disarm it)";
+    return IMB_EINVAL;
+  }
+  A->armed = false;
+  const imb_config& cfg = *v.cfg;
+  const int np = *v.np;
+  const int pstride = std::max(cfg.max_particles, 1);
+  const int nsteps = A->run_nsteps, k = A->k;
+  hipStream_t st = v.stream;
+  DeviceLayout& d = *v.d;
+  const double* wd[3];
+  for (int c = 0; c < 3; ++c) wd[c] = A->has_w[c] ? d.w + (size_t)c * pstride : nullptr;
+  int rc = IMB_OK;
+  drop_graphs(sim);
 
   // ---- reverse sweep
   const bool timing = *v.timing;
@@ -695,7 +742,6 @@ extern "C" int imb_adjoint(imb_sim* sim, int32_t nsteps, int32_t k, const double
 
   rc = sync_and_check(sim);
   if (rc) return rc;
-  hipEventElapsedTime(&A->fwd_ms, A->ev[0], A->ev[1]);
   hipEventElapsedTime(&A->bwd_ms, A->ev[2], A->ev[3]);
   if (timing) {
     for (size_t i = 0; i + 1 < A->kev.size(); i += 2) {
@@ -722,8 +768,6 @@ extern "C" int imb_adjoint(imb_sim* sim, int32_t nsteps, int32_t k, const double
       return hip_fail(v.err, hipGetLastError(), "hipMemcpy(gradients)");
   if (gg && hipMemcpy(gg, A->gg, 2 * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
     return hip_fail(v.err, hipGetLastError(), "hipMemcpy(dJ/dg)");
-  if (J && hipMemcpy(J, d.J, sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
-    return hip_fail(v.err, hipGetLastError(), "hipMemcpy(J)");
   if (gf0) {
     const size_t n = (size_t)NQ * cfg.nx * cfg.ny;
     if (!A->gf0 && take_t(A, n, &A->gf0)) {
@@ -745,6 +789,26 @@ extern "C" int imb_adjoint(imb_sim* sim, int32_t nsteps, int32_t k, const double
     if (rc) return rc;
   }
   return IMB_OK;
+}
+
+extern "C" int imb_adjoint_forward(imb_sim* sim, int32_t nsteps, int32_t k_ckpt,
+                                   const double* wfx, const double* wfy, const double* wtz,
+                                   double* J) {
+  return adjoint_forward(sim, nsteps, k_ckpt, wfx, wfy, wtz, J);
+}
+
+extern "C" int imb_adjoint_backward(imb_sim* sim, double* gx0, double* gy0, double* gvx,
+                                    double* gvy, double* gom, double* gg, double* gf0) {
+  return adjoint_reverse(sim, gx0, gy0, gvx, gvy, gom, gg, gf0);
+}
+
+extern "C" int imb_adjoint(imb_sim* sim, int32_t nsteps, int32_t k, const double* wfx,
+                           const double* wfy, const double* wtz, double* gx0, double* gy0,
+                           double* gvx, double* gvy, double* gom, double* gg, double* J,
+                           double* gf0) {
+  int rc = adjoint_forward(sim, nsteps, k, wfx, wfy, wtz, J);
+  if (rc) return rc;
+  return adjoint_reverse(sim, gx0, gy0, gvx, gvy, gom, gg, gf0);
 }
 
 extern "C" int imb_get_adjoint_timing(imb_sim* sim, double* forward_ms, double* reverse_ms,

@@ -119,12 +119,29 @@ void launch_gather(int storage, const LatticeArgs& a, const void* src, double* f
   else gather_t<StoreF16>(a, src, fq, rho, ux, uy, s);
 }
 
-// Streaming copy: 16-byte vector loads/stores, grid-stride; the byte tail is copied per byte.
-__global__ void k_copy(uint4* __restrict__ dst, const uint4* __restrict__ src, size_t n16,
-                       unsigned char* dtail, const unsigned char* stail, int ntail) {
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
-    dst[i] = src[i];
+// Streaming copy: each thread moves COPY_UNROLL 16-byte vectors per trip, every load of the trip
+// issued before its stores, with non-temporal loads and stores (nothing is reused); the byte
+// tail is copied per byte.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int COPY_UNROLL = 4;
+__global__ __launch_bounds__(256) void k_copy(u32x4* __restrict__ dst,
+                                              const u32x4* __restrict__ src, size_t n16,
+                                              unsigned char* dtail, const unsigned char* stail,
+                                              int ntail) {
+  const size_t chunk = (size_t)256 * COPY_UNROLL;
+  for (size_t base = (size_t)blockIdx.x * chunk; base < n16; base += (size_t)gridDim.x * chunk) {
+    u32x4 v[COPY_UNROLL];
+#pragma unroll
+    for (int u = 0; u < COPY_UNROLL; ++u) {
+      const size_t i = base + (size_t)u * 256 + threadIdx.x;
+      if (i < n16) v[u] = __builtin_nontemporal_load(src + i);
+    }
+#pragma unroll
+    for (int u = 0; u < COPY_UNROLL; ++u) {
+      const size_t i = base + (size_t)u * 256 + threadIdx.x;
+      if (i < n16) __builtin_nontemporal_store(v[u], dst + i);
+    }
+  }
   if (blockIdx.x == 0 && (int)threadIdx.x < ntail) dtail[threadIdx.x] = stail[threadIdx.x];
 }
 
@@ -144,8 +161,12 @@ static int copy_grid(size_t n16) {
 void launch_copy(void* dst, const void* src, size_t n_bytes, hipStream_t s) {
   const size_t n16 = n_bytes / 16;
   const int ntail = (int)(n_bytes - n16 * 16);
-  hipLaunchKernelGGL(k_copy, dim3(copy_grid(n16)), dim3(256), 0, s, (uint4*)dst,
-                     (const uint4*)src, n16, (unsigned char*)dst + n16 * 16,
+  // one trip per workgroup up to 2^20 workgroups (16 GiB), grid-stride beyond
+  size_t g = (n16 + 256 * COPY_UNROLL - 1) / (256 * COPY_UNROLL);
+  if (g > (1u << 20)) g = 1u << 20;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)g), dim3(256), 0, s, (u32x4*)dst,
+                     (const u32x4*)src, n16, (unsigned char*)dst + n16 * 16,
                      (const unsigned char*)src + n16 * 16, ntail);
 }
 

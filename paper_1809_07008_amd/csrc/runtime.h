@@ -63,6 +63,8 @@ void enqueue_step(imb_sim* s, const double* wfx, const double* wfy, const double
 int sync_and_check(imb_sim* s);
 int reset_device_error(imb_sim* s);
 void free_adjoint(imb_sim* s);
+// Forgets a forward pass waiting for its reverse sweep (the disks or the state were replaced).
+void disarm_adjoint(imb_sim* s);
 void drop_graphs(imb_sim* s);
 
 // Simulation whose memory is carved for `layout_cfg` (same lattice and particle capacity as

@@ -605,6 +605,7 @@ int imb_set_particles(imb_sim* s, int32_t n, const double* x, const double* y, c
   }
   hipStreamSynchronize(s->stream);
   drop_graphs(s);
+  disarm_adjoint(s);
   s->np = n;
   ParticleState& ps = s->d.ps;
   const size_t mp = (size_t)std::max(s->cfg.max_particles, 1);
@@ -678,6 +679,23 @@ int imb_set_graphs(imb_sim* s, int enable) {
   drop_graphs(s);
   s->use_graphs = enable != 0;
   return IMB_OK;
+}
+
+int imb_prepare_graphs(imb_sim* s) {
+  if (!s) return IMB_EINVAL;
+  hipStreamSynchronize(s->stream);
+  if (!s->use_graphs) return IMB_OK;
+  for (int li = 0; li < 2; ++li)
+    for (int start = 0; start < 2; ++start) {
+      hipGraphExec_t& ge = s->graph[li][start];
+      if (!ge) ge = capture_steps(s, li ? GRAPH_LONG : 2, start);
+      if (!ge) {  // capture unsupported: imb_step launches directly
+        s->use_graphs = false;
+        return IMB_OK;
+      }
+      if (hipGraphUpload(ge, s->stream) != hipSuccess) hipGetLastError();
+    }
+  return sync_and_check(s);
 }
 
 int imb_get_forces(imb_sim* s, double* fx, double* fy, double* tz) {
@@ -816,6 +834,7 @@ int imb_load_state(imb_sim* s, const void* host_buf, size_t bytes) {
   const char* in = (const char*)host_buf + sizeof h;
   hipStreamSynchronize(s->stream);
   drop_graphs(s);
+  disarm_adjoint(s);
   s->cur = 0;
   s->np = h.np;
   s->steps = h.steps;

@@ -50,7 +50,8 @@ EXPORTED = [
     "imb_get_solid_field", "imb_set_graphs", "imb_get_adjoint_timing",
     "imb_batch_get_populations", "imb_batch_get_launch", "imb_batch_autotune",
     "imb_batch_get_timing", "imb_batch_last_error", "imb_batch_set_schedule",
-    "imb_batch_get_schedule",
+    "imb_batch_get_schedule", "imb_prepare_graphs", "imb_adjoint_forward",
+    "imb_adjoint_backward",
 ]
 
 
@@ -104,6 +105,7 @@ def load_library():
         "imb_set_particles": (C.c_int, [_VP, C.c_int32, _D, _D, _D, _D, _D, _D, _I32]),
         "imb_step": (C.c_int, [_VP, C.c_int32]),
         "imb_set_graphs": (C.c_int, [_VP, C.c_int]),
+        "imb_prepare_graphs": (C.c_int, [_VP]),
         "imb_get_forces": (C.c_int, [_VP, _D, _D, _D]),
         "imb_get_particles": (C.c_int, [_VP, _D, _D, _D, _D, _D]),
         "imb_get_counts": (C.c_int, [_VP, _I32, P(C.c_int64)]),
@@ -116,6 +118,8 @@ def load_library():
         "imb_copy_kernel": (C.c_int, [_VP, _VP, C.c_size_t, _VP]),
         "imb_adjoint": (C.c_int, [_VP, C.c_int32, C.c_int32, _D, _D, _D, _D, _D, _D, _D, _D,
                                   _D, _D, _D]),
+        "imb_adjoint_forward": (C.c_int, [_VP, C.c_int32, C.c_int32, _D, _D, _D, _D]),
+        "imb_adjoint_backward": (C.c_int, [_VP, _D, _D, _D, _D, _D, _D, _D]),
         "imb_get_adjoint_timing": (C.c_int, [_VP, _D, _D, _D, P(C.c_int64), _D,
                                              P(C.c_int64)]),
         "imb_batch_required_bytes": (C.c_int, [C.c_int32, P(Config), P(C.c_size_t)]),
@@ -321,6 +325,10 @@ class Simulation:
     def set_graphs(self, on: bool):
         self._check(load_library().imb_set_graphs(self._h, 1 if on else 0), "imb_set_graphs")
 
+    def prepare_graphs(self):
+        """Captures and uploads every step graph imb_step may replay (imb_prepare_graphs)."""
+        self._check(load_library().imb_prepare_graphs(self._h), "imb_prepare_graphs")
+
     def set_kernel_timing(self, on: bool):
         self._check(load_library().imb_set_kernel_timing(self._h, 1 if on else 0),
                     "imb_set_kernel_timing")
@@ -359,6 +367,33 @@ class Simulation:
         res = {k: v[:n] for k, v in zip(names, outs)}
         res["g"] = gg
         res["J"] = float(J[0])
+        if populations:
+            res["f0"] = gf0
+        return res
+
+    def adjoint_forward(self, nsteps: int, k_ckpt: int, wfx=None, wfy=None, wtz=None) -> float:
+        """Forward pass of a differentiated run (imb_adjoint_forward): advances nsteps keeping
+        the checkpoints, returns J and arms one reverse sweep."""
+        n = self.n
+        w = [None if a is None else _f64(a, n) for a in (wfx, wfy, wtz)]
+        J = np.zeros(1)
+        self._check(load_library().imb_adjoint_forward(self._h, int(nsteps), int(k_ckpt),
+                                                       *(_dp(a) for a in w), _dp(J)),
+                    "imb_adjoint_forward")
+        return float(J[0])
+
+    def adjoint_backward(self, populations: bool = False):
+        """Reverse sweep of the armed forward pass (imb_adjoint_backward): the gradients as
+        :meth:`adjoint` returns them, without J."""
+        m = max(self.n, 1)
+        outs = [np.zeros(m) for _ in range(5)]
+        gg = np.zeros(2)
+        gf0 = np.zeros((9, self.cfg.ny, self.cfg.nx)) if populations else None
+        self._check(load_library().imb_adjoint_backward(self._h, *(_dp(o) for o in outs),
+                                                        _dp(gg), _dp(gf0)),
+                    "imb_adjoint_backward")
+        res = {k: v[: self.n] for k, v in zip(["x0", "y0", "vx", "vy", "om"], outs)}
+        res["g"] = gg
         if populations:
             res["f0"] = gf0
         return res

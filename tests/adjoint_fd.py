@@ -85,3 +85,15 @@ def block_errors(adj: dict, fd: dict, names=PARAMS + ("g",)) -> dict:
         nf = np.linalg.norm(f)
         errs[name] = float(np.linalg.norm(a - f) / nf) if nf > 0 else float(np.linalg.norm(a))
     return errs
+
+
+def elementwise_errors(adj: dict, fd: dict, names=PARAMS + ("g",)) -> dict:
+    """Per gradient block, the element-wise relative errors |a_i - f_i| / |f_i| (array)."""
+    errs = {}
+    for name in names:
+        if name not in fd:
+            continue
+        a = np.asarray(adj[name] if name in adj else adj[name + "0"], float)
+        f = np.asarray(fd[name], float)
+        errs[name] = np.abs(a - f) / np.where(f != 0.0, np.abs(f), 1.0)
+    return errs

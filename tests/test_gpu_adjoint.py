@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
-from adjoint_fd import block_errors, fd_gradient, objective, base_state
+from adjoint_fd import block_errors, elementwise_errors, fd_gradient, objective, base_state
 from paper_1809_07008_amd import imb
 from paper_1809_07008_amd import workloads as W
 
@@ -160,21 +160,50 @@ def test_adjoint_no_disks_body_force_only():
     assert np.all(res["g"] == 0.0)
 
 
-def test_adjoint_512x256_fp32_against_golden():
-    """20 disks of diameter 20 at rest in a 512x256 channel, 200 steps, checkpoint every 20:
-    gradient of the summed x-drag against the stored FP64 finite differences."""
+def _golden_512x256():
     with open(os.path.join(HERE, "golden", "adjoint_512x256_n20.json")) as fh:
         gold = json.load(fh)
+    fd = {k: np.array(v) for k, v in gold["gradient"].items()}
+    return gold, fd
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_adjoint_512x256_against_golden_elementwise(storage):
+    """20 disks of diameter 20 at rest in a 512x256 channel, 200 steps, checkpoint every 20:
+    gradient of the summed x-drag against the stored FP64 central differences, element by
+    element, every block (positions, velocities, spins, body force)."""
+    gold, fd = _golden_512x256()
     case = W.adjoint_channel(seed=gold["seed"])
     n = case.particles.n
-    sim = imb.simulation_from_case(case, storage="f32", tile_w=32, tile_rows=2)
+    sim = imb.simulation_from_case(case, storage=storage, tile_w=32, tile_rows=2)
     res = sim.adjoint(case.steps, 20, wfx=np.ones(n))
-    assert abs(res["J"] - gold["J"]) <= 1e-4 * abs(gold["J"])
-    fd = {k: np.array(v) for k, v in gold["gradient"].items()}
-    errs = block_errors(res, fd)
-    print("512x256 fp32 block errors", errs)
-    for name in ("x", "y", "vx", "vy", "g"):
-        assert errs[name] < 1e-4, (name, errs[name])
+    assert abs(res["J"] - gold["J"]) <= (1e-12 if storage == "f64" else 1e-4) * abs(gold["J"])
+    errs = elementwise_errors(res, fd)
+    for name, e in errs.items():
+        print("512x256 %s %s: max element rel err %.3e (element %d, |fd| %.3e), median %.3e"
+              % (storage, name, e.max(), int(np.argmax(e)), abs(fd[name][int(np.argmax(e))]),
+                 np.median(e)))
+    for name, e in errs.items():
+        f = np.abs(fd[name])
+        if storage == "f64":
+            # the central differences themselves are good to about 2e-5 here (the solid ratio is
+            # only piecewise C2 in the position, and a velocity step moves a disk 200 h by the
+            # last step, across cell-edge kinks); measured: 2.0e-5 at worst (vx, vy)
+            assert e.max() < 1e-4, (name, e.max(), int(np.argmax(e)))
+            continue
+        # FP32: every element of the position, velocity and body-force blocks within 1e-4 of
+        # itself.  The spin gradients are sums of lever-arm moments that cancel (the block spans
+        # four decades, 0.07 to 447): in FP32 they hold 1e-4 as a block (norm-wise) and 2e-3
+        # element by element (measured 1.2e-3); elements below 1e-3 of the block's largest are
+        # held to 2e-6 of that largest, about 30 FP32 unit roundoffs of the block scale.  The
+        # FP64 form above holds every spin element to 1e-4 (measured 7e-9).
+        a = np.asarray(res[name] if name in res else res[name + "0"])
+        big = f >= 1e-3 * f.max()
+        bar = 2e-3 if name == "om" else 1e-4
+        assert e[big].max() < bar, (name, e[big].max())
+        if (~big).any():
+            assert (np.abs(a - fd[name])[~big]).max() <= 2e-6 * f.max(), name
+        assert np.linalg.norm(a - fd[name]) <= 1e-4 * np.linalg.norm(fd[name]), name
 
 
 def test_autograd_function_matches_library_and_gradcheck():
@@ -198,3 +227,24 @@ def test_autograd_function_matches_library_and_gradcheck():
     # numerical Jacobian of the Function's own forward against its backward
     assert torch.autograd.gradcheck(lambda *a: drag_objective(*a, setup), (*t, g), eps=1e-6,
                                     atol=1e-7, rtol=1e-4, fast_mode=True)
+
+
+def test_split_forward_backward_equals_one_call():
+    """imb_adjoint_forward then imb_adjoint_backward gives imb_adjoint's J and gradients bit for
+    bit; the sweep needs an armed forward pass (set_particles and a completed sweep disarm it);
+    stepping in between does not change the gradients."""
+    case = small_case(steps=14)
+    ref = gpu_adjoint(case, k=5)
+    sim = imb.simulation_from_case(case)
+    J = sim.adjoint_forward(case.steps, 5, **WEIGHTS)
+    assert J == ref["J"]
+    sim.step(3)  # the sweep works on its own copies of the states and tables
+    res = sim.adjoint_backward()
+    for name in ("x0", "y0", "vx", "vy", "om", "g"):
+        assert np.array_equal(res[name], ref[name]), name
+    with pytest.raises(imb.ImbError):
+        sim.adjoint_backward()
+    sim.adjoint_forward(case.steps, 5, **WEIGHTS)
+    sim.set_case_particles(case.particles)
+    with pytest.raises(imb.ImbError):
+        sim.adjoint_backward()
