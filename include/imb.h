@@ -156,6 +156,18 @@ int imb_set_particles(imb_sim* sim, int32_t n, const double* x, const double* y,
  * Asynchronous (returns once the work is queued).  nsteps >= 0. */
 int imb_step(imb_sim* sim, int32_t nsteps);
 
+/* For callers that cannot allocate device memory or create HIP objects (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the coupled steps of imb_step,
+ * launched directly on the simulation's stream (no graph capture, no event, no allocation).
+ * The per-disk force and torque that each step's lattice kernel hands to its particle phase are
+ * kept in a library-wide device array (256 KiB per GPU, held until the process ends) instead of
+ * the simulation's buffer; every step writes every entry it reads, so nothing needs clearing.
+ * Limits: at most 8192 disks (IMB_EINVAL beyond); the current HIP device must be the one the
+ * simulation was created on (IMB_EINVAL otherwise).  All calls on one GPU share that array:
+ * calls that can overlap in time on one GPU (different streams, different host threads) race
+ * and must be ordered by the caller.  Results equal imb_step's bit for bit.  Asynchronous. */
+int imb_step_noalloc(imb_sim* sim, int32_t nsteps);
+
 /* imb_step replays captured HIP graphs of 2 or 32 steps (captured on first use, re-captured
  * after imb_set_particles / imb_load_state); enable = 0 makes it launch every kernel directly.
  * Per-kernel timing (imb_set_kernel_timing) always launches directly.  Synchronises. */

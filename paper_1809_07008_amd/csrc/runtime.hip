@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -182,6 +183,7 @@ struct imb_sim {
   // captured step chains: graph[len][start buffer]; len index 0 = 2 steps, 1 = GRAPH_LONG steps
   hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   bool use_graphs = true;
+  int device = -1;  // the HIP device current at creation (its memory and stream live there)
 };
 
 static constexpr int GRAPH_LONG = 32;
@@ -270,6 +272,23 @@ void enqueue_step(imb_sim* s, const double* wfx, const double* wfy, const double
     pa.do_finalize = 1; pa.do_dem = 1; pa.do_table = 1;
     pa.wfx = wfx; pa.wfy = wfy; pa.wtz = wtz; pa.J = J;
     timed(1, [&](hipEvent_t e0, hipEvent_t e1) { launch_particle_phase(pa, s->stream, e0, e1); });
+  }
+  s->cur ^= 1;
+  s->steps++;
+}
+
+// The same step with the per-disk force and torque of the lattice kernel kept in `force`
+// (capacity >= np) instead of the simulation's buffer, launched directly (no graph, no event).
+static void enqueue_step_into(imb_sim* s, double4* force) {
+  const int c = s->cur;
+  LatticeArgs la = lattice_args(s, s->d.f[c], s->d.f[c ^ 1]);
+  la.force = force;
+  launch_lattice_step(s->cfg.storage, la, s->stream);
+  if (s->np > 0) {
+    ParticleArgs pa = particle_args(s, c ^ 1);
+    pa.do_finalize = 1; pa.do_dem = 1; pa.do_table = 1;
+    pa.direct = force;
+    launch_particle_phase(pa, s->stream);
   }
   s->cur ^= 1;
   s->steps++;
@@ -373,6 +392,10 @@ int create_sim(const imb_config* cfg, const imb_config* layout_cfg, void* hip_st
   if (!s->cfg.tile_w) s->cfg.tile_w = 64;
   if (!s->cfg.tile_rows) s->cfg.tile_rows = 1;
   s->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&s->device) != hipSuccess) {
+    hipGetLastError();
+    s->device = -1;
+  }
   sim_geometry(s->cfg, &s->g);
   s->layout_cfg = *layout_cfg;
   if (!s->layout_cfg.tile_w) s->layout_cfg.tile_w = 64;
@@ -679,6 +702,45 @@ int imb_set_graphs(imb_sim* s, int enable) {
   drop_graphs(s);
   s->use_graphs = enable != 0;
   return IMB_OK;
+}
+
+// ------------------------------------------------------- stepping without allocation
+// imb_step_noalloc keeps the per-disk force and torque that the lattice kernel hands to the
+// particle phase in this file-scope device array (one copy on every GPU the library runs on,
+// held until the process ends) instead of in the simulation's buffer.  Host code never passes
+// the array's name to a kernel: its device address is resolved once per device with
+// hipGetSymbolAddress and kept in g_scratch_ptr.
+static constexpr int NOALLOC_MAX_DISKS = 8192;  // 256 KiB
+static constexpr int NOALLOC_MAX_DEVICES = 64;
+static __device__ __align__(256) double4 scratch[NOALLOC_MAX_DISKS];
+static std::mutex g_scratch_mu;
+static double4* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+int imb_step_noalloc(imb_sim* s, int32_t nsteps) {
+  if (!s || nsteps < 0) return IMB_EINVAL;
+  if (s->np > NOALLOC_MAX_DISKS) {
+    s->err = "imb_step_noalloc: more disks than its scratch holds (8192)";
+    return IMB_EINVAL;
+  }
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return hip_fail(&s->err, hipGetLastError(), "hipGetDevice");
+  if (dev != s->device || dev < 0 || dev >= NOALLOC_MAX_DEVICES) {
+    s->err = "imb_step_noalloc: the current device is not the one the simulation was created on";
+    return IMB_EINVAL;
+  }
+  double4* ptr = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+      void* p = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !p) return hip_fail(&s->err, e, "hipGetSymbolAddress(scratch)");
+      g_scratch_ptr[dev] = (double4*)p;
+    }
+    ptr = g_scratch_ptr[dev];
+  }
+  for (int k = 0; k < nsteps; ++k) enqueue_step_into(s, ptr);
+  return launch_check(s, "step_noalloc");
 }
 
 int imb_prepare_graphs(imb_sim* s) {

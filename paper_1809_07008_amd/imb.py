@@ -51,7 +51,7 @@ EXPORTED = [
     "imb_batch_get_populations", "imb_batch_get_launch", "imb_batch_autotune",
     "imb_batch_get_timing", "imb_batch_last_error", "imb_batch_set_schedule",
     "imb_batch_get_schedule", "imb_prepare_graphs", "imb_adjoint_forward",
-    "imb_adjoint_backward",
+    "imb_adjoint_backward", "imb_step_noalloc",
 ]
 
 
@@ -104,6 +104,7 @@ def load_library():
         "imb_get_solid_field": (C.c_int, [_VP, _D]),
         "imb_set_particles": (C.c_int, [_VP, C.c_int32, _D, _D, _D, _D, _D, _D, _I32]),
         "imb_step": (C.c_int, [_VP, C.c_int32]),
+        "imb_step_noalloc": (C.c_int, [_VP, C.c_int32]),
         "imb_set_graphs": (C.c_int, [_VP, C.c_int]),
         "imb_prepare_graphs": (C.c_int, [_VP]),
         "imb_get_forces": (C.c_int, [_VP, _D, _D, _D]),
@@ -282,6 +283,10 @@ class Simulation:
 
     def step(self, n: int = 1):
         self._check(load_library().imb_step(self._h, int(n)), "imb_step")
+
+    def step_noalloc(self, n: int = 1):
+        """imb_step_noalloc: the same steps, launched directly, with no allocation."""
+        self._check(load_library().imb_step_noalloc(self._h, int(n)), "imb_step_noalloc")
 
     def forces(self):
         m = max(self.n, 1)
