@@ -16,6 +16,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
+_SRC3 = os.path.join(_HERE, "oracle3d.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 GCC_FLAGS = ["-O2", "-fPIC", "-shared", "-std=c99", "-D_GNU_SOURCE", "-ffp-contract=off",
@@ -24,9 +25,10 @@ GCC_FLAGS = ["-O2", "-fPIC", "-shared", "-std=c99", "-D_GNU_SOURCE", "-ffp-contr
 
 def build(force: bool = False) -> str:
     """Compile liboracle.so (always when ``force``)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    newest = max(os.path.getmtime(_SRC), os.path.getmtime(_SRC3))
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < newest:
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", *GCC_FLAGS, _SRC, "-o", tmp, "-lm"])
+        subprocess.check_call(["gcc", *GCC_FLAGS, _SRC, _SRC3, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -38,6 +40,12 @@ class _Cfg(C.Structure):
                 ("kn", C.c_double), ("zeta", C.c_double), ("rho_s", C.c_double),
                 ("eps_subcells", C.c_int32), ("uw_bot", C.c_double), ("uw_top", C.c_double),
                 ("kt", C.c_double), ("mu", C.c_double)]
+
+
+class _Cfg3(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("walls", C.c_int32),
+                ("eps_subcells", C.c_int32), ("tau0", C.c_double), ("gx", C.c_double),
+                ("gy", C.c_double), ("gz", C.c_double), ("rho0", C.c_double)]
 
 
 _lib = None
@@ -79,6 +87,24 @@ def _load():
                                        _D]
         lib.o_step_count.restype = C.c_long
         lib.o_step_count.argtypes = [C.c_void_p]
+        # three-dimensional oracle (oracle3d.c)
+        lib.o3_create.restype = C.c_void_p
+        lib.o3_create.argtypes = [C.POINTER(_Cfg3)]
+        lib.o3_destroy.argtypes = [C.c_void_p]
+        lib.o3_init_equilibrium.argtypes = [C.c_void_p] + [C.c_double] * 4
+        lib.o3_set_populations.argtypes = [C.c_void_p, _D]
+        lib.o3_get_populations.argtypes = [C.c_void_p, _D]
+        lib.o3_get_fields.argtypes = [C.c_void_p, _D, _D, _D, _D]
+        lib.o3_set_spheres.argtypes = [C.c_void_p, C.c_int] + [_D] * 10 + [_I]
+        lib.o3_step.argtypes = [C.c_void_p, C.c_int]
+        lib.o3_get_forces.argtypes = [C.c_void_p, _D, _D]
+        lib.o3_force_scales.argtypes = [C.c_void_p, _D, _D]
+        lib.o3_get_spheres.argtypes = [C.c_void_p, _D, _D, _D]
+        lib.o3_solid_field.argtypes = [C.c_void_p, _D]
+        lib.o3_subcell_fraction.restype = C.c_double
+        lib.o3_subcell_fraction.argtypes = [C.c_double] * 4 + [C.c_int]
+        lib.o3_collide_cell.argtypes = [_D, C.c_int, _D, _D, _D, _D, C.c_double, C.c_double,
+                                        C.c_double, C.c_double, _D, _D, _D, _D]
         _lib = lib
     return _lib
 
@@ -277,3 +303,130 @@ class OracleSim:
     @property
     def step_count(self) -> int:
         return int(_load().o_step_count(self._h))
+
+
+# ----------------------------------------------------------------- D3Q19 spheres (oracle3d.c)
+def subcell_fraction3(r: float, dx: float, dy: float, dz: float, n: int) -> float:
+    """The paper's cell-decomposition solid ratio in 3D: the share of the n^3 sub-cell centres of
+    the unit cell centred at (dx, dy, dz) strictly inside the sphere of radius r at the origin."""
+    return float(_load().o3_subcell_fraction(r, dx, dy, dz, n))
+
+
+def collide_cell3(f, eps=(), d=(), v=(), w=(), tau=0.6, g=(0.0, 0.0, 0.0)):
+    """One D3Q19 cell (Eqs. 1, 12-16).  Returns (f_out[19], dF[n,3], dT[n,3], B_tot)."""
+    lib = _load()
+    f = _f64(f)
+    n = len(eps)
+    eps = _f64(eps) if n else np.zeros(1)
+    d, v, w = ((_f64(a).reshape(-1) if n else np.zeros(3)) for a in (d, v, w))
+    fout = np.zeros(19)
+    dF = np.zeros(3 * max(n, 1))
+    dT = np.zeros(3 * max(n, 1))
+    bt = np.zeros(1)
+    lib.o3_collide_cell(_dp(f), n, _dp(eps), _dp(d), _dp(v), _dp(w), tau, g[0], g[1], g[2],
+                        _dp(fout), _dp(dF), _dp(dT), _dp(bt))
+    return fout, dF[: 3 * n].reshape(n, 3), dT[: 3 * n].reshape(n, 3), float(bt[0])
+
+
+@dataclass
+class OracleConfig3:
+    nx: int
+    ny: int
+    nz: int
+    tau0: float
+    walls: bool = True
+    eps_subcells: int = 5       # n of the paper's n^3 sub-cell decomposition
+    gx: float = 0.0
+    gy: float = 0.0
+    gz: float = 0.0
+    rho0: float = 1.0
+
+
+class OracleSim3:
+    """One three-dimensional oracle simulation (D3Q19, spheres, FP64, CPU)."""
+
+    def __init__(self, cfg: OracleConfig3):
+        lib = _load()
+        self.cfg = cfg
+        c = _Cfg3(cfg.nx, cfg.ny, cfg.nz, 1 if cfg.walls else 0, cfg.eps_subcells, cfg.tau0,
+                  cfg.gx, cfg.gy, cfg.gz, cfg.rho0)
+        self._h = lib.o3_create(C.byref(c))
+        if not self._h:
+            raise ValueError("oracle3: invalid configuration %r" % (cfg,))
+        self.np = 0
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.o3_destroy(h)
+            self._h = None
+
+    @property
+    def shape(self):
+        return (self.cfg.nz, self.cfg.ny, self.cfg.nx)
+
+    def init_equilibrium(self, rho=1.0, ux=0.0, uy=0.0, uz=0.0):
+        _load().o3_init_equilibrium(self._h, rho, ux, uy, uz)
+
+    def set_populations(self, f):
+        f = _f64(f)
+        assert f.shape == (19,) + self.shape
+        _load().o3_set_populations(self._h, _dp(f))
+
+    def populations(self) -> np.ndarray:
+        f = np.zeros((19,) + self.shape)
+        _load().o3_get_populations(self._h, _dp(f))
+        return f
+
+    def fields(self):
+        a = [np.zeros(self.shape) for _ in range(4)]
+        _load().o3_get_fields(self._h, *(_dp(v) for v in a))
+        return tuple(a)
+
+    def set_spheres(self, x, y, z, r, v=None, w=None, mode=None):
+        n = len(x)
+        v = np.zeros((n, 3)) if v is None else np.asarray(v, float).reshape(n, 3)
+        w = np.zeros((n, 3)) if w is None else np.asarray(w, float).reshape(n, 3)
+        mode = np.ascontiguousarray(np.ones(n, np.int32) if mode is None else mode, np.int32)
+        cols = [_f64(x), _f64(y), _f64(z), _f64(r)] + [_f64(v[:, k]) for k in range(3)] + \
+               [_f64(w[:, k]) for k in range(3)]
+        if n == 0:
+            cols = [np.zeros(1) for _ in range(10)]
+            mode = np.ones(1, np.int32)
+        rc = _load().o3_set_spheres(self._h, n, *(_dp(c) for c in cols),
+                                    mode.ctypes.data_as(_I))
+        if rc:
+            raise ValueError("oracle3: invalid spheres (code %d)" % rc)
+        self.np = n
+
+    def step(self, n: int = 1):
+        rc = _load().o3_step(self._h, int(n))
+        if rc:
+            raise RuntimeError("oracle3: step failed (code %d)" % rc)
+
+    def forces(self):
+        """(F[n,3], T[n,3]) on each sphere in the last step."""
+        m = max(self.np, 1)
+        F, T = np.zeros(3 * m), np.zeros(3 * m)
+        _load().o3_get_forces(self._h, _dp(F), _dp(T))
+        return F[: 3 * self.np].reshape(-1, 3), T[: 3 * self.np].reshape(-1, 3)
+
+    def force_scales(self):
+        """Per sphere: (sum over covered cells of |dF|, sum of |d| |dF|) of the last step."""
+        m = max(self.np, 1)
+        a, b = np.zeros(m), np.zeros(m)
+        _load().o3_force_scales(self._h, _dp(a), _dp(b))
+        return a[: self.np], b[: self.np]
+
+    def spheres(self):
+        m = max(self.np, 1)
+        a = [np.zeros(m) for _ in range(3)]
+        _load().o3_get_spheres(self._h, *(_dp(v) for v in a))
+        return tuple(v[: self.np] for v in a)
+
+    def solid_field(self) -> np.ndarray:
+        e = np.zeros(self.shape)
+        rc = _load().o3_solid_field(self._h, _dp(e))
+        if rc:
+            raise RuntimeError("oracle3: mapping failed (code %d)" % rc)
+        return e
