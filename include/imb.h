@@ -323,6 +323,82 @@ int imb_batch_get_timing(imb_batch* b, int32_t nsteps, double* ms);
 /* Message of the last failure on this batch (b = NULL: of the last failed create). */
 const char* imb_batch_last_error(const imb_batch* b);
 
+/* ------------------------------------------------------- three dimensions: D3Q19 with spheres
+ * The lattice step of the paper's own three-dimensional method (Sec. 2 with the D3Q19 set of
+ * Table 1; Sec. 2.2, Eqs. 12-16 for the spheres), for fixed spheres and spheres moving with a
+ * prescribed velocity (no DEM): BGK with the body force G_i = 3 w_i rho (c_i . g), the
+ * immersed-moving-boundary collision with the paper's cell-decomposition solid ratio (the share
+ * of the n^3 sub-cell centres of a cell strictly inside the sphere), pull streaming (periodic in
+ * x and z; half-way bounce-back walls at y = -1/2 and ny - 1/2 with IMB_FLAG_WALLS, else
+ * periodic y), and the force and torque vectors on every sphere (Eqs. 15, 16, force on the
+ * sphere).  Several spheres in one cell: eps_tot = min(1, sum eps_p), split in proportion.
+ * Node (x, y, z) owns the unit cube centred on it.
+ * D3Q19 velocity order q (populations exchanged through this interface, FP64 [19][nz][ny][nx]):
+ *   0 rest; 1-6: +x -x +y -y +z -z; 7-10: (+1,+1,0) (-1,-1,0) (+1,-1,0) (-1,+1,0);
+ *   11-14: (+1,0,+1) (-1,0,-1) (+1,0,-1) (-1,0,+1); 15-18: (0,+1,+1) (0,-1,-1) (0,+1,-1) (0,-1,+1).
+ * Fields are FP64 [nz][ny][nx]; per-sphere vectors are FP64 [n][3].  Errors and threading as for
+ * imb_sim; messages from imb3_last_error. */
+typedef struct imb3_config {
+  int32_t nx, ny, nz;      /* lattice size: nx >= 1, ny >= 2, nz >= 1 */
+  int32_t storage;         /* IMB_STORAGE_F64 or IMB_STORAGE_F32 (deviations f - w rho0) */
+  double tau0;             /* BGK relaxation time, > 1/2 (Eq. 5) */
+  double gx, gy, gz;       /* body-force acceleration on the fluid */
+  double rho0;             /* reference density (initial state, deviation storage) */
+  int32_t max_spheres;     /* capacity, 0..256 */
+  int32_t eps_subcells;    /* n of the paper's n^3 sub-cell solid ratio, 1..64 (the paper: 5) */
+  uint32_t flags;          /* IMB_FLAG_WALLS: walls in y */
+  int32_t tile_w;          /* tile width 16, 32 or 64 (tile = tile_w x 256/tile_w cells of one
+                              z layer); 0 picks the one with the fewest padded cells */
+  int32_t reserved;        /* must be 0 */
+  int32_t reserved2;       /* must be 0 */
+} imb3_config;
+
+typedef struct imb3_sim imb3_sim;
+
+/* Defaults: 32^3, F64, tau0 0.6, rho0 1, no body force, 8 spheres, n = 5, walls, tile auto. */
+void imb3_config_default(imb3_config* cfg);
+int imb3_required_bytes(const imb3_config* cfg, size_t* bytes);
+/* As imb_create: dev_buf (caller-owned, 256-byte aligned, >= imb3_required_bytes) or NULL for a
+ * library allocation; the fluid starts at rest at rho0 with no spheres.  Synchronises. */
+int imb3_create(const imb3_config* cfg, void* hip_stream, void* dev_buf, size_t dev_bytes,
+                imb3_sim** out);
+void imb3_destroy(imb3_sim* sim);
+/* f = f^eq(rho, u) everywhere (Eq. 2).  Asynchronous. */
+int imb3_init_equilibrium(imb3_sim* sim, double rho, double ux, double uy, double uz);
+/* f = f^eq(rho, (ux_of_y[y], 0, 0)): a shear flow along x (host array of ny values), e.g. the
+ * undisturbed Poiseuille profile as a starting state.  Synchronises. */
+int imb3_init_shear(imb3_sim* sim, double rho, const double* ux_of_y);
+/* Post-stream populations, host FP64 [19][nz][ny][nx].  Synchronise. */
+int imb3_set_populations(imb3_sim* sim, const double* host_f);
+int imb3_get_populations(imb3_sim* sim, double* host_f);
+/* Density and velocity of the post-stream populations (Eqs. 3, 4), host FP64 [nz][ny][nx] each
+ * (any may be NULL).  Synchronises. */
+int imb3_get_fields(imb3_sim* sim, double* rho, double* ux, double* uy, double* uz);
+/* eps_tot of every cell for the current sphere positions, host FP64 [nz][ny][nx].  Synchronises. */
+int imb3_get_solid_field(imb3_sim* sim, double* host_eps);
+/* Replaces all spheres (host arrays of length n): centre, radius, velocity, angular velocity,
+ * mode IMB_MODE_FIXED or IMB_MODE_PRESCRIBED (moves by its velocity once per step).  Requires
+ * n <= max_spheres, r > 0, 2 (r + 2) < nx, ny and nz, the centre inside the lattice (between the
+ * walls with IMB_FLAG_WALLS), and at most 4096 tiles per sphere box.  Synchronises. */
+int imb3_set_spheres(imb3_sim* sim, int32_t n, const double* x, const double* y, const double* z,
+                     const double* r, const double* vx, const double* vy, const double* vz,
+                     const double* wx, const double* wy, const double* wz, const int32_t* mode);
+/* Enqueues nsteps steps (replays captured graphs of 32 steps).  Asynchronous. */
+int imb3_step(imb3_sim* sim, int32_t nsteps);
+/* Force F[n][3] and torque T[n][3] on each sphere from the last step (host, any may be NULL).
+ * Synchronises. */
+int imb3_get_forces(imb3_sim* sim, double* F, double* T);
+/* Current sphere centres and radii, host FP64 [n][4] (x, y, z, r).  Synchronises. */
+int imb3_get_spheres(imb3_sim* sim, double* xyzr);
+int imb3_sync(imb3_sim* sim);
+/* Per-kernel timing with HIP events recorded at each launch's start and end (direct launches
+ * while enabled): summed milliseconds and counts of the lattice kernel and the force
+ * finalisation since the last enable. */
+int imb3_set_kernel_timing(imb3_sim* sim, int enable);
+int imb3_get_kernel_timing(imb3_sim* sim, double* lattice_ms, int64_t* lattice_launches,
+                           double* finalize_ms, int64_t* finalize_launches);
+const char* imb3_last_error(const imb3_sim* sim);
+
 /* ------------------------------------------------------------------------ misc */
 const char* imb_strerror(int code);
 const char* imb_last_error(const imb_sim* sim);

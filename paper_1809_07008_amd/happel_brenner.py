@@ -1,0 +1,174 @@
+"""Poiseuille flow past a fixed sphere (Sec. 3.1 of the paper) on the D3Q19 path, against the
+Happel-Brenner estimates of the hydrodynamic force and torque (Eqs. 18, 19).
+
+Set-up (Sec. 3.1.1): a sphere of radius R = 1 mm between two no-slip walls l_y = 10 mm apart,
+its centre h = 2.5 mm from the lower wall and half-way in x and z; periodic x and z with
+l_x = l_z = 40 mm; flow driven by a body force equivalent to a pressure gradient
+G = 2.5e-5 Pa/m; rho = 1000 kg/m^3, mu = 1e-3 Pa s.  With N lattice cells per diameter the
+lattice is 20N x 5N x 20N cells and the walls sit half-way, at y = -1/2 and y = 5N - 1/2.
+
+Readings (where the printed text is garbled): in Eqs. (18) and (19) the wall distance is the
+centre-to-nearest-wall distance h (so q = R/h = 0.4), and U is the undisturbed velocity at the
+centre, G h (l_y - h) / (2 mu); with these the equations give exactly the analytic values of the
+Table 3 caption, 5.7628e-12 N and 8.1537e-16 N m.
+
+The flow is Stokes flow (Re ~ 1e-3 or less here), so force and torque are linear in the driving;
+the lattice run uses a body force that gives a centre velocity of 1e-5 lattice units and compares
+lattice-unit results with the estimates evaluated in lattice units; relative errors are what the
+paper reports.  The run starts from the exact discrete Poiseuille profile of the empty channel and
+runs for a number of e-folding times of the slowest channel mode.
+
+    python -m paper_1809_07008_amd.happel_brenner --N 5 10 20 --tau 1.0
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import time
+
+import numpy as np
+
+# the paper's physical set-up (Sec. 3.1.1)
+R_PHYS = 1.0e-3       # m
+LY_PHYS = 10.0e-3     # m, wall gap
+H_PHYS = 2.5e-3       # m, centre to the lower wall
+G_PHYS = 2.5e-5       # Pa/m
+MU_PHYS = 1.0e-3      # Pa s
+RHO_PHYS = 1000.0     # kg/m^3
+
+# Table 3 of the paper: N, n_sub, tau, F_x (1e-12 N), T_z (1e-16 N m), error F (%), error T (%)
+TABLE3 = [
+    (5, 5, 1.0, 4.7375, 5.5904, 17.7910, 31.4374),
+    (10, 5, 1.0, 5.3606, 7.2359, 6.9793, 11.2560),
+    (20, 5, 1.0, 5.5462, 7.7928, 3.7595, 4.4260),
+    (25, 5, 1.0, 5.5709, 7.8732, 3.3305, 3.4398),
+    (20, 2, 1.0, 5.5553, 7.8202, 3.6016, 4.0905),
+    (20, 4, 1.0, 5.5484, 7.8001, 3.7203, 4.3372),
+    (20, 10, 1.0, 5.5476, 7.7986, 3.7343, 4.3546),
+    (20, 5, 0.8, 5.5829, 7.9051, 3.1223, 3.0488),
+    (20, 5, 0.62, 5.6166, 8.0031, 2.5379, 1.8471),
+    (20, 5, 0.53, 5.6385, 8.0608, 2.1564, 1.1390),
+]
+
+
+def happel_brenner(R: float, h: float, mu: float, U: float):
+    """Eqs. (18), (19) with q = R / h: the drag F_x and torque T_z on a sphere of radius R whose
+    centre is h from a plane wall, in a shear flow of velocity U at the centre."""
+    q = R / h
+    F = 6.0 * math.pi * mu * R * U * (1.0 - q * q / 9.0) / (
+        1.0 - 0.6526 * q + 0.316 * q ** 3 - 0.242 * q ** 4)
+    T = 8.0 / 3.0 * math.pi * mu * R * R * U * q * (1.0 + 0.0758 * q + 0.049 * q * q)
+    return F, T
+
+
+def physical_reference():
+    """The Table 3 caption's analytic values from the physical set-up."""
+    U = G_PHYS / (2.0 * MU_PHYS) * H_PHYS * (LY_PHYS - H_PHYS)
+    return happel_brenner(R_PHYS, H_PHYS, MU_PHYS, U)
+
+
+def poiseuille_profile(ny: int, tau: float, g: float) -> np.ndarray:
+    """The exact discrete steady profile of the empty channel for this scheme (half-way
+    bounce-back walls, first-order forcing, u = m / rho): the parabola plus the scheme's slip."""
+    nu = (tau - 0.5) / 3.0
+    lam = (tau - 0.5) ** 2
+    y = np.arange(ny)
+    yc = (ny - 1) / 2.0
+    return (g / (2.0 * nu) * ((ny / 2.0) ** 2 - (y - yc) ** 2)
+            + g * (16.0 * lam - 3.0) / (24.0 * nu) - g / 2.0)
+
+
+class Setup:
+    """Lattice-unit set-up at resolution N (cells per diameter) and relaxation time tau."""
+
+    def __init__(self, N: int, tau: float, n_sub: int = 5, u_centre: float = 1e-5):
+        self.N, self.tau, self.n_sub = N, tau, n_sub
+        self.nx = self.nz = 20 * N
+        self.ny = 5 * N
+        self.R = N / 2.0
+        self.h = 1.25 * N                      # centre to the lower wall (at y = -1/2)
+        self.ly = 5.0 * N
+        self.nu = (tau - 0.5) / 3.0
+        # body force giving the undisturbed centre velocity u_centre (parabola of the gap)
+        self.g = u_centre * 2.0 * self.nu / (self.h * (self.ly - self.h))
+        self.U = self.g / (2.0 * self.nu) * self.h * (self.ly - self.h)
+        self.centre = ((self.nx - 1) / 2.0, self.h - 0.5, (self.nz - 1) / 2.0)
+
+    def reference(self):
+        return happel_brenner(self.R, self.h, self.nu, self.U)  # rho = 1
+
+    def efold_steps(self) -> float:
+        """e-folding time of the slowest mode of the channel (diffusion across the gap)."""
+        return self.ly ** 2 / (self.nu * math.pi ** 2)
+
+
+def run(N: int, tau: float = 1.0, n_sub: int = 5, storage: str = "f32", efolds: float = 8.0,
+        chunk: int = 0, log=print):
+    """Runs the benchmark on the GPU; returns a dict with the force, torque, their relative
+    errors against Eqs. (18), (19) and the paper's Table 3 errors where it has the case."""
+    from . import imb
+    s = Setup(N, tau, n_sub)
+    cfg = imb.make_config3(s.nx, s.ny, s.nz, tau, storage, walls=True, g=(s.g, 0.0, 0.0),
+                           max_spheres=1, eps_subcells=n_sub)
+    sim = imb.Simulation3(cfg)
+    sim.init_shear(poiseuille_profile(s.ny, tau, s.g))
+    sim.set_spheres([s.centre[0]], [s.centre[1]], [s.centre[2]], [s.R])
+    total = int(math.ceil(efolds * s.efold_steps() / 32.0) * 32)
+    chunk = chunk or max(32, int(math.ceil(s.efold_steps() / 32.0)) * 32)
+    Fref, Tref = s.reference()
+    t0 = time.perf_counter()
+    done = 0
+    hist = []
+    while done < total:
+        n = min(chunk, total - done)
+        sim.step(n)
+        done += n
+        F, T = sim.forces()
+        hist.append((done, float(F[0, 0]), float(T[0, 2])))
+        if log:
+            log("N=%d tau=%.2f: %d/%d steps, F_x/F_HB = %.6f, T_z/T_HB = %.6f (%.1f s)"
+                % (N, tau, done, total, F[0, 0] / Fref, -T[0, 2] / Tref,
+                   time.perf_counter() - t0))
+    wall = time.perf_counter() - t0
+    F, T = sim.forces()
+    sim.close()
+    Fx = float(F[0, 0])
+    # the sphere is below the channel centre: the shear turns it clockwise about z (T_z < 0);
+    # the estimate gives the magnitude
+    Tz = float(T[0, 2])
+    out = {"N": N, "tau": tau, "n_sub": n_sub, "storage": storage, "cells": s.nx * s.ny * s.nz,
+           "steps": done, "efolds": efolds, "seconds": round(wall, 2),
+           "mlups": round(s.nx * s.ny * s.nz * done / wall / 1e6, 1),
+           "Fx_over_HB": Fx / Fref, "Tz_over_HB": -Tz / Tref,
+           "err_F_percent": abs(Fref - Fx) / Fref * 100.0,
+           "err_T_percent": abs(Tref + Tz) / Tref * 100.0,
+           "last_change_F": abs(hist[-1][1] - hist[-2][1]) / abs(hist[-1][1]) if len(hist) > 1
+           else None,
+           "lift_over_drag": float(F[0, 1]) / Fx, "side_over_drag": float(F[0, 2]) / Fx}
+    for row in TABLE3:
+        if row[0] == N and row[1] == n_sub and abs(row[2] - tau) < 1e-9:
+            out["paper_err_F_percent"] = row[5]
+            out["paper_err_T_percent"] = row[6]
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description="Poiseuille flow past a fixed sphere (D3Q19)")
+    ap.add_argument("--N", type=int, nargs="+", default=[5, 10])
+    ap.add_argument("--tau", type=float, nargs="+", default=[1.0])
+    ap.add_argument("--n-sub", type=int, default=5)
+    ap.add_argument("--storage", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--efolds", type=float, default=8.0)
+    args = ap.parse_args(argv)
+    import torch
+    if not torch.cuda.is_available():
+        raise SystemExit("needs a GPU")
+    for N in args.N:
+        for tau in args.tau:
+            res = run(N, tau, args.n_sub, args.storage, args.efolds)
+            print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

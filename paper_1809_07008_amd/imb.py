@@ -52,6 +52,11 @@ EXPORTED = [
     "imb_batch_get_timing", "imb_batch_last_error", "imb_batch_set_schedule",
     "imb_batch_get_schedule", "imb_prepare_graphs", "imb_adjoint_forward",
     "imb_adjoint_backward", "imb_step_noalloc",
+    "imb3_config_default", "imb3_required_bytes", "imb3_create", "imb3_destroy",
+    "imb3_init_equilibrium", "imb3_init_shear", "imb3_set_populations", "imb3_get_populations",
+    "imb3_get_fields", "imb3_get_solid_field", "imb3_set_spheres", "imb3_step",
+    "imb3_get_forces", "imb3_get_spheres", "imb3_sync", "imb3_set_kernel_timing",
+    "imb3_get_kernel_timing", "imb3_last_error",
 ]
 
 
@@ -71,6 +76,14 @@ class Config(C.Structure):
                 ("tile_rows", C.c_int32), ("eps_subcells", C.c_int32), ("reserved", C.c_int32),
                 ("wall_ux_bottom", C.c_double), ("wall_ux_top", C.c_double),
                 ("kt", C.c_double), ("mu", C.c_double)]
+
+
+class Config3(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("storage", C.c_int32),
+                ("tau0", C.c_double), ("gx", C.c_double), ("gy", C.c_double),
+                ("gz", C.c_double), ("rho0", C.c_double), ("max_spheres", C.c_int32),
+                ("eps_subcells", C.c_int32), ("flags", C.c_uint32), ("tile_w", C.c_int32),
+                ("reserved", C.c_int32), ("reserved2", C.c_int32)]
 
 
 _lib = None
@@ -141,6 +154,25 @@ def load_library():
         "imb_batch_last_error": (C.c_char_p, [_VP]),
         "imb_batch_set_schedule": (C.c_int, [_VP, C.c_int32]),
         "imb_batch_get_schedule": (C.c_int, [_VP, _I32]),
+        "imb3_config_default": (None, [P(Config3)]),
+        "imb3_required_bytes": (C.c_int, [P(Config3), P(C.c_size_t)]),
+        "imb3_create": (C.c_int, [P(Config3), _VP, _VP, C.c_size_t, P(_VP)]),
+        "imb3_destroy": (None, [_VP]),
+        "imb3_init_equilibrium": (C.c_int, [_VP, C.c_double, C.c_double, C.c_double,
+                                            C.c_double]),
+        "imb3_init_shear": (C.c_int, [_VP, C.c_double, _D]),
+        "imb3_set_populations": (C.c_int, [_VP, _D]),
+        "imb3_get_populations": (C.c_int, [_VP, _D]),
+        "imb3_get_fields": (C.c_int, [_VP, _D, _D, _D, _D]),
+        "imb3_get_solid_field": (C.c_int, [_VP, _D]),
+        "imb3_set_spheres": (C.c_int, [_VP, C.c_int32] + [_D] * 10 + [_I32]),
+        "imb3_step": (C.c_int, [_VP, C.c_int32]),
+        "imb3_get_forces": (C.c_int, [_VP, _D, _D]),
+        "imb3_get_spheres": (C.c_int, [_VP, _D]),
+        "imb3_sync": (C.c_int, [_VP]),
+        "imb3_set_kernel_timing": (C.c_int, [_VP, C.c_int]),
+        "imb3_get_kernel_timing": (C.c_int, [_VP, _D, P(C.c_int64), _D, P(C.c_int64)]),
+        "imb3_last_error": (C.c_char_p, [_VP]),
         "imb_strerror": (C.c_char_p, [C.c_int]),
         "imb_last_error": (C.c_char_p, [_VP]),
         "imb_version": (C.c_char_p, []),
@@ -567,3 +599,135 @@ def batch_from_cases(cases, tile_w=32, tile_rows=2, stream=None) -> Batch:
     for k, c in enumerate(cases):
         b.set_case_particles(k, c.particles)
     return b
+
+
+# ------------------------------------------------------- three dimensions: D3Q19 with spheres
+def make_config3(nx, ny, nz, tau0, storage="f64", walls=True, g=(0.0, 0.0, 0.0), rho0=1.0,
+                 max_spheres=8, eps_subcells=5, tile_w=0) -> Config3:
+    c = Config3()
+    load_library().imb3_config_default(C.byref(c))
+    c.nx, c.ny, c.nz, c.tau0 = int(nx), int(ny), int(nz), float(tau0)
+    c.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    c.gx, c.gy, c.gz = (float(v) for v in g)
+    c.rho0 = float(rho0)
+    c.max_spheres = int(max_spheres)
+    c.eps_subcells = int(eps_subcells)
+    c.flags = FLAG_WALLS if walls else 0
+    c.tile_w = int(tile_w)
+    return c
+
+
+class Simulation3:
+    """One D3Q19 simulation with spheres (imb3_*); device memory is a torch uint8 tensor."""
+
+    def __init__(self, cfg: Config3, stream=None, device="cuda"):
+        lib = load_library()
+        self.cfg = cfg
+        self._h = None
+        nbytes = C.c_size_t()
+        self._check(lib.imb3_required_bytes(C.byref(cfg), C.byref(nbytes)),
+                    "imb3_required_bytes", handle=False)
+        self._buf = _device_buffer(nbytes.value + 256, device)
+        ptr = self._buf.data_ptr()
+        off = (-ptr) % 256
+        h = C.c_void_p()
+        self._check(lib.imb3_create(C.byref(cfg), _stream_handle(stream), C.c_void_p(ptr + off),
+                                    nbytes.value, C.byref(h)), "imb3_create", handle=False)
+        self._h = h
+        self.n = 0
+
+    def _check(self, rc, what, handle=True):
+        if rc != IMB_OK:
+            msg = load_library().imb3_last_error(self._h if handle else None)
+            raise ImbError(rc, what, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().imb3_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def shape(self):
+        return (self.cfg.nz, self.cfg.ny, self.cfg.nx)
+
+    def init_equilibrium(self, rho=1.0, ux=0.0, uy=0.0, uz=0.0):
+        self._check(load_library().imb3_init_equilibrium(self._h, rho, ux, uy, uz),
+                    "imb3_init_equilibrium")
+
+    def init_shear(self, ux_of_y, rho=1.0):
+        u = _f64(ux_of_y, self.cfg.ny)
+        self._check(load_library().imb3_init_shear(self._h, rho, _dp(u)), "imb3_init_shear")
+
+    def set_populations(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        if f.shape != (19,) + self.shape:
+            raise ValueError("populations must have shape (19, nz, ny, nx)")
+        self._check(load_library().imb3_set_populations(self._h, _dp(f)), "imb3_set_populations")
+
+    def populations(self) -> np.ndarray:
+        f = np.empty((19,) + self.shape)
+        self._check(load_library().imb3_get_populations(self._h, _dp(f)), "imb3_get_populations")
+        return f
+
+    def fields(self):
+        a = [np.empty(self.shape) for _ in range(4)]
+        self._check(load_library().imb3_get_fields(self._h, *(_dp(v) for v in a)),
+                    "imb3_get_fields")
+        return tuple(a)
+
+    def solid_field(self) -> np.ndarray:
+        e = np.empty(self.shape)
+        self._check(load_library().imb3_get_solid_field(self._h, _dp(e)), "imb3_get_solid_field")
+        return e
+
+    def set_spheres(self, x, y, z, r, v=None, w=None, mode=None):
+        n = len(x)
+        v = np.zeros((n, 3)) if v is None else np.asarray(v, float).reshape(n, 3)
+        w = np.zeros((n, 3)) if w is None else np.asarray(w, float).reshape(n, 3)
+        cols = [_f64(x, n), _f64(y, n), _f64(z, n), _f64(r, n)] + \
+               [_f64(v[:, k], n) for k in range(3)] + [_f64(w[:, k], n) for k in range(3)]
+        md = np.ascontiguousarray(np.full(n, MODE_FIXED, np.int32) if mode is None else mode,
+                                  np.int32)
+        if n == 0:
+            cols = [np.zeros(1) for _ in range(10)]
+            md = np.ones(1, np.int32)
+        self._check(load_library().imb3_set_spheres(self._h, n, *(_dp(c) for c in cols),
+                                                    md.ctypes.data_as(_I32)), "imb3_set_spheres")
+        self.n = n
+
+    def step(self, n: int = 1):
+        self._check(load_library().imb3_step(self._h, int(n)), "imb3_step")
+
+    def sync(self):
+        self._check(load_library().imb3_sync(self._h), "imb3_sync")
+
+    def forces(self):
+        """(F[n,3], T[n,3]) on each sphere in the last step."""
+        m = max(self.n, 1)
+        F, T = np.zeros(3 * m), np.zeros(3 * m)
+        self._check(load_library().imb3_get_forces(self._h, _dp(F), _dp(T)), "imb3_get_forces")
+        return F[: 3 * self.n].reshape(-1, 3), T[: 3 * self.n].reshape(-1, 3)
+
+    def spheres(self) -> np.ndarray:
+        a = np.zeros(4 * max(self.n, 1))
+        self._check(load_library().imb3_get_spheres(self._h, _dp(a)), "imb3_get_spheres")
+        return a[: 4 * self.n].reshape(-1, 4)
+
+    def set_kernel_timing(self, on: bool):
+        self._check(load_library().imb3_set_kernel_timing(self._h, 1 if on else 0),
+                    "imb3_set_kernel_timing")
+
+    def kernel_timing(self):
+        lm, fm = C.c_double(), C.c_double()
+        ln, fn = C.c_int64(), C.c_int64()
+        self._check(load_library().imb3_get_kernel_timing(self._h, C.byref(lm), C.byref(ln),
+                                                          C.byref(fm), C.byref(fn)),
+                    "imb3_get_kernel_timing")
+        return {"lattice_ms": lm.value, "lattice_launches": ln.value,
+                "finalize_ms": fm.value, "finalize_launches": fn.value}

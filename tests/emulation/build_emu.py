@@ -1,7 +1,8 @@
 """Builds the CPU emulation of libimb (test infrastructure): the kernel sources of
 paper_1809_07008_amd/csrc compiled by g++ against the emulated HIP headers of this directory, with
-AddressSanitizer, into _build/emu/libimb_emu.so.  The only source edit is the dynamic-LDS
-declaration of the particle-phase kernel, which becomes a pointer to the emulated buffer."""
+AddressSanitizer, into _build/emu/libimb_emu.so.  The only source edits are the dynamic-LDS
+declaration of the particle-phase kernel, which becomes a pointer to the emulated buffer, and
+clang's four-element vector attribute, written as g++'s vector_size(16)."""
 from __future__ import annotations
 
 import concurrent.futures as cf
@@ -28,6 +29,9 @@ def build() -> str:
     for f in glob.glob(os.path.join(CSRC, "*.hip")):
         text = open(f).read().replace("extern __shared__ double lds[];",
                                       "double* lds = (double*)emu_dyn_lds();")
+        # clang's vector extension written in g++'s form
+        text = text.replace("__attribute__((ext_vector_type(4)))",
+                            "__attribute__((vector_size(16)))")
         with open(os.path.join(src, os.path.basename(f)[:-4] + ".cpp"), "w") as fh:
             fh.write(text)
     units = glob.glob(os.path.join(src, "*.cpp")) + [os.path.join(HERE, "emu.cpp")]

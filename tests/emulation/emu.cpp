@@ -183,6 +183,15 @@ hipError_t hipGraphInstantiate(hipGraphExec_t*, hipGraph_t, void*, char*, size_t
 hipError_t hipGraphDestroy(hipGraph_t) { return hipSuccess; }
 hipError_t hipGraphExecDestroy(hipGraphExec_t) { return hipSuccess; }
 hipError_t hipGraphLaunch(hipGraphExec_t, hipStream_t) { return hipErrorNotSupported; }
+hipError_t hipGraphUpload(hipGraphExec_t, hipStream_t) { return hipErrorNotSupported; }
+hipError_t hipGetDevice(int* device) {
+  *device = 0;
+  return hipSuccess;
+}
+hipError_t hipGetSymbolAddress(void** ptr, const void* symbol) {
+  *ptr = const_cast<void*>(symbol);
+  return hipSuccess;
+}
 struct emu_event {
   std::chrono::steady_clock::time_point t;
   hipStream_t st = nullptr;  // deferring stream it was recorded on, and its launch count then

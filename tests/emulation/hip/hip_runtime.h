@@ -29,6 +29,9 @@ using std::fmax; using std::floor; using std::ceil; using std::asin; using std::
 #define __restrict__ __restrict
 #define __shared__ static
 #define __launch_bounds__(...)
+#define __align__(n) __attribute__((aligned(n)))
+#define __builtin_nontemporal_load(p) (*(p))
+#define __builtin_nontemporal_store(v, p) (*(p) = (v))
 
 struct dim3 {
   unsigned x = 1, y = 1, z = 1;
@@ -140,6 +143,11 @@ hipError_t hipGraphInstantiate(hipGraphExec_t*, hipGraph_t, void*, char*, size_t
 hipError_t hipGraphDestroy(hipGraph_t);
 hipError_t hipGraphExecDestroy(hipGraphExec_t);
 hipError_t hipGraphLaunch(hipGraphExec_t, hipStream_t);
+hipError_t hipGraphUpload(hipGraphExec_t, hipStream_t);
+hipError_t hipGetDevice(int* device);
+// a device variable's address: in the emulation, its host address
+#define HIP_SYMBOL(sym) ((const void*)&(sym))
+hipError_t hipGetSymbolAddress(void** ptr, const void* symbol);
 hipError_t hipEventCreate(hipEvent_t*);
 hipError_t hipEventCreateWithFlags(hipEvent_t*, unsigned);
 hipError_t hipStreamWaitEvent(hipStream_t, hipEvent_t, unsigned);

@@ -211,7 +211,64 @@ def batch():
     check("batch autotune", True, str(b.launch()))
 
 
+def no_allocation_step():
+    """imb_step_noalloc (per-disk forces in the library-wide array) equals imb_step, twice in a
+    row, the second on a smaller simulation."""
+    for case, steps in ((moving_case(), 3), (overlap_case(True), 2)):
+        a, b = sim_of(case, "f32"), sim_of(case, "f32")
+        a.step(steps)
+        b.step_noalloc(steps)
+        same = np.array_equal(a.populations(), b.populations()) and all(
+            np.array_equal(u, v) for u, v in zip(a.forces() + a.particles(),
+                                                  b.forces() + b.particles()))
+        check("step_noalloc equals step (%s)" % case.name, same, "")
+
+
+def three_d():
+    """D3Q19 with spheres against the 3D oracle: fixed and prescribed spheres across the periodic
+    seams, two spheres sharing cells, walls and periodic y, random populations, every tile width."""
+    from oracle import OracleConfig3, OracleSim3
+    rng = np.random.default_rng(7)
+    cases = [  # nx, ny, nz, walls, tile_w, spheres (x, y, z, r, v, w, mode)
+        (19, 13, 11, True, 16, [(0.4, 6.3, 5.2, 3.1, (0.0, 0.0, 0.0), (0.0, 0.002, 0.0), 1),
+                                (8.7, 6.9, 10.6, 2.6, (0.02, -0.01, 0.005), (0.0, 0.0, 0.0), 2)]),
+        (22, 16, 12, False, 32, [(11.2, 0.5, 4.4, 3.3, (0.01, 0.0, 0.0), (0.001, 0.0, -0.002), 2),
+                                (14.6, 3.8, 4.9, 2.4, (0.0, 0.0, 0.0), (0.0, 0.0, 0.0), 1)]),
+        (70, 12, 11, True, 64, [(35.5, 4.0, 3.5, 2.9, (0.0, 0.0, 0.0), (0.0, 0.0, 0.0), 1)]),
+    ]
+    for nx, ny, nz, walls, tw, sph in cases:
+        f0 = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)[:, None, None, None] * (
+            1.0 + 0.03 * rng.uniform(-1, 1, (19, nz, ny, nx)))
+        x, y, z, r = (np.array([t[k] for t in sph]) for k in range(4))
+        v = np.array([t[4] for t in sph])
+        w = np.array([t[5] for t in sph])
+        mode = np.array([t[6] for t in sph], np.int32)
+        ref = OracleSim3(OracleConfig3(nx=nx, ny=ny, nz=nz, tau0=0.7, walls=walls, gx=2e-5,
+                                       gy=-1e-5, gz=5e-6, eps_subcells=4))
+        ref.set_populations(f0)
+        ref.set_spheres(x, y, z, r, v, w, mode)
+        ref.step(3)
+        for storage, tol in (("f64", 1e-12), ("f32", 1e-4)):
+            cfg = imb.make_config3(nx, ny, nz, 0.7, storage, walls, (2e-5, -1e-5, 5e-6),
+                                   max_spheres=4, eps_subcells=4, tile_w=tw)
+            s = imb.Simulation3(cfg, S, device="cpu")
+            s.set_populations(f0)
+            s.set_spheres(x, y, z, r, v, w, mode)
+            s.step(3)
+            Fg, Tg = s.forces()
+            Fo, To = ref.forces()
+            ferr = max(np.abs(Fg - Fo).max() / np.abs(Fo).max(),
+                       np.abs(Tg - To).max() / np.abs(To).max())
+            perr = np.abs(s.populations() - ref.populations()).max()
+            check("3d %s %dx%dx%d walls=%s tile %d" % (storage, nx, ny, nz, walls, tw),
+                  ferr < tol and perr < (1e-14 if storage == "f64" else 1e-6),
+                  "force %.2e populations %.2e" % (ferr, perr))
+            ok = np.abs(s.spheres()[:, :3] - np.stack(ref.spheres(), 1)).max() < 1e-12
+            check("3d spheres move as prescribed", ok, "")
+
+
 if __name__ == "__main__":
-    for fn in (spring_table_limit, fp64_parity, wide_tiles, reduced_precision, roundtrip, adjoint, batch):
+    for fn in (three_d, no_allocation_step, spring_table_limit, fp64_parity, wide_tiles,
+               reduced_precision, roundtrip, adjoint, batch):
         fn()
     print("all emulated cases passed", flush=True)

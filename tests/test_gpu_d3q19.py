@@ -1,0 +1,151 @@
+"""GPU: the D3Q19 lattice step with spheres (imb3_* through the C-ABI) against the three-dimensional
+FP64 oracle, and the paper's benchmark of Sec. 3.1 (Poiseuille flow past a fixed sphere) against
+the Happel-Brenner estimates and the paper's own Table 3 errors."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import OracleConfig3, OracleSim3
+from paper_1809_07008_amd import happel_brenner as hb
+from paper_1809_07008_amd import imb
+
+pytestmark = pytest.mark.gpu
+
+W3 = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+
+
+def random_f(rng, nx, ny, nz, amp=0.03):
+    return W3[:, None, None, None] * (1.0 + amp * rng.uniform(-1, 1, (19, nz, ny, nx)))
+
+
+def pair(nx, ny, nz, walls, tau, g, n, spheres, storage="f64", tile_w=0, f0=None):
+    x, y, z, r, v, w, mode = spheres
+    ref = OracleSim3(OracleConfig3(nx=nx, ny=ny, nz=nz, tau0=tau, walls=walls, gx=g[0],
+                                   gy=g[1], gz=g[2], eps_subcells=n))
+    sim = imb.Simulation3(imb.make_config3(nx, ny, nz, tau, storage, walls, g,
+                                           max_spheres=max(len(x), 1), eps_subcells=n,
+                                           tile_w=tile_w))
+    if f0 is not None:
+        ref.set_populations(f0)
+        sim.set_populations(f0)
+    ref.set_spheres(x, y, z, r, v, w, mode)
+    sim.set_spheres(x, y, z, r, v, w, mode)
+    return sim, ref
+
+
+def sphere_set(rng, nx, ny, nz, k, rmin, rmax, walls):
+    x = rng.uniform(0, nx, k)
+    z = rng.uniform(0, nz, k)
+    r = rng.uniform(rmin, rmax, k)
+    y = rng.uniform(r + 0.5, ny - r - 1.5) if walls else rng.uniform(0, ny, k)
+    v = rng.normal(0, 0.01, (k, 3))
+    w = rng.normal(0, 0.002, (k, 3))
+    mode = rng.integers(1, 3, k).astype(np.int32)
+    return x, np.atleast_1d(y), z, r, v, w, mode
+
+
+def assert_forces3(sim, ref, tol=1e-12):
+    """Each sphere's force and torque within tol of the oracle's conditioning scales of the sums
+    (sum over the covered cells of |dF|, of |d| |dF|)."""
+    (Fg, Tg), (Fo, To) = sim.forces(), ref.forces()
+    sF, sT = ref.force_scales()
+    ef = (np.abs(Fg - Fo).max(axis=1) / sF).max()
+    et = (np.abs(Tg - To).max(axis=1) / sT).max()
+    print("3d forces: max error / scale %.3e (force) %.3e (torque)" % (ef, et))
+    assert ef <= tol and et <= tol
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_fp64_parity_random_channels(seed):
+    """Ragged lattices, every tile width, walls or periodic y, 1-3 fixed or prescribed spheres
+    (some across the periodic seams), spin, body force in all three axes, random populations."""
+    rng = np.random.default_rng(300 + seed)
+    nx, ny, nz = (int(v) for v in rng.integers(18, 46, 3))
+    walls = seed % 3 != 2
+    tile_w = [0, 16, 32, 64, 16, 32][seed]
+    k = 1 + seed % 3
+    sph = sphere_set(rng, nx, ny, nz, k, 2.0, min(nx, ny, nz) / 2 - 2.6, walls)
+    if seed % 2:
+        sph[0][0] = 0.3  # across the x seam
+    g = tuple(rng.normal(0, 1e-5, 3))
+    f0 = random_f(rng, nx, ny, nz)
+    sim, ref = pair(nx, ny, nz, walls, float(rng.uniform(0.52, 1.0)), g, int(rng.integers(2, 7)),
+                    sph, tile_w=tile_w, f0=f0)
+    assert np.abs(sim.solid_field() - ref.solid_field()).max() == 0.0
+    sim.step(12)
+    ref.step(12)
+    fg, fo = sim.populations(), ref.populations()
+    assert np.abs(fg - fo).max() <= 1e-12 * np.abs(fo).max()
+    assert_forces3(sim, ref)
+    assert np.abs(sim.spheres()[:, :3] - np.stack(ref.spheres(), 1)).max() < 1e-12
+
+
+def test_fp32_against_fp64_oracle():
+    rng = np.random.default_rng(320)
+    nx, ny, nz = 48, 30, 40
+    sph = sphere_set(rng, nx, ny, nz, 2, 5.0, 7.0, True)
+    sim, ref = pair(nx, ny, nz, True, 0.7, (2e-5, 0, 0), 5, sph, storage="f32")
+    sim.step(60)
+    ref.step(60)
+    (Fg, Tg), (Fo, To) = sim.forces(), ref.forces()
+    ferr = np.abs(Fg - Fo).max() / np.abs(Fo).max()
+    _, ux, _, _ = sim.fields()
+    _, uxo, _, _ = ref.fields()
+    uerr = np.abs(ux - uxo).max() / np.abs(uxo).max()
+    print("fp32 3d: force %.2e velocity %.2e" % (ferr, uerr))
+    assert ferr < 1e-4 and uerr < 1e-4
+
+
+def test_plane_poiseuille_fp64_closed_form():
+    """No spheres, walls in y, g along x: the exact discrete profile of the scheme."""
+    ny, tau, g = 12, 0.8, 1e-5
+    sim = imb.Simulation3(imb.make_config3(4, ny, 3, tau, "f64", True, (g, 0, 0), max_spheres=0))
+    nu = (tau - 0.5) / 3
+    sim.step(int(60 * ny * ny / (nu * math.pi ** 2)))
+    rho, ux, uy, uz = sim.fields()
+    prof = hb.poiseuille_profile(ny, tau, g)
+    assert np.abs(rho * ux - prof[None, :, None]).max() < 1e-10 * prof.max()
+    assert np.abs(uy).max() < 1e-10 * prof.max() and np.abs(uz).max() < 1e-10 * prof.max()
+
+
+def test_graph_replay_equals_direct_launches_and_is_deterministic():
+    rng = np.random.default_rng(330)
+    sph = sphere_set(rng, 40, 24, 36, 2, 4.0, 6.0, True)
+    outs = []
+    for timing in (False, True, False):
+        sim = imb.Simulation3(imb.make_config3(40, 24, 36, 0.6, "f32", True, (1e-5, 0, 0),
+                                               max_spheres=2))
+        sim.set_spheres(*sph)
+        sim.set_kernel_timing(timing)  # timing launches every kernel directly
+        sim.step(70)
+        outs.append((sim.populations(), sim.forces()))
+    for a in outs[1:]:
+        assert np.array_equal(a[0], outs[0][0])
+        for u, v in zip(a[1], outs[0][1]):
+            assert np.array_equal(u, v)
+
+
+def test_set_spheres_rejects_out_of_range():
+    sim = imb.Simulation3(imb.make_config3(30, 20, 30, 0.7, "f32", True, max_spheres=1))
+    with pytest.raises(imb.ImbError):
+        sim.set_spheres([15.0], [10.0], [15.0], [9.0])       # 2 (r + 2) >= ny
+    with pytest.raises(imb.ImbError):
+        sim.set_spheres([15.0], [-0.6], [15.0], [3.0])       # centre beyond the wall
+    with pytest.raises(imb.ImbError):
+        sim.set_spheres([15.0, 5.0], [10.0] * 2, [15.0] * 2, [3.0] * 2)  # over capacity
+
+
+@pytest.mark.parametrize("N", [5, 10])
+def test_happel_brenner_benchmark(N):
+    """Sec. 3.1: N cells per diameter, tau = 1, the paper's n_sub = 5; after eight e-folding times
+    of the channel the force and torque have converged, and their errors against Eqs. (18), (19)
+    are those of the method at this resolution: the paper's Table 3 gives 17.8 % / 31.4 %
+    (N = 5) and 7.0 % / 11.3 % (N = 10)."""
+    res = hb.run(N, 1.0, 5, "f32", efolds=8.0, log=print)
+    print(res)
+    assert res["last_change_F"] < 1e-4
+    assert abs(res["lift_over_drag"]) < 0.1 and abs(res["side_over_drag"]) < 1e-5
+    assert res["Fx_over_HB"] < 1.0 and res["Tz_over_HB"] < 1.0  # transparent-particle underestimate
+    assert abs(res["err_F_percent"] - res["paper_err_F_percent"]) < 3.0
+    assert abs(res["err_T_percent"] - res["paper_err_T_percent"]) < 6.0

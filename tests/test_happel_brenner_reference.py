@@ -1,0 +1,59 @@
+"""The benchmark's analytic reference (Eqs. 18, 19 of the paper with the reading q = R / h and U
+the undisturbed velocity at the sphere centre) against the values the paper prints for it (Table
+3 caption), and the table as transcribed in the benchmark module against its own error columns.
+CPU only."""
+import os
+
+import pytest
+
+from paper_1809_07008_amd import happel_brenner as hb
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "happel_brenner_table3.txt")
+
+
+def _golden():
+    vals, rows = {}, []
+    for line in open(GOLDEN):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        parts = line.split()
+        if parts[0] == "row":
+            rows.append(tuple(float(v) for v in parts[1:]))
+        else:
+            vals[parts[0]] = float(parts[1])
+    return vals, rows
+
+
+def test_reference_reproduces_the_table3_caption():
+    vals, _ = _golden()
+    F, T = hb.physical_reference()
+    assert abs(F - vals["F_analytic_N"]) <= 5e-5 * vals["F_analytic_N"]
+    assert abs(T - vals["T_analytic_Nm"]) <= 5e-5 * vals["T_analytic_Nm"]
+
+
+def test_reading_of_the_wall_distance():
+    """With q = R / l_y (the printed symbol taken literally) the caption's values are not
+    reproduced; with q = R / h they are (the reading the benchmark uses)."""
+    vals, _ = _golden()
+    U = hb.G_PHYS / (2 * hb.MU_PHYS) * hb.H_PHYS * (hb.LY_PHYS - hb.H_PHYS)
+    F_lit, _ = hb.happel_brenner(hb.R_PHYS, hb.LY_PHYS, hb.MU_PHYS, U)
+    assert abs(F_lit - vals["F_analytic_N"]) > 0.1 * vals["F_analytic_N"]
+
+
+def test_table3_transcription_matches_its_error_columns():
+    vals, rows = _golden()
+    assert [tuple(r) for r in rows] == [tuple(float(v) for v in r) for r in hb.TABLE3]
+    for N, nsub, tau, F, T, eF, eT in rows:
+        assert abs(abs(vals["F_analytic_N"] - F * 1e-12) / vals["F_analytic_N"] * 100 - eF) < 2e-3
+        assert abs(abs(vals["T_analytic_Nm"] - T * 1e-16) / vals["T_analytic_Nm"] * 100 - eT) < 2e-3
+
+
+@pytest.mark.parametrize("N,tau", [(5, 1.0), (20, 0.53)])
+def test_lattice_setup_is_the_paper_geometry(N, tau):
+    s = hb.Setup(N, tau)
+    assert (s.nx, s.ny, s.nz) == (20 * N, 5 * N, 20 * N)
+    assert s.R / s.h == pytest.approx(0.4) and s.ly / (2 * s.R) == pytest.approx(5.0)
+    # the lower wall sits at y = -1/2: the centre is h above it
+    assert s.centre[1] + 0.5 == pytest.approx(s.h)
+    assert s.U == pytest.approx(1e-5)
