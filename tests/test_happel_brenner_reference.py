@@ -56,4 +56,4 @@ def test_lattice_setup_is_the_paper_geometry(N, tau):
     assert s.R / s.h == pytest.approx(0.4) and s.ly / (2 * s.R) == pytest.approx(5.0)
     # the lower wall sits at y = -1/2: the centre is h above it
     assert s.centre[1] + 0.5 == pytest.approx(s.h)
-    assert s.U == pytest.approx(1e-5)
+    assert s.U * 2 * s.R / s.nu == pytest.approx(1e-3)
