@@ -23,7 +23,8 @@
  *   Eqs. (15), (16)      hydrodynamic force and torque; the printed sum is the momentum the fluid
  *                         gains, so the force on the particle is its negative.
  *   Eqs. (7), (8)        DEM overlap and normal spring-dashpot force; with kt, mu a tangential
- *                        spring-dashpot with a Coulomb limit (contact_forces, tangential).
+ *                        spring-dashpot with a Coulomb limit (contact_forces, tangential); or the
+ *                        simplified Hertz-Mindlin law Sec. 2.1 adopts (normal_law).
  *   Eqs. (10), (11), (17) Newton's equations integrated by velocity Verlet with N_sub sub-cycles per
  *                         lattice step, the hydrodynamic force and torque held fixed (Sec. 2.3).
  *   Sec. 3.3.2           Smagorinsky sub-grid model (closed form of the Hou et al. model, see
@@ -82,6 +83,9 @@ typedef struct {
   double uw_bot, uw_top; /* x-velocity of the wall at y = -1/2 and of the wall at y = ny - 1/2 */
   double kt;      /* tangential contact stiffness (0 with mu = 0: normal force only) */
   double mu;      /* Coulomb friction coefficient of the tangential contact force */
+  int32_t contact_model; /* 0: linear spring-dashpot (kn, kt); 1: Hertz-Mindlin (young, poisson) */
+  double young;   /* Young's modulus of the disks (Hertz-Mindlin) */
+  double poisson; /* Poisson's ratio of the disks (Hertz-Mindlin) */
 } ocfg;
 
 typedef struct {
@@ -313,7 +317,8 @@ void o_destroy(osim *s);
 
 osim *o_create(const ocfg *c) {
   if (!c || c->nx < 2 || c->ny < 2 || !(c->tau0 > 0.5) || c->cs < 0.0 || c->n_sub < 1 ||
-      !(c->kt >= 0.0) || !(c->mu >= 0.0) ||
+      !(c->kt >= 0.0) || !(c->mu >= 0.0) || c->contact_model < 0 || c->contact_model > 1 ||
+      (c->contact_model == 1 && (!(c->young > 0.0) || !(c->poisson >= 0.0 && c->poisson < 0.5))) ||
       c->eps_subcells < 0 || (!c->walls && (c->uw_bot != 0.0 || c->uw_top != 0.0)))
     return NULL;
   osim *s = (osim *)calloc(1, sizeof(osim));
@@ -446,12 +451,11 @@ static double nearest_image(double d, int n) {
  * |F_t| <= mu max(F_n, 0), where sliding resets s = -F_t / k_t; the force F_t t acts on i with
  * torque l_i F_t.  A wall is a partner at rest in y moving along x at its wall velocity.  A
  * contact that has ended leaves s = 0. */
-static double tangential(const osim *s, double *spring, double vt, double fn, double meff,
-                         int advance) {
-  double kt = s->c.kt, mu = s->c.mu;
+static double tangential(const osim *s, double *spring, double vt, double fn, double kt,
+                         double ct, int advance) {
+  double mu = s->c.mu;
   double dt = 1.0 / s->c.n_sub;
   double sp = advance ? *spring + vt * dt : *spring;
-  double ct = 2.0 * s->c.zeta * sqrt(kt * meff);
   double ft = -kt * sp - ct * vt;
   double cap = mu * (fn > 0.0 ? fn : 0.0);
   if (fabs(ft) > cap) {
@@ -462,10 +466,42 @@ static double tangential(const osim *s, double *spring, double vt, double fn, do
   return ft;
 }
 
+/* The contact law of one contact of overlap delta (> 0), effective radius rstar and mass meff,
+ * with a partner that is another disk (wall = 0) or a wall (wall = 1): the normal force
+ * k delta + c v_n and the tangential stiffness and damping.
+ *   linear (Eq. 8 with constant coefficients): k = k_n, c = 2 zeta sqrt(k_n m_eff);
+ *     tangential k_t and c_t = 2 zeta sqrt(k_t m_eff).
+ *   Hertz-Mindlin, the simplified form the paper adopts (Sec. 2.1, after Di Renzo & Di Maio):
+ *     normal stiffness S_n = 2 E* sqrt(R* delta), elastic force (4/3) E* sqrt(R*) delta^(3/2)
+ *     (= S_n delta * 2/3), damping c_n = 2 sqrt(5/6) zeta sqrt(S_n m_eff);
+ *     tangential stiffness S_t = 8 G* sqrt(R* delta), c_t = 2 sqrt(5/6) zeta sqrt(S_t m_eff);
+ *     two disks of the same material: 1/E* = 2 (1 - nu^2) / E, 1/G* = 2 (2 - nu) / G with
+ *     G = E / (2 (1 + nu)); against a rigid wall 1/E* = (1 - nu^2) / E, 1/G* = (2 - nu) / G.
+ * Returns the normal force; *kt, *ct receive the tangential coefficients. */
+static double normal_law(const osim *s, double delta, double vn, double rstar, double meff,
+                         int wall, double *kt, double *ct) {
+  double zeta = s->c.zeta;
+  if (s->c.contact_model == 1) {
+    double E = s->c.young, nu = s->c.poisson;
+    double G = E / (2.0 * (1.0 + nu));
+    double Es = wall ? E / (1.0 - nu * nu) : E / (2.0 * (1.0 - nu * nu));
+    double Gs = wall ? G / (2.0 - nu) : G / (2.0 * (2.0 - nu));
+    double root = sqrt(rstar * delta);
+    double Sn = 2.0 * Es * root;
+    double St = 8.0 * Gs * root;
+    double damp = 2.0 * sqrt(5.0 / 6.0) * zeta;
+    *kt = St;
+    *ct = damp * sqrt(St * meff);
+    return 4.0 / 3.0 * Es * root * delta + damp * sqrt(Sn * meff) * vn;
+  }
+  *kt = s->c.kt;
+  *ct = 2.0 * zeta * sqrt(s->c.kt * meff);
+  return s->c.kn * delta + 2.0 * zeta * sqrt(s->c.kn * meff) * vn;
+}
+
 static void contact_forces(osim *s, int advance) {
   int np = s->np;
-  double kn = s->c.kn, zeta = s->c.zeta;
-  int tang = s->c.kt > 0.0 || s->c.mu > 0.0;
+  int tang = s->c.contact_model == 1 ? s->c.mu > 0.0 : (s->c.kt > 0.0 || s->c.mu > 0.0);
   for (int i = 0; i < np; ++i) {
     double fx = 0.0, fy = 0.0, tz = 0.0;
     if (s->mode[i] == 0) {
@@ -483,8 +519,9 @@ static void contact_forces(osim *s, int advance) {
           double vn = (s->vx[i] - s->vx[j]) * nxu + (s->vy[i] - s->vy[j]) * nyu;
           double mj = disk_mass(s, j);
           double meff = mi * mj / (mi + mj);
-          double cn = 2.0 * zeta * sqrt(kn * meff);
-          double fn = kn * delta + cn * vn;
+          double rstar = s->r[i] * s->r[j] / (s->r[i] + s->r[j]);
+          double kt, ct;
+          double fn = normal_law(s, delta, vn, rstar, meff, 0, &kt, &ct);
           fx += -fn * nxu;
           fy += -fn * nyu;
           if (tang) {
@@ -492,7 +529,7 @@ static void contact_forces(osim *s, int advance) {
             double li = s->r[i] - 0.5 * delta, lj = s->r[j] - 0.5 * delta;
             double vt = (s->vx[i] - s->vx[j]) * tx + (s->vy[i] - s->vy[j]) * ty +
                         s->om[i] * li + s->om[j] * lj;
-            double ft = tangential(s, &s->ht[(size_t)i * np + j], vt, fn, meff, advance);
+            double ft = tangential(s, &s->ht[(size_t)i * np + j], vt, fn, kt, ct, advance);
             fx += ft * tx;
             fy += ft * ty;
             tz += li * ft;
@@ -502,16 +539,16 @@ static void contact_forces(osim *s, int advance) {
         }
       }
       if (s->c.walls) {
-        double cn = 2.0 * zeta * sqrt(kn * mi);
         double db = s->r[i] - (s->y[i] + 0.5); /* wall at y = -1/2, n = (0,-1), t = (1,0) */
         if (db > 0.0) {
           double vn = -s->vy[i];
-          double fn = kn * db + cn * vn;
+          double kt, ct;
+          double fn = normal_law(s, db, vn, s->r[i], mi, 1, &kt, &ct);
           fy += fn;
           if (tang) {
             double l = s->r[i] - 0.5 * db;
             double vt = (s->vx[i] - s->c.uw_bot) + s->om[i] * l;
-            double ft = tangential(s, &s->hwb[i], vt, fn, mi, advance);
+            double ft = tangential(s, &s->hwb[i], vt, fn, kt, ct, advance);
             fx += ft;
             tz += l * ft;
           }
@@ -521,12 +558,13 @@ static void contact_forces(osim *s, int advance) {
         double dt = s->r[i] - ((s->c.ny - 0.5) - s->y[i]); /* wall at y = ny-1/2, n = (0,1) */
         if (dt > 0.0) {
           double vn = s->vy[i];
-          double fn = kn * dt + cn * vn;
+          double kt, ct;
+          double fn = normal_law(s, dt, vn, s->r[i], mi, 1, &kt, &ct);
           fy += -fn;
           if (tang) { /* t = (-1, 0) */
             double l = s->r[i] - 0.5 * dt;
             double vt = -(s->vx[i] - s->c.uw_top) + s->om[i] * l;
-            double ft = tangential(s, &s->hwt[i], vt, fn, mi, advance);
+            double ft = tangential(s, &s->hwt[i], vt, fn, kt, ct, advance);
             fx += -ft;
             tz += l * ft;
           }

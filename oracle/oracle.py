@@ -39,7 +39,8 @@ class _Cfg(C.Structure):
                 ("gx", C.c_double), ("gy", C.c_double), ("rho0", C.c_double),
                 ("kn", C.c_double), ("zeta", C.c_double), ("rho_s", C.c_double),
                 ("eps_subcells", C.c_int32), ("uw_bot", C.c_double), ("uw_top", C.c_double),
-                ("kt", C.c_double), ("mu", C.c_double)]
+                ("kt", C.c_double), ("mu", C.c_double), ("contact_model", C.c_int32),
+                ("young", C.c_double), ("poisson", C.c_double)]
 
 
 class _Cfg3(C.Structure):
@@ -182,6 +183,9 @@ class OracleConfig:
     uw_top: float = 0.0         # x-velocity of the top wall (y = ny - 1/2), walls only
     kt: float = 0.0             # tangential contact stiffness
     mu: float = 0.0             # Coulomb friction coefficient
+    contact_model: int = 0      # 0 linear spring-dashpot, 1 Hertz-Mindlin
+    young: float = 0.0          # Young's modulus (Hertz-Mindlin)
+    poisson: float = 0.0        # Poisson's ratio (Hertz-Mindlin)
 
 
 class OracleSim:
@@ -192,7 +196,8 @@ class OracleSim:
         self.cfg = cfg
         c = _Cfg(cfg.nx, cfg.ny, 1 if cfg.walls else 0, cfg.n_sub, cfg.tau0, cfg.cs, cfg.gx,
                  cfg.gy, cfg.rho0, cfg.kn, cfg.zeta, cfg.rho_s, cfg.eps_subcells,
-                 cfg.uw_bot, cfg.uw_top, cfg.kt, cfg.mu)
+                 cfg.uw_bot, cfg.uw_top, cfg.kt, cfg.mu, cfg.contact_model, cfg.young,
+                 cfg.poisson)
         self._h = lib.o_create(C.byref(c))
         if not self._h:
             raise ValueError("oracle: invalid configuration %r" % (cfg,))

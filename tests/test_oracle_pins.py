@@ -830,3 +830,116 @@ def test_single_disk_channel_conditioning_of_the_forces():
     print("one-ulp radius change: drag %.2e, lift %.2e of the force scale" % (dfx, dfy))
     assert 1e-14 < dfx < 1e-11
     assert dfy < 1e-11
+
+
+# ---- the simplified Hertz-Mindlin contact law (Sec. 2.1 adopts it after Di Renzo & Di Maio)
+
+def _hertz_pair(v0, zeta, E=10.0, nu=0.3, n_sub=200, mu=0.0):
+    s = OracleSim(OracleConfig(nx=200, ny=100, tau0=0.7, walls=False, n_sub=n_sub, zeta=zeta,
+                               contact_model=1, young=E, poisson=nu, mu=mu))
+    s.set_particles([80.0, 100.5], [50.0, 50.0], [10.0, 10.0], [v0, -v0], [0.0, 0.0],
+                    [0.0, 0.0], [W.MODE_FREE, W.MODE_FREE])
+    return s
+
+
+def _collide_and_time(s, gap0, v_rel, steps):
+    """Runs the head-on pair through its contact; returns (contact duration, rebound speed):
+    the contact starts at gap0 / v_rel exactly (free flight), and its end is extrapolated back
+    from the free flight after it."""
+    for _ in range(steps):
+        s.dem_steps(1)
+    x, y, vx, vy, om = s.particles()
+    v_out = vx[1] - vx[0]
+    gap = (x[1] - x[0]) - 20.0
+    t_end = steps - gap / v_out
+    return t_end - gap0 / v_rel, v_out
+
+
+def test_hertz_impact_duration_and_elastic_rebound():
+    """Undamped Hertzian impact (F = 4/3 E* sqrt(R*) d^(3/2), E* = E / (2 (1 - nu^2)) for two
+    disks of one material, R* = r/2, m* = m/2): the rebound speed equals the approach speed, and
+    the contact lasts t_c = (2 d_max / v) * (2/5) B(2/5, 1/2) with the largest overlap
+    d_max = (15 m* v^2 / (16 E* sqrt(R*)))^(2/5) (Hertz: energy and the force law alone)."""
+    from scipy.special import beta
+    E, nu, r = 10.0, 0.3, 10.0
+    Es = E / (2 * (1 - nu * nu))
+    m = math.pi * r * r
+    mstar, rstar = m / 2, r / 2
+    for v0 in (0.01, 0.02):
+        v = 2 * v0
+        dmax = (15 * mstar * v * v / (16 * Es * math.sqrt(rstar))) ** 0.4
+        tc = 2 * dmax / v * 0.4 * beta(0.4, 0.5)
+        s = _hertz_pair(v0, 0.0, E, nu)
+        t, v_out = _collide_and_time(s, 0.5, v, int(0.5 / v + tc) + 5)
+        assert abs(v_out / v - 1.0) < 1e-4, (v0, v_out / v)
+        assert abs(t / tc - 1.0) < 2e-3, (v0, t, tc)
+        x, y, vx, vy, om = s.particles()
+        assert abs(m * vx.sum()) < 1e-14  # momentum
+
+
+def test_hertz_damped_restitution_is_independent_of_impact_speed():
+    """With the damping 2 sqrt(5/6) zeta sqrt(S_n m*) and S_n = 2 E* sqrt(R* d) the equation of
+    a head-on impact has no scale: the restitution coefficient depends on zeta alone, not on the
+    impact speed, and falls as zeta grows."""
+    es = {}
+    for zeta in (0.1, 0.3):
+        for v0 in (0.005, 0.02):
+            v = 2 * v0
+            s = _hertz_pair(v0, zeta)
+            _, v_out = _collide_and_time(s, 0.5, v, int(0.5 / v) + 40)
+            es[zeta, v0] = v_out / v
+    assert abs(es[0.1, 0.005] - es[0.1, 0.02]) < 1e-3
+    assert abs(es[0.3, 0.005] - es[0.3, 0.02]) < 1e-3
+    assert 0 < es[0.3, 0.02] < es[0.1, 0.02] < 1
+
+
+def test_hertz_wall_impact():
+    """A disk striking the wall at y = -1/2: the wall is rigid, E* = E / (1 - nu^2), R* = r,
+    m* = m; undamped, it leaves at its impact speed after t_c of the same closed form."""
+    from scipy.special import beta
+    E, nu, r, v = 10.0, 0.25, 6.0, 0.03
+    s = OracleSim(OracleConfig(nx=100, ny=80, tau0=0.7, n_sub=200, zeta=0.0, contact_model=1,
+                               young=E, poisson=nu))
+    s.set_particles([50.0], [r - 0.5 + 0.3], [r], [0.0], [-v], [0.0], [W.MODE_FREE])
+    Es = E / (1 - nu * nu)
+    m = math.pi * r * r
+    dmax = (15 * m * v * v / (16 * Es * math.sqrt(r))) ** 0.4
+    tc = 2 * dmax / v * 0.4 * beta(0.4, 0.5)
+    steps = int(0.3 / v + tc) + 5
+    s.dem_steps(steps)
+    x, y, vx, vy, om = (a[0] for a in s.particles())
+    gap = y - (r - 0.5)
+    t_end = steps - gap / vy
+    assert abs(vy / v - 1.0) < 1e-4
+    assert abs((t_end - 0.3 / v) / tc - 1.0) < 2e-3
+
+
+def test_hertz_mindlin_sliding_disk_obeys_coulomb_then_rolls():
+    """The Mindlin tangential spring S_t = 8 G* sqrt(R* d) with the Coulomb limit: while the
+    pressed disk slides the friction is mu times the normal force, and it ends rolling at
+    2 v0 / 3 (angular momentum about the contact point, whatever the tangential law)."""
+    r, F, v0, mu = 5.0, 1.0, 0.05, 0.2
+    s = OracleSim(OracleConfig(nx=400, ny=40, tau0=0.7, zeta=0.1, n_sub=40, mu=mu,
+                               contact_model=1, young=200.0, poisson=0.3))
+    Es = 200.0 / (1 - 0.09)
+    delta0 = (F / (4 / 3 * Es * math.sqrt(r))) ** (2 / 3)
+    s.set_particles([50.0], [r - 0.5 - delta0], [r], [v0], [0.0], [0.0], [W.MODE_FREE])
+    s.set_loads([0.0], [-F], [0.0])
+    fcy0 = s.contacts()[1][0]
+    assert fcy0 == pytest.approx(F, rel=1e-12)  # the static Hertz overlap carries the load
+    sliding = 0
+    for _ in range(6):
+        s.dem_steps(1)
+        fcx, fcy, tcz = (a[0] for a in s.contacts())
+        x, y, vx, vy, om = (a[0] for a in s.particles())
+        if vx + om * r > 1e-3:
+            assert abs(fcx) == pytest.approx(mu * fcy, rel=1e-14, abs=0.0) and fcx < 0.0
+            sliding += 1
+    assert sliding >= 4
+    s.dem_steps(600)
+    x, y, vx, vy, om = (a[0] for a in s.particles())
+    m = np.pi * r * r
+    I = 0.5 * m * r * r
+    l = r - 0.5 * delta0
+    assert vx == pytest.approx(v0 / (1.0 + I / (m * l * l)), rel=3e-3)
+    assert abs(vx + om * l) <= 2e-3 * v0
