@@ -94,7 +94,24 @@ typedef struct imb_config {
                               state.  imb_adjoint rejects kt or mu > 0.  Finite, >= 0. */
   double mu;               /* Coulomb limit |F_t| <= mu max(F_n, 0); a sliding contact resets
                               s = -F_t / kt.  Finite, >= 0. */
+  int32_t contact_model;   /* IMB_CONTACT_LINEAR (kn, kt above) or IMB_CONTACT_HERTZ_MINDLIN:
+                              the simplified Hertz-Mindlin law Sec. 2.1 adopts, taken for the
+                              disks as for spheres: normal force 4/3 E* sqrt(R*) d^(3/2) +
+                              2 sqrt(5/6) zeta sqrt(S_n m*) v_n, S_n = 2 E* sqrt(R* d); with
+                              mu > 0 the Mindlin spring S_t = 8 G* sqrt(R* d), damping
+                              2 sqrt(5/6) zeta sqrt(S_t m*), and the Coulomb limit;
+                              R* = r_a r_b / (r_a + r_b) (wall: r); disks of one material:
+                              E* = young / (2 (1 - poisson^2)), G* = G / (2 (2 - poisson)),
+                              G = young / (2 (1 + poisson)); a rigid wall: E* = young /
+                              (1 - poisson^2), G* = G / (2 - poisson).  kn and kt are then
+                              unused. */
+  int32_t reserved2;       /* must be 0 */
+  double young;            /* Young's modulus (Hertz-Mindlin), > 0 */
+  double poisson;          /* Poisson's ratio (Hertz-Mindlin), 0 <= poisson < 1/2 */
 } imb_config;
+
+#define IMB_CONTACT_LINEAR 0
+#define IMB_CONTACT_HERTZ_MINDLIN 1
 
 typedef struct imb_sim imb_sim;
 

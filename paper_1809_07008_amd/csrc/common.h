@@ -142,6 +142,10 @@ struct ParticleArgs {
   int np, nx, ny, walls, n_sub;
   double kn, zeta, rho_s;
   double kt, mu;          // tangential stiffness and friction (both 0: normal force only)
+  int hertz;              // 1: Hertz-Mindlin law (kn, kt unused), 0: linear spring-dashpot
+  double es_pp, es_pw;    // Hertz-Mindlin E* of a disk pair and of a disk against a wall
+  double gs_pp, gs_pw;    //   and G*
+  double hm_damp;         //   2 sqrt(5/6) zeta
   double uw_bot, uw_top;  // wall velocities along x (the walls' tangential slip)
   int tiles_x, tiles_y, tw, th;
   ParticleState s;

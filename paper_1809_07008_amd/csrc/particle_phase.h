@@ -29,23 +29,40 @@ namespace imb {
 constexpr int PP_DOUBLES = 7;  // LDS doubles per disk: x, y, vx, vy, r, the step's reach, spin
 
 // Tangential contact force (2D Cundall-Strack, with a Coulomb limit): the spring s of the contact
-// grows by the slip v_t over one sub-step when `advance`; F_t = -k_t s - c_t v_t with
-// c_t = 2 zeta sqrt(k_t m_eff), limited to mu max(F_n, 0), a sliding contact resetting the spring
-// to -F_t / k_t.  Returns F_t (along t = (-n_y, n_x) of the disk's own normal n).
+// grows by the slip v_t over one sub-step when `advance`; F_t = -k_t s - c_t v_t with the
+// contact law's tangential stiffness k_t and damping c_t (contact_law), limited to
+// mu max(F_n, 0), a sliding contact resetting the spring to -F_t / k_t.  Returns F_t (along
+// t = (-n_y, n_x) of the disk's own normal n).
 __device__ inline double tangential_force(const ParticleArgs& a, double* spring, double vt,
-                                          double fn, double meff, bool advance) {
+                                          double fn, double kt, double ct, bool advance) {
 #pragma clang fp contract(off)
   const double dt = 1.0 / a.n_sub;
   double sp = advance ? *spring + vt * dt : *spring;
-  const double ct = 2.0 * a.zeta * sqrt(a.kt * meff);
-  double ft = -a.kt * sp - ct * vt;
+  double ft = -kt * sp - ct * vt;
   const double cap = a.mu * (fn > 0.0 ? fn : 0.0);
   if (fabs(ft) > cap) {
     ft = ft > 0.0 ? cap : -cap;
-    sp = a.kt > 0.0 ? -ft / a.kt : 0.0;
+    sp = kt > 0.0 ? -ft / kt : 0.0;
   }
   *spring = sp;
   return ft;
+}
+
+// The simplified Hertz-Mindlin law (Sec. 2.1 adopts it, after Di Renzo & Di Maio) of a contact
+// of overlap delta > 0, effective radius rstar and mass meff, against another disk (E* = es,
+// G* = gs of the pair) or a rigid wall: returns the normal force
+// 4/3 E* sqrt(R*) delta^(3/2) + 2 sqrt(5/6) zeta sqrt(S_n m*) v_n with S_n = 2 E* sqrt(R* delta),
+// and the tangential stiffness S_t = 8 G* sqrt(R* delta) and damping 2 sqrt(5/6) zeta
+// sqrt(S_t m*) of the Mindlin spring.
+__device__ inline double hertz_law(const ParticleArgs& a, double delta, double vn, double rstar,
+                                   double meff, double es, double gs, double* kt, double* ct) {
+#pragma clang fp contract(off)
+  const double root = sqrt(rstar * delta);
+  const double Sn = 2.0 * es * root;
+  const double St = 8.0 * gs * root;
+  *kt = St;
+  *ct = a.hm_damp * sqrt(St * meff);
+  return 4.0 / 3.0 * es * root * delta + a.hm_damp * sqrt(Sn * meff) * vn;
 }
 
 __device__ inline double nearest_image(double d, int n) {
@@ -192,7 +209,7 @@ __device__ __attribute__((always_inline)) void particle_phase(const ParticleArgs
   // the step's reach of each disk (the classification below), published with the mirror
   double* sB = sr + np;
   double* som = sB + np;  // spins, for the partners' slip in tangential contacts
-  const bool tang = a.kt > 0.0 || a.mu > 0.0;
+  const bool tang = a.hertz ? a.mu > 0.0 : (a.kt > 0.0 || a.mu > 0.0);
   double Bq = 0.0;
   if (own && a.do_dem) {
     const double qax = (0.0 + Fx) / m_p, qay = (0.0 + Fy) / m_p;
@@ -278,8 +295,16 @@ __device__ __attribute__((always_inline)) void particle_phase(const ParticleArgs
           const double vn = (pvx - svx[j]) * nxu + (pvy - svy[j]) * nyu;
           const double mj = a.rho_s * M_PI * sr[j] * sr[j];
           const double meff = mi * mj / (mi + mj);
-          const double cn = 2.0 * zeta * sqrt(kn * meff);
-          const double fn = kn * delta + cn * vn;
+          double fn, kt_c, ct_c;
+          if (a.hertz) {
+            const double rstar = r * sr[j] / (r + sr[j]);
+            fn = hertz_law(a, delta, vn, rstar, meff, a.es_pp, a.gs_pp, &kt_c, &ct_c);
+          } else {
+            const double cn = 2.0 * zeta * sqrt(kn * meff);
+            fn = kn * delta + cn * vn;
+            kt_c = a.kt;
+            ct_c = 2.0 * zeta * sqrt(a.kt * meff);
+          }
           fx += -fn * nxu;
           fy += -fn * nyu;
           if (tang) {
@@ -288,7 +313,7 @@ __device__ __attribute__((always_inline)) void particle_phase(const ParticleArgs
             const double vt = (pvx - svx[j]) * tx + (pvy - svy[j]) * ty + pom * li + som[j] * lj;
             int k = find(j + 1);
             double sp = k >= 0 ? hsp[k] : 0.0;
-            const double ft = tangential_force(a, &sp, vt, fn, meff, advance);
+            const double ft = tangential_force(a, &sp, vt, fn, kt_c, ct_c, advance);
             fx += ft * tx;
             fy += ft * ty;
             tz += li * ft;
@@ -331,12 +356,19 @@ __device__ __attribute__((always_inline)) void particle_phase(const ParticleArgs
       const double db = r - (py + 0.5);  // wall at y = -1/2: n = (0, -1), t = (1, 0)
       if (db > 0.0) {
         const double vn = -pvy;
-        const double fn = kn * db + cn * vn;
+        double fn, kt_c, ct_c;
+        if (a.hertz) {
+          fn = hertz_law(a, db, vn, r, mi, a.es_pw, a.gs_pw, &kt_c, &ct_c);
+        } else {
+          fn = kn * db + cn * vn;
+          kt_c = a.kt;
+          ct_c = 2.0 * zeta * sqrt(a.kt * mi);
+        }
         fy += fn;
         if (tang) {
           const double l = r - 0.5 * db;
           const double vt = (pvx - a.uw_bot) + pom * l;
-          const double ft = tangential_force(a, &hw[0], vt, fn, mi, advance);
+          const double ft = tangential_force(a, &hw[0], vt, fn, kt_c, ct_c, advance);
           fx += ft;
           tz += l * ft;
         }
@@ -346,12 +378,19 @@ __device__ __attribute__((always_inline)) void particle_phase(const ParticleArgs
       const double dt = r - ((a.ny - 0.5) - py);  // wall at y = ny - 1/2: n = (0, 1), t = (-1, 0)
       if (dt > 0.0) {
         const double vn = pvy;
-        const double fn = kn * dt + cn * vn;
+        double fn, kt_c, ct_c;
+        if (a.hertz) {
+          fn = hertz_law(a, dt, vn, r, mi, a.es_pw, a.gs_pw, &kt_c, &ct_c);
+        } else {
+          fn = kn * dt + cn * vn;
+          kt_c = a.kt;
+          ct_c = 2.0 * zeta * sqrt(a.kt * mi);
+        }
         fy += -fn;
         if (tang) {
           const double l = r - 0.5 * dt;
           const double vt = -(pvx - a.uw_top) + pom * l;
-          const double ft = tangential_force(a, &hw[1], vt, fn, mi, advance);
+          const double ft = tangential_force(a, &hw[1], vt, fn, kt_c, ct_c, advance);
           fx += -ft;
           tz += l * ft;
         }

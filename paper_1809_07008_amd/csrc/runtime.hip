@@ -110,6 +110,12 @@ int validate_config(const imb_config* c, std::string* why) {
   if (!(c->kt >= 0.0 && c->kt < 1e300) || !(c->mu >= 0.0 && c->mu < 1e300))
     return bad("kt and mu must be finite and >= 0");
   if (c->n_sub < 1 || c->n_sub > 100000) return bad("n_sub must be in 1..100000");
+  if (c->contact_model != IMB_CONTACT_LINEAR && c->contact_model != IMB_CONTACT_HERTZ_MINDLIN)
+    return bad("unknown contact_model");
+  if (c->contact_model == IMB_CONTACT_HERTZ_MINDLIN &&
+      (!(c->young > 0.0 && c->young < 1e300) || !(c->poisson >= 0.0 && c->poisson < 0.5)))
+    return bad("Hertz-Mindlin needs young > 0 and 0 <= poisson < 0.5");
+  if (c->reserved2 != 0) return bad("reserved2 must be 0");
   if (!(c->rho0 > 0.0)) return bad("rho0 must be positive");
   if (!(c->kn >= 0.0) || !(c->damping_ratio >= 0.0) || !(c->rho_solid > 0.0))
     return bad("DEM parameters out of range");
@@ -227,6 +233,16 @@ ParticleArgs particle_args(imb_sim* s, int out_slot) {
   a.n_sub = s->cfg.n_sub; a.kn = s->cfg.kn; a.zeta = s->cfg.damping_ratio;
   a.rho_s = s->cfg.rho_solid;
   a.kt = s->cfg.kt; a.mu = s->cfg.mu;
+  a.hertz = s->cfg.contact_model == IMB_CONTACT_HERTZ_MINDLIN ? 1 : 0;
+  if (a.hertz) {  // evaluated as the simplified Hertz-Mindlin law defines them
+    const double E = s->cfg.young, nu = s->cfg.poisson;
+    const double G = E / (2.0 * (1.0 + nu));
+    a.es_pp = E / (2.0 * (1.0 - nu * nu));
+    a.es_pw = E / (1.0 - nu * nu);
+    a.gs_pp = G / (2.0 * (2.0 - nu));
+    a.gs_pw = G / (2.0 - nu);
+    a.hm_damp = 2.0 * sqrt(5.0 / 6.0) * s->cfg.damping_ratio;
+  }
   a.uw_bot = s->cfg.wall_ux_bottom; a.uw_top = s->cfg.wall_ux_top;
   a.tiles_x = s->g.tiles_x; a.tiles_y = s->g.tiles_y; a.tw = s->g.tw; a.th = s->g.th;
   a.s = s->d.ps; a.tab = s->d.tab[out_slot]; a.err = s->d.err;
@@ -480,6 +496,7 @@ void imb_config_default(imb_config* c) {
   c->flags = IMB_FLAG_WALLS; c->tile_w = 64; c->tile_rows = 1;
   c->eps_subcells = 0; c->reserved = 0; c->wall_ux_bottom = 0.0; c->wall_ux_top = 0.0;
   c->kt = 0.0; c->mu = 0.0;
+  c->contact_model = IMB_CONTACT_LINEAR; c->reserved2 = 0; c->young = 0.0; c->poisson = 0.0;
 }
 
 int imb_required_bytes(const imb_config* cfg, size_t* bytes) {

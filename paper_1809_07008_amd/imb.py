@@ -30,6 +30,7 @@ def _device_buffer(nbytes: int, device):
 STORAGE = {"f64": 0, "f32": 1, "f16": 2}
 FLAG_WALLS = 1
 MODE_FREE, MODE_FIXED, MODE_PRESCRIBED = 0, 1, 2
+CONTACT_LINEAR, CONTACT_HERTZ_MINDLIN = 0, 1
 
 IMB_OK = 0
 IMB_BATCH_PERSISTENT = 0  # one persistent kernel per imb_batch_step call
@@ -75,7 +76,8 @@ class Config(C.Structure):
                 ("max_particles", C.c_int32), ("flags", C.c_uint32), ("tile_w", C.c_int32),
                 ("tile_rows", C.c_int32), ("eps_subcells", C.c_int32), ("reserved", C.c_int32),
                 ("wall_ux_bottom", C.c_double), ("wall_ux_top", C.c_double),
-                ("kt", C.c_double), ("mu", C.c_double)]
+                ("kt", C.c_double), ("mu", C.c_double), ("contact_model", C.c_int32),
+                ("reserved2", C.c_int32), ("young", C.c_double), ("poisson", C.c_double)]
 
 
 class Config3(C.Structure):
@@ -198,7 +200,8 @@ def _f64(a, n=None) -> np.ndarray:
 
 def make_config(nx, ny, tau0, storage="f64", walls=True, cs=0.0, gx=0.0, gy=0.0, rho0=1.0,
                 n_sub=10, kn=1.0e3, zeta=0.1, rho_s=1.0, max_particles=64, tile_w=64,
-                tile_rows=1, eps_subcells=0, uw_bot=0.0, uw_top=0.0, kt=0.0, mu=0.0) -> Config:
+                tile_rows=1, eps_subcells=0, uw_bot=0.0, uw_top=0.0, kt=0.0, mu=0.0,
+                contact_model=0, young=0.0, poisson=0.0) -> Config:
     c = Config()
     load_library().imb_config_default(C.byref(c))
     c.nx, c.ny, c.tau0 = int(nx), int(ny), float(tau0)
@@ -211,6 +214,8 @@ def make_config(nx, ny, tau0, storage="f64", walls=True, cs=0.0, gx=0.0, gy=0.0,
     c.eps_subcells = int(eps_subcells)
     c.wall_ux_bottom, c.wall_ux_top = float(uw_bot), float(uw_top)
     c.kt, c.mu = float(kt), float(mu)
+    c.contact_model = int(contact_model)
+    c.young, c.poisson = float(young), float(poisson)
     return c
 
 
@@ -220,7 +225,8 @@ def config_from_case(case, max_particles=None, tile_w=64, tile_rows=1, storage=N
     return make_config(case.nx, case.ny, case.tau0, storage or case.storage, case.walls, case.cs,
                        case.gx, case.gy, case.rho0, case.n_sub, case.kn, case.zeta, case.rho_s,
                        max(n, 1) if max_particles is None else max_particles, tile_w, tile_rows,
-                       case.eps_subcells, case.uw_bot, case.uw_top, case.kt, case.mu)
+                       case.eps_subcells, case.uw_bot, case.uw_top, case.kt, case.mu,
+                       case.contact_model, case.young, case.poisson)
 
 
 def _stream_handle(stream=None):

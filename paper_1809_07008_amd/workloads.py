@@ -65,6 +65,9 @@ class Case:
     uw_top: float = 0.0         # x-velocity of the top wall (walls only)
     kt: float = 0.0             # tangential contact stiffness (with mu: the tangential force)
     mu: float = 0.0             # Coulomb friction coefficient of the tangential contact force
+    contact_model: int = 0      # 0 linear spring-dashpot (kn, kt), 1 Hertz-Mindlin
+    young: float = 0.0          # Young's modulus (Hertz-Mindlin)
+    poisson: float = 0.0        # Poisson's ratio (Hertz-Mindlin)
     particles: Particles = field(default_factory=Particles.empty)
 
     @property

@@ -37,7 +37,9 @@ def oracle_of(case):
                                gx=case.gx, gy=case.gy, rho0=case.rho0, n_sub=case.n_sub,
                                kn=case.kn, zeta=case.zeta, rho_s=case.rho_s,
                                eps_subcells=case.eps_subcells, uw_bot=case.uw_bot,
-                               uw_top=case.uw_top, kt=case.kt, mu=case.mu))
+                               uw_top=case.uw_top, kt=case.kt, mu=case.mu,
+                               contact_model=case.contact_model, young=case.young,
+                               poisson=case.poisson))
     p = case.particles
     r.set_particles(p.x, p.y, p.r, p.vx, p.vy, p.om, p.mode)
     return r
@@ -71,7 +73,11 @@ def fp64_parity():
                  overlap_case(True).with_(eps_subcells=5), W.couette_channel("f64", steps=6),
                  moving_case().with_(uw_bot=0.02, uw_top=-0.01),
                  W.frictional_disks(6, True, steps=3), W.frictional_disks(8, False, steps=3),
-                 W.frictional_disks(6, True, steps=3, mu=0.05)):
+                 W.frictional_disks(6, True, steps=3, mu=0.05),
+                 W.frictional_disks(6, True, steps=3).with_(contact_model=1, young=100.0,
+                                                            poisson=0.3),
+                 W.touching_disks(8, False, steps=2).with_(contact_model=1, young=100.0,
+                                                           poisson=0.3)):
         s = sim_of(case, "f64")
         s.step(case.steps)
         ref = oracle_of(case)
@@ -87,8 +93,8 @@ def fp64_parity():
             if not case.walls:
                 d[1] -= case.ny * np.round(d[1] / case.ny)
             kerr = np.abs(d).max()
-        check("fp64 parity %s walls=%s eps_subcells=%d mu=%g" % (case.name, case.walls,
-                                                                  case.eps_subcells, case.mu),
+        check("fp64 parity %s walls=%s eps_subcells=%d mu=%g law=%d" % (
+                  case.name, case.walls, case.eps_subcells, case.mu, case.contact_model),
               ferr < 1e-12 and perr < 1e-13 and kerr < 1e-12,
               "force %.2e populations %.2e disks %.2e" % (ferr, perr, kerr))
 

@@ -40,6 +40,7 @@ int main(void) {
   O(nx) O(ny) O(storage) O(n_sub) O(tau0) O(smag_cs) O(gx) O(gy) O(rho0) O(kn)
   O(damping_ratio) O(rho_solid) O(max_particles) O(flags) O(tile_w) O(tile_rows)
   O(eps_subcells) O(reserved) O(wall_ux_bottom) O(wall_ux_top) O(kt) O(mu)
+  O(contact_model) O(reserved2) O(young) O(poisson)
   return 0;
 }
 ''')
@@ -113,3 +114,19 @@ def test_host_memory_is_refused_for_the_hip_library():
     case = workloads.single_disk_channel()
     with pytest.raises(ValueError):
         imb.Simulation(imb.config_from_case(case), device="cpu")
+
+
+def test_config3_struct_layout_matches_header(tmp_path):
+    prog = tmp_path / "layout3.c"
+    names = [n for n, _ in imb.Config3._fields_]
+    prog.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"imb.h\"\n"
+                    "int main(void) {\n  printf(\"size %zu\\n\", sizeof(imb3_config));\n" +
+                    "".join('  printf("%s %%zu\\n", offsetof(imb3_config, %s));\n' % (n, n)
+                            for n in names) + "  return 0;\n}\n")
+    exe = tmp_path / "layout3"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)])
+    vals = dict(line.split() for line in subprocess.check_output([str(exe)]).decode().split("\n")
+                if line.strip())
+    assert int(vals["size"]) == C.sizeof(imb.Config3)
+    for name in names:
+        assert int(vals[name]) == getattr(imb.Config3, name).offset, name

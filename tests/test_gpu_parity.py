@@ -20,7 +20,9 @@ def oracle_for(case, f0=None):
                                  cs=case.cs, gx=case.gx, gy=case.gy, rho0=case.rho0,
                                  n_sub=case.n_sub, kn=case.kn, zeta=case.zeta, rho_s=case.rho_s,
                                  eps_subcells=case.eps_subcells, uw_bot=case.uw_bot,
-                                 uw_top=case.uw_top, kt=case.kt, mu=case.mu))
+                                 uw_top=case.uw_top, kt=case.kt, mu=case.mu,
+                                 contact_model=case.contact_model, young=case.young,
+                                 poisson=case.poisson))
     if f0 is not None:
         ref.set_populations(f0)
     p = case.particles
@@ -342,6 +344,32 @@ def test_frictional_disks_dem_fp64_parity(rows, walls, mu):
     om, om0 = np.array(ref.particles()[4]), np.array(plain.particles()[4])
     assert np.abs(om - om0).max() > 1e-4
     assert np.abs(np.array(ref.contacts()[2])).max() > 0.0
+
+
+@pytest.mark.parametrize("rows,walls,mu", [(6, True, 0.3), (8, False, 0.0), (6, True, 0.05)])
+def test_hertz_mindlin_dem_fp64_parity(rows, walls, mu):
+    """The touching packing under the simplified Hertz-Mindlin law (Sec. 2.1): the normal force
+    4/3 E* sqrt(R*) d^(3/2) with its damping, with mu > 0 the Mindlin spring and the Coulomb
+    limit; disk-disk and disk-wall E*, G*.  FP64 parity with the oracle after 20 steps, and the
+    trajectories differ from the linear law's."""
+    case = W.frictional_disks(rows, walls, steps=20, mu=mu).with_(
+        storage="f64", contact_model=imb.CONTACT_HERTZ_MINDLIN, young=100.0, poisson=0.3)
+    sim, ref = gpu_for(case, tile_w=32, tile_rows=2), oracle_for(case)
+    sim.step(case.steps)
+    ref.step(case.steps)
+    assert_parity(sim, ref)
+    lin = oracle_for(case.with_(contact_model=0))
+    lin.step(case.steps)
+    assert np.abs(np.array(ref.particles()[2]) - np.array(lin.particles()[2])).max() > 1e-5
+
+
+def test_hertz_mindlin_approaching_disks_fp64_parity():
+    case = W.approaching_disks(steps=300).with_(storage="f64", contact_model=1, young=300.0,
+                                                poisson=0.25)
+    sim, ref = gpu_for(case, tile_w=32, tile_rows=2), oracle_for(case)
+    sim.step(case.steps)
+    ref.step(case.steps)
+    assert_parity(sim, ref, pos_tol=1e-9)
 
 
 def test_frictional_state_roundtrip_continues_identically():

@@ -943,3 +943,42 @@ def test_hertz_mindlin_sliding_disk_obeys_coulomb_then_rolls():
     l = r - 0.5 * delta0
     assert vx == pytest.approx(v0 / (1.0 + I / (m * l * l)), rel=3e-3)
     assert abs(vx + om * l) <= 2e-3 * v0
+
+
+def test_mindlin_sticking_disk_oscillates_at_the_tangential_stiffness():
+    """A disk resting on the wall under a load, given a small speed along the wall with a large
+    mu (it sticks), undamped: the slip s of the contact point obeys s'' = -S_t (1/m + l^2/I) s
+    with S_t = 8 G* sqrt(R* d0), G* = G / (2 - nu) against the wall, G = E / (2 (1 + nu)), so the
+    disk's speed oscillates at that frequency about v0 m l^2 / (I + m l^2)."""
+    E, nu, r, F, v0 = 10.0, 0.3, 5.0, 0.01, 1e-3
+    Es = E / (1 - nu * nu)
+    Gs = E / (2 * (1 + nu)) / (2 - nu)
+    d0 = (F / (4 / 3 * Es * math.sqrt(r))) ** (2 / 3)
+    s = OracleSim(OracleConfig(nx=400, ny=40, tau0=0.7, zeta=0.0, n_sub=40, mu=10.0,
+                               contact_model=1, young=E, poisson=nu))
+    s.set_particles([50.0], [r - 0.5 - d0], [r], [v0], [0.0], [0.0], [W.MODE_FREE])
+    s.set_loads([0.0], [-F], [0.0])
+    m = math.pi * r * r
+    I = 0.5 * m * r * r
+    l = r - 0.5 * d0
+    omega = math.sqrt(8 * Gs * math.sqrt(r * d0) * (1 / m + l * l / I))
+    mean = v0 * m * l * l / (I + m * l * l)
+    n = 240
+    vx = np.empty(n)
+    for k in range(n):
+        s.dem_steps(1)
+        vx[k] = s.particles()[2][0]
+    t = np.arange(1, n + 1, dtype=float)
+    # least squares over a grid of frequencies: v = a + b cos(w t) + c sin(w t)
+    ws = omega * np.linspace(0.9, 1.1, 4001)
+    res = []
+    for w in ws:
+        A = np.stack([np.ones(n), np.cos(w * t), np.sin(w * t)], 1)
+        coef, r2, *_ = np.linalg.lstsq(A, vx, rcond=None)
+        res.append(float(r2[0]) if len(r2) else 0.0)
+    k = int(np.argmin(res))
+    assert abs(ws[k] / omega - 1.0) < 1e-3, ws[k] / omega
+    A = np.stack([np.ones(n), np.cos(ws[k] * t), np.sin(ws[k] * t)], 1)
+    coef = np.linalg.lstsq(A, vx, rcond=None)[0]
+    assert coef[0] == pytest.approx(mean, rel=1e-3)
+    assert math.hypot(coef[1], coef[2]) == pytest.approx(v0 - mean, rel=1e-2)
