@@ -194,6 +194,45 @@ def hbm_control(tile, steps: int = 100, n: int = 512):
                                        2)}
 
 
+def slab_share(storage: str, tile, nslabs: int = 8, steps: int = 200):
+    """One device's share of the 2048x1024 channel split in y into eight 2048x128 slabs, the
+    shape each of eight GPUs would hold: every slab's lattice kernel (HIP events at each
+    launch), the kernel that stands in for the face transfers and the force all-reduce, and the
+    particle phase that every slab replicates; also the whole eight-slab step run on this one
+    device (graph replay)."""
+    from paper_1809_07008_amd import imb, workloads
+    case = workloads.moving_disks(seed=0, storage=storage)
+    sl = imb.slabs_from_case(case, nslabs, storage=storage, tile_w=tile[0], tile_rows=tile[1])
+    y0, rows = sl.layout()
+    sl.step(34)  # captures and replays the 2- and 32-step graphs
+    sl.sync()
+    t0 = time.perf_counter()
+    sl.step(steps)
+    sl.sync()
+    all_s = (time.perf_counter() - t0) / steps
+    sl.set_kernel_timing(True)
+    sl.step(steps)
+    lat, xch, par, n = sl.kernel_timing()
+    sl.close()
+    lat_us = lat * 1e3 / n
+    bpl = bytes_per_lup(storage)
+    cells = case.nx * rows
+    gbps = cells * bpl / (lat_us * 1e-6) / 1e9
+    es = {"f64": 8, "f32": 4, "f16": 2}[storage]
+    return {"workload": "moving_disks_2048x1024_n500 as %d slabs" % nslabs,
+            "slab_rows": rows.tolist(),
+            "lattice_kernel_us": [round(v, 2) for v in lat_us],
+            "lattice_kernel_us_max": round(float(lat_us.max()), 2),
+            "lattice_kernel_GBps_min": round(float(gbps.min()), 1),
+            "lattice_kernel_frac_of_8TBps_min": round(float(gbps.min()) / HBM_PEAK_GBS, 4),
+            "exchange_us_all_slabs": round(xch * 1e3 / n, 2),
+            "particle_phase_us": round(float(par.mean()) * 1e3 / n, 2),
+            "face_bytes_per_slab_per_step": 2 * 3 * case.nx * es,
+            "force_share_bytes_per_step": case.particles.n * 24,
+            "share_compute_us_per_step": round(float(lat_us.max() + par.mean() * 1e3 / n), 2),
+            "all_slabs_one_device_ms_per_step": round(all_s * 1e3, 4)}
+
+
 def memory_calibration(sizes=(158 * 2 ** 20, 2400 * 2 ** 20), reps: int = 20):
     """Attainable bandwidth of plain device copies (two bytes moved per byte copied), HIP events
     on the current stream: the library's copy kernel (several 16-byte loads in flight per lane,
@@ -305,10 +344,13 @@ def main(argv=None):
                     help="only run the copy kernel over this many bytes (counter calibration)")
     ap.add_argument("--batch-only", action="store_true",
                     help="only run the batched form (64 channels) and print its JSON")
+    ap.add_argument("--slab-only", action="store_true",
+                    help="only run the eight-slab share of the lattice and print its JSON")
     args = ap.parse_args(argv)
     if args.gpus != 1:
-        print("bench.py: this build runs on exactly one GPU (got --gpus %d); the lattice would "
-              "shard in y slabs across GPUs, which is not built." % args.gpus, file=sys.stderr)
+        print("bench.py: this build runs on exactly one GPU (got --gpus %d); one GPU's share of "
+              "a lattice split in y slabs is measured by --slab-only (and in the default run), "
+              "but no run spans several GPUs." % args.gpus, file=sys.stderr)
         return 2
 
     import torch
@@ -322,6 +364,11 @@ def main(argv=None):
         return copy_calibration(args.copy_bytes)
     if args.batch_only:
         print(json.dumps({"mode": "batch_only", "batch": batch_throughput()}), flush=True)
+        return 0
+    if args.slab_only:
+        print(json.dumps({"mode": "slab_only",
+                          "slab_share": slab_share(args.storage, (args.tile_w, args.tile_rows))}),
+              flush=True)
         return 0
     case = workloads.moving_disks(seed=args.seed, storage=args.storage)
     sim = imb.simulation_from_case(case, storage=args.storage, tile_w=args.tile_w,
@@ -398,6 +445,8 @@ def main(argv=None):
         out["batch"] = batch_throughput()
         print("bench: batch %.3f ms per step" % out["batch"]["tuned_ms_per_step"],
               file=sys.stderr, flush=True)
+        out["slab_share"] = slab_share(args.storage, (args.tile_w, args.tile_rows))
+        print("bench: slab share %s" % out["slab_share"], file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(out), flush=True)

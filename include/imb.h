@@ -340,6 +340,64 @@ int imb_batch_get_timing(imb_batch* b, int32_t nsteps, double* ms);
 /* Message of the last failure on this batch (b = NULL: of the last failed create). */
 const char* imb_batch_last_error(const imb_batch* b);
 
+/* ------------------------------------------------------- one GPU's share of a split lattice
+ * A lattice split in y into nslabs slabs of whole tile rows, as one device of a multi-GPU run
+ * would hold it: each slab stores only its rows and runs the coupled step of imb_step on them
+ * (Sec. 2.2, Eqs. 1, 2, 12-14 per cell; Eqs. 15, 16 per disk over the slab's own cells).  Pull
+ * streaming across a slab face needs the populations that cross it (c_y = +1 from the slab
+ * below, -1 from the slab above): each slab's population planes hold a ghost row on each side,
+ * into which those three rows of the neighbour's boundary row are copied between steps.  Each
+ * slab writes its share of every disk's force and torque (zero for disks whose box misses it).
+ * After the slabs' lattice kernels one kernel does every ghost-row copy (standing in for the
+ * transfer between devices) and sums the shares in slab order (standing in for the
+ * all-reduce); the particle phase then runs once per slab on identical inputs (replicated DEM),
+ * each writing the disk tables of its own rows.  Walls end the lowest and highest slabs; without walls they are
+ * neighbours across the periodic boundary.  Every slab lives on the calling thread's current
+ * device and works on hip_stream.  Results equal imb_sim's up to the order of the per-disk sums
+ * (bit for bit where forces do not feed back: fixed or prescribed disks).
+ * Host arrays as for imb_sim (populations [9][ny][nx] FP64).  Errors: IMB_EINVAL for bad
+ * arguments (nslabs outside 2..16 or more slabs than tile rows), otherwise as imb_create /
+ * imb_step; messages from imb_slab_last_error. */
+typedef struct imb_slab imb_slab;
+
+/* Splits cfg's lattice (validated as by imb_create) into nslabs slabs and allocates them; the
+ * fluid starts at rest at rho0 with no disks.  Synchronises. */
+int imb_slab_create(const imb_config* cfg, int32_t nslabs, void* hip_stream, imb_slab** out);
+void imb_slab_destroy(imb_slab* s);
+/* First row and row count of each slab (host arrays of nslabs). */
+int imb_slab_layout(const imb_slab* s, int32_t* y0, int32_t* rows);
+/* As imb_init_equilibrium, imb_set_populations, imb_get_populations and imb_get_fields, on the
+ * whole lattice (each slab handles its rows and its halo rows).  Synchronise. */
+int imb_slab_init_equilibrium(imb_slab* s, double rho, double ux, double uy);
+int imb_slab_set_populations(imb_slab* s, const double* host_f);
+int imb_slab_get_populations(imb_slab* s, double* host_f);
+int imb_slab_get_fields(imb_slab* s, double* rho, double* ux, double* uy);
+/* As imb_set_particles, on every slab.  Synchronises. */
+int imb_slab_set_particles(imb_slab* s, int32_t n, const double* x, const double* y,
+                           const double* r, const double* vx, const double* vy, const double* om,
+                           const int32_t* mode);
+/* Enqueues nsteps coupled steps of every slab (replays captured graphs of 2 and 32 steps unless
+ * kernel timing is on).  Asynchronous. */
+int imb_slab_step(imb_slab* s, int32_t nsteps);
+/* Summed hydrodynamic force and torque on each disk from the last step (as imb_get_forces). */
+int imb_slab_get_forces(imb_slab* s, double* fx, double* fy, double* tz);
+/* Slab `slab`'s share of each disk's force and torque from the last step.  Synchronises. */
+int imb_slab_get_partial_forces(imb_slab* s, int32_t slab, double* fx, double* fy, double* tz);
+/* Slab `slab`'s copy of the disk state (as imb_get_particles).  Synchronises. */
+int imb_slab_get_particles(imb_slab* s, int32_t slab, double* x, double* y, double* vx,
+                           double* vy, double* om);
+/* Per-kernel timing with HIP events at each launch's start and end (direct launches while
+ * enabled).  imb_slab_get_kernel_timing returns, since the last enable, the summed milliseconds
+ * of each slab's lattice kernel and particle phase (host arrays of nslabs, may be NULL), of the
+ * exchange kernel, and the number of timed steps.  Synchronises. */
+int imb_slab_set_kernel_timing(imb_slab* s, int enable);
+int imb_slab_get_kernel_timing(imb_slab* s, double* lattice_ms, double* exchange_ms,
+                               double* particle_ms, int64_t* nsteps);
+/* Waits for the stream and checks every slab's device error flags. */
+int imb_slab_sync(imb_slab* s);
+/* Message of the last failure on s (s = NULL: of the last failed imb_slab_create). */
+const char* imb_slab_last_error(const imb_slab* s);
+
 /* ------------------------------------------------------- three dimensions: D3Q19 with spheres
  * The lattice step of the paper's own three-dimensional method (Sec. 2 with the D3Q19 set of
  * Table 1; Sec. 2.2, Eqs. 12-16 for the spheres), for fixed spheres and spheres moving with a

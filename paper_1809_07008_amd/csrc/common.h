@@ -90,6 +90,14 @@ struct LatticeArgs {
   const int* nbr;        // [np][NBMAX] neighbour lists (ascending ids) and their lengths
   const int* nnbr;
   double4* force;        // [np] force and torque of this step (Fx, Fy, Tz, 0)
+  // The rows [y0, y0 + nyl) of the lattice that this step updates (a slab of a lattice split in
+  // y; the whole lattice: y0 = 0, nyl = ny).  Lattice row y is stored in plane row y - yoff: a
+  // slab's planes hold a ghost row on each side (yoff = y0 - 1), where its neighbours' crossing
+  // populations are copied between steps (ghost_lo, ghost_hi: that neighbour exists; a wall
+  // otherwise).  Tile rows count inside the window: tile row ty is lattice tile row ty + ty_off
+  // of the tiles_yg that the lattice has.
+  int y0, nyl, yoff, ty_off, tiles_yg;
+  int ghost_lo, ghost_hi;
 };
 
 // The momentum a moving wall takes from population j sent into it (through y = -1/2 when
@@ -148,6 +156,7 @@ struct ParticleArgs {
   double hm_damp;         //   2 sqrt(5/6) zeta
   double uw_bot, uw_top;  // wall velocities along x (the walls' tangential slip)
   int tiles_x, tiles_y, tw, th;
+  int tiles_yg, ty_off;   // the lattice's tile rows; band lists cover rows [ty_off, +tiles_y)
   ParticleState s;
   ParticleTable tab;
   const double4* direct;  // [np] force and torque of the step (Fx, Fy, Tz, 0)

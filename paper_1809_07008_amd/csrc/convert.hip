@@ -3,8 +3,8 @@
 // the moments of Eqs. (3), (4), and plain streaming copy / fill kernels.
 //
 // The stored planes s are what the pull step reads: post-stream f_i(x) = s_i(x - c_i), or
-// s_{-i}(x) when x - c_i lies beyond a wall.  This map is one-to-one, so "unstream" writes each
-// s entry exactly once.
+// s_{-i}(x) when x - c_i lies beyond a wall.  This map is one-to-one, so "unstream" computes each
+// s entry once, from the one population that it becomes.
 #include "step.h"
 
 namespace imb {
@@ -29,32 +29,49 @@ __device__ inline double decode_load(const typename St::S* src, long long idx, i
   else return (double)v;
 }
 
+// Stored entry i of cell (x, y) (lattice coordinates): the population that the pull of the next
+// step delivers to (x + c_i), or, where that lies beyond a wall, the one that the bounce-back
+// returns to (x, y) itself as population -i.  A slab also fills its ghost rows y0 - 1 and
+// y0 + nyl (where it has a neighbour there) with the populations that cross into it.
 template <class St>
 __global__ void k_unstream(LatticeArgs a, const double* fq, Feq9 feq, typename St::S* dst) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
-  if (x >= a.nx || y >= a.ny) return;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = a.y0 - 1 + (int)blockIdx.y;  // grid rows: the window and the rows next to it
+  if (x >= a.nx) return;
+  const bool lo = y == a.y0 - 1, hi = y == a.y0 + a.nyl;
+  if ((lo && !a.ghost_lo) || (hi && !a.ghost_hi)) return;
+  int yc = y;  // the cell's lattice row (a ghost row wraps in a periodic lattice)
+  if (yc < 0) yc += a.ny;
+  if (yc >= a.ny) yc -= a.ny;
   for (int i = 0; i < NQ; ++i) {
-    const double f = fq ? fq[((long long)i * a.ny + y) * a.nx + x] : feq.v[i];
-    int xs = x - cx_of(i), ys = y - cy_of(i);
-    xs = xs < 0 ? xs + a.nx : (xs >= a.nx ? xs - a.nx : xs);
-    if (ys < 0 || ys >= a.ny) {
+    if ((lo && cy_of(i) <= 0) || (hi && cy_of(i) >= 0)) continue;  // not crossing into the slab
+    int xa = x + cx_of(i), ya = yc + cy_of(i);
+    int qa = i;
+    if (ya < 0 || ya >= a.ny) {
       if (a.walls) {
-        encode_store<St>(dst, (long long)opp_of(i) * a.plane + (long long)y * a.pitch + x, f,
-                         opp_of(i), a.rho0);
-        continue;
+        xa = x;
+        ya = yc;
+        qa = opp_of(i);
+      } else {
+        ya = ya < 0 ? ya + a.ny : ya - a.ny;
       }
-      ys = ys < 0 ? ys + a.ny : ys - a.ny;
     }
-    encode_store<St>(dst, (long long)i * a.plane + (long long)ys * a.pitch + xs, f, i, a.rho0);
+    xa = xa < 0 ? xa + a.nx : (xa >= a.nx ? xa - a.nx : xa);
+    const double f = fq ? fq[((long long)qa * a.ny + ya) * a.nx + xa] : feq.v[qa];
+    encode_store<St>(dst, (long long)i * a.plane + (long long)(y - a.yoff) * a.pitch + x, f, i,
+                     a.rho0);
   }
 }
 
+// Post-stream populations, density and velocity of the window's cells (pull_load's rule, in
+// FP64), written at their lattice rows of [q][ny][nx] outputs.
 template <class St>
 __global__ void k_gather(LatticeArgs a, const typename St::S* src, double* fq, double* rho,
                          double* ux, double* uy) {
 #pragma clang fp contract(off)
-  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
-  if (x >= a.nx || y >= a.ny) return;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = a.y0 + (int)blockIdx.y;
+  if (x >= a.nx || y >= a.y0 + a.nyl) return;
+  const bool slab = a.nyl != a.ny;
   double f[NQ];
   for (int i = 0; i < NQ; ++i) {
     int xs = x - cx_of(i), ys = y - cy_of(i);
@@ -64,13 +81,13 @@ __global__ void k_gather(LatticeArgs a, const typename St::S* src, double* fq, d
     if (ys < 0 || ys >= a.ny) {
       if (a.walls) {
         q = opp_of(i);
-        idx = (long long)q * a.plane + (long long)y * a.pitch + x;
+        idx = (long long)q * a.plane + (long long)(y - a.yoff) * a.pitch + x;
         f[i] = decode_load<St>(src, idx, q, a.rho0);
         continue;
       }
-      ys = ys < 0 ? ys + a.ny : ys - a.ny;
+      if (!slab) ys = ys < 0 ? ys + a.ny : ys - a.ny;  // a slab reads its ghost row
     }
-    idx = (long long)i * a.plane + (long long)ys * a.pitch + xs;
+    idx = (long long)i * a.plane + (long long)(ys - a.yoff) * a.pitch + xs;
     f[i] = decode_load<St>(src, idx, q, a.rho0);
   }
   const long long c = (long long)y * a.nx + x;
@@ -93,7 +110,7 @@ void unstream_t(const LatticeArgs& a, const double* fq, const double* feq9, void
   Feq9 fe{};
   if (feq9)
     for (int i = 0; i < NQ; ++i) fe.v[i] = feq9[i];
-  dim3 grid((a.nx + 255) / 256, a.ny);
+  dim3 grid((a.nx + 255) / 256, a.nyl + 2);
   hipLaunchKernelGGL(k_unstream<St>, grid, dim3(256), 0, s, a, fq, fe, (typename St::S*)dst);
 }
 
@@ -107,7 +124,7 @@ void launch_unstream(int storage, const LatticeArgs& a, const double* fq, const 
 template <class St>
 void gather_t(const LatticeArgs& a, const void* src, double* fq, double* rho, double* ux,
               double* uy, hipStream_t s) {
-  dim3 grid((a.nx + 255) / 256, a.ny);
+  dim3 grid((a.nx + 255) / 256, a.nyl);
   hipLaunchKernelGGL(k_gather<St>, grid, dim3(256), 0, s, a, (const typename St::S*)src, fq, rho,
                      ux, uy);
 }

@@ -22,8 +22,8 @@
 namespace imb {
 
 // Plain update of the uncovered cells of one tile (one BLOCK-thread workgroup): only they are
-// loaded and stored.
-template <class St>
+// loaded and stored.  W: the lattice is a window of rows with ghost rows (tile.h, pull_load).
+template <class St, bool W = false>
 __device__ void fluid_tile(const LatticeArgs& a, int tile) {
   using T = typename St::T;
   using S = typename St::S;
@@ -36,7 +36,14 @@ __device__ void fluid_tile(const LatticeArgs& a, int tile) {
   const int tw = 1 << a.tw_log, th = BLOCK >> a.tw_log;
   const int lx = tid & (tw - 1), ly = tid >> a.tw_log;
   const int x = tx * tw + lx;
-  const int ybase = ty * th * a.rows + ly;
+  const int y0 = W ? a.y0 : 0;           // first row of the window
+  const int yend = W ? y0 + a.nyl : a.ny;
+  const int nyl = W ? a.nyl : a.ny;
+  const int yoff = W ? a.yoff : 0;       // plane row of lattice row y: y - yoff
+  // the plane rows next to the window hold its neighbours' rows (ghost rows) or lie beyond a
+  // wall
+  const bool lo_ok = W && a.ghost_lo, hi_ok = W && a.ghost_hi;
+  const int ybase = y0 + ty * th * a.rows + ly;
   const S* src = (const S*)a.src;
   S* dst = (S*)a.dst;
 
@@ -53,7 +60,7 @@ __device__ void fluid_tile(const LatticeArgs& a, int tile) {
   // this thread's cell of pass rr exists and no disk covers it (a covered cell is loaded and
   // stored by the workgroup of its lowest-id covering disk)
   auto live = [&](int y) {
-    if (x >= a.nx || y >= a.ny) return false;
+    if (x >= a.nx || y >= yend) return false;
     for (int j = 0; j < n; ++j) {
       T dx, dy;
       lever_arm(a, s_pl[j], x, y, &dx, &dy);
@@ -62,11 +69,12 @@ __device__ void fluid_tile(const LatticeArgs& a, int tile) {
     return true;
   };
   auto load = [&](int rr, int y, T f[NQ]) {
-    // every cell of pass rr has its eight neighbours inside the lattice (uniform)
-    const int ylo = ybase - ly + rr * th;
-    const bool inner = off32 && xin && ylo >= 1 && ylo + th <= a.ny - 1;
-    if (inner) pull_load_inner<St>(a, src, (unsigned)(y * a.pitch + x) * (unsigned)sizeof(S), f);
-    else pull_load<St>(a, src, x, y, f);
+    // every cell of pass rr has its eight neighbours in stored rows (uniform)
+    const int ylo = ybase - ly + rr * th - y0;  // window row of the pass's first row
+    const bool inner = off32 && xin && (ylo >= 1 || lo_ok) && (ylo + th <= nyl - 1 || hi_ok);
+    if (inner)
+      pull_load_inner<St>(a, src, (unsigned)((y - yoff) * a.pitch + x) * (unsigned)sizeof(S), f);
+    else pull_load<St, W>(a, src, x, y, f);
   };
   auto update = [&](int y, const T f[NQ]) {
     T fo[NQ];
@@ -80,10 +88,11 @@ __device__ void fluid_tile(const LatticeArgs& a, int tile) {
     }
     if (!(rho > T(0)) || !isfinite(rho)) atomicOr(a.err, ERR_RHO);
     wall_adjust<T>(a, y, fo);
-    const long long base = (long long)y * a.pitch + x;
+    const long long base = (long long)(y - yoff) * a.pitch + x;
     S out[NQ];
     if constexpr (St::stochastic) {
-      const unsigned r0 = pcg_hash(seed * 0x9E3779B9u + (unsigned)base);
+      // the random words follow the lattice cell, not its place in the window
+      const unsigned r0 = pcg_hash(seed * 0x9E3779B9u + (unsigned)((long long)y * a.pitch + x));
 #pragma unroll
       for (int i = 0; i < NQ; ++i) out[i] = St::encode_sr(fo[i], pcg_hash(r0 + (unsigned)i));
     } else {
@@ -112,13 +121,13 @@ __device__ void fluid_tile(const LatticeArgs& a, int tile) {
   } else {
     // passes in pairs: both passes' loads are in flight before either is updated
     for (int rr = 0; rr < a.rows; rr += 2) {
-      const int y0 = ybase + rr * th, y1 = y0 + th;
-      const bool l0 = live(y0), l1 = rr + 1 < a.rows && live(y1);
+      const int ya = ybase + rr * th, yb = ya + th;
+      const bool l0 = live(ya), l1 = rr + 1 < a.rows && live(yb);
       T f0[NQ], f1[NQ];
-      if (l0) load(rr, y0, f0);
-      if (l1) load(rr + 1, y1, f1);
-      if (l0) update(y0, f0);
-      if (l1) update(y1, f1);
+      if (l0) load(rr, ya, f0);
+      if (l1) load(rr + 1, yb, f1);
+      if (l0) update(ya, f0);
+      if (l1) update(yb, f1);
     }
   }
   if constexpr (St::stochastic) {
@@ -127,8 +136,10 @@ __device__ void fluid_tile(const LatticeArgs& a, int tile) {
 }
 
 // Covered cells of disk p's box, one BLOCK-thread workgroup: IMB collision of the cells p owns,
-// p's own force and torque over every cell it covers, written to a.force[p].
-template <class St>
+// p's own force and torque over every cell it covers, written to a.force[p].  W: only the cells
+// in the window, and a.force[p] is the window's share of the sums (zero when the disk's box
+// misses the window).
+template <class St, bool W = false>
 __device__ void disk_cells(const LatticeArgs& a, int p) {
   using T = typename St::T;
   using S = typename St::S;
@@ -137,45 +148,65 @@ __device__ void disk_cells(const LatticeArgs& a, int p) {
   __shared__ T s_ce[MAXC][BLOCK];         //   and their solid ratios
   __shared__ Acc<T> s_fr[WAVES][3];
   __shared__ int s_rx0[64], s_rpre[65];   // row-wise cell enumeration (rows of the box <= 64)
+  __shared__ unsigned long long s_rmask[64];  // per row: the entries that can reach it
 
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   const S* src = (const S*)a.src;
   S* dst = (S*)a.dst;
+  const int y0 = W ? a.y0 : 0;
+  // a cell row (after the periodic wrap) that the stored planes hold
+  auto in_window = [&](int y) { return !W || (y >= y0 && y < y0 + a.nyl); };
+  const double4 pp = a.tab.pos[p];
+  if constexpr (W) {
+    // rows the disk can cover against the window, with its periodic images in y
+    int r0 = (int)floor(pp.y - pp.z - 0.5), r1 = (int)ceil(pp.y + pp.z + 0.5);
+    bool touch = false;
+    if (a.walls) {
+      touch = r1 >= y0 && r0 < y0 + a.nyl;
+    } else {
+      for (int sh = -1; sh <= 1; ++sh) {
+        const int lo = y0 + sh * a.ny;
+        touch = touch || (r1 >= lo && r0 < lo + a.nyl);
+      }
+    }
+    if (!touch) {  // block-uniform
+      if (tid == 0) a.force[p] = make_double4(0.0, 0.0, 0.0, 0.0);
+      return;
+    }
+  }
   int nn = a.nnbr[p];
   if (nn > NBMAX) nn = NBMAX;
   if (nn < 0) nn = 0;
   const int nd = nn + 1;
-  // entry k: p itself or neighbour k - 1, placed at its rank by id
-  if (tid < nd) {
-    const int q = tid == 0 ? p : a.nbr[(long long)p * NBMAX + tid - 1];
-    int rank = 0;
-    if (tid == 0) {
-      for (int k = 0; k < nn; ++k) rank += a.nbr[(long long)p * NBMAX + k] < p;
-    } else {
-      rank = (tid - 1) + (q > p ? 1 : 0);
+  // Entry k: p itself or neighbour k - 1, placed at its rank by id (wave 0, one lane each; the
+  // neighbour list is ascending, and p's rank is the count of smaller neighbour ids)
+  if (wave == 0) {
+    const int q = lane == 0 ? p : (lane < nd ? a.nbr[(long long)p * NBMAX + lane - 1] : -1);
+    const int nlow = (int)__popcll(__ballot(lane > 0 && lane < nd && q < p));
+    if (lane < nd) {
+      const int rank = lane == 0 ? nlow : (lane - 1) + (q > p ? 1 : 0);
+      const double4 ps = a.tab.pos[q];
+      const double4 vl = a.tab.vel[q];
+      const double flx = floor(ps.x), fly = floor(ps.y);
+      PEntry<T> e;
+      e.ix = (int)flx;
+      e.iy = (int)fly;
+      e.pid = q;
+      e.slot = 0;
+      e.fx = (T)(ps.x - flx);
+      e.fy = (T)(ps.y - fly);
+      e.r = (T)ps.z;
+      e.vx = (T)vl.x;
+      e.vy = (T)vl.y;
+      e.om = (T)vl.z;
+      if (rank >= 0 && rank < nd) s_de[rank] = e;
     }
-    const double4 ps = a.tab.pos[q];
-    const double4 vl = a.tab.vel[q];
-    const double flx = floor(ps.x), fly = floor(ps.y);
-    PEntry<T> e;
-    e.ix = (int)flx;
-    e.iy = (int)fly;
-    e.pid = q;
-    e.slot = 0;
-    e.fx = (T)(ps.x - flx);
-    e.fy = (T)(ps.y - fly);
-    e.r = (T)ps.z;
-    e.vx = (T)vl.x;
-    e.vy = (T)vl.y;
-    e.om = (T)vl.z;
-    if (rank >= 0 && rank < nd) s_de[rank] = e;
   }
   unsigned seed = 0u;
   if constexpr (St::stochastic) seed = a.seed[a.seed_slot];
-  __syncthreads();
 
   // the cells the disk can cover: [floor(X - r - 1/2), ceil(X + r + 1/2)] in x and y
-  const double4 pp = a.tab.pos[p];
   const int ix0 = (int)floor(pp.x - pp.z - 0.5), ix1 = (int)ceil(pp.x + pp.z + 0.5);
   int iy0 = (int)floor(pp.y - pp.z - 0.5), iy1 = (int)ceil(pp.y + pp.z + 0.5);
   if (a.walls) {
@@ -187,39 +218,61 @@ __device__ void disk_cells(const LatticeArgs& a, int p) {
   // Row by row, only the cells whose nearest point to the centre can lie within r: in the row at
   // y-distance ny from the centre (to the row's nearest edge) those with |x - X| < s + 1/2,
   // s = sqrt(r^2 - ny^2), widened by 1e-3 so that no rounding of the exact test drops a cell.
-  // Rows start at s_rx0[k]; s_rpre holds the prefix counts.  Boxes taller than a wavefront
-  // walk the whole box.
+  // Rows start at s_rx0[k]; s_rpre holds the prefix counts (wave 1, one lane per row, while
+  // wave 0 fills the entries).  Boxes taller than a wavefront walk the whole box.
   const bool rowwise = boxed && bh <= 64;
   int ncell = boxed ? bw * bh : 0;
-  if (rowwise) {
-    if (tid < 64) {
-      int x0 = 0, len = 0;
-      if (tid < bh) {
-        const double dy = (double)(iy0 + tid) - pp.y;
-        const double ny = dy - 0.5 > 0.0 ? dy - 0.5 : (dy + 0.5 < 0.0 ? dy + 0.5 : 0.0);
-        const double q = pp.z * pp.z - ny * ny;
-        if (q > 0.0) {
-          const double sw = sqrt(q) + 1e-3;
-          int lo = (int)floor(pp.x - sw - 0.5) + 1, hi = (int)ceil(pp.x + sw + 0.5) - 1;
-          lo = lo > ix0 ? lo : ix0;
-          hi = hi < ix1 ? hi : ix1;
-          if (hi >= lo) {
-            x0 = lo;
-            len = hi - lo + 1;
-          }
+  if (rowwise && wave == 1) {
+    int x0 = 0, len = 0;
+    int ywin = iy0 + lane;  // the row's lattice row
+    if (!a.walls) ywin = ywin < 0 ? ywin + a.ny : (ywin >= a.ny ? ywin - a.ny : ywin);
+    if (lane < bh && in_window(ywin)) {
+      const double dy = (double)(iy0 + lane) - pp.y;
+      const double ny = dy - 0.5 > 0.0 ? dy - 0.5 : (dy + 0.5 < 0.0 ? dy + 0.5 : 0.0);
+      const double q = pp.z * pp.z - ny * ny;
+      if (q > 0.0) {
+        const double sw = sqrt(q) + 1e-3;
+        int lo = (int)floor(pp.x - sw - 0.5) + 1, hi = (int)ceil(pp.x + sw + 0.5) - 1;
+        lo = lo > ix0 ? lo : ix0;
+        hi = hi < ix1 ? hi : ix1;
+        if (hi >= lo) {
+          x0 = lo;
+          len = hi - lo + 1;
         }
       }
-      int incl = len;
+    }
+    int incl = len;
 #pragma unroll
-      for (int off = 1; off < 64; off <<= 1) {
-        const int v = __shfl_up(incl, off, 64);
-        if (tid >= off) incl += v;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int v = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += v;
+    }
+    if (lane < bh) {
+      s_rx0[lane] = x0;
+      s_rpre[lane + 1] = incl;
+    }
+    if (lane == 0) s_rpre[0] = 0;
+  }
+  __syncthreads();
+  if (rowwise) {
+    // Per row, the entries whose disk reaches it: the row's cells lie within 1/2 of its centre
+    // line in y, so a disk more than r + 1/2 (+ 1e-3 against rounding) away from that line in y
+    // covers none of them; the covering test below runs on the others only, in id order.
+    if (wave == 0 && lane < bh) {
+      unsigned long long m = 0ull;
+      const int yr = iy0 + lane;
+      for (int k = 0; k < nd; ++k) {
+        const PEntry<T>& e = s_de[k];
+        int dj = yr - e.iy;
+        if (!a.walls) {
+          const int hy = a.ny / 2;
+          if (dj > hy) dj -= a.ny;
+          else if (dj < -hy) dj += a.ny;
+        }
+        const double dyc = (double)dj - (double)e.fy;
+        if (fabs(dyc) <= (double)e.r + 0.501) m |= 1ull << k;
       }
-      if (tid < bh) {
-        s_rx0[tid] = x0;
-        s_rpre[tid + 1] = incl;
-      }
-      if (tid == 0) s_rpre[0] = 0;
+      s_rmask[lane] = m;
     }
     __syncthreads();
     ncell = s_rpre[bh];
@@ -229,6 +282,7 @@ __device__ void disk_cells(const LatticeArgs& a, int p) {
   Acc<T> afx{T(0), T(0)}, afy{T(0), T(0)}, atz{T(0), T(0)};
   for (int c = tid; c < ncell; c += BLOCK) {
     int x, y;
+    unsigned long long cand = nd >= 64 ? ~0ull : (1ull << nd) - 1ull;  // entries to test
     if (rowwise) {  // the row holding cell c: s_rpre[k] <= c < s_rpre[k + 1]
       int lo = 0, hi = bh;
       while (hi - lo > 1) {
@@ -238,32 +292,46 @@ __device__ void disk_cells(const LatticeArgs& a, int p) {
       }
       x = s_rx0[lo] + (c - s_rpre[lo]);
       y = iy0 + lo;
+      cand = s_rmask[lo];
     } else {
       x = ix0 + c % bw;
       y = iy0 + c / bw;
     }
     x = x < 0 ? x + a.nx : (x >= a.nx ? x - a.nx : x);
     if (!a.walls) y = y < 0 ? y + a.ny : (y >= a.ny ? y - a.ny : y);
-    // covering disks of the cell, ascending id; the cell belongs to the first of them
+    if (!in_window(y)) continue;
+    // covering disks of the cell, ascending id; the cell belongs to the first of them.  The
+    // solid ratio of p itself (every cell here but a rare few) is evaluated once, after the
+    // loop, so that a wavefront runs the cut-cell area once however p ranks among its lanes'
+    // candidates; other covering disks (cells shared by two disks) get theirs in the loop.
     int nc = 0, own = -1;
     bool owner = true;
-    for (int k = 0; k < nd; ++k) {
+    T pdx = T(0), pdy = T(0);
+    for (; cand; cand &= cand - 1ull) {
+      const int k = (int)__builtin_ctzll(cand);
       T dx, dy;
       lever_arm(a, s_de[k], x, y, &dx, &dy);
       if (!covers_cell<T>(s_de[k].r, dx, dy)) continue;
-      if (s_de[k].pid != p && own < 0) owner = false;  // a lower id covers the cell
-      if (s_de[k].pid == p) own = nc;
+      const bool self = s_de[k].pid == p;
+      if (!self && own < 0) owner = false;  // a lower id covers the cell
       if (nc >= MAXC) {
         atomicOr(a.err, ERR_CELL);
         continue;
       }
       s_cj[nc][tid] = k;
-      s_ce[nc][tid] = cell_solid_ratio<T>(s_de[k].r, dx, dy, a.eps_sub);
+      if (self) {
+        own = nc;
+        pdx = dx;
+        pdy = dy;
+      } else {
+        s_ce[nc][tid] = cell_solid_ratio<T>(s_de[k].r, dx, dy, a.eps_sub);
+      }
       ++nc;
     }
     if (own < 0) continue;  // p does not cover this cell
+    s_ce[own][tid] = cell_solid_ratio<T>((T)pp.z, pdx, pdy, a.eps_sub);
     T f[NQ], fo[NQ];
-    pull_load<St>(a, src, x, y, f);
+    pull_load<St, W>(a, src, x, y, f);
     auto disk = [&](int k) {
       Disk<T> d;
       const PEntry<T>& e = s_de[s_cj[k][tid]];
@@ -289,19 +357,20 @@ __device__ void disk_cells(const LatticeArgs& a, int p) {
     if (!owner) continue;
     if (!(rho > T(0)) || !isfinite(rho)) atomicOr(a.err, ERR_RHO);
     wall_adjust<T>(a, y, fo);
-    const long long off = (long long)y * a.pitch + x;
+    const long long off = (long long)(y - (W ? a.yoff : 0)) * a.pitch + x;
+    S out[NQ];
     if constexpr (St::stochastic) {
-      const unsigned r0 = pcg_hash(seed * 0x9E3779B9u + (unsigned)off);
+      const unsigned r0 = pcg_hash(seed * 0x9E3779B9u + (unsigned)((long long)y * a.pitch + x));
 #pragma unroll
-      for (int i = 0; i < NQ; ++i)
-        St::store_sr(dst, (long long)i * a.plane + off, fo[i], pcg_hash(r0 + (unsigned)i));
+      for (int i = 0; i < NQ; ++i) out[i] = St::encode_sr(fo[i], pcg_hash(r0 + (unsigned)i));
     } else {
 #pragma unroll
-      for (int i = 0; i < NQ; ++i) St::store(dst, (long long)i * a.plane + off, fo[i], T(0));
+      for (int i = 0; i < NQ; ++i) out[i] = St::encode(fo[i]);
     }
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) dst[(long long)i * a.plane + off] = out[i];
   }
   // the disk's force and torque: wave sums, then the waves in a fixed order
-  const int lane = tid & 63, wave = tid >> 6;
   const Acc<T> w0 = wave_sum(afx), w1 = wave_sum(afy), w2 = wave_sum(atz);
   if (lane == 0) {
     s_fr[wave][0] = w0;

@@ -708,23 +708,30 @@ __device__ __attribute__((always_inline)) void particle_phase(const ParticleArgs
   if (a.do_table && have) {
     if (!isfinite(nx_) || !isfinite(ny_)) {
       nbx = make_int4(0, 0, 0, 0);
-    } else if (!tile_box(nx_, ny_, r, a.nx, a.ny, a.walls, a.tiles_x, a.tiles_y, a.tw, a.th,
+    } else if (!tile_box(nx_, ny_, r, a.nx, a.ny, a.walls, a.tiles_x, a.tiles_yg, a.tw, a.th,
                          &nbx)) {
       atomicOr(a.err, ERR_SLOTS);
       nbx = make_int4(0, 0, 0, 0);
     }
   }
-  // ---- band lists: counting sort of (tile row, disk) pairs in LDS
+  // ---- band lists: counting sort of (tile row, disk) pairs in LDS, for the tile rows
+  // [ty_off, ty_off + tiles_y) of the lattice's tiles_yg (all of them unless a slab)
   int* cnt = (int*)lds;
   const int nbands = a.tiles_y;
+  auto band_of = [&](int k) {  // band of the box's k-th tile row, or -1 outside the window
+    int ty = nbx.z + k;
+    ty = ty < a.tiles_yg ? ty : ty - a.tiles_yg;
+    ty -= a.ty_off;
+    return ty >= 0 && ty < nbands ? ty : -1;
+  };
   int total = 0;
   if (a.do_table) {
     for (int k = threadIdx.x; k <= nbands; k += NT) cnt[k] = 0;
     __syncthreads();
     if (have)
       for (int k = 0; k < nbx.w; ++k) {
-        const int ty = nbx.z + k < nbands ? nbx.z + k : nbx.z + k - nbands;
-        atomicAdd(&cnt[ty], 1);
+        const int ty = band_of(k);
+        if (ty >= 0) atomicAdd(&cnt[ty], 1);
       }
     __syncthreads();
     total = block_exclusive_scan<NT>(cnt, nbands, s_wave);
@@ -733,7 +740,8 @@ __device__ __attribute__((always_inline)) void particle_phase(const ParticleArgs
     __syncthreads();  // every offset is read before the fill below advances cnt
     if (have)
       for (int k = 0; k < nbx.w; ++k) {
-        const int ty = nbx.z + k < nbands ? nbx.z + k : nbx.z + k - nbands;
+        const int ty = band_of(k);
+        if (ty < 0) continue;
         const int pos = atomicAdd(&cnt[ty], 1);
         if (pos < np * MAXSLOT) a.band_ids[pos] = p;
         else atomicOr(a.err, ERR_BAND);

@@ -9,9 +9,13 @@ namespace imb {
 
 struct Geometry {
   int tw, tw_log, th, rows;  // tile: tw x th cells (th already includes rows)
-  int tiles_x, tiles_y;
+  int tiles_x, tiles_y;      // tiles of the stored window
   int pitch;
   long long plane;
+  // the updated window: rows [y0, y0 + nyl) of the lattice, starting at lattice tile row ty_off
+  // of tiles_yg, lattice row y in plane row y - yoff (the whole lattice: 0, ny, 0, 0, tiles_y;
+  // a slab's planes hold nyl + 2 rows, a ghost row on each side: yoff = y0 - 1)
+  int y0, nyl, yoff, ty_off, tiles_yg;
 };
 
 struct DeviceLayout {
@@ -48,8 +52,10 @@ struct SimView {
 };
 
 size_t align_up(size_t v, size_t a);
-void sim_geometry(const imb_config& c, Geometry* g);
-size_t layout(const imb_config& c, char* base, DeviceLayout* L);
+// Geometry of the window of `rows` rows from y0 (rows = 0: the whole lattice); y0 must be a
+// multiple of the tile height.
+void sim_geometry(const imb_config& c, Geometry* g, int y0 = 0, int rows = 0);
+size_t layout(const imb_config& c, char* base, DeviceLayout* L, int y0 = 0, int rows = 0);
 int validate_config(const imb_config* c, std::string* why);
 int hip_fail(std::string* err, hipError_t e, const char* what);
 int map_device_error(int bits);
@@ -71,7 +77,14 @@ void drop_graphs(imb_sim* s);
 // cfg; its tile shape only sets how many tile rows the band lists can hold), so that the tile
 // shape can later change in place (set_tile_shape).
 int create_sim(const imb_config* cfg, const imb_config* layout_cfg, void* hip_stream,
-               void* dev_buf, size_t dev_bytes, imb_sim** out);
+               void* dev_buf, size_t dev_bytes, imb_sim** out, int win_y0 = 0,
+               int win_rows = 0);
+// A simulation of the window [y0, y0 + rows) of cfg's lattice (one slab of a lattice split in
+// y): its planes hold a ghost row on each side, which its step reads where set_window_ghosts
+// says that a neighbouring slab (not a wall) lies there.
+int create_window_sim(const imb_config* cfg, int y0, int rows, void* hip_stream, imb_sim** out);
+void set_window_ghosts(imb_sim* s, int below, int above);
+const char* create_error();
 // Changes the tile shape (geometry only; the band capacity must cover the new tile rows) and
 // rebuilds the disk tables for it.  Asynchronous.
 int set_tile_shape(imb_sim* s, int tile_w, int tile_rows);

@@ -39,21 +39,26 @@ static size_t storage_bytes(int storage) {
   return storage == IMB_STORAGE_F64 ? 8 : (storage == IMB_STORAGE_F32 ? 4 : 2);
 }
 
-void sim_geometry(const imb_config& c, Geometry* g) {
+void sim_geometry(const imb_config& c, Geometry* g, int y0, int rows) {
   g->tw = c.tile_w ? c.tile_w : 64;
   g->rows = c.tile_rows ? c.tile_rows : 1;
   g->tw_log = 0;
   while ((1 << g->tw_log) < g->tw) g->tw_log++;
   g->th = (BLOCK >> g->tw_log) * g->rows;
+  g->y0 = rows > 0 ? y0 : 0;
+  g->nyl = rows > 0 ? rows : c.ny;
+  g->yoff = rows > 0 ? g->y0 - 1 : 0;
   g->tiles_x = (c.nx + g->tw - 1) / g->tw;
-  g->tiles_y = (c.ny + g->th - 1) / g->th;
+  g->tiles_y = (g->nyl + g->th - 1) / g->th;
+  g->tiles_yg = (c.ny + g->th - 1) / g->th;
+  g->ty_off = g->y0 / g->th;
   g->pitch = (int)align_up((size_t)c.nx, 64);
-  g->plane = (long long)g->pitch * c.ny;
+  g->plane = (long long)g->pitch * (rows > 0 ? g->nyl + 2 : g->nyl);
 }
 
-size_t layout(const imb_config& c, char* base, DeviceLayout* L) {
+size_t layout(const imb_config& c, char* base, DeviceLayout* L, int y0, int rows) {
   Geometry g;
-  sim_geometry(c, &g);
+  sim_geometry(c, &g, y0, rows);
   const size_t mp = (size_t)std::max(c.max_particles, 1);
   const size_t es = storage_bytes(c.storage);
   Carver cv{base};
@@ -190,6 +195,10 @@ struct imb_sim {
   hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   bool use_graphs = true;
   int device = -1;  // the HIP device current at creation (its memory and stream live there)
+  // a slab of a lattice split in y (window rows; 0 = the whole lattice) and whether its ghost
+  // rows below and above hold a neighbouring slab's rows
+  int win_y0 = 0, win_rows = 0;
+  int ghost[2] = {0, 0};
 };
 
 static constexpr int GRAPH_LONG = 32;
@@ -213,6 +222,9 @@ LatticeArgs lattice_args(imb_sim* s, const void* src, void* dst) {
   }
   a.rho0 = s->cfg.rho0;
   a.src = src; a.dst = dst;
+  a.y0 = s->g.y0; a.nyl = s->g.nyl; a.yoff = s->g.yoff;
+  a.ty_off = s->g.ty_off; a.tiles_yg = s->g.tiles_yg;
+  a.ghost_lo = s->ghost[0]; a.ghost_hi = s->ghost[1];
   // the tables of the step reading this source (no source: those of the stored state)
   const int t = src ? (src == s->d.f[1] ? 1 : 0) : s->cur;
   a.np = s->np; a.tab = s->d.tab[t]; a.err = s->d.err;
@@ -245,6 +257,7 @@ ParticleArgs particle_args(imb_sim* s, int out_slot) {
   }
   a.uw_bot = s->cfg.wall_ux_bottom; a.uw_top = s->cfg.wall_ux_top;
   a.tiles_x = s->g.tiles_x; a.tiles_y = s->g.tiles_y; a.tw = s->g.tw; a.th = s->g.th;
+  a.tiles_yg = s->g.tiles_yg; a.ty_off = s->g.ty_off;
   a.s = s->d.ps; a.tab = s->d.tab[out_slot]; a.err = s->d.err;
   a.band_off = s->d.band_off[out_slot]; a.band_ids = s->d.band_ids[out_slot];
   a.direct = s->d.force;
@@ -393,7 +406,7 @@ static hipGraphExec_t capture_steps(imb_sim* s, int len, int start) {
 namespace imb {
 
 int create_sim(const imb_config* cfg, const imb_config* layout_cfg, void* hip_stream,
-               void* dev_buf, size_t dev_bytes, imb_sim** out) {
+               void* dev_buf, size_t dev_bytes, imb_sim** out, int win_y0, int win_rows) {
   if (!out) return IMB_EINVAL;
   *out = nullptr;
   std::string why;
@@ -412,11 +425,13 @@ int create_sim(const imb_config* cfg, const imb_config* layout_cfg, void* hip_st
     hipGetLastError();
     s->device = -1;
   }
-  sim_geometry(s->cfg, &s->g);
+  s->win_y0 = win_rows > 0 ? win_y0 : 0;
+  s->win_rows = win_rows > 0 ? win_rows : 0;
+  sim_geometry(s->cfg, &s->g, s->win_y0, s->win_rows);
   s->layout_cfg = *layout_cfg;
   if (!s->layout_cfg.tile_w) s->layout_cfg.tile_w = 64;
   if (!s->layout_cfg.tile_rows) s->layout_cfg.tile_rows = 1;
-  const size_t need = layout(s->layout_cfg, nullptr, nullptr);
+  const size_t need = layout(s->layout_cfg, nullptr, nullptr, s->win_y0, s->win_rows);
   if (dev_buf) {
     if (dev_bytes < need || ((uintptr_t)dev_buf & 255)) {
       g_create_error = "bound device buffer too small or not 256-byte aligned";
@@ -436,7 +451,7 @@ int create_sim(const imb_config* cfg, const imb_config* layout_cfg, void* hip_st
     s->owns = true;
   }
   s->mem_bytes = need;
-  layout(s->layout_cfg, s->mem, &s->d);
+  layout(s->layout_cfg, s->mem, &s->d, s->win_y0, s->win_rows);
   launch_fill_zero(s->mem, need, s->stream);
   rc = imb_init_equilibrium(s, s->cfg.rho0, 0.0, 0.0);
   if (!rc) rc = sync_and_check(s);
@@ -451,11 +466,26 @@ int create_sim(const imb_config* cfg, const imb_config* layout_cfg, void* hip_st
 
 int tile_rows_capacity(const imb_sim* s) {
   Geometry g;
-  sim_geometry(s->layout_cfg, &g);
+  sim_geometry(s->layout_cfg, &g, s->win_y0, s->win_rows);
   return g.tiles_y;
 }
 
+int create_window_sim(const imb_config* cfg, int y0, int rows, void* hip_stream, imb_sim** out) {
+  return create_sim(cfg, cfg, hip_stream, nullptr, 0, out, y0, rows);
+}
+
+void set_window_ghosts(imb_sim* s, int below, int above) {
+  s->ghost[0] = below ? 1 : 0;
+  s->ghost[1] = above ? 1 : 0;
+}
+
+const char* create_error() { return g_create_error.c_str(); }
+
 int set_tile_shape(imb_sim* s, int tile_w, int tile_rows) {
+  if (s->win_rows) {
+    s->err = "a slab's tile shape is fixed by its split";
+    return IMB_EINVAL;
+  }
   imb_config c = s->cfg;
   c.tile_w = tile_w;
   c.tile_rows = tile_rows;
@@ -630,7 +660,7 @@ int imb_set_particles(imb_sim* s, int32_t n, const double* x, const double* y, c
     if (ok && walls) ok = y[p] >= -0.5 && y[p] <= ny - 0.5;
     if (ok && !walls) ok = y[p] >= 0.0 && y[p] < ny;
     int4 b;
-    if (ok && !tile_box(x[p], y[p], r[p], nx, ny, walls, s->g.tiles_x, s->g.tiles_y, s->g.tw,
+    if (ok && !tile_box(x[p], y[p], r[p], nx, ny, walls, s->g.tiles_x, s->g.tiles_yg, s->g.tw,
                         s->g.th, &b)) {
       snprintf(buf, sizeof buf, "disk %d spans more than %d tiles", p, MAXSLOT);
       s->err = buf;

@@ -1,6 +1,7 @@
 // step.hip -- the lattice part of a coupled step as one kernel: workgroups [0, np) are the
 // disks' (disk_cells: covered cells, each disk's force and torque), the rest the tiles'
-// (fluid_tile: the cells no disk covers).  The disks' longer, latency-bound work is dispatched
+// (fluid_tile: the cells no disk covers).  A second instantiation runs a window of rows of a
+// lattice split in y (one slab, with halo faces).  The disks' longer, latency-bound work is dispatched
 // first and overlaps the tiles' streaming.  The particle phase follows as its own one-workgroup
 // kernel (particles.hip) on the same stream.
 #include <hip/hip_ext.h>
@@ -10,25 +11,29 @@
 
 namespace imb {
 
-template <class St>
+// W: the lattice is a window of rows of a larger one (a slab), with halo faces.
+template <class St, bool W>
 __device__ __forceinline__ void lattice_roles(const LatticeArgs& a) {
   const int b = blockIdx.x;
   if (b < a.np) {
-    disk_cells<St>(a, b);
+    disk_cells<St, W>(a, b);
     return;
   }
-  fluid_tile<St>(a, xcd_remap(b - a.np, a.tiles_x * a.tiles_y));
+  fluid_tile<St, W>(a, xcd_remap(b - a.np, a.tiles_x * a.tiles_y));
 }
 
 // FP32 arithmetic (FP32 or FP16 storage): held to 80 VGPRs, six wavefronts per SIMD.
-template <class St>
+template <class St, bool W>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void k_step(
     LatticeArgs a) {
-  lattice_roles<St>(a);
+  lattice_roles<St, W>(a);
 }
 
 // FP64 arithmetic needs more registers than that budget (it would spill).
-__global__ __launch_bounds__(BLOCK) void k_step_f64(LatticeArgs a) { lattice_roles<StoreF64>(a); }
+template <bool W>
+__global__ __launch_bounds__(BLOCK) void k_step_f64(LatticeArgs a) {
+  lattice_roles<StoreF64, W>(a);
+}
 
 // eps_tot of every cell (diagnostic / parity of the solid-ratio stage alone).
 template <class T>
@@ -61,10 +66,18 @@ void launch_lattice_step(int storage, const LatticeArgs& a, hipStream_t s, hipEv
     if (e0 || e1) hipExtLaunchKernelGGL(kernel, grid, dim3(BLOCK), 0, s, e0, e1, 0, a);
     else hipLaunchKernelGGL(kernel, grid, dim3(BLOCK), 0, s, a);
   };
+  if (a.nyl != a.ny) {  // a slab
+    switch (storage) {
+      case IMB_STORAGE_F64: go(k_step_f64<true>); break;
+      case IMB_STORAGE_F32: go(k_step<StoreF32, true>); break;
+      default: go(k_step<StoreF16, true>); break;
+    }
+    return;
+  }
   switch (storage) {
-    case IMB_STORAGE_F64: go(k_step_f64); break;
-    case IMB_STORAGE_F32: go(k_step<StoreF32>); break;
-    default: go(k_step<StoreF16>); break;
+    case IMB_STORAGE_F64: go(k_step_f64<false>); break;
+    case IMB_STORAGE_F32: go(k_step<StoreF32, false>); break;
+    default: go(k_step<StoreF16, false>); break;
   }
 }
 

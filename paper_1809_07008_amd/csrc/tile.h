@@ -15,8 +15,9 @@ struct PEntry {
 };
 
 // Disks whose tile box contains tile (tx, ty), sorted by id (so every sum over them has a fixed
-// order).  Candidates come from the tile row's band list written by the particle phase.  Returns
-// the count (capped at LMAX; overflow latches ERR_TILE_LIST).  Block-uniform control flow.
+// order).  Candidates come from the tile row's band list written by the particle phase; ty
+// counts inside the window (boxes are in lattice tile rows, ty + ty_off).  Returns the count
+// (capped at LMAX; overflow latches ERR_TILE_LIST).  Block-uniform control flow.
 template <class T>
 __device__ int build_tile_list(const LatticeArgs& a, int tx, int ty, PEntry<T>* pl, int* s_cnt,
                                int* s_pid, int* s_slot) {
@@ -30,7 +31,7 @@ __device__ int build_tile_list(const LatticeArgs& a, int tx, int ty, PEntry<T>* 
     int p = -1, slot = -1;
     if (k < b1) {
       p = a.band_ids[k];
-      slot = box_slot(a.tab.box[p], tx, ty, a.tiles_x, a.tiles_y);
+      slot = box_slot(a.tab.box[p], tx, ty + a.ty_off, a.tiles_x, a.tiles_yg);
     }
     const bool hit = slot >= 0;
     const unsigned long long m = __ballot(hit);
@@ -128,11 +129,14 @@ __device__ inline int covering_disks(const LatticeArgs& a, const PEntry<T>* pl, 
   return nc;
 }
 
-// Pull-stream load of the 9 populations arriving at (x, y).
-template <class St>
+// Pull-stream load of the 9 populations arriving at (x, y) (lattice coordinates).  W: the
+// lattice is a slab whose plane rows run from y0 - 1 to y0 + nyl (ghost rows included), so a
+// source row beyond the window is read from a ghost row instead of wrapping around the lattice.
+template <class St, bool W = false>
 __device__ inline void pull_load(const LatticeArgs& a, const typename St::S* src, int x, int y,
                                  typename St::T f[NQ]) {
   using T = typename St::T;
+  const int yoff = W ? a.yoff : 0;
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
     int xs = x - cx_of(i), ys = y - cy_of(i);
@@ -140,13 +144,13 @@ __device__ inline void pull_load(const LatticeArgs& a, const typename St::S* src
     long long idx;
     if (ys < 0 || ys >= a.ny) {
       if (a.walls) {  // half-way bounce-back: the link left through the wall and came back
-        idx = (long long)opp_of(i) * a.plane + (long long)y * a.pitch + x;
+        idx = (long long)opp_of(i) * a.plane + (long long)(y - yoff) * a.pitch + x;
         f[i] = St::load(src, idx, T(0));
         continue;
       }
-      ys = ys < 0 ? ys + a.ny : ys - a.ny;
+      if (!W) ys = ys < 0 ? ys + a.ny : ys - a.ny;
     }
-    idx = (long long)i * a.plane + (long long)ys * a.pitch + xs;
+    idx = (long long)i * a.plane + (long long)(ys - yoff) * a.pitch + xs;
     f[i] = St::load(src, idx, T(0));
   }
 }

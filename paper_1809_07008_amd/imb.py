@@ -58,6 +58,11 @@ EXPORTED = [
     "imb3_get_fields", "imb3_get_solid_field", "imb3_set_spheres", "imb3_step",
     "imb3_get_forces", "imb3_get_spheres", "imb3_sync", "imb3_set_kernel_timing",
     "imb3_get_kernel_timing", "imb3_last_error",
+    "imb_slab_create", "imb_slab_destroy", "imb_slab_layout", "imb_slab_init_equilibrium",
+    "imb_slab_set_populations", "imb_slab_get_populations", "imb_slab_get_fields",
+    "imb_slab_set_particles", "imb_slab_step", "imb_slab_get_forces",
+    "imb_slab_get_partial_forces", "imb_slab_get_particles", "imb_slab_set_kernel_timing",
+    "imb_slab_get_kernel_timing", "imb_slab_sync", "imb_slab_last_error",
 ]
 
 
@@ -175,6 +180,22 @@ def load_library():
         "imb3_set_kernel_timing": (C.c_int, [_VP, C.c_int]),
         "imb3_get_kernel_timing": (C.c_int, [_VP, _D, P(C.c_int64), _D, P(C.c_int64)]),
         "imb3_last_error": (C.c_char_p, [_VP]),
+        "imb_slab_create": (C.c_int, [P(Config), C.c_int32, _VP, P(_VP)]),
+        "imb_slab_destroy": (None, [_VP]),
+        "imb_slab_layout": (C.c_int, [_VP, _I32, _I32]),
+        "imb_slab_init_equilibrium": (C.c_int, [_VP, C.c_double, C.c_double, C.c_double]),
+        "imb_slab_set_populations": (C.c_int, [_VP, _D]),
+        "imb_slab_get_populations": (C.c_int, [_VP, _D]),
+        "imb_slab_get_fields": (C.c_int, [_VP, _D, _D, _D]),
+        "imb_slab_set_particles": (C.c_int, [_VP, C.c_int32, _D, _D, _D, _D, _D, _D, _I32]),
+        "imb_slab_step": (C.c_int, [_VP, C.c_int32]),
+        "imb_slab_get_forces": (C.c_int, [_VP, _D, _D, _D]),
+        "imb_slab_get_partial_forces": (C.c_int, [_VP, C.c_int32, _D, _D, _D]),
+        "imb_slab_get_particles": (C.c_int, [_VP, C.c_int32, _D, _D, _D, _D, _D]),
+        "imb_slab_set_kernel_timing": (C.c_int, [_VP, C.c_int]),
+        "imb_slab_get_kernel_timing": (C.c_int, [_VP, _D, _D, _D, P(C.c_int64)]),
+        "imb_slab_sync": (C.c_int, [_VP]),
+        "imb_slab_last_error": (C.c_char_p, [_VP]),
         "imb_strerror": (C.c_char_p, [C.c_int]),
         "imb_last_error": (C.c_char_p, [_VP]),
         "imb_version": (C.c_char_p, []),
@@ -605,6 +626,143 @@ def batch_from_cases(cases, tile_w=32, tile_rows=2, stream=None) -> Batch:
     for k, c in enumerate(cases):
         b.set_case_particles(k, c.particles)
     return b
+
+
+# ------------------------------------------------------- one GPU's share of a split lattice
+class Slabs:
+    """The lattice of ``cfg`` split in y into ``nslabs`` slabs (imb_slab_*): each slab stores its
+    rows and exchanges its faces with its neighbours; the library allocates the memory on the
+    current device."""
+
+    def __init__(self, cfg: Config, nslabs: int, stream=None):
+        lib = load_library()
+        self.cfg = cfg
+        self.nslabs = int(nslabs)
+        self._h = None
+        h = C.c_void_p()
+        self._check(lib.imb_slab_create(C.byref(cfg), self.nslabs, _stream_handle(stream),
+                                        C.byref(h)), "imb_slab_create", handle=False)
+        self._h = h
+        self.n = 0
+
+    def _check(self, rc, what, handle=True):
+        if rc != IMB_OK:
+            msg = load_library().imb_slab_last_error(self._h if handle else None)
+            raise ImbError(rc, what, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().imb_slab_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def shape(self):
+        return (self.cfg.ny, self.cfg.nx)
+
+    def layout(self):
+        """(first row, row count) of each slab."""
+        y0 = np.zeros(self.nslabs, np.int32)
+        rows = np.zeros(self.nslabs, np.int32)
+        self._check(load_library().imb_slab_layout(self._h, y0.ctypes.data_as(_I32),
+                                                   rows.ctypes.data_as(_I32)), "imb_slab_layout")
+        return y0, rows
+
+    def init_equilibrium(self, rho=1.0, ux=0.0, uy=0.0):
+        self._check(load_library().imb_slab_init_equilibrium(self._h, rho, ux, uy),
+                    "imb_slab_init_equilibrium")
+
+    def set_populations(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        if f.shape != (9, self.cfg.ny, self.cfg.nx):
+            raise ValueError("populations must have shape (9, ny, nx)")
+        self._check(load_library().imb_slab_set_populations(self._h, _dp(f)),
+                    "imb_slab_set_populations")
+
+    def populations(self) -> np.ndarray:
+        f = np.empty((9, self.cfg.ny, self.cfg.nx))
+        self._check(load_library().imb_slab_get_populations(self._h, _dp(f)),
+                    "imb_slab_get_populations")
+        return f
+
+    def fields(self):
+        rho, ux, uy = (np.empty(self.shape) for _ in range(3))
+        self._check(load_library().imb_slab_get_fields(self._h, _dp(rho), _dp(ux), _dp(uy)),
+                    "imb_slab_get_fields")
+        return rho, ux, uy
+
+    def set_particles(self, x, y, r, vx=None, vy=None, om=None, mode=None):
+        n = len(x)
+        z = np.zeros(n)
+        arrs = [_f64(a, n) for a in (x, y, r, z if vx is None else vx, z if vy is None else vy,
+                                      z if om is None else om)]
+        md = np.ascontiguousarray(np.zeros(n, np.int32) if mode is None else mode, np.int32)
+        if n == 0:
+            arrs = [np.zeros(1) for _ in range(6)]
+            md = np.zeros(1, np.int32)
+        self._check(load_library().imb_slab_set_particles(self._h, n, *(_dp(a) for a in arrs),
+                                                          md.ctypes.data_as(_I32)),
+                    "imb_slab_set_particles")
+        self.n = n
+
+    def set_case_particles(self, p):
+        self.set_particles(p.x, p.y, p.r, p.vx, p.vy, p.om, p.mode)
+
+    def step(self, n: int = 1):
+        self._check(load_library().imb_slab_step(self._h, int(n)), "imb_slab_step")
+
+    def forces(self):
+        m = max(self.n, 1)
+        fx, fy, tz = np.zeros(m), np.zeros(m), np.zeros(m)
+        self._check(load_library().imb_slab_get_forces(self._h, _dp(fx), _dp(fy), _dp(tz)),
+                    "imb_slab_get_forces")
+        return fx[:self.n], fy[:self.n], tz[:self.n]
+
+    def partial_forces(self, slab: int):
+        m = max(self.n, 1)
+        fx, fy, tz = np.zeros(m), np.zeros(m), np.zeros(m)
+        self._check(load_library().imb_slab_get_partial_forces(self._h, int(slab), _dp(fx),
+                                                               _dp(fy), _dp(tz)),
+                    "imb_slab_get_partial_forces")
+        return fx[:self.n], fy[:self.n], tz[:self.n]
+
+    def particles(self, slab: int = 0):
+        m = max(self.n, 1)
+        a = [np.zeros(m) for _ in range(5)]
+        self._check(load_library().imb_slab_get_particles(self._h, int(slab),
+                                                          *(_dp(v) for v in a)),
+                    "imb_slab_get_particles")
+        return tuple(v[:self.n] for v in a)
+
+    def set_kernel_timing(self, enable: bool):
+        self._check(load_library().imb_slab_set_kernel_timing(self._h, int(bool(enable))),
+                    "imb_slab_set_kernel_timing")
+
+    def kernel_timing(self):
+        """(lattice ms per slab, exchange ms, particle-phase ms per slab, timed steps)."""
+        lat = np.zeros(self.nslabs)
+        par = np.zeros(self.nslabs)
+        xch = C.c_double()
+        n = C.c_int64()
+        self._check(load_library().imb_slab_get_kernel_timing(self._h, _dp(lat), C.byref(xch),
+                                                              _dp(par), C.byref(n)),
+                    "imb_slab_get_kernel_timing")
+        return lat, xch.value, par, n.value
+
+    def sync(self):
+        self._check(load_library().imb_slab_sync(self._h), "imb_slab_sync")
+
+
+def slabs_from_case(case, nslabs, storage=None, tile_w=64, tile_rows=1, stream=None) -> Slabs:
+    """Slabs of a workload case, particles uploaded, fluid at rest."""
+    s = Slabs(config_from_case(case, None, tile_w, tile_rows, storage), nslabs, stream)
+    s.set_case_particles(case.particles)
+    return s
 
 
 # ------------------------------------------------------- three dimensions: D3Q19 with spheres

@@ -230,6 +230,52 @@ def no_allocation_step():
         check("step_noalloc equals step (%s)" % case.name, same, "")
 
 
+def slab_cases():
+    """A lattice split in y: the slabs' composition against the FP64 oracle (free disks, walls
+    and periodic, disks spanning up to four slabs and the periodic seam), and bit for bit
+    against the whole lattice where forces do not feed back (fixed and prescribed disks, FP32
+    and FP16)."""
+    seam = overlap_case(False)
+    p = seam.particles.copy()
+    p.y[3] = 1.2  # across the periodic boundary in y
+    seam = seam.with_(particles=p)
+    for case, tile, nslab in ((moving_case(), (32, 2), 2), (moving_case(), (64, 1), 10),
+                              (seam, (32, 2), 3), (seam, (64, 1), 4),
+                              (moving_case().with_(uw_bot=0.02, uw_top=-0.01), (64, 1), 3)):
+        ref = oracle_of(case)
+        ref.step(case.steps)
+        sl = imb.Slabs(imb.config_from_case(case, None, tile[0], tile[1], "f64"), nslab, S)
+        sl.set_case_particles(case.particles)
+        sl.step(case.steps)
+        fx, fy, tz = sl.forces()
+        Fx, Fy, Tz = ref.forces()
+        scale = max(np.abs(Fx).max(), np.abs(Fy).max(), 1e-300)
+        ferr = max(np.abs(fx - Fx).max(), np.abs(fy - Fy).max(), np.abs(tz - Tz).max() / 10) / scale
+        perr = np.abs(sl.populations() - ref.populations()).max()
+        same = all(np.array_equal(a, b) for k in range(1, nslab)
+                   for a, b in zip(sl.particles(0), sl.particles(k)))
+        check("slabs fp64 %s x%d tile %dx%d" % (case.name, nslab, *tile),
+              ferr < 1e-12 and perr < 1e-14 and same,
+              "force %.2e populations %.2e replicas equal %s" % (ferr, perr, same))
+    fixed = seam.particles.copy()
+    fixed.mode[:] = np.array([1, 2, 2, 1], np.int32)
+    for storage in ("f32", "f16"):
+        case = seam.with_(particles=fixed, storage=storage)
+        whole = sim_of(case, storage, (64, 1))
+        whole.step(3)
+        sl = imb.Slabs(imb.config_from_case(case, None, 64, 1, storage), 3, S)
+        sl.set_case_particles(case.particles)
+        sl.step(3)
+        fw, fs = whole.forces(), sl.forces()
+        ferr = max(np.abs(a - b).max() for a, b in zip(fw, fs)) / np.abs(fw[0]).max()
+        parts = [sl.partial_forces(k) for k in range(3)]
+        psum = [sum(pk[c] for pk in parts) for c in range(3)]
+        check("slabs %s equal the whole lattice (fixed disks)" % storage,
+              np.array_equal(whole.populations(), sl.populations()) and ferr < 1e-5 and
+              all(np.array_equal(a, b) for a, b in zip(psum, fs)),
+              "force %.1e" % ferr)
+
+
 def three_d():
     """D3Q19 with spheres against the 3D oracle: fixed and prescribed spheres across the periodic
     seams, two spheres sharing cells, walls and periodic y, random populations, every tile width."""
@@ -274,7 +320,7 @@ def three_d():
 
 
 if __name__ == "__main__":
-    for fn in (three_d, no_allocation_step, spring_table_limit, fp64_parity, wide_tiles,
+    for fn in (slab_cases, three_d, no_allocation_step, spring_table_limit, fp64_parity, wide_tiles,
                reduced_precision, roundtrip, adjoint, batch):
         fn()
     print("all emulated cases passed", flush=True)
