@@ -239,6 +239,26 @@ __host__ __device__ inline unsigned pcg_hash(unsigned v) {
   return (word >> 22u) ^ word;
 }
 
+// The random words of one cell's stochastic-rounding stores: w0 = pcg_hash of (step counter,
+// lattice cell), then four xorshift32 steps (Marsaglia, Xorshift RNGs, J. Stat. Softw. 8(14),
+// 2003; shifts 13, 17, 5), so a cell costs one hash instead of one per population.  The normal
+// binary16 range uses the top 13 bits of a word (encode_sr), so each word serves two
+// populations: population 2k takes word k, population 2k + 1 word k shifted left by 13 (its
+// bits 6..18 on top).
+__device__ inline void sr_words(unsigned seed, unsigned cell, unsigned rnd[NQ]) {
+  unsigned w = pcg_hash(seed * 0x9E3779B9u + cell);
+#pragma unroll
+  for (int k = 0; k < (NQ + 1) / 2; ++k) {
+    if (k > 0) {
+      w ^= w << 13;
+      w ^= w >> 17;
+      w ^= w << 5;
+    }
+    rnd[2 * k] = w;
+    if (2 * k + 1 < NQ) rnd[2 * k + 1] = w << 13;
+  }
+}
+
 // Block index -> tile index so that consecutive tiles run on the same XCD (workgroups are
 // dispatched round-robin over the 8 XCDs, each with its own L2).
 __device__ inline int xcd_remap(int b, int n) {

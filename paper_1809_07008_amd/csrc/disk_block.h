@@ -92,9 +92,10 @@ __device__ void fluid_tile(const LatticeArgs& a, int tile) {
     S out[NQ];
     if constexpr (St::stochastic) {
       // the random words follow the lattice cell, not its place in the window
-      const unsigned r0 = pcg_hash(seed * 0x9E3779B9u + (unsigned)((long long)y * a.pitch + x));
+      unsigned rnd[NQ];
+      sr_words(seed, (unsigned)((long long)y * a.pitch + x), rnd);
 #pragma unroll
-      for (int i = 0; i < NQ; ++i) out[i] = St::encode_sr(fo[i], pcg_hash(r0 + (unsigned)i));
+      for (int i = 0; i < NQ; ++i) out[i] = St::encode_sr(fo[i], rnd[i]);
     } else {
 #pragma unroll
       for (int i = 0; i < NQ; ++i) out[i] = St::encode(fo[i]);
@@ -360,9 +361,10 @@ __device__ void disk_cells(const LatticeArgs& a, int p) {
     const long long off = (long long)(y - (W ? a.yoff : 0)) * a.pitch + x;
     S out[NQ];
     if constexpr (St::stochastic) {
-      const unsigned r0 = pcg_hash(seed * 0x9E3779B9u + (unsigned)((long long)y * a.pitch + x));
+      unsigned rnd[NQ];
+      sr_words(seed, (unsigned)((long long)y * a.pitch + x), rnd);
 #pragma unroll
-      for (int i = 0; i < NQ; ++i) out[i] = St::encode_sr(fo[i], pcg_hash(r0 + (unsigned)i));
+      for (int i = 0; i < NQ; ++i) out[i] = St::encode_sr(fo[i], rnd[i]);
     } else {
 #pragma unroll
       for (int i = 0; i < NQ; ++i) out[i] = St::encode(fo[i]);

@@ -131,6 +131,34 @@ struct AreaWalk {
   }
 };
 
+// The crossings of one edge of the walk, from the powers ps, pe of its start and end corners:
+// an edge running from inside to outside holds exactly one exit, from outside to inside one
+// entry, inside to inside none, outside to outside none or an entry and an exit (the circle
+// dips into it).  So the walk's vertices alternate consistently even where a corner lies
+// within rounding of the circle and the half-chord test alone would disagree with the corner's
+// power.  cc_in, cc_out: edge coordinates of the entry and exit points of the edge's line
+// (+-h); the offset of a crossing runs from the edge's lower end `low` (power plow) to its
+// upper end (power phigh) and is clamped to the edge; `fixed` is the other cell coordinate.
+template <class T>
+__host__ __device__ inline void edge_crossings(AreaWalk<T>& w, T ps, T pe, T plow, T phigh,
+                                               bool line_cut, T cc_in, T cc_out, T low, T high,
+                                               T fixed, bool horizontal) {
+  const bool si = ps >= T(0), ei = pe >= T(0);
+  auto put = [&](T cc, int kind) {
+    const T off = fmin(T(1), fmax(T(0), crossing_offset(cc, low, plow, phigh)));
+    if (horizontal) w.add(off, fixed, kind);
+    else w.add(fixed, off, kind);
+  };
+  if (!si && ei) {
+    put(cc_in, 1);
+  } else if (si && !ei) {
+    put(cc_out, 2);
+  } else if (!si && !ei && line_cut && fmin(cc_in, cc_out) > low && fmax(cc_in, cc_out) < high) {
+    put(cc_in, 1);
+    put(cc_out, 2);
+  }
+}
+
 template <class T>
 __host__ __device__ __noinline__ T cut_cell_fraction(T r, T dx, T dy) {
   // edges (rounded; they only locate the crossings, whose offsets come from the exact corner
@@ -142,33 +170,29 @@ __host__ __device__ __noinline__ T cut_cell_fraction(T r, T dx, T dy) {
   w.r = r; w.prev_kind = -1; w.first_kind = -1; w.twice_area = T(0); w.seg = T(0);
   w.u0 = w.v0 = w.pu = w.pv = T(0);
   w.cx = -x0; w.cy = -y0;
-  // bottom edge: (x0, y0) -> (x1, y0), u increasing; crossings x = -h (entry), +h (exit)
+  // bottom edge: (x0, y0) -> (x1, y0), u increasing; entry at x = -h, exit at +h
   if (p00 >= T(0)) w.add(T(0), T(0), 0);
-  if (fabs(y0) < r) {
+  {
     const T h = half_chord(r, y0);
-    if (-h > x0 && -h < x1) w.add(crossing_offset(-h, x0, p00, p10), T(0), 1);
-    if (h > x0 && h < x1) w.add(crossing_offset(h, x0, p00, p10), T(0), 2);
+    edge_crossings(w, p00, p10, p00, p10, fabs(y0) < r, -h, h, x0, x1, T(0), true);
   }
-  // right edge: (x1, y0) -> (x1, y1), v increasing; crossings y = -h (entry), +h (exit)
+  // right edge: (x1, y0) -> (x1, y1), v increasing; entry at y = -h, exit at +h
   if (p10 >= T(0)) w.add(T(1), T(0), 0);
-  if (fabs(x1) < r) {
+  {
     const T h = half_chord(r, x1);
-    if (-h > y0 && -h < y1) w.add(T(1), crossing_offset(-h, y0, p10, p11), 1);
-    if (h > y0 && h < y1) w.add(T(1), crossing_offset(h, y0, p10, p11), 2);
+    edge_crossings(w, p10, p11, p10, p11, fabs(x1) < r, -h, h, y0, y1, T(1), false);
   }
-  // top edge: (x1, y1) -> (x0, y1), u decreasing; crossings x = +h (entry), -h (exit)
+  // top edge: (x1, y1) -> (x0, y1), u decreasing; entry at x = +h, exit at -h
   if (p11 >= T(0)) w.add(T(1), T(1), 0);
-  if (fabs(y1) < r) {
+  {
     const T h = half_chord(r, y1);
-    if (h > x0 && h < x1) w.add(crossing_offset(h, x0, p01, p11), T(1), 1);
-    if (-h > x0 && -h < x1) w.add(crossing_offset(-h, x0, p01, p11), T(1), 2);
+    edge_crossings(w, p11, p01, p01, p11, fabs(y1) < r, h, -h, x0, x1, T(1), true);
   }
-  // left edge: (x0, y1) -> (x0, y0), v decreasing; crossings y = +h (entry), -h (exit)
+  // left edge: (x0, y1) -> (x0, y0), v decreasing; entry at y = +h, exit at -h
   if (p01 >= T(0)) w.add(T(0), T(1), 0);
-  if (fabs(x0) < r) {
+  {
     const T h = half_chord(r, x0);
-    if (h > y0 && h < y1) w.add(T(0), crossing_offset(h, y0, p00, p01), 1);
-    if (-h > y0 && -h < y1) w.add(T(0), crossing_offset(-h, y0, p00, p01), 2);
+    edge_crossings(w, p01, p00, p00, p01, fabs(x0) < r, h, -h, y0, y1, T(0), false);
   }
   T e;
   if (w.prev_kind < 0) {
@@ -178,6 +202,84 @@ __host__ __device__ __noinline__ T cut_cell_fraction(T r, T dx, T dy) {
     e = w.finish();
   }
   return fmin(T(1), fmax(T(0), e));
+}
+
+// Single precision, the common cut (a disk of radius >= 2 whose circle crosses the cell's
+// boundary exactly twice): without branches, from the corners' sides of the circle.  The
+// corners inside form one run; the entry lies on the edge that arrives at its first corner, the
+// exit on the edge that leaves its last.  In cell coordinates the bottom and left edges add
+// nothing to the shoelace sum, the right and top edges their inside lengths, the chord from
+// exit to entry its cross product; the circular segment beyond that chord is
+// r^2 (phi - sin phi) / 2 with phi - sin phi = 4 t^3 sum_k C(2k, k) 4^-k t^(2k) / (2k + 3),
+// t = chord / 2r (the series of 4 int_0^t s^2 (1 - s^2)^(-1/2) ds), five terms for t <= 1/4.
+// Returns false (and the caller takes the exact walk) for a corner within rounding of the
+// circle, a disk reaching an edge whose both ends lie outside it, a smaller disk or a longer
+// chord.
+__host__ __device__ inline bool one_arc_fraction(float r, float dx, float dy, float* eps) {
+  if (!(r >= 2.0f)) return false;
+  const float x0 = dx - 0.5f, x1 = dx + 0.5f, y0 = dy - 0.5f, y1 = dy + 0.5f;
+  const float rr = r * r;
+  // corner powers, counter-clockwise from (x0, y0); their rounding stays below tau
+  const float q0 = rr - (x0 * x0 + y0 * y0), q1 = rr - (x1 * x1 + y0 * y0);
+  const float q2 = rr - (x1 * x1 + y1 * y1), q3 = rr - (x0 * x0 + y1 * y1);
+  const float tau = 1e-6f * (r + 1.0f) * (r + 1.0f);
+  if (fabsf(q0) <= tau || fabsf(q1) <= tau || fabsf(q2) <= tau || fabsf(q3) <= tau) return false;
+  const bool in0 = q0 > 0.0f, in1 = q1 > 0.0f, in2 = q2 > 0.0f, in3 = q3 > 0.0f;
+  // edge e runs from corner e to corner e + 1: its line coordinate l_e and the parameter
+  // s = base_e - h (entry) or base_e + h (exit) of its crossings, h the half chord at l_e
+  auto chord = [&](float l) {
+    const float a = fabsf(l);
+    return a < r ? sqrtf((r - a) * (r + a)) : -1.0f;
+  };
+  const float h0 = chord(y0), h1 = chord(x1), h2 = chord(y1), h3 = chord(x0);
+  const float b0 = -x0, b1 = -y0, b2 = x1, b3 = y1;  // an edge's crossings: s = b -+ h
+  // an edge with both ends outside must not meet the disk
+  auto dips = [&](bool a, bool b, float h, float base) {
+    return !a && !b && h >= 0.0f && base + h > 0.0f && base - h < 1.0f;
+  };
+  if (dips(in0, in1, h0, b0) || dips(in1, in2, h1, b1) || dips(in2, in3, h2, b2) ||
+      dips(in3, in0, h3, b3))
+    return false;
+  const int nin = (!in0 && in1) + (!in1 && in2) + (!in2 && in3) + (!in3 && in0);
+  if (nin != 1) return false;  // with one entry there is one exit
+  // entry edge: outside start, inside end; exit edge: inside start, outside end
+  const int ent = (!in0 && in1) ? 0 : ((!in1 && in2) ? 1 : ((!in2 && in3) ? 2 : 3));
+  const int ext = (in0 && !in1) ? 0 : ((in1 && !in2) ? 1 : ((in2 && !in3) ? 2 : 3));
+  const float he = ent == 0 ? h0 : (ent == 1 ? h1 : (ent == 2 ? h2 : h3));
+  const float hx = ext == 0 ? h0 : (ext == 1 ? h1 : (ext == 2 ? h2 : h3));
+  if (he < 0.0f || hx < 0.0f) return false;
+  // The crossings' parameters from the exact power P of the nearer corner, which lies outside:
+  // the entry edge's start corner, s = P / (c - h), and the exit edge's end corner,
+  // s = 1 + P / (h + d) (c = x0, y0, -x1, -y1 and d = x1, y1, -x0, -y0 by edge), as the
+  // walk's crossing offsets, so a crossing near a corner keeps full relative precision.
+  // Corner k is at (x0 or x1, y0 or y1) with signs (-,-), (+,-), (+,+), (-,+).
+  const int ke = ent, kx = (ext + 1) & 3;
+  const float pe = corner_power(r, dx, dy, (ke == 1 || ke == 2) ? 1.0f : -1.0f,
+                                ke >= 2 ? 1.0f : -1.0f);
+  const float px = corner_power(r, dx, dy, (kx == 1 || kx == 2) ? 1.0f : -1.0f,
+                                kx >= 2 ? 1.0f : -1.0f);
+  const float ce = ent == 0 ? x0 : (ent == 1 ? y0 : (ent == 2 ? -x1 : -y1));
+  const float cx = ext == 0 ? x1 : (ext == 1 ? y1 : (ext == 2 ? -x0 : -y0));
+  const float se = fminf(1.0f, fmaxf(0.0f, pe / (ce - he)));
+  const float sx = fminf(1.0f, fmaxf(0.0f, 1.0f + px / (hx + cx)));
+  // the points in cell coordinates: edge 0 (s, 0), 1 (1, s), 2 (1 - s, 1), 3 (0, 1 - s)
+  const float eu = ent == 0 ? se : (ent == 1 ? 1.0f : (ent == 2 ? 1.0f - se : 0.0f));
+  const float ev = ent == 0 ? 0.0f : (ent == 1 ? se : (ent == 2 ? 1.0f : 1.0f - se));
+  const float xu = ext == 0 ? sx : (ext == 1 ? 1.0f : (ext == 2 ? 1.0f - sx : 0.0f));
+  const float xv = ext == 0 ? 0.0f : (ext == 1 ? sx : (ext == 2 ? 1.0f : 1.0f - sx));
+  // inside lengths of the right and top edges
+  const float len1 = in1 && in2 ? 1.0f : (in1 ? sx : (in2 ? 1.0f - se : 0.0f));
+  const float len2 = in2 && in3 ? 1.0f : (in2 ? sx : (in3 ? 1.0f - se : 0.0f));
+  const float twice = len1 + len2 + (xu * ev - eu * xv);
+  const float du = eu - xu, dv = ev - xv;
+  const float t2 = (du * du + dv * dv) / (4.0f * rr);
+  if (t2 > 0.0625f) return false;
+  const float t = sqrtf(t2);
+  const float series =
+      4.0f / 3.0f +
+      t2 * (2.0f / 5.0f + t2 * (3.0f / 14.0f + t2 * (5.0f / 36.0f + t2 * (35.0f / 352.0f))));
+  *eps = fminf(1.0f, fmaxf(0.0f, 0.5f * twice + 0.5f * rr * t * t2 * series));
+  return true;
 }
 
 // eps of the unit cell centred at (dx, dy) relative to the disk centre.  The cut-cell branch is
@@ -244,6 +346,10 @@ __host__ __device__ inline T cell_solid_ratio(T r, T dx, T dy, int n) {
   const T fx = fabs(x0) > fabs(x1) ? fabs(x0) : fabs(x1);
   const T fy = fabs(y0) > fabs(y1) ? fabs(y0) : fabs(y1);
   if (fx * fx + fy * fy <= r * r) return T(1);
+  if constexpr (sizeof(T) == 4) {  // single precision: the common cut without branches
+    float e;
+    if (n == 0 && one_arc_fraction(r, dx, dy, &e)) return e;
+  }
   return cut_ratio(r, dx, dy, n);
 }
 
