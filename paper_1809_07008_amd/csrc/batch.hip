@@ -125,7 +125,8 @@ __device__ __attribute__((noinline)) void particle_phase_call(const ParticleArgs
   particle_phase<BLOCK>(a, lds);
 }
 
-__global__ __launch_bounds__(BLOCK) void k_batch(BatchArgs B, const BatchChannel* __restrict__ ch) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void k_batch(
+    BatchArgs B, const BatchChannel* __restrict__ ch) {
   __shared__ int s_item, s_abort;
   __shared__ int s_hch[2][MAX_BATCH];
   __shared__ int s_hpref[2][MAX_BATCH + 1];
