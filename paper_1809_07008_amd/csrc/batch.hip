@@ -244,7 +244,7 @@ struct imb_batch {
   std::vector<BatchChannel> h_ch;
   std::vector<int> h_half;
   int half_n[2] = {0, 0}, half_t[2] = {0, 0}, half_d[2] = {0, 0};
-  int all_d = 0, all_t = 0;    // disks and tiles of all channels
+  int all_d = 0, all_t = 0;    // disk items (dparts per disk) and tiles of all channels
   int schedule = IMB_BATCH_PERSISTENT;
   int grid = 0, grid_user = 0, occupancy = 0;
   int tile_w = 32, tile_rows = 2;
@@ -354,7 +354,7 @@ int refresh(imb_batch* b) {
       hpref[h * (MAX_BATCH + 1) + k] = acc;
       hdpref[h * (MAX_BATCH + 1) + k] = dacc;
       acc += tiles[hc[h][k]];
-      dacc += b->h_ch[hc[h][k]].la[0].np;
+      dacc += b->h_ch[hc[h][k]].la[0].np * b->h_ch[hc[h][k]].la[0].dparts;  // disk items
     }
     for (size_t k = hc[h].size(); k <= (size_t)MAX_BATCH; ++k) {
       hpref[h * (MAX_BATCH + 1) + k] = acc;
@@ -371,7 +371,7 @@ int refresh(imb_batch* b) {
     for (int c = 0; c < b->nch; ++c) {
       all[c] = dacc;
       all[MAX_BATCH + 1 + c] = tacc;
-      dacc += b->h_ch[c].la[0].np;
+      dacc += b->h_ch[c].la[0].np * b->h_ch[c].la[0].dparts;
       tacc += tiles[c];
     }
     for (int c = b->nch; c <= MAX_BATCH; ++c) {

@@ -21,6 +21,11 @@ constexpr int MAXSLOT = 64;        // tiles per disk box (partial-sum slots per 
 constexpr int MAX_BANDS = 6144;    // tile rows (bands) of one lattice
 constexpr int NBMAX = 32;          // DEM neighbour-list capacity per disk
 constexpr int MAX_PARTICLES = 512;
+// Most workgroups of the lattice step per disk (a simulation's `dparts`, 1 or 2): each takes a
+// contiguous part of the disk's cells and writes its own share of the disk's force and torque,
+// force[dparts p + part].  Two halve a disk's latency where few disks run beside few tiles (a
+// slab); on a whole lattice the tiles hide it and one per disk is faster.
+constexpr int DISK_PARTS = 2;
 constexpr int PBLOCK = 512;        // threads of the particle-phase workgroup (one per disk)
 constexpr int HK = 6;         // tangential springs per disk (disks touching it at once)
 constexpr double DEM_SKIN = 5.0;   // neighbour-list skin (lattice units)
@@ -89,7 +94,8 @@ struct LatticeArgs {
   int seed_slot;         //   seed[seed_slot], tile 0 writes seed[seed_slot ^ 1] = it + 1
   const int* nbr;        // [np][NBMAX] neighbour lists (ascending ids) and their lengths
   const int* nnbr;
-  double4* force;        // [np] force and torque of this step (Fx, Fy, Tz, 0)
+  double4* force;        // [np][dparts] shares of each disk's force and torque (Fx, Fy, Tz, 0)
+  int dparts;            // workgroups (and shares) per disk, 1 or 2
   // The rows [y0, y0 + nyl) of the lattice that this step updates (a slab of a lattice split in
   // y; the whole lattice: y0 = 0, nyl = ny).  Lattice row y is stored in plane row y - yoff: a
   // slab's planes hold a ghost row on each side (yoff = y0 - 1), where its neighbours' crossing
@@ -159,7 +165,8 @@ struct ParticleArgs {
   int tiles_yg, ty_off;   // the lattice's tile rows; band lists cover rows [ty_off, +tiles_y)
   ParticleState s;
   ParticleTable tab;
-  const double4* direct;  // [np] force and torque of the step (Fx, Fy, Tz, 0)
+  const double4* direct;  // [np][dparts] shares of the step's force and torque, added in order
+  int dparts;
   int build_lists;        // maintain the neighbour lists even when no disk is free
   int* band_off;   // written with the table: per tile row, the disks whose box touches it
   int* band_ids;   // capacity np * MAXSLOT

@@ -136,12 +136,14 @@ __device__ void fluid_tile(const LatticeArgs& a, int tile) {
   }
 }
 
-// Covered cells of disk p's box, one BLOCK-thread workgroup: IMB collision of the cells p owns,
-// p's own force and torque over every cell it covers, written to a.force[p].  W: only the cells
-// in the window, and a.force[p] is the window's share of the sums (zero when the disk's box
-// misses the window).
+// Covered cells of disk p's box, a.dparts BLOCK-thread workgroups per disk (item = dparts p +
+// part; each takes a contiguous part of the disk's cell enumeration): IMB collision of the
+// cells p owns, p's force and torque over the part's cells that p covers, written to
+// a.force[item].  W: only the cells in the window, so the shares are the window's (zero when the
+// disk's box misses the window).
 template <class St, bool W = false>
-__device__ void disk_cells(const LatticeArgs& a, int p) {
+__device__ void disk_cells(const LatticeArgs& a, int item) {
+  const int p = item / a.dparts, part = item - p * a.dparts;
   using T = typename St::T;
   using S = typename St::S;
   __shared__ PEntry<T> s_de[NBMAX + 1];  // disk p and its neighbours, ascending id
@@ -172,7 +174,7 @@ __device__ void disk_cells(const LatticeArgs& a, int p) {
       }
     }
     if (!touch) {  // block-uniform
-      if (tid == 0) a.force[p] = make_double4(0.0, 0.0, 0.0, 0.0);
+      if (tid == 0) a.force[item] = make_double4(0.0, 0.0, 0.0, 0.0);
       return;
     }
   }
@@ -281,7 +283,10 @@ __device__ void disk_cells(const LatticeArgs& a, int p) {
 
   const T tau0 = (T)a.tau0, csm = (T)a.cs, gx = (T)a.gx, gy = (T)a.gy, rho0 = (T)a.rho0;
   Acc<T> afx{T(0), T(0)}, afy{T(0), T(0)}, atz{T(0), T(0)};
-  for (int c = tid; c < ncell; c += BLOCK) {
+  // this workgroup's part of the enumeration
+  const int cpart = a.dparts > 1 ? (ncell + 1) / 2 : ncell;
+  const int cbeg = part * cpart, cend = cbeg + cpart < ncell ? cbeg + cpart : ncell;
+  for (int c = cbeg + tid; c < cend; c += BLOCK) {
     int x, y;
     unsigned long long cand = nd >= 64 ? ~0ull : (1ull << nd) - 1ull;  // entries to test
     if (rowwise) {  // the row holding cell c: s_rpre[k] <= c < s_rpre[k + 1]
@@ -389,7 +394,7 @@ __device__ void disk_cells(const LatticeArgs& a, int p) {
       for (int w = 1; w < WAVES; ++w) v.add(s_fr[w][c]);
       out[c] = (double)v.hi + (double)v.lo;
     }
-    a.force[p] = make_double4(out[0], out[1], out[2], 0.0);
+    a.force[item] = make_double4(out[0], out[1], out[2], 0.0);
   }
 }
 

@@ -184,10 +184,16 @@ __device__ __attribute__((always_inline)) void particle_phase(const ParticleArgs
   // ---- 1. forces of the step that just ran
   double Fx = 0.0, Fy = 0.0, Tz = 0.0;
   if (have && a.do_finalize) {
-    const double4 d = a.direct[p];
-    Fx = d.x;
-    Fy = d.y;
-    Tz = d.z;
+    const double4 d0 = a.direct[a.dparts * p];
+    Fx = d0.x;
+    Fy = d0.y;
+    Tz = d0.z;
+    if (a.dparts > 1) {  // the second share
+      const double4 d1 = a.direct[a.dparts * p + 1];
+      Fx += d1.x;
+      Fy += d1.y;
+      Tz += d1.z;
+    }
   } else if (have) {
     Fx = s.Fx[p];
     Fy = s.Fy[p];

@@ -31,7 +31,7 @@ struct DeviceLayout {
   double* J;
   double* w;  // objective weights wfx, wfy, wtz (3 x capacity)
   unsigned* seed;  // [2] stochastic-rounding step counters
-  double4* force;  // [capacity] per-disk force and torque written by the lattice step
+  double4* force;  // [capacity][DISK_PARTS] per-disk force and torque shares of the lattice step
 };
 
 struct AdjointState;

@@ -89,7 +89,7 @@ size_t layout(const imb_config& c, char* base, DeviceLayout* L, int y0, int rows
   d.J = cv.take<double>(1);
   d.w = cv.take<double>(3 * mp);
   d.seed = cv.take<unsigned>(2);
-  d.force = cv.take<double4>(mp);
+  d.force = cv.take<double4>(mp * DISK_PARTS);
   if (L) *L = d;
   return align_up(cv.off, 256);
 }
@@ -199,6 +199,7 @@ struct imb_sim {
   // rows below and above hold a neighbouring slab's rows
   int win_y0 = 0, win_rows = 0;
   int ghost[2] = {0, 0};
+  int dparts = 1;  // lattice-step workgroups per disk (2 for a slab)
 };
 
 static constexpr int GRAPH_LONG = 32;
@@ -235,6 +236,7 @@ LatticeArgs lattice_args(imb_sim* s, const void* src, void* dst) {
   a.nbr = s->d.ps.nbr;
   a.nnbr = s->d.ps.nnbr;
   a.force = s->d.force;
+  a.dparts = s->dparts;
   return a;
 }
 
@@ -261,6 +263,7 @@ ParticleArgs particle_args(imb_sim* s, int out_slot) {
   a.s = s->d.ps; a.tab = s->d.tab[out_slot]; a.err = s->d.err;
   a.band_off = s->d.band_off[out_slot]; a.band_ids = s->d.band_ids[out_slot];
   a.direct = s->d.force;
+  a.dparts = s->dparts;
   a.build_lists = 1;
   return a;
 }
@@ -427,6 +430,7 @@ int create_sim(const imb_config* cfg, const imb_config* layout_cfg, void* hip_st
   }
   s->win_y0 = win_rows > 0 ? win_y0 : 0;
   s->win_rows = win_rows > 0 ? win_rows : 0;
+  s->dparts = win_rows > 0 ? DISK_PARTS : 1;  // a slab's few disks: two workgroups each
   sim_geometry(s->cfg, &s->g, s->win_y0, s->win_rows);
   s->layout_cfg = *layout_cfg;
   if (!s->layout_cfg.tile_w) s->layout_cfg.tile_w = 64;
@@ -757,7 +761,7 @@ int imb_set_graphs(imb_sim* s, int enable) {
 // held until the process ends) instead of in the simulation's buffer.  Host code never passes
 // the array's name to a kernel: its device address is resolved once per device with
 // hipGetSymbolAddress and kept in g_scratch_ptr.
-static constexpr int NOALLOC_MAX_DISKS = 8192;  // 256 KiB
+static constexpr int NOALLOC_MAX_DISKS = 8192;  // one share per disk: 256 KiB
 static constexpr int NOALLOC_MAX_DEVICES = 64;
 static __device__ __align__(256) double4 scratch[NOALLOC_MAX_DISKS];
 static std::mutex g_scratch_mu;
@@ -765,7 +769,7 @@ static double4* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
 
 int imb_step_noalloc(imb_sim* s, int32_t nsteps) {
   if (!s || nsteps < 0) return IMB_EINVAL;
-  if (s->np > NOALLOC_MAX_DISKS) {
+  if (s->np * s->dparts > NOALLOC_MAX_DISKS) {
     s->err = "imb_step_noalloc: more disks than its scratch holds (8192)";
     return IMB_EINVAL;
   }

@@ -44,8 +44,8 @@ struct ExchangeArgs {
   const RowCopy* copy;             // [ncopy] rows of `words` 32-bit words (16-bit: half_words)
   int ncopy, words, half_words;
   int nslab, np;
-  const double4* part[MAX_SLABS];  // each slab's share of the per-disk force and torque
-  double4* sum;                    // their sum in slab order
+  const double4* part[MAX_SLABS];  // each slab's shares of the per-disk force and torque
+  double4* sum;                    // [np][DISK_PARTS]: their sum in slab order, in the first
 };
 
 // Grid: x over the words of a row, y over the copies; the extra row y = ncopy sums the forces.
@@ -63,16 +63,21 @@ __global__ __launch_bounds__(256) void k_exchange(ExchangeArgs a) {
     }
     return;
   }
+  static_assert(DISK_PARTS == 2, "a slab's disks have two shares each");
+  auto share = [&](int r, int p) {  // slab r's share: its two workgroups' parts added
+    const double4 u = a.part[r][DISK_PARTS * p], v = a.part[r][DISK_PARTS * p + 1];
+    return make_double4(u.x + v.x, u.y + v.y, u.z + v.z, 0.0);
+  };
   for (int p = t; p < a.np; p += stride) {
-    double4 s = a.part[0][p];
+    double4 s = share(0, p);
     for (int r = 1; r < a.nslab; ++r) {
-      const double4 v = a.part[r][p];
+      const double4 v = share(r, p);
       s.x += v.x;
       s.y += v.y;
       s.z += v.z;
     }
-    s.w = 0.0;
-    a.sum[p] = s;
+    a.sum[DISK_PARTS * p] = s;  // the particle phase adds the second slot, zero
+    a.sum[DISK_PARTS * p + 1] = make_double4(0.0, 0.0, 0.0, 0.0);
   }
 }
 
@@ -326,7 +331,7 @@ int imb_slab_create(const imb_config* cfg, int32_t nslabs, void* hip_stream, imb
   const size_t ncopy = tab[0].size();
   const size_t tab_bytes = align_up(std::max(ncopy, (size_t)1) * sizeof(RowCopy), 256);
   const size_t mp = (size_t)std::max(cfg->max_particles, 1);
-  const size_t bytes = 2 * tab_bytes + mp * sizeof(double4);
+  const size_t bytes = 2 * tab_bytes + mp * DISK_PARTS * sizeof(double4);
   hipError_t e = hipMalloc((void**)&S->xmem, bytes);
   if (e != hipSuccess) {
     S->xmem = nullptr;
@@ -526,18 +531,20 @@ int imb_slab_get_forces(imb_slab* S, double* fx, double* fy, double* tz) {
 
 int imb_slab_get_partial_forces(imb_slab* S, int32_t slab, double* fx, double* fy, double* tz) {
   if (!S || slab < 0 || slab >= S->n) return IMB_EINVAL;
-  std::vector<double4> h((size_t)std::max(S->np, 1));
+  std::vector<double4> h((size_t)std::max(S->np, 1) * DISK_PARTS);
   if (S->np > 0) {
-    hipError_t e = hipMemcpyAsync(h.data(), S->view[slab].d->force, S->np * sizeof(double4),
+    hipError_t e = hipMemcpyAsync(h.data(), S->view[slab].d->force,
+                                  (size_t)S->np * DISK_PARTS * sizeof(double4),
                                   hipMemcpyDeviceToHost, S->stream);
     if (e != hipSuccess) return slab_fail(S, e, "hipMemcpyAsync");
   }
   const int rc = slab_sync(S);
   if (rc) return rc;
-  for (int p = 0; p < S->np; ++p) {
-    if (fx) fx[p] = h[p].x;
-    if (fy) fy[p] = h[p].y;
-    if (tz) tz[p] = h[p].z;
+  for (int p = 0; p < S->np; ++p) {  // the slab's share: its two workgroups' parts added
+    const double4 u = h[DISK_PARTS * p], v = h[DISK_PARTS * p + 1];
+    if (fx) fx[p] = u.x + v.x;
+    if (fy) fy[p] = u.y + v.y;
+    if (tz) tz[p] = u.z + v.z;
   }
   return IMB_OK;
 }

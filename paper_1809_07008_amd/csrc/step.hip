@@ -1,5 +1,6 @@
-// step.hip -- the lattice part of a coupled step as one kernel: workgroups [0, np) are the
-// disks' (disk_cells: covered cells, each disk's force and torque), the rest the tiles'
+// step.hip -- the lattice part of a coupled step as one kernel: workgroups [0, dparts np) are
+// the disks' (disk_cells: covered cells, each disk's force and torque, one or two workgroups per
+// disk), the rest the tiles'
 // (fluid_tile: the cells no disk covers).  A second instantiation runs a window of rows of a
 // lattice split in y (one slab, with halo faces).  The disks' longer, latency-bound work is dispatched
 // first and overlaps the tiles' streaming.  The particle phase follows as its own one-workgroup
@@ -15,11 +16,12 @@ namespace imb {
 template <class St, bool W>
 __device__ __forceinline__ void lattice_roles(const LatticeArgs& a) {
   const int b = blockIdx.x;
-  if (b < a.np) {
+  const int nd = a.np * a.dparts;  // disk items: dparts per disk
+  if (b < nd) {
     disk_cells<St, W>(a, b);
     return;
   }
-  fluid_tile<St, W>(a, xcd_remap(b - a.np, a.tiles_x * a.tiles_y));
+  fluid_tile<St, W>(a, xcd_remap(b - nd, a.tiles_x * a.tiles_y));
 }
 
 // FP32 arithmetic (FP32 or FP16 storage): held to 80 VGPRs, six wavefronts per SIMD.
@@ -61,7 +63,7 @@ __global__ __launch_bounds__(BLOCK) void k_solid_field(LatticeArgs a, double* ep
 
 void launch_lattice_step(int storage, const LatticeArgs& a, hipStream_t s, hipEvent_t e0,
                          hipEvent_t e1) {
-  const dim3 grid(a.np + a.tiles_x * a.tiles_y);
+  const dim3 grid(a.np * a.dparts + a.tiles_x * a.tiles_y);
   auto go = [&](auto kernel) {
     if (e0 || e1) hipExtLaunchKernelGGL(kernel, grid, dim3(BLOCK), 0, s, e0, e1, 0, a);
     else hipLaunchKernelGGL(kernel, grid, dim3(BLOCK), 0, s, a);
