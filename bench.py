@@ -233,6 +233,29 @@ def slab_share(storage: str, tile, nslabs: int = 8, steps: int = 200):
             "all_slabs_one_device_ms_per_step": round(all_s * 1e3, 4)}
 
 
+def hbm_control_density(tile, steps: int = 50, nch: int = 32):
+    """The headline's disk density at the HBM-resident size: 32 independent 2048x512 channels of
+    the moving-disk workload with 250 disks each (33.5 M cells and 8000 disks, as many cells as
+    the 8192x4096 control and the 2048x1024 channel's 500 disks per 2.1 M cells; 2.4 GB per
+    population copy), advanced by the batched form's per-step schedule.  Whole-step time per
+    step (HIP events around one graph replay)."""
+    from paper_1809_07008_amd import imb, workloads
+    cases = [workloads.moving_disks(seed=k, nx=2048, ny=512, n=250, storage="f32")
+             for k in range(nch)]
+    cells = sum(c.cells for c in cases)
+    b = imb.batch_from_cases(cases, tile_w=tile[0], tile_rows=tile[1])
+    b.set_schedule(imb.IMB_BATCH_PER_STEP)
+    b.step(4)
+    ms = b.timed_steps(steps) / steps
+    b.close()
+    return {"workload": "%d channels of moving_disks_2048x512_n250" % nch, "cells": cells,
+            "disks": int(sum(c.particles.n for c in cases)), "ms_per_step": round(ms, 4),
+            "mlups": round(cells / (ms * 1e-3) / 1e6, 1),
+            "whole_step_GBps": round(cells * bytes_per_lup("f32") / (ms * 1e-3) / 1e9, 1),
+            "whole_step_frac_of_8TBps": round(cells * bytes_per_lup("f32") / (ms * 1e-3) / 8e12,
+                                              4)}
+
+
 def memory_calibration(sizes=(158 * 2 ** 20, 2400 * 2 ** 20), reps: int = 20):
     """Attainable bandwidth of plain device copies (two bytes moved per byte copied), HIP events
     on the current stream: the library's copy kernel (several 16-byte loads in flight per lane,
@@ -439,6 +462,9 @@ def main(argv=None):
         print("bench: calibration %s" % out["memory_calibration"], file=sys.stderr, flush=True)
         out["hbm_control"] = hbm_control((args.tile_w, args.tile_rows))
         print("bench: hbm control %s" % out["hbm_control"], file=sys.stderr, flush=True)
+        out["hbm_control_density"] = hbm_control_density((args.tile_w, args.tile_rows))
+        print("bench: hbm control at the headline density %s" % out["hbm_control_density"],
+              file=sys.stderr, flush=True)
         out["subcell"] = subcell_estimate(args.storage, (args.tile_w, args.tile_rows))
         out["adjoint"] = adjoint_ratio((args.tile_w, args.tile_rows))
         print("bench: adjoint ratio %.3f" % out["adjoint"]["ratio"], file=sys.stderr, flush=True)
