@@ -367,7 +367,7 @@ void imb_slab_destroy(imb_slab* s);
 /* First row and row count of each slab (host arrays of nslabs). */
 int imb_slab_layout(const imb_slab* s, int32_t* y0, int32_t* rows);
 /* As imb_init_equilibrium, imb_set_populations, imb_get_populations and imb_get_fields, on the
- * whole lattice (each slab handles its rows and its halo rows).  Synchronise. */
+ * whole lattice (each slab handles its rows and its ghost rows).  Synchronise. */
 int imb_slab_init_equilibrium(imb_slab* s, double rho, double ux, double uy);
 int imb_slab_set_populations(imb_slab* s, const double* host_f);
 int imb_slab_get_populations(imb_slab* s, double* host_f);

@@ -429,7 +429,7 @@ int imb_slab_set_populations(imb_slab* S, const double* host_f) {
   hipError_t e = hipMemcpyAsync(S->stage, host_f, n * sizeof(double), hipMemcpyHostToDevice,
                                 S->stream);
   if (e != hipSuccess) return slab_fail(S, e, "hipMemcpyAsync");
-  for (int r = 0; r < S->n; ++r) {  // each slab's rows and both halo rows
+  for (int r = 0; r < S->n; ++r) {  // each slab's rows and both ghost rows
     LatticeArgs a = lattice_args(S->rank[r], nullptr, nullptr);
     launch_unstream(S->cfg.storage, a, S->stage, nullptr, S->view[r].d->f[*S->view[r].cur],
                     S->stream);

@@ -1,10 +1,9 @@
 // step.hip -- the lattice part of a coupled step as one kernel: workgroups [0, dparts np) are
 // the disks' (disk_cells: covered cells, each disk's force and torque, one or two workgroups per
-// disk), the rest the tiles'
-// (fluid_tile: the cells no disk covers).  A second instantiation runs a window of rows of a
-// lattice split in y (one slab, with halo faces).  The disks' longer, latency-bound work is dispatched
-// first and overlaps the tiles' streaming.  The particle phase follows as its own one-workgroup
-// kernel (particles.hip) on the same stream.
+// disk), the rest the tiles' (fluid_tile: the cells no disk covers).  A second instantiation
+// runs a window of rows of a lattice split in y (one slab, with ghost rows).  The disks' longer,
+// latency-bound work is dispatched first and overlaps the tiles' streaming.  The particle phase
+// follows as its own one-workgroup kernel (particles.hip) on the same stream.
 #include <hip/hip_ext.h>
 
 #include "disk_block.h"
@@ -12,7 +11,7 @@
 
 namespace imb {
 
-// W: the lattice is a window of rows of a larger one (a slab), with halo faces.
+// W: the lattice is a window of rows of a larger one (a slab), with ghost rows.
 template <class St, bool W>
 __device__ __forceinline__ void lattice_roles(const LatticeArgs& a) {
   const int b = blockIdx.x;
