@@ -198,14 +198,16 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
 // Per-step schedule: the lattice part of every channel as one ordinary launch (the disk items
 // of all channels first, then their tiles; the same device code as k_step), then one
 // particle-phase workgroup per channel.  No grid barrier and no device-wide fence: the kernel
-// boundaries order the steps.
+// boundaries order the steps.  The tiles of all channels, concatenated in channel order, are
+// handed out XCD-aware (each XCD takes a contiguous run of them, so tiles that share rows and
+// halo lines share an L2).
 // The channel index is uniform over the workgroup and the tables are read-only during the
 // launch, so a channel's arguments are read with scalar loads instead of occupying vector
 // registers.
 // Held to six wavefronts per SIMD (80 VGPRs) like the single-simulation lattice kernel.
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void k_batch_lattice(
     const BatchChannel* __restrict__ ch, const int* __restrict__ dpref,
-    const int* __restrict__ tpref, int nch, int ndisk, int parity) {
+    const int* __restrict__ tpref, int nch, int ndisk, int ntile, int parity) {
   const int b = blockIdx.x;
   if (b < ndisk) {
     const int k = __builtin_amdgcn_readfirstlane(find_slot(dpref, nch, b));
@@ -213,7 +215,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
     disk_cells<StoreF32>(la, b - dpref[k]);
     return;
   }
-  const int t = b - ndisk;
+  const int t = xcd_remap(b - ndisk, ntile);
   const int k = __builtin_amdgcn_readfirstlane(find_slot(tpref, nch, t));
   const LatticeArgs la = ch[k].la[parity];
   fluid_tile<StoreF32>(la, t - tpref[k]);
@@ -429,7 +431,7 @@ void enqueue_batch(imb_batch* b, int nsteps, int parity, hipStream_t s) {
       const int par = (parity + n) & 1;
       hipLaunchKernelGGL(k_batch_lattice, dim3(b->all_d + b->all_t), dim3(BLOCK), 0, s, b->d_ch,
                          (const int*)b->d_all, (const int*)(b->d_all + MAX_BATCH + 1), b->nch,
-                         b->all_d, par);
+                         b->all_d, b->all_t, par);
       hipLaunchKernelGGL(k_batch_particles, dim3(b->nch), dim3(BLOCK), 0, s, b->d_ch, par);
     }
     return;
