@@ -15,7 +15,7 @@
 // prescribed motion (dJ/dV += n dJ/dX^n).
 //
 // Memory: the forward pass keeps every k-th stored state (checkpoints) and the per-step disk
-// tables (positions, tile boxes, band lists: a few KB per step); the reverse sweep recomputes
+// tables (positions, tile boxes, band masks: a few KB per step); the reverse sweep recomputes
 // the states of one segment from its checkpoint into a ring of k - 1 states, then walks the
 // segment backwards.  Traffic per reverse step: the recomputation (9 reads + 9 writes per cell)
 // and the adjoint step (9 pulled state reads, 9 adjoint reads, 9 adjoint writes).
@@ -71,7 +71,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_step(AdjointArgs A) {
   using S = typename St::S;
   const LatticeArgs& a = A.la;
   __shared__ PEntry<T> s_pl[LMAX];
-  __shared__ int s_cnt[WAVES];
+  __shared__ int s_cnt[2 * WAVES];
   __shared__ int s_pid[LMAX], s_slot[LMAX];
   __shared__ unsigned s_touch;
   __shared__ Acc<T> s_red[WAVES][LMAX][NG];
@@ -332,6 +332,7 @@ __global__ __launch_bounds__(BLOCK) void k_pull_adjoint(LatticeArgs a, const T* 
 // ------------------------------------------------------------------------------ host side
 struct AdjointState {
   int nseg = 0, k = 0, nsteps = 0, np_cap = 0;
+  int tiles_x = 0, tiles_y = 0;  // tile grid of the per-tile buffers (band masks, gg_blk)
   size_t state_bytes = 0, lam_bytes = 0;
   std::vector<void*> ckpt;  // nseg stored states
   std::vector<void*> ring;  // k - 1 stored states
@@ -340,8 +341,7 @@ struct AdjointState {
   int4* h_box = nullptr;
   double4* h_pos = nullptr;
   double4* h_vel = nullptr;
-  int* h_boff = nullptr;
-  int* h_bids = nullptr;
+  unsigned long long* h_mask = nullptr;
   int* h_nbr = nullptr;     // neighbour lists of every step (the lattice step's covering tests)
   int* h_nnbr = nullptr;
   double* part = nullptr;   // 2 x [MAXSLOT][NG][pstride]
@@ -367,7 +367,7 @@ static void release(AdjointState* A) {
   A->owned.clear();
   A->ckpt.clear();
   A->ring.clear();
-  A->nseg = A->k = A->nsteps = A->np_cap = 0;
+  A->nseg = A->k = A->nsteps = A->np_cap = A->tiles_x = A->tiles_y = 0;
 }
 
 void disarm_adjoint(imb_sim* s) {
@@ -419,7 +419,7 @@ static int ensure_adjoint(SimView& v, int nsteps, int k) {
   const size_t es = elem_bytes(v.cfg->storage);
   const size_t sb = NQ * (size_t)v.g->plane * es;
   if (A->nseg == nseg && A->k == k && A->nsteps >= nsteps && A->state_bytes == sb &&
-      A->np_cap == pstride)
+      A->np_cap == pstride && A->tiles_x == v.g->tiles_x && A->tiles_y == v.g->tiles_y)
     return IMB_OK;
   release(A);
   int rc = IMB_OK;
@@ -432,8 +432,7 @@ static int ensure_adjoint(SimView& v, int nsteps, int k) {
   if (!rc) rc = take_t(A, slots * pstride, &A->h_box);
   if (!rc) rc = take_t(A, slots * pstride, &A->h_pos);
   if (!rc) rc = take_t(A, slots * pstride, &A->h_vel);
-  if (!rc) rc = take_t(A, slots * (v.g->tiles_y + 1), &A->h_boff);
-  if (!rc) rc = take_t(A, slots * (size_t)pstride * MAXSLOT, &A->h_bids);
+  if (!rc) rc = take_t(A, slots * MASK_WORDS * v.g->tiles_y, &A->h_mask);
   if (!rc) rc = take_t(A, slots * (size_t)pstride * NBMAX, &A->h_nbr);
   if (!rc) rc = take_t(A, slots * (size_t)pstride, &A->h_nnbr);
   if (!rc) rc = take_t(A, 2 * (size_t)MAXSLOT * NG * pstride, &A->part);
@@ -451,13 +450,14 @@ static int ensure_adjoint(SimView& v, int nsteps, int k) {
   A->state_bytes = sb;
   A->lam_bytes = sb;
   A->np_cap = pstride;
+  A->tiles_x = v.g->tiles_x;  // the tile grid the per-tile buffers are sized for
+  A->tiles_y = v.g->tiles_y;
   return IMB_OK;
 }
 
 struct TableSlot {
   ParticleTable tab;
-  int* boff;
-  int* bids;
+  unsigned long long* mask;
   int* nbr;
   int* nnbr;
 };
@@ -468,22 +468,20 @@ static TableSlot table_slot(const SimView& v, AdjointState* A, int n) {
   t.tab.box = A->h_box + (size_t)n * pstride;
   t.tab.pos = A->h_pos + (size_t)n * pstride;
   t.tab.vel = A->h_vel + (size_t)n * pstride;
-  t.boff = A->h_boff + (size_t)n * (v.g->tiles_y + 1);
-  t.bids = A->h_bids + (size_t)n * pstride * MAXSLOT;
+  t.mask = A->h_mask + (size_t)n * MASK_WORDS * v.g->tiles_y;
   t.nbr = A->h_nbr + (size_t)n * pstride * NBMAX;
   t.nnbr = A->h_nnbr + (size_t)n * pstride;
   return t;
 }
 
-static void copy_table(const SimView& v, const ParticleTable& dt, int* dboff, int* dbids,
-                       const ParticleTable& st, const int* sboff, const int* sbids,
+static void copy_table(const SimView& v, const ParticleTable& dt, unsigned long long* dmask,
+                       const ParticleTable& st, const unsigned long long* smask,
                        hipStream_t s) {
   const int pstride = std::max(v.cfg->max_particles, 1);
   launch_copy(dt.box, st.box, sizeof(int4) * pstride, s);
   launch_copy(dt.pos, st.pos, sizeof(double4) * pstride, s);
   launch_copy(dt.vel, st.vel, sizeof(double4) * pstride, s);
-  launch_copy(dboff, sboff, sizeof(int) * (v.g->tiles_y + 1), s);
-  launch_copy(dbids, sbids, sizeof(int) * (size_t)pstride * MAXSLOT, s);
+  launch_copy(dmask, smask, sizeof(unsigned long long) * MASK_WORDS * v.g->tiles_y, s);
 }
 
 static void copy_lists(const SimView& v, int* dnbr, int* dnnbr, const int* snbr, const int* snnbr,
@@ -573,11 +571,10 @@ static int adjoint_forward(imb_sim* sim, int32_t nsteps, int32_t k, const double
   // the tables of the stored state, and those the state after the last step will use
   const int c0 = *v.cur;
   const ParticleTable live = d.tab[c0];
-  int* const live_boff = d.band_off[c0];
-  int* const live_bids = d.band_ids[c0];
+  unsigned long long* const live_mask = d.band_mask[c0];
   {
     TableSlot t0 = table_slot(v, A, 0);
-    copy_table(v, t0.tab, t0.boff, t0.bids, live, live_boff, live_bids, st);
+    copy_table(v, t0.tab, t0.mask, live, live_mask, st);
     copy_lists(v, t0.nbr, t0.nnbr, d.ps.nbr, d.ps.nnbr, st);
   }
   launch_copy(A->ckpt[0], d.f[*v.cur], A->state_bytes, st);
@@ -595,8 +592,7 @@ static int adjoint_forward(imb_sim* sim, int32_t nsteps, int32_t k, const double
     const TableSlot tn = table_slot(v, A, n);
     LatticeArgs la = lattice_args(sim, src, dst);
     la.tab = tn.tab;
-    la.band_off = tn.boff;
-    la.band_ids = tn.bids;
+    la.band_mask = tn.mask;
     la.nbr = tn.nbr;
     la.nnbr = tn.nnbr;
     const TableSlot tn1 = table_slot(v, A, n + 1);
@@ -605,8 +601,7 @@ static int adjoint_forward(imb_sim* sim, int32_t nsteps, int32_t k, const double
     pa.do_dem = 1;
     pa.do_table = 1;
     pa.tab = tn1.tab;
-    pa.band_off = tn1.boff;
-    pa.band_ids = tn1.bids;
+    pa.band_mask = tn1.mask;
     pa.wfx = wd[0];
     pa.wfy = wd[1];
     pa.wtz = wd[2];
@@ -623,7 +618,7 @@ static int adjoint_forward(imb_sim* sim, int32_t nsteps, int32_t k, const double
   *v.steps += nsteps;
   {  // the stored state's tables are the ones of the step after the last
     TableSlot tN = table_slot(v, A, nsteps);
-    copy_table(v, d.tab[last], d.band_off[last], d.band_ids[last], tN.tab, tN.boff, tN.bids, st);
+    copy_table(v, d.tab[last], d.band_mask[last], tN.tab, tN.mask, st);
   }
   const hipError_t fe = hipGetLastError();
   if (fe != hipSuccess) return hip_fail(v.err, fe, "adjoint forward launch");
@@ -692,8 +687,7 @@ static int adjoint_reverse(imb_sim* sim, double* gx0, double* gy0, double* gvx, 
       const TableSlot tn = table_slot(v, A, n);
       LatticeArgs la = lattice_args(sim, rs, dst);
       la.tab = tn.tab;
-      la.band_off = tn.boff;
-      la.band_ids = tn.bids;
+      la.band_mask = tn.mask;
       la.nbr = tn.nbr;
       la.nnbr = tn.nnbr;
       timed(false, [&] { launch_lattice_step(cfg.storage, la, st); });
@@ -706,8 +700,7 @@ static int adjoint_reverse(imb_sim* sim, double* gx0, double* gy0, double* gvx, 
       AdjointArgs aa{};
       aa.la = lattice_args(sim, sprev, nullptr);
       aa.la.tab = tn.tab;
-      aa.la.band_off = tn.boff;
-      aa.la.band_ids = tn.bids;
+      aa.la.band_mask = tn.mask;
       aa.lam_in = A->lam[li];
       aa.lam_out = A->lam[li ^ 1];
       aa.wfx = wd[0];

@@ -264,7 +264,7 @@ namespace {
 thread_local std::string g_batch_error;
 
 imb_config layout_config(const imb_config& c) {
-  imb_config l = c;  // the widest band list any tile shape can need
+  imb_config l = c;  // the most band-mask rows any tile shape can need
   l.tile_w = 256;
   l.tile_rows = 1;
   return l;
@@ -330,6 +330,7 @@ int refresh(imb_batch* b) {
       pa.do_finalize = 1;
       pa.do_dem = 1;
       pa.do_table = 1;
+      pa.lds_doubles = PP_LDS;
       b->h_ch[c].la[k] = lattice_args(s, v.d->f[k], v.d->f[k ^ 1]);
       b->h_ch[c].pa[k] = pa;
     }

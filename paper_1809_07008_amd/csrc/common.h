@@ -21,6 +21,7 @@ constexpr int MAXSLOT = 64;        // tiles per disk box (partial-sum slots per 
 constexpr int MAX_BANDS = 6144;    // tile rows (bands) of one lattice
 constexpr int NBMAX = 32;          // DEM neighbour-list capacity per disk
 constexpr int MAX_PARTICLES = 512;
+constexpr int MASK_WORDS = MAX_PARTICLES / 64;  // 64-bit words of a tile row's disk mask
 // Most workgroups of the lattice step per disk (a simulation's `dparts`, 1 or 2): each takes a
 // contiguous part of the disk's cells and writes its own share of the disk's force and torque,
 // force[dparts p + part].  Two halve a disk's latency where few disks run beside few tiles (a
@@ -41,7 +42,6 @@ enum : int {
   ERR_NBR = 16,        // DEM neighbour list full
   ERR_MOVE = 32,       // a disk moved more than MAX_MOVE in one step
   ERR_LEFT = 64,       // a disk centre left the channel between the walls
-  ERR_BAND = 128,      // band list capacity exceeded
   ERR_CONTACTS = 256,  // a disk touches more than HK other disks at once (tangential springs)
 };
 
@@ -86,8 +86,9 @@ struct LatticeArgs {
   void* dst;             // post-collision populations of this step
   int np;
   ParticleTable tab;
-  const int* band_off;   // [tiles_y + 1]: disks whose box touches tile row ty are
-  const int* band_ids;   //   band_ids[band_off[ty] .. band_off[ty + 1])
+  // [MASK_WORDS][tiles_y]: bit l of word w of tile row ty is set when disk 64 w + l's box
+  // touches the row
+  const unsigned long long* band_mask;
   int pstride;           // per-disk array stride (max_particles)
   int* err;
   unsigned* seed;        // [2] step counters of the stochastic rounding: this step reads
@@ -162,14 +163,15 @@ struct ParticleArgs {
   double hm_damp;         //   2 sqrt(5/6) zeta
   double uw_bot, uw_top;  // wall velocities along x (the walls' tangential slip)
   int tiles_x, tiles_y, tw, th;
-  int tiles_yg, ty_off;   // the lattice's tile rows; band lists cover rows [ty_off, +tiles_y)
+  int tiles_yg, ty_off;   // the lattice's tile rows; band masks cover rows [ty_off, +tiles_y)
   ParticleState s;
   ParticleTable tab;
   const double4* direct;  // [np][dparts] shares of the step's force and torque, added in order
   int dparts;
   int build_lists;        // maintain the neighbour lists even when no disk is free
-  int* band_off;   // written with the table: per tile row, the disks whose box touches it
-  int* band_ids;   // capacity np * MAXSLOT
+  unsigned long long* band_mask;  // written with the table: per tile row, the disks whose box
+                                  // touches it ([MASK_WORDS][tiles_y], as LatticeArgs reads it)
+  int lds_doubles;                // the LDS the phase's launch gives it (set by the launch)
   int do_finalize, do_dem, do_table, init_contacts;
   const double *wfx, *wfy, *wtz;  // objective weights (adjoint forward); may be null
   double* J;                      // objective accumulator; null = not accumulated

@@ -28,7 +28,7 @@ __device__ void fluid_tile(const LatticeArgs& a, int tile) {
   using T = typename St::T;
   using S = typename St::S;
   __shared__ PEntry<T> s_pl[LMAX];
-  __shared__ int s_cnt[WAVES];
+  __shared__ int s_cnt[2 * WAVES];
   __shared__ int s_pid[LMAX], s_slot[LMAX];
 
   const int tid = threadIdx.x;

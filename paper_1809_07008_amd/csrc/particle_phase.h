@@ -7,7 +7,7 @@
 //      spring-dashpot with a Coulomb limit; the contact force is evaluated after each
 //      drift from the new positions and half-step velocities and reused by the next kick;
 //      prescribed disks move by V once per step, fixed disks stay;
-//   3. the disk table (tile box, position, velocity) and the per-tile-row (band) candidate lists
+//   3. the disk table (tile box, position, velocity) and the per-tile-row (band) candidate masks
 //      that the next lattice step reads.
 //
 // Contacts are searched in a Verlet neighbour list (skin DEM_SKIN) rebuilt whenever a disk has
@@ -140,7 +140,8 @@ __device__ inline int block_exclusive_scan(int* cnt, int n, int* s_wave) {
 // every global store is issued after the last barrier, so barriers never wait on memory; each
 // disk's state lives in its own thread's registers and only positions and velocities that other
 // disks' contact tests read are mirrored in LDS.
-// One disk per thread: NT >= np.  `lds` holds max(PP_DOUBLES np doubles, tiles_y + 1 ints).
+// One disk per thread: NT >= np.  `lds` holds a.lds_doubles >= max(PP_DOUBLES np, MASK_WORDS)
+// doubles.
 template <int NT>
 __device__ __attribute__((always_inline)) void particle_phase(const ParticleArgs& a, double* lds) {
 #pragma clang fp contract(off)
@@ -709,7 +710,6 @@ __device__ __attribute__((always_inline)) void particle_phase(const ParticleArgs
     }
   }
   // ---- table: tile box of the new position
-  __syncthreads();  // LDS is reused below
   int4 nbx = make_int4(0, 0, 0, 0);
   if (a.do_table && have) {
     if (!isfinite(nx_) || !isfinite(ny_)) {
@@ -720,38 +720,33 @@ __device__ __attribute__((always_inline)) void particle_phase(const ParticleArgs
       nbx = make_int4(0, 0, 0, 0);
     }
   }
-  // ---- band lists: counting sort of (tile row, disk) pairs in LDS, for the tile rows
-  // [ty_off, ty_off + tiles_y) of the lattice's tiles_yg (all of them unless a slab)
-  int* cnt = (int*)lds;
-  const int nbands = a.tiles_y;
-  auto band_of = [&](int k) {  // band of the box's k-th tile row, or -1 outside the window
-    int ty = nbx.z + k;
-    ty = ty < a.tiles_yg ? ty : ty - a.tiles_yg;
-    ty -= a.ty_off;
-    return ty >= 0 && ty < nbands ? ty : -1;
-  };
-  int total = 0;
+  // ---- band masks: bit p mod 64 of word p / 64 of tile row t is set when disk p's box touches
+  // the window's tile row t (lattice tile row t + ty_off of the tiles_yg the lattice has).  Built
+  // in LDS ([MASK_WORDS][R] words for R rows at a time, R from the LDS the launch gives) with one
+  // atomic OR per (disk, row) of its box, then stored word-major (coalesced).
   if (a.do_table) {
-    for (int k = threadIdx.x; k <= nbands; k += NT) cnt[k] = 0;
-    __syncthreads();
-    if (have)
-      for (int k = 0; k < nbx.w; ++k) {
-        const int ty = band_of(k);
-        if (ty >= 0) atomicAdd(&cnt[ty], 1);
+    unsigned long long* sm = (unsigned long long*)lds;
+    const int nbands = a.tiles_y;
+    const int R = a.lds_doubles / MASK_WORDS < nbands ? a.lds_doubles / MASK_WORDS : nbands;
+    const bool any = have && nbx.y > 0;
+    for (int t0 = 0; t0 < nbands; t0 += R) {
+      const int tn = nbands - t0 < R ? nbands - t0 : R;
+      __syncthreads();  // LDS is free (the DEM's tables, or the last chunk's stores, are done)
+      for (int i = threadIdx.x; i < MASK_WORDS * R; i += NT) sm[i] = 0ull;
+      __syncthreads();
+      if (any)
+        for (int k = 0; k < nbx.w; ++k) {
+          int t = nbx.z + k;
+          t = t < a.tiles_yg ? t : t - a.tiles_yg;
+          t -= a.ty_off + t0;
+          if (t >= 0 && t < tn) atomicOr(&sm[(p >> 6) * R + t], 1ull << (p & 63));
+        }
+      __syncthreads();
+      for (int i = threadIdx.x; i < MASK_WORDS * tn; i += NT) {
+        const int w = i / tn, t = i - w * tn;
+        a.band_mask[(size_t)w * nbands + t0 + t] = sm[w * R + t];
       }
-    __syncthreads();
-    total = block_exclusive_scan<NT>(cnt, nbands, s_wave);
-    for (int k = threadIdx.x; k < nbands; k += NT) a.band_off[k] = cnt[k];
-    if (threadIdx.x == 0) a.band_off[nbands] = total;
-    __syncthreads();  // every offset is read before the fill below advances cnt
-    if (have)
-      for (int k = 0; k < nbx.w; ++k) {
-        const int ty = band_of(k);
-        if (ty < 0) continue;
-        const int pos = atomicAdd(&cnt[ty], 1);
-        if (pos < np * MAXSLOT) a.band_ids[pos] = p;
-        else atomicOr(a.err, ERR_BAND);
-      }
+    }
   }
 
   // ---- all remaining global stores

@@ -22,11 +22,10 @@ struct DeviceLayout {
   void* f[2];
   ParticleState ps;
   // disk tables, double-buffered: the lattice step whose source populations are f[k] reads
-  // tab[k], band_off[k], band_ids[k]; the particle phase after it writes the other copy, so it
-  // can run while the tiles of the same step still read theirs
+  // tab[k] and band_mask[k]; the particle phase after it writes the other copy, so it can run
+  // while the tiles of the same step still read theirs
   ParticleTable tab[2];
-  int* band_off[2];
-  int* band_ids[2];
+  unsigned long long* band_mask[2];  // [MASK_WORDS][tiles_y]
   int* err;
   double* J;
   double* w;  // objective weights wfx, wfy, wtz (3 x capacity)
@@ -74,7 +73,7 @@ void disarm_adjoint(imb_sim* s);
 void drop_graphs(imb_sim* s);
 
 // Simulation whose memory is carved for `layout_cfg` (same lattice and particle capacity as
-// cfg; its tile shape only sets how many tile rows the band lists can hold), so that the tile
+// cfg; its tile shape only sets how many tile rows the band masks can hold), so that the tile
 // shape can later change in place (set_tile_shape).
 int create_sim(const imb_config* cfg, const imb_config* layout_cfg, void* hip_stream,
                void* dev_buf, size_t dev_bytes, imb_sim** out, int win_y0 = 0,

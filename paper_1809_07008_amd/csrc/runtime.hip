@@ -82,8 +82,7 @@ size_t layout(const imb_config& c, char* base, DeviceLayout* L, int y0, int rows
     d.tab[k].box = cv.take<int4>(mp);
     d.tab[k].pos = cv.take<double4>(mp);
     d.tab[k].vel = cv.take<double4>(mp);
-    d.band_off[k] = cv.take<int>((size_t)g.tiles_y + 1);
-    d.band_ids[k] = cv.take<int>(mp * MAXSLOT);
+    d.band_mask[k] = cv.take<unsigned long long>((size_t)MASK_WORDS * g.tiles_y);
   }
   d.err = cv.take<int>(1);
   d.J = cv.take<double>(1);
@@ -157,7 +156,6 @@ std::string describe_device_error(int bits) {
   std::string s;
   if (bits & ERR_TILE_LIST) s += "more than 32 disk boxes touch one tile; ";
   if (bits & ERR_SLOTS) s += "a disk box spans more than 64 tiles; ";
-  if (bits & ERR_BAND) s += "band list overflow; ";
   if (bits & ERR_CELL) s += "more than 4 disks cover one cell or one thread column; ";
   if (bits & ERR_RHO) s += "non-finite or non-positive density; ";
   if (bits & ERR_NBR) s += "DEM neighbour list overflow; ";
@@ -229,7 +227,7 @@ LatticeArgs lattice_args(imb_sim* s, const void* src, void* dst) {
   // the tables of the step reading this source (no source: those of the stored state)
   const int t = src ? (src == s->d.f[1] ? 1 : 0) : s->cur;
   a.np = s->np; a.tab = s->d.tab[t]; a.err = s->d.err;
-  a.band_off = s->d.band_off[t]; a.band_ids = s->d.band_ids[t];
+  a.band_mask = s->d.band_mask[t];
   a.pstride = std::max(s->cfg.max_particles, 1);
   a.seed = s->d.seed;
   a.seed_slot = t;
@@ -261,7 +259,7 @@ ParticleArgs particle_args(imb_sim* s, int out_slot) {
   a.tiles_x = s->g.tiles_x; a.tiles_y = s->g.tiles_y; a.tw = s->g.tw; a.th = s->g.th;
   a.tiles_yg = s->g.tiles_yg; a.ty_off = s->g.ty_off;
   a.s = s->d.ps; a.tab = s->d.tab[out_slot]; a.err = s->d.err;
-  a.band_off = s->d.band_off[out_slot]; a.band_ids = s->d.band_ids[out_slot];
+  a.band_mask = s->d.band_mask[out_slot];
   a.direct = s->d.force;
   a.dparts = s->dparts;
   a.build_lists = 1;

@@ -40,7 +40,7 @@ __global__ __launch_bounds__(BLOCK) void k_step_f64(LatticeArgs a) {
 template <class T>
 __global__ __launch_bounds__(BLOCK) void k_solid_field(LatticeArgs a, double* eps_out) {
   __shared__ PEntry<T> s_pl[LMAX];
-  __shared__ int s_cnt[WAVES];
+  __shared__ int s_cnt[2 * WAVES];
   __shared__ int s_pid[LMAX], s_slot[LMAX];
   __shared__ CellScratch<T> cs;
   const int tid = threadIdx.x;

@@ -15,52 +15,66 @@ struct PEntry {
 };
 
 // Disks whose tile box contains tile (tx, ty), sorted by id (so every sum over them has a fixed
-// order).  Candidates come from the tile row's band list written by the particle phase; ty
-// counts inside the window (boxes are in lattice tile rows, ty + ty_off).  Returns the count
-// (capped at LMAX; overflow latches ERR_TILE_LIST).  Block-uniform control flow.
+// order).  The tile row's band mask (particle phase) names the disks whose box touches the row:
+// wavefront w reads words w and w + WAVES of it (scalar loads) and its lanes test the boxes of
+// the disks 64 w + lane and 64 (w + WAVES) + lane that are set; one barrier orders the hits by
+// id.  ty counts inside the window (boxes are in lattice tile rows, ty + ty_off).  Returns the
+// count (capped at LMAX; overflow latches ERR_TILE_LIST).  Block-uniform control flow.  s_cnt
+// holds 2 WAVES ints.
+static_assert(MASK_WORDS == 2 * WAVES, "two band-mask words per wavefront");
 template <class T>
 __device__ int build_tile_list(const LatticeArgs& a, int tx, int ty, PEntry<T>* pl, int* s_cnt,
                                int* s_pid, int* s_slot) {
-  if (a.np == 0) return 0;
-  const int b0 = a.band_off[ty], b1 = a.band_off[ty + 1];
-  if (b1 <= b0) return 0;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  int base = 0;
-  for (int k0 = b0; k0 < b1; k0 += BLOCK) {
-    const int k = k0 + tid;
-    int p = -1, slot = -1;
-    if (k < b1) {
-      p = a.band_ids[k];
-      slot = box_slot(a.tab.box[p], tx, ty + a.ty_off, a.tiles_x, a.tiles_yg);
-    }
-    const bool hit = slot >= 0;
-    const unsigned long long m = __ballot(hit);
-    const int below = __popcll(m & ((1ull << lane) - 1ull));
-    if (lane == 0) s_cnt[wave] = __popcll(m);
-    __syncthreads();
-    int off = base, total = 0;
-#pragma unroll
-    for (int w = 0; w < WAVES; ++w) {
-      if (w < wave) off += s_cnt[w];
-      total += s_cnt[w];
-    }
-    if (hit) {
-      const int q = off + below;
-      if (q < LMAX) {
-        s_pid[q] = p;
-        s_slot[q] = slot;
-      } else {
-        atomicOr(a.err, ERR_TILE_LIST);
-      }
-    }
-    base += total;
-    __syncthreads();
+  const int np = a.np;
+  if (np == 0) return 0;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int tyg = ty + a.ty_off;
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  const int w1 = wave + WAVES;
+  const unsigned long long c0 = 64 * wave < np ? a.band_mask[wave * a.tiles_y + ty] : 0ull;
+  const unsigned long long c1 = 64 * w1 < np ? a.band_mask[w1 * a.tiles_y + ty] : 0ull;
+  const int p0 = 64 * wave + lane, p1 = 64 * w1 + lane;
+  int s0 = -1, s1 = -1;  // a set bit names a disk below np
+  if ((c0 >> lane) & 1ull) s0 = box_slot(a.tab.box[p0], tx, tyg, a.tiles_x, a.tiles_yg);
+  if ((c1 >> lane) & 1ull) s1 = box_slot(a.tab.box[p1], tx, tyg, a.tiles_x, a.tiles_yg);
+  const unsigned long long m0 = __ballot(s0 >= 0), m1 = __ballot(s1 >= 0);
+  if (lane == 0) {
+    s_cnt[wave] = __popcll(m0);
+    s_cnt[WAVES + wave] = __popcll(m1);
   }
+  __syncthreads();
+  int off0 = 0, off1 = 0, base = 0;
+#pragma unroll
+  for (int w = 0; w < WAVES; ++w) {
+    if (w < wave) {
+      off0 += s_cnt[w];
+      off1 += s_cnt[WAVES + w];
+    }
+    off1 += s_cnt[w];  // every hit of the first words precedes the second words'
+    base += s_cnt[w] + s_cnt[WAVES + w];
+  }
+  const int q0 = off0 + __popcll(m0 & lt), q1 = off1 + __popcll(m1 & lt);
+  if (s0 >= 0) {
+    if (q0 < LMAX) {
+      s_pid[q0] = p0;
+      s_slot[q0] = s0;
+    } else {
+      atomicOr(a.err, ERR_TILE_LIST);
+    }
+  }
+  if (s1 >= 0) {
+    if (q1 < LMAX) {
+      s_pid[q1] = p1;
+      s_slot[q1] = s1;
+    } else {
+      atomicOr(a.err, ERR_TILE_LIST);
+    }
+  }
+  __syncthreads();
   const int n = base < LMAX ? base : LMAX;
-  if (tid < n) {
+  if (tid < n) {  // s_pid is ascending: entry tid is the tid-th smallest id
     const int p = s_pid[tid];
-    int rank = 0;
-    for (int q = 0; q < n; ++q) rank += s_pid[q] < p;
     const double4 ps = a.tab.pos[p];
     const double4 vl = a.tab.vel[p];
     const double flx = floor(ps.x), fly = floor(ps.y);
@@ -75,7 +89,7 @@ __device__ int build_tile_list(const LatticeArgs& a, int tx, int ty, PEntry<T>* 
     e.vx = (T)vl.x;
     e.vy = (T)vl.y;
     e.om = (T)vl.z;
-    pl[rank] = e;
+    pl[tid] = e;
   }
   __syncthreads();
   return n;

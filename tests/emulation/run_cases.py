@@ -66,8 +66,9 @@ def overlap_case(walls):
     return W.Case("emu_overlap", 64, 36, tau0=0.7, steps=3, walls=walls, gx=1e-5, particles=p)
 
 
-def fp64_parity():
-    for case in (moving_case(), overlap_case(True), overlap_case(False),
+def fp64_parity(part=(0, 1)):
+    """FP64 parity with the oracle; part = (k, n) runs the cases whose index is k mod n."""
+    for i, case in enumerate((moving_case(), overlap_case(True), overlap_case(False),
                  W.touching_disks(6, True, steps=2), W.touching_disks(8, False, steps=2),
                  W.approaching_disks(steps=12), moving_case().with_(eps_subcells=4),
                  overlap_case(True).with_(eps_subcells=5), W.couette_channel("f64", steps=6),
@@ -77,7 +78,9 @@ def fp64_parity():
                  W.frictional_disks(6, True, steps=3).with_(contact_model=1, young=100.0,
                                                             poisson=0.3),
                  W.touching_disks(8, False, steps=2).with_(contact_model=1, young=100.0,
-                                                           poisson=0.3)):
+                                                           poisson=0.3))):
+        if i % part[1] != part[0]:
+            continue
         s = sim_of(case, "f64")
         s.step(case.steps)
         ref = oracle_of(case)
@@ -319,8 +322,18 @@ def three_d():
             check("3d spheres move as prescribed", ok, "")
 
 
+ALL = (slab_cases, three_d, no_allocation_step, spring_table_limit, fp64_parity, wide_tiles,
+       reduced_precision, roundtrip, adjoint, batch)
+
+
 if __name__ == "__main__":
-    for fn in (slab_cases, three_d, no_allocation_step, spring_table_limit, fp64_parity, wide_tiles,
-               reduced_precision, roundtrip, adjoint, batch):
-        fn()
+    # arguments: case functions to run (all without any); "fp64_parity:k/n" runs part k of n
+    for spec in sys.argv[1:] or [fn.__name__ for fn in ALL]:
+        name, _, part = spec.partition(":")
+        fn = {f.__name__: f for f in ALL}[name]
+        if part:
+            k, n = part.split("/")
+            fn(part=(int(k), int(n)))
+        else:
+            fn()
     print("all emulated cases passed", flush=True)

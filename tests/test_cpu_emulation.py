@@ -18,18 +18,40 @@ def _asan_runtime():
     return path if os.path.isabs(path) and os.path.exists(path) else None
 
 
+# The emulated cases in four processes that run at once (each workgroup's threads are operating
+# system threads, so one process keeps only a few cores busy), of about equal length.
+GROUPS = (["fp64_parity:0/2", "slab_cases"],
+          ["fp64_parity:1/2", "batch", "roundtrip", "reduced_precision"],
+          ["three_d", "adjoint", "spring_table_limit"],
+          ["wide_tiles", "no_allocation_step"])
+
+
 @pytest.mark.skipif(_asan_runtime() is None, reason="g++ with AddressSanitizer not available")
-def test_kernels_under_cpu_emulation_with_address_sanitizer():
+def test_kernels_under_cpu_emulation_with_address_sanitizer(tmp_path):
     import build_emu
     lib = build_emu.build()
     env = dict(os.environ, LD_PRELOAD=_asan_runtime(), ASAN_OPTIONS="detect_leaks=0",
-               EMU_LIB=lib, OMP_NUM_THREADS="4")
-    r = subprocess.run([sys.executable, os.path.join(HERE, "emulation", "run_cases.py")],
-                       env=env, capture_output=True, text=True, timeout=1200)
-    print(r.stdout)
-    assert "AddressSanitizer" not in r.stderr, r.stderr[-6000:]
-    assert r.returncode == 0, r.stdout[-3000:] + r.stderr[-3000:]
-    assert "all emulated cases passed" in r.stdout
+               EMU_LIB=lib, OMP_NUM_THREADS="2")
+    procs = []
+    for k, group in enumerate(GROUPS):
+        out = open(tmp_path / ("group%d.out" % k), "w+")
+        procs.append((group, out, subprocess.Popen(
+            [sys.executable, os.path.join(HERE, "emulation", "run_cases.py"), *group],
+            env=env, stdout=out, stderr=subprocess.STDOUT, text=True)))
+    failures = []
+    for group, out, p in procs:
+        try:
+            rc = p.wait(timeout=1200)
+        except subprocess.TimeoutExpired:
+            p.kill()
+            rc = "timeout"
+        out.seek(0)
+        text = out.read()
+        out.close()
+        print(text)
+        if "AddressSanitizer" in text or rc != 0 or "all emulated cases passed" not in text:
+            failures.append("%s: exit %s\n%s" % (" ".join(group), rc, text[-4000:]))
+    assert not failures, "\n".join(failures)
 
 
 def test_fp16_stochastic_rounding_matches_its_rule(tmp_path):
