@@ -201,24 +201,21 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
 // boundaries order the steps.  The tiles of all channels, concatenated in channel order, are
 // handed out XCD-aware (each XCD takes a contiguous run of them, so tiles that share rows and
 // halo lines share an L2).
-// The channel index is uniform over the workgroup and the tables are read-only during the
-// launch, so a channel's arguments are read with scalar loads instead of occupying vector
-// registers.
+// Workgroup b finds its channel and item in one scalar load from a table built on the host
+// (a search over the channels' prefix sums took a chain of dependent loads per workgroup).  The
+// channel index is uniform over the workgroup and the tables are read-only during the launch,
+// so a channel's arguments are read with scalar loads instead of occupying vector registers.
 // Held to six wavefronts per SIMD (80 VGPRs) like the single-simulation lattice kernel.
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void k_batch_lattice(
-    const BatchChannel* __restrict__ ch, const int* __restrict__ dpref,
-    const int* __restrict__ tpref, int nch, int ndisk, int ntile, int parity) {
+    const BatchChannel* __restrict__ ch, const unsigned* __restrict__ blk, int ndisk, int ntile,
+    int parity) {
   const int b = blockIdx.x;
-  if (b < ndisk) {
-    const int k = __builtin_amdgcn_readfirstlane(find_slot(dpref, nch, b));
-    const LatticeArgs la = ch[k].la[parity];
-    disk_cells<StoreF32>(la, b - dpref[k]);
-    return;
-  }
-  const int t = xcd_remap(b - ndisk, ntile);
-  const int k = __builtin_amdgcn_readfirstlane(find_slot(tpref, nch, t));
-  const LatticeArgs la = ch[k].la[parity];
-  fluid_tile<StoreF32>(la, t - tpref[k]);
+  const int j = b < ndisk ? b : ndisk + xcd_remap(b - ndisk, ntile);
+  const unsigned e = __builtin_amdgcn_readfirstlane(blk[j]);  // (channel << 24) | item
+  const LatticeArgs la = ch[e >> 24].la[parity];
+  const int item = (int)(e & 0xFFFFFFu);
+  if (b < ndisk) disk_cells<StoreF32>(la, item);
+  else fluid_tile<StoreF32>(la, item);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_batch_particles(const BatchChannel* __restrict__ ch,
@@ -241,7 +238,9 @@ struct imb_batch {
   bool owns = false;
   BatchChannel* d_ch = nullptr;
   int* d_half = nullptr;
-  int* d_all = nullptr;  // [2][MAX_BATCH + 1]: disk and tile prefix sums over all channels
+  unsigned* d_blk = nullptr;  // per-step schedule: (channel << 24) | item of every disk item and
+                              // tile, all channels' disk items first, then their tiles
+  size_t blk_cap = 0;         // entries d_blk holds (the finest tile shape's count)
   unsigned* d_sync = nullptr;
   std::vector<BatchChannel> h_ch;
   std::vector<int> h_half;
@@ -302,11 +301,31 @@ int validate_batch(int32_t nsim, const imb_config* cfgs, std::string* why) {
   return IMB_OK;
 }
 
-size_t table_bytes(int nsim) {
+// Entries of the per-step schedule's workgroup table: every channel's disk items and its tiles
+// under the tile shape with the most tiles.
+size_t block_table_entries(int nsim, const imb_config* cfgs) {
+  size_t n = 0;
+  for (int c = 0; c < nsim; ++c) {
+    size_t most = 0;
+    for (int tw = 16; tw <= 256; tw *= 2)
+      for (int rows = 1; rows <= 4; rows *= 2) {
+        imb_config t = cfgs[c];
+        t.tile_w = tw;
+        t.tile_rows = rows;
+        Geometry g;
+        sim_geometry(t, &g);
+        most = std::max(most, (size_t)g.tiles_x * g.tiles_y);
+      }
+    n += (size_t)std::max(cfgs[c].max_particles, 1) * DISK_PARTS + most;
+  }
+  return n;
+}
+
+size_t table_bytes(int nsim, const imb_config* cfgs) {
   return align_up(sizeof(BatchChannel) * nsim, 256) +
          align_up(sizeof(int) * 2 * (3 * MAX_BATCH + 2), 256) +
-         align_up(sizeof(int) * 2 * (MAX_BATCH + 1), 256) +
-         align_up(sizeof(unsigned) * SYNC_WORDS, 256);
+         align_up(sizeof(unsigned) * SYNC_WORDS, 256) +
+         align_up(sizeof(unsigned) * block_table_entries(nsim, cfgs), 256);
 }
 
 void drop_batch_graphs(imb_batch* b) {
@@ -367,31 +386,31 @@ int refresh(imb_batch* b) {
     b->half_t[h] = acc;
     b->half_d[h] = dacc;
   }
-  // all channels in order (per-step schedule)
-  std::vector<int> all(2 * (MAX_BATCH + 1), 0);
-  {
-    int dacc = 0, tacc = 0;
-    for (int c = 0; c < b->nch; ++c) {
-      all[c] = dacc;
-      all[MAX_BATCH + 1 + c] = tacc;
-      dacc += b->h_ch[c].la[0].np * b->h_ch[c].la[0].dparts;
-      tacc += tiles[c];
-    }
-    for (int c = b->nch; c <= MAX_BATCH; ++c) {
-      all[c] = dacc;
-      all[MAX_BATCH + 1 + c] = tacc;
-    }
-    b->all_d = dacc;
-    b->all_t = tacc;
+  // all channels in order (per-step schedule): disk items, then tiles
+  b->all_d = 0;
+  b->all_t = 0;
+  for (int c = 0; c < b->nch; ++c) {
+    b->all_d += b->h_ch[c].la[0].np * b->h_ch[c].la[0].dparts;
+    b->all_t += tiles[c];
+  }
+  if ((size_t)b->all_d + b->all_t > b->blk_cap) {
+    b->err = "batch workgroup table too small for the tile shape";
+    return IMB_EINVAL;
+  }
+  std::vector<unsigned> blk((size_t)b->all_d + b->all_t);
+  for (int c = 0, d = 0, t = b->all_d; c < b->nch; ++c) {
+    const int nd = b->h_ch[c].la[0].np * b->h_ch[c].la[0].dparts;
+    for (int i = 0; i < nd; ++i) blk[d++] = ((unsigned)c << 24) | (unsigned)i;
+    for (int i = 0; i < tiles[c]; ++i) blk[t++] = ((unsigned)c << 24) | (unsigned)i;
   }
   hipError_t e = hipMemcpyAsync(b->d_ch, b->h_ch.data(), sizeof(BatchChannel) * b->nch,
                                 hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(b->d_half, b->h_half.data(), sizeof(int) * b->h_half.size(),
                        hipMemcpyHostToDevice, b->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(b->d_all, all.data(), sizeof(int) * all.size(), hipMemcpyHostToDevice,
-                       b->stream);
+  if (e == hipSuccess && !blk.empty())
+    e = hipMemcpyAsync(b->d_blk, blk.data(), sizeof(unsigned) * blk.size(),
+                       hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) {
     b->err = std::string("batch table upload: ") + hipGetErrorString(e);
@@ -431,8 +450,7 @@ void enqueue_batch(imb_batch* b, int nsteps, int parity, hipStream_t s) {
     for (int n = 0; n < nsteps; ++n) {
       const int par = (parity + n) & 1;
       hipLaunchKernelGGL(k_batch_lattice, dim3(b->all_d + b->all_t), dim3(BLOCK), 0, s, b->d_ch,
-                         (const int*)b->d_all, (const int*)(b->d_all + MAX_BATCH + 1), b->nch,
-                         b->all_d, b->all_t, par);
+                         (const unsigned*)b->d_blk, b->all_d, b->all_t, par);
       hipLaunchKernelGGL(k_batch_particles, dim3(b->nch), dim3(BLOCK), 0, s, b->d_ch, par);
     }
     return;
@@ -554,7 +572,7 @@ int imb_batch_required_bytes(int32_t nsim, const imb_config* cfgs, size_t* bytes
   std::string why;
   const int rc = validate_batch(nsim, cfgs, &why);
   if (rc) return rc;
-  size_t total = table_bytes(nsim);
+  size_t total = table_bytes(nsim, cfgs);
   for (int c = 0; c < nsim; ++c) total += align_up(layout(layout_config(cfgs[c]), nullptr, nullptr), 256);
   *bytes = total;
   return IMB_OK;
@@ -598,10 +616,11 @@ int imb_batch_create(int32_t nsim, const imb_config* cfgs, void* hip_stream, voi
   off += align_up(sizeof(BatchChannel) * nsim, 256);
   b->d_half = (int*)(b->mem + off);
   off += align_up(sizeof(int) * 2 * (3 * MAX_BATCH + 2), 256);
-  b->d_all = (int*)(b->mem + off);
-  off += align_up(sizeof(int) * 2 * (MAX_BATCH + 1), 256);
   b->d_sync = (unsigned*)(b->mem + off);
   off += align_up(sizeof(unsigned) * SYNC_WORDS, 256);
+  b->d_blk = (unsigned*)(b->mem + off);
+  b->blk_cap = block_table_entries(nsim, cfgs);
+  off += align_up(sizeof(unsigned) * b->blk_cap, 256);
   launch_fill_zero(b->mem, off, b->stream);
   b->tile_w = cfgs[0].tile_w ? cfgs[0].tile_w : 64;
   b->tile_rows = cfgs[0].tile_rows ? cfgs[0].tile_rows : 1;
