@@ -1,15 +1,20 @@
 // d3q19.hip -- the three-dimensional lattice step with immersed spheres (D3Q19, Table 1 of the
 // paper; Sec. 2.2 and Eqs. 12-16) and its C-ABI (imb3_* in include/imb.h).
 //
-// One step is two kernels on the simulation's stream:
-//   k_step3     one 256-thread workgroup per tile (tw x th cells of one z layer): pull streaming
-//               (periodic x and z, half-way bounce-back walls in y or periodic y), the IMB
-//               collision of every cell with the spheres whose boxes touch the tile (the paper's
-//               cell-decomposition solid ratio), and per sphere the tile's force and torque
-//               partial (wave sums, compensated in FP32), written to the sphere's slot for the
-//               tile -- no atomics;
+// One step is three kernels on the simulation's stream:
+//   k_plain3    one 256-thread workgroup per tile (tw x th cells of one z layer): a tile that no
+//               sphere's box touches is streamed (pull: periodic x and z, half-way bounce-back
+//               walls in y or periodic y) and collided (BGK with the body force); any other tile
+//               is appended to the step's list of sphere tiles;
+//   k_step3     one workgroup per listed tile: the same streaming, the IMB collision of every
+//               cell with the spheres whose boxes touch the tile (the paper's cell-decomposition
+//               solid ratio), and per sphere the tile's force and torque partial (wave sums,
+//               compensated in FP32), written to the sphere's slot for the tile -- no atomics on
+//               the sums;
 //   k_finalize3 one workgroup: every sphere's force and torque as the fixed-order sum of its
-//               slots, then prescribed spheres move by their velocity.
+//               slots, then prescribed spheres move by their velocity; clears the tile list.
+// The sphere path holds the covering spheres' solid ratios and forces per cell; in its own
+// kernel its registers do not lower the occupancy of the plain tiles, nearly all of them.
 // Populations are stored as structure of arrays f[19][nz][ny][pitch], two copies (A-B); the
 // step pulls from the previous step's post-collision copy.
 #include <hip/hip_ext.h>
@@ -44,6 +49,9 @@ struct Lattice3Args {
   double* F;               // [np][3] force on each sphere of the last step
   double* Tq;              // [np][3] torque
   int* err;
+  int* sph_tiles;          // this step's tiles that a sphere's box touches (k_plain3 appends)
+  int* sph_count;          // [1] their number; k_finalize3 clears it for the next step
+  int sph_grid;            // workgroups of the k_step3 launch (>= any step's sphere tiles)
 };
 
 template <class T>
@@ -67,6 +75,61 @@ __device__ inline long long pull_index3(const Lattice3Args& a, int i, int x, int
   return (long long)i * a.plane + (long long)zs * a.zstride + (long long)ys * a.pitch + xs;
 }
 
+// A tile that no sphere's box touches: pull, BGK with the body force, store.  Every wavefront
+// tests every sphere's box (so the answer is uniform without a barrier); a touched tile is
+// appended to the step's sphere tiles instead.
+template <class St>
+__global__ __launch_bounds__(BLOCK) void k_plain3(Lattice3Args a) {
+  using T = typename St::T;
+  using S = typename St::S;
+  const int tiles = a.tiles_x * a.tiles_y * a.nz;
+  const int b = xcd_remap(blockIdx.x, tiles);
+  const int tx = b % a.tiles_x, rest = b / a.tiles_x;
+  const int ty = rest % a.tiles_y, z = rest / a.tiles_y;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int tw = 1 << a.tw_log;
+  bool touched = false;
+  for (int p0 = 0; p0 < a.np && !touched; p0 += 64) {
+    const int p = p0 + lane;
+    bool hit = false;
+    if (p < a.np) {
+      const double4 ps = a.pos[p];
+      const Box3 bx = sphere_box3(ps.x, ps.y, ps.z, ps.w, a.nx, a.ny, a.nz, a.walls, tw, a.th,
+                                  a.tiles_x, a.tiles_y);
+      hit = box3_slot(bx, tx, ty, z, a.tiles_x, a.tiles_y, a.nz) >= 0;
+    }
+    touched = __ballot(hit) != 0ull;
+  }
+  if (touched) {
+    if (tid == 0) {
+      const int k = atomicAdd(a.sph_count, 1);  // below `tiles`: each tile once per step
+      if (k < tiles) a.sph_tiles[k] = b;
+    }
+    return;
+  }
+  const int x = tx * tw + (tid & (tw - 1)), y = ty * a.th + (tid >> a.tw_log);
+  if (x >= a.nx || y >= a.ny) return;
+  const S* src = (const S*)a.src;
+  S* dst = (S*)a.dst;
+  T f[NQ3], fo[NQ3];
+#pragma unroll
+  for (int i = 0; i < NQ3; ++i) f[i] = St::decode(src[pull_index3(a, i, x, y, z)]);
+  auto none = [&](int) { return Sph<T>{}; };
+  auto drop = [&](int, T, T, T, T, T, T) {};
+  T rho;
+  if constexpr (St::deviation) {
+    rho = collide3_dev(f, 0, none, drop, (T)a.rho0, (T)a.tau0, (T)a.gx, (T)a.gy, (T)a.gz, fo);
+  } else {
+    rho = collide3_plain(f, 0, none, drop, a.tau0, a.gx, a.gy, a.gz, fo);
+  }
+  if (!(rho > T(0)) || !isfinite(rho)) atomicOr(a.err, ERR_RHO);
+  const long long base = (long long)z * a.zstride + (long long)y * a.pitch + x;
+#pragma unroll
+  for (int i = 0; i < NQ3; ++i) dst[(long long)i * a.plane + base] = St::encode(fo[i]);
+}
+
+// One tile of the step's sphere tiles (workgroup k takes entry k of the list; the launch has
+// sph_grid workgroups, at least as many as any step lists).
 template <class St>
 __global__ __launch_bounds__(BLOCK) void k_step3(Lattice3Args a) {
   using T = typename St::T;
@@ -75,9 +138,12 @@ __global__ __launch_bounds__(BLOCK) void k_step3(Lattice3Args a) {
   __shared__ int s_ncand;
   __shared__ double4 s_pos[MAXCAND3], s_vel[MAXCAND3], s_spin[MAXCAND3];
   __shared__ Acc<T> s_red[WAVES][NPART3];
+  __shared__ T s_off[64];  // sub-cell offsets (a.nsub <= 64)
 
-  const int tiles = a.tiles_x * a.tiles_y * a.nz;
-  const int b = xcd_remap(blockIdx.x, tiles);
+  const int nlist = *a.sph_count;
+  if ((int)blockIdx.x >= nlist) return;
+  subcell_offsets<T>(s_off, a.nsub, (int)threadIdx.x);  // complete at the first barrier below
+  const int b = a.sph_tiles[blockIdx.x];
   const int tx = b % a.tiles_x, rest = b / a.tiles_x;
   const int ty = rest % a.tiles_y, z = rest / a.tiles_y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -86,14 +152,18 @@ __global__ __launch_bounds__(BLOCK) void k_step3(Lattice3Args a) {
   const S* src = (const S*)a.src;
   S* dst = (S*)a.dst;
 
-  // spheres whose box holds this tile, ascending id (wavefront 0, ballot compaction)
+  // spheres whose box holds this tile, ascending id (wavefront 0, ballot compaction), with
+  // their position, velocity and spin (loaded together, kept for the listed ones)
   if (wave == 0) {
     int base = 0;
     for (int p0 = 0; p0 < a.np; p0 += 64) {
       const int p = p0 + lane;
       int slot = -1;
+      double4 ps{}, vl{}, sp{};
       if (p < a.np) {
-        const double4 ps = a.pos[p];
+        ps = a.pos[p];
+        vl = a.vel[p];
+        sp = a.spin[p];
         const Box3 bx = sphere_box3(ps.x, ps.y, ps.z, ps.w, a.nx, a.ny, a.nz, a.walls, tw, a.th,
                                     a.tiles_x, a.tiles_y);
         slot = box3_slot(bx, tx, ty, z, a.tiles_x, a.tiles_y, a.nz);
@@ -104,6 +174,9 @@ __global__ __launch_bounds__(BLOCK) void k_step3(Lattice3Args a) {
         if (q < MAXCAND3) {
           s_cand[q] = p;
           s_slot[q] = slot;
+          s_pos[q] = ps;
+          s_vel[q] = vl;
+          s_spin[q] = sp;
         } else {
           atomicOr(a.err, ERR_TILE_LIST);
         }
@@ -114,13 +187,6 @@ __global__ __launch_bounds__(BLOCK) void k_step3(Lattice3Args a) {
   }
   __syncthreads();
   const int ncand = s_ncand;
-  if (tid < ncand) {
-    const int p = s_cand[tid];
-    s_pos[tid] = a.pos[p];
-    s_vel[tid] = a.vel[p];
-    s_spin[tid] = a.spin[p];
-  }
-  __syncthreads();
 
   const bool live = x < a.nx && y < a.ny;
   // covering spheres of this cell: candidate index and solid ratio (ascending id)
@@ -139,7 +205,7 @@ __global__ __launch_bounds__(BLOCK) void k_step3(Lattice3Args a) {
     for (int j = 0; j < ncand; ++j) {
       T dx, dy, dz;
       sphere_lever<T>(a, s_pos[j], x, y, z, &dx, &dy, &dz);
-      const T e = sphere_ratio<T>((T)s_pos[j].w, dx, dy, dz, a.nsub);
+      const T e = sphere_ratio<T>((T)s_pos[j].w, dx, dy, dz, a.nsub, s_off);
       if (e > T(0)) {
         if (nc < MAXC3) {
 #pragma unroll
@@ -264,6 +330,10 @@ __global__ __launch_bounds__(BLOCK) void k_finalize3(Lattice3Args a) {
     ps.z = nzp;
     a.pos[p] = ps;
   }
+  if (threadIdx.x == 0) {  // the sphere tiles of this step are done: clear the list
+    if (*a.sph_count > a.sph_grid) atomicOr(a.err, ERR_TILE_LIST);
+    *a.sph_count = 0;
+  }
 }
 
 // Host FP64 [19][nz][ny][nx] post-stream populations (or the equilibrium of (rho, ux(y), uy, uz)
@@ -345,13 +415,16 @@ __global__ void k_gather3(Lattice3Args a, const typename St::S* src, double* fq,
 // arithmetic precision.
 template <class T>
 __global__ void k_solid3(Lattice3Args a, double* eps) {
+  __shared__ T s_off[64];  // sub-cell offsets (a.nsub <= 64 <= blockDim.x)
+  subcell_offsets<T>(s_off, a.nsub, (int)threadIdx.x);
+  __syncthreads();
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
   if (x >= a.nx || y >= a.ny || z >= a.nz) return;
   double s = 0.0;
   for (int p = 0; p < a.np; ++p) {
     T dx, dy, dz;
     sphere_lever<T>(a, a.pos[p], x, y, z, &dx, &dy, &dz);
-    s += (double)sphere_ratio<T>((T)a.pos[p].w, dx, dy, dz, a.nsub);
+    s += (double)sphere_ratio<T>((T)a.pos[p].w, dx, dy, dz, a.nsub, s_off);
   }
   eps[((long long)z * a.ny + y) * a.nx + x] = s;
 }
@@ -380,6 +453,9 @@ struct imb3_sim {
   int* mode = nullptr;
   double *F = nullptr, *Tq = nullptr, *part = nullptr;
   int* err = nullptr;
+  int* sph_tiles = nullptr;  // the step's sphere tiles and their number (k_plain3 -> k_step3)
+  int* sph_count = nullptr;
+  int sph_grid = 0;          // k_step3 workgroups: bounds the sphere tiles of any step
   double* stage = nullptr;  // readback staging (library-owned)
   size_t stage_bytes = 0;
   int cur = 0, np = 0;
@@ -455,11 +531,15 @@ size_t layout3(const imb3_config& c, char* base, imb3_sim* s) {
   char* Tq = take(mp * 3 * sizeof(double));
   char* part = take(mp * MAXSLOT3 * NPART3 * sizeof(double));
   char* err = take(sizeof(int));
+  char* sph_tiles = take((size_t)g.tiles_x * g.tiles_y * c.nz * sizeof(int));
+  char* sph_count = take(sizeof(int));
   if (s) {
     s->f[0] = f0; s->f[1] = f1;
     s->pos = (double4*)pos; s->vel = (double4*)vel; s->spin = (double4*)spin;
     s->mode = (int*)mode; s->F = (double*)F; s->Tq = (double*)Tq; s->part = (double*)part;
     s->err = (int*)err;
+    s->sph_tiles = (int*)sph_tiles;
+    s->sph_count = (int*)sph_count;
     s->tw = g.tw; s->tw_log = g.tw_log; s->th = g.th; s->tiles_x = g.tiles_x;
     s->tiles_y = g.tiles_y; s->pitch = g.pitch; s->plane = g.plane;
   }
@@ -507,6 +587,7 @@ Lattice3Args args3(imb3_sim* s, const void* src, void* dst) {
   a.src = src; a.dst = dst;
   a.np = s->np; a.pos = s->pos; a.vel = s->vel; a.spin = s->spin; a.mode = s->mode;
   a.part = s->part; a.F = s->F; a.Tq = s->Tq; a.err = s->err;
+  a.sph_tiles = s->sph_tiles; a.sph_count = s->sph_count; a.sph_grid = s->sph_grid;
   return a;
 }
 
@@ -520,23 +601,32 @@ void enqueue_step3(imb3_sim* s) {
   const int c = s->cur;
   Lattice3Args a = args3(s, s->f[c], s->f[c ^ 1]);
   const dim3 grid((unsigned)(s->tiles_x * s->tiles_y * s->cfg.nz));
+  const bool spheres = s->np > 0;
+  // timing: e0 at the plain kernel's start, e1 at the end of the last lattice kernel
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (s->timing) {
     e0 = new_event();
     e1 = new_event();
   }
+  auto go = [&](auto kernel, dim3 g, hipEvent_t start, hipEvent_t stop) {
+    if (start || stop)
+      hipExtLaunchKernelGGL(kernel, g, dim3(BLOCK), 0, s->stream, start, stop, 0, a);
+    else
+      hipLaunchKernelGGL(kernel, g, dim3(BLOCK), 0, s->stream, a);
+  };
+  const dim3 sgrid((unsigned)std::max(s->sph_grid, 1));
   if (s->cfg.storage == IMB_STORAGE_F64) {
-    if (e0) hipExtLaunchKernelGGL(k_step3<StoreF64>, grid, dim3(BLOCK), 0, s->stream, e0, e1, 0, a);
-    else hipLaunchKernelGGL(k_step3<StoreF64>, grid, dim3(BLOCK), 0, s->stream, a);
+    go(k_plain3<StoreF64>, grid, e0, spheres ? nullptr : e1);
+    if (spheres) go(k_step3<StoreF64>, sgrid, nullptr, e1);
   } else {
-    if (e0) hipExtLaunchKernelGGL(k_step3<StoreF32>, grid, dim3(BLOCK), 0, s->stream, e0, e1, 0, a);
-    else hipLaunchKernelGGL(k_step3<StoreF32>, grid, dim3(BLOCK), 0, s->stream, a);
+    go(k_plain3<StoreF32>, grid, e0, spheres ? nullptr : e1);
+    if (spheres) go(k_step3<StoreF32>, sgrid, nullptr, e1);
   }
   if (e0) {
     s->ev[0].push_back(e0);
     s->ev[0].push_back(e1);
   }
-  if (s->np > 0) {
+  if (spheres) {
     hipEvent_t g0 = nullptr, g1 = nullptr;
     if (s->timing) {
       g0 = new_event();
@@ -865,9 +955,18 @@ int imb3_set_spheres(imb3_sim* s, int32_t n, const double* x, const double* y, c
     hv[p] = make_double4(vx[p], vy[p], vz[p], 0.0);
     hw[p] = make_double4(wx[p], wy[p], wz[p], 0.0);
   }
+  // workgroups of the sphere-tile launch: the sum over spheres of the most tiles a box of the
+  // sphere's radius can span anywhere (a run of m cells spans at most m / w + 2 tiles of width w)
+  long long grid = 0;
+  for (int p = 0; p < n; ++p) {
+    const long long m = (long long)std::floor(2.0 * r[p] + 4.0);
+    grid += std::min<long long>(s->tiles_x, m / s->tw + 2) *
+            std::min<long long>(s->tiles_y, m / s->th + 2) * std::min<long long>(c.nz, m);
+  }
   hipStreamSynchronize(s->stream);
   drop_graphs3(s);
   s->np = n;
+  s->sph_grid = (int)std::min<long long>(grid, (long long)s->tiles_x * s->tiles_y * c.nz);
   hipError_t e = hipSuccess;
   if (n > 0) {
     e = hipMemcpy(s->pos, hp.data(), n * sizeof(double4), hipMemcpyHostToDevice);

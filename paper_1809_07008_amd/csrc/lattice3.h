@@ -126,22 +126,29 @@ __device__ inline T axis_d3(int c, double X, int n, bool periodic) {
 // point is not inside gives 0, one whose farthest corner is inside or on the surface gives 1
 // (every sub-cell centre is then strictly inside), so only cut cells count centres.
 template <class T>
-__device__ __noinline__ T sphere_subcells(T r, T dx, T dy, T dz, int n) {
+__device__ __noinline__ T sphere_subcells(T r, T dx, T dy, T dz, int n, const T* off) {
   const T r2 = r * r;
   int inside = 0;
   for (int k = 0; k < n; ++k) {
-    const T zc = dz + (T)((k + 0.5) / n - 0.5);
+    const T zc = dz + off[k];
     const T z2 = zc * zc;
     for (int j = 0; j < n; ++j) {
-      const T yc = dy + (T)((j + 0.5) / n - 0.5);
+      const T yc = dy + off[j];
       const T yz2 = yc * yc + z2;
       for (int i = 0; i < n; ++i) {
-        const T xc = dx + (T)((i + 0.5) / n - 0.5);
+        const T xc = dx + off[i];
         inside += xc * xc + yz2 < r2 ? 1 : 0;
       }
     }
   }
   return (T)inside / ((T)n * (T)n * (T)n);
+}
+
+// The sub-cell centres' offsets from the cell centre along one axis, (k + 1/2)/n - 1/2 for
+// k < n (evaluated in FP64, then rounded to T), for sphere_subcells; off holds n values.
+template <class T>
+__device__ inline void subcell_offsets(T* off, int n, int k) {
+  if (k < n) off[k] = (T)((k + 0.5) / n - 0.5);
 }
 
 template <class T>
@@ -152,12 +159,12 @@ __device__ inline T cell_near2(T d) {  // squared distance to the nearest point 
 }
 
 template <class T>
-__device__ inline T sphere_ratio(T r, T dx, T dy, T dz, int n) {
+__device__ inline T sphere_ratio(T r, T dx, T dy, T dz, int n, const T* off) {
   const T r2 = r * r;
   if (cell_near2(dx) + cell_near2(dy) + cell_near2(dz) >= r2) return T(0);
   const T fx = fabs(dx) + T(0.5), fy = fabs(dy) + T(0.5), fz = fabs(dz) + T(0.5);
   if (fx * fx + fy * fy + fz * fz <= r2) return T(1);
-  return sphere_subcells(r, dx, dy, dz, n);
+  return sphere_subcells(r, dx, dy, dz, n, off);
 }
 
 // ---------------------------------------------------------------- collision, FP64 (plain f)
