@@ -126,6 +126,35 @@ def test_graph_replay_equals_direct_launches_and_is_deterministic():
             assert np.array_equal(u, v)
 
 
+def test_sphere_set_changes_between_steps():
+    """The per-step list of sphere tiles starts empty whatever ran before: spheres, then none,
+    then a dozen with overlapping boxes (more listed tiles than one sphere's box), then two
+    again, each leg checked against the oracle run through the same changes."""
+    rng = np.random.default_rng(340)
+    nx, ny, nz = 44, 26, 38
+    f0 = random_f(rng, nx, ny, nz)
+    sim = imb.Simulation3(imb.make_config3(nx, ny, nz, 0.7, "f64", True, (1e-5, 0, 0),
+                                           max_spheres=12, eps_subcells=3))
+    ref = OracleSim3(OracleConfig3(nx=nx, ny=ny, nz=nz, tau0=0.7, walls=True, gx=1e-5, gy=0.0,
+                                   gz=0.0, eps_subcells=3))
+    sim.set_populations(f0)
+    ref.set_populations(f0)
+    none = tuple(np.zeros(0) for _ in range(4)) + (np.zeros((0, 3)), np.zeros((0, 3)),
+                                                   np.zeros(0, np.int32))
+    legs = [sphere_set(rng, nx, ny, nz, 2, 3.0, 5.0, True), none,
+            sphere_set(rng, nx, ny, nz, 12, 2.0, 4.0, True),
+            sphere_set(rng, nx, ny, nz, 2, 3.0, 5.0, True)]
+    for k, sph in enumerate(legs):
+        sim.set_spheres(*sph)
+        ref.set_spheres(*sph)
+        sim.step(7)
+        ref.step(7)
+        fg, fo = sim.populations(), ref.populations()
+        assert np.abs(fg - fo).max() <= 1e-12 * np.abs(fo).max(), k
+        if len(sph[0]):
+            assert_forces3(sim, ref)
+
+
 def test_set_spheres_rejects_out_of_range():
     sim = imb.Simulation3(imb.make_config3(30, 20, 30, 0.7, "f32", True, max_spheres=1))
     with pytest.raises(imb.ImbError):
