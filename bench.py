@@ -37,11 +37,11 @@ def lattice_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(storage: str, tile) -> float | None:
+def measured_traffic(storage: str, tile, disks: int = 500) -> float | None:
     """HBM-side bytes per lattice-kernel launch from the committed rocprofv3 counter summary
     (FETCH_SIZE + WRITE_SIZE, each scaled by what the counter reads for a copy kernel of known
-    size), or None when the summary is missing, was taken for another storage format or tile,
-    or the kernel's sources have changed since."""
+    size), or None when the summary is missing, was taken for another storage format, tile or
+    disk count, or the kernel's sources have changed since."""
     try:
         with open(COUNTERS) as fh:
             kv = dict(line.split(":", 1) for line in fh if ":" in line and not line.startswith("#"))
@@ -50,7 +50,7 @@ def measured_traffic(storage: str, tile) -> float | None:
     kv = {k.strip(): v.strip() for k, v in kv.items()}
     try:
         if (kv["kernel_source_sha256"] != lattice_source_hash() or kv["storage"] != storage
-                or kv["tile"] != "%dx%d" % tuple(tile)):
+                or kv["tile"] != "%dx%d" % tuple(tile) or int(kv["disks"]) != disks):
             return None
         fetch_scale = float(kv["copy_bytes"]) / (float(kv["copy_fetch_kib"]) * 1024.0)
         write_scale = float(kv["copy_bytes"]) / (float(kv["copy_write_kib"]) * 1024.0)
@@ -361,6 +361,9 @@ def main(argv=None):
                     help="skip the adjoint/forward ratio and the batched form (profiling the "
                          "forward step alone)")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--disks", type=int, default=500,
+                    help="disks of the 2048x1024 channel (500: the headline workload; 0: the "
+                         "lattice alone, a control)")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch kernels directly instead of replaying captured graphs")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -393,7 +396,7 @@ def main(argv=None):
                           "slab_share": slab_share(args.storage, (args.tile_w, args.tile_rows))}),
               flush=True)
         return 0
-    case = workloads.moving_disks(seed=args.seed, storage=args.storage)
+    case = workloads.moving_disks(seed=args.seed, storage=args.storage, n=args.disks)
     sim = imb.simulation_from_case(case, storage=args.storage, tile_w=args.tile_w,
                                    tile_rows=args.tile_rows)
     if args.no_graphs:
@@ -428,7 +431,8 @@ def main(argv=None):
     achieved = step_bytes / (lat_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(args.storage, (args.tile_w, args.tile_rows)),
+                "traffic": measured_traffic(args.storage, (args.tile_w, args.tile_rows),
+                                            args.disks),
                 "kernel_source_sha256": lattice_source_hash(),
                 "kernel": "k_step<%s>" % {"f64": "StoreF64", "f32": "StoreF32",
                                           "f16": "StoreF16"}[args.storage],
@@ -450,7 +454,7 @@ def main(argv=None):
         "vs_baseline": None,
         "dtype": args.storage,
         "data": "synthetic (seeded disks, fluid at rest)",
-        "config": {"workload": "moving_disks_2048x1024_n500", "nx": case.nx, "ny": case.ny,
+        "config": {"workload": case.name, "nx": case.nx, "ny": case.ny,
                    "disks": case.particles.n, "tau0": case.tau0, "smagorinsky_cs": case.cs,
                    "storage": args.storage, "tile": [args.tile_w, args.tile_rows],
                    "parallelism": "single GPU"},
