@@ -167,6 +167,25 @@ def test_moving_disks_full_size_fp64_short():
     assert np.abs(uxg - uxo).max() < 1e-12 * umax and np.abs(uyg - uyo).max() < 1e-12 * umax
 
 
+def test_maximum_disk_count_fp64_parity():
+    """512 free disks, the particle phase's capacity (one disk per thread of its workgroup; the
+    band masks' second words hold disks 256-511): FP64 parity for 8 coupled steps, and a
+    capacity of 513 is rejected at set-up."""
+    case = W.moving_disks(seed=5, nx=1536, ny=768, n=512, storage="f64")
+    assert case.particles.n == 512
+    sim, ref = gpu_for(case, tile_w=32, tile_rows=2), oracle_for(case)
+    sim.step(8)
+    ref.step(8)
+    assert_forces_fp64(sim, ref)
+    for a, b in zip(sim.particles(), ref.particles()):
+        assert np.abs(a - b).max() < 1e-10
+    assert rel_inf(sim.populations(), ref.populations()) < 1e-12
+    cfg = imb.config_from_case(case, None, 32, 2, "f64")
+    cfg.max_particles = 513
+    with pytest.raises(imb.ImbError):
+        imb.Simulation(cfg)
+
+
 def test_no_particles_and_minimal_grid():
     rng = np.random.default_rng(9)
     for nx, ny, walls in ((2, 2, True), (3, 2, False), (5, 7, True)):
