@@ -137,7 +137,8 @@ __device__ inline int block_exclusive_scan(int* cnt, int n, int* s_wave) {
 }
 
 // Latency layout: every global load the phase needs is issued in one batch at the start and
-// every global store is issued after the last barrier, so barriers never wait on memory; each
+// every global store is issued after the last barrier (band masks of more tile rows than one
+// round of LDS holds aside), so barriers never wait on memory; each
 // disk's state lives in its own thread's registers and only positions and velocities that other
 // disks' contact tests read are mirrored in LDS.
 // One disk per thread: NT >= np.  `lds` holds a.lds_doubles >= max(PP_DOUBLES np, MASK_WORDS)
