@@ -75,19 +75,10 @@ __device__ inline long long pull_index3(const Lattice3Args& a, int i, int x, int
   return (long long)i * a.plane + (long long)zs * a.zstride + (long long)ys * a.pitch + xs;
 }
 
-// A tile that no sphere's box touches: pull, BGK with the body force, store.  Every wavefront
-// tests every sphere's box (so the answer is uniform without a barrier); a touched tile is
-// appended to the step's sphere tiles instead.
-template <class St>
-__global__ __launch_bounds__(BLOCK) void k_plain3(Lattice3Args a) {
-  using T = typename St::T;
-  using S = typename St::S;
-  const int tiles = a.tiles_x * a.tiles_y * a.nz;
-  const int b = xcd_remap(blockIdx.x, tiles);
-  const int tx = b % a.tiles_x, rest = b / a.tiles_x;
-  const int ty = rest % a.tiles_y, z = rest / a.tiles_y;
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int tw = 1 << a.tw_log;
+// Does any sphere's box hold tile (tx, ty, z)?  Every wavefront tests every sphere, so the
+// answer is uniform over the workgroup without a barrier.
+__device__ __forceinline__ bool tile_touched3(const Lattice3Args& a, int tx, int ty, int z) {
+  const int lane = threadIdx.x & 63, tw = 1 << a.tw_log;
   bool touched = false;
   for (int p0 = 0; p0 < a.np && !touched; p0 += 64) {
     const int p = p0 + lane;
@@ -100,13 +91,15 @@ __global__ __launch_bounds__(BLOCK) void k_plain3(Lattice3Args a) {
     }
     touched = __ballot(hit) != 0ull;
   }
-  if (touched) {
-    if (tid == 0) {
-      const int k = atomicAdd(a.sph_count, 1);  // below `tiles`: each tile once per step
-      if (k < tiles) a.sph_tiles[k] = b;
-    }
-    return;
-  }
+  return touched;
+}
+
+// The cells of a tile that no sphere's box touches: pull, BGK with the body force, store.
+template <class St>
+__device__ __forceinline__ void plain_cells3(const Lattice3Args& a, int tx, int ty, int z) {
+  using T = typename St::T;
+  using S = typename St::S;
+  const int tid = threadIdx.x, tw = 1 << a.tw_log;
   const int x = tx * tw + (tid & (tw - 1)), y = ty * a.th + (tid >> a.tw_log);
   if (x >= a.nx || y >= a.ny) return;
   const S* src = (const S*)a.src;
@@ -128,10 +121,28 @@ __global__ __launch_bounds__(BLOCK) void k_plain3(Lattice3Args a) {
   for (int i = 0; i < NQ3; ++i) dst[(long long)i * a.plane + base] = St::encode(fo[i]);
 }
 
-// One tile of the step's sphere tiles (workgroup k takes entry k of the list; the launch has
-// sph_grid workgroups, at least as many as any step lists).
+// A tile that no sphere's box touches is streamed and collided; a touched one is appended to
+// the step's sphere tiles instead.
 template <class St>
-__global__ __launch_bounds__(BLOCK) void k_step3(Lattice3Args a) {
+__global__ __launch_bounds__(BLOCK) void k_plain3(Lattice3Args a) {
+  const int tiles = a.tiles_x * a.tiles_y * a.nz;
+  const int b = xcd_remap(blockIdx.x, tiles);
+  const int tx = b % a.tiles_x, rest = b / a.tiles_x;
+  const int ty = rest % a.tiles_y, z = rest / a.tiles_y;
+  if (tile_touched3(a, tx, ty, z)) {
+    if (threadIdx.x == 0) {
+      const int k = atomicAdd(a.sph_count, 1);  // below `tiles`: each tile once per step
+      if (k < tiles) a.sph_tiles[k] = b;
+    }
+    return;
+  }
+  plain_cells3<St>(a, tx, ty, z);
+}
+
+// The cells of tile b, which some sphere's box touches: the IMB collision with the covering
+// spheres and each listed sphere's force and torque partial for the tile.
+template <class St>
+__device__ __forceinline__ void sphere_cells3(const Lattice3Args& a, int b) {
   using T = typename St::T;
   using S = typename St::S;
   __shared__ int s_cand[MAXCAND3], s_slot[MAXCAND3];
@@ -140,10 +151,7 @@ __global__ __launch_bounds__(BLOCK) void k_step3(Lattice3Args a) {
   __shared__ Acc<T> s_red[WAVES][NPART3];
   __shared__ T s_off[64];  // sub-cell offsets (a.nsub <= 64)
 
-  const int nlist = *a.sph_count;
-  if ((int)blockIdx.x >= nlist) return;
   subcell_offsets<T>(s_off, a.nsub, (int)threadIdx.x);  // complete at the first barrier below
-  const int b = a.sph_tiles[blockIdx.x];
   const int tx = b % a.tiles_x, rest = b / a.tiles_x;
   const int ty = rest % a.tiles_y, z = rest / a.tiles_y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -285,6 +293,15 @@ __global__ __launch_bounds__(BLOCK) void k_step3(Lattice3Args a) {
     __syncthreads();
   }
 }
+
+// One tile of the step's sphere tiles (workgroup k takes entry k of the list; the launch has
+// sph_grid workgroups, at least as many as any step lists).
+template <class St>
+__global__ __launch_bounds__(BLOCK) void k_step3(Lattice3Args a) {
+  if ((int)blockIdx.x >= *a.sph_count) return;
+  sphere_cells3<St>(a, a.sph_tiles[blockIdx.x]);
+}
+
 
 // Every sphere's force and torque (the sum of its slots in slot order per lane, then a fixed
 // butterfly across the wavefront), then the prescribed spheres move by their velocity.
