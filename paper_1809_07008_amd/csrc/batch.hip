@@ -397,6 +397,11 @@ int refresh(imb_batch* b) {
     b->err = "batch workgroup table too small for the tile shape";
     return IMB_EINVAL;
   }
+  for (int c = 0; c < b->nch; ++c)
+    if (tiles[c] >= (1 << 24)) {  // a table entry holds the item in its low 24 bits
+      b->err = "channel " + std::to_string(c) + ": more than 2^24 tiles";
+      return IMB_EINVAL;
+    }
   std::vector<unsigned> blk((size_t)b->all_d + b->all_t);
   for (int c = 0, d = 0, t = b->all_d; c < b->nch; ++c) {
     const int nd = b->h_ch[c].la[0].np * b->h_ch[c].la[0].dparts;
