@@ -152,6 +152,7 @@ __device__ void disk_cells(const LatticeArgs& a, int item) {
   __shared__ Acc<T> s_fr[WAVES][3];
   __shared__ int s_rx0[64], s_rpre[65];   // row-wise cell enumeration (rows of the box <= 64)
   __shared__ unsigned long long s_rmask[64];  // per row: the entries that can reach it
+  __shared__ T s_off[64];                 // sub-cell offsets when eps_sub > 0 (eps_sub <= 64)
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -180,6 +181,9 @@ __device__ void disk_cells(const LatticeArgs& a, int item) {
   }
   int nn = a.nnbr[p];
   if (nn > NBMAX) nn = NBMAX;
+  // the sub-cell offsets of the paper's estimate, read by the cell loop after the barriers below
+  if (tid < a.eps_sub) s_off[tid] = subcell_offset<T>(tid, a.eps_sub);
+  const T* off = a.eps_sub > 0 ? s_off : nullptr;
   if (nn < 0) nn = 0;
   const int nd = nn + 1;
   // Entry k: p itself or neighbour k - 1, placed at its rank by id (wave 0, one lane each; the
@@ -330,12 +334,12 @@ __device__ void disk_cells(const LatticeArgs& a, int item) {
         pdx = dx;
         pdy = dy;
       } else {
-        s_ce[nc][tid] = cell_solid_ratio<T>(s_de[k].r, dx, dy, a.eps_sub);
+        s_ce[nc][tid] = cell_solid_ratio<T>(s_de[k].r, dx, dy, a.eps_sub, off);
       }
       ++nc;
     }
     if (own < 0) continue;  // p does not cover this cell
-    s_ce[own][tid] = cell_solid_ratio<T>((T)pp.z, pdx, pdy, a.eps_sub);
+    s_ce[own][tid] = cell_solid_ratio<T>((T)pp.z, pdx, pdy, a.eps_sub, off);
     T f[NQ], fo[NQ];
     pull_load<St, W>(a, src, x, y, f);
     auto disk = [&](int k) {

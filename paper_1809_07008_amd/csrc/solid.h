@@ -310,15 +310,23 @@ __host__ __device__ inline T solid_fraction(T r, T dx, T dy) {
   return cut_cell_fraction(r, dx, dy);
 }
 
+// Offset of the k-th of n sub-cell centres from the cell centre along one axis, (k + 1/2)/n - 1/2
+// (evaluated in FP64, then rounded to T).
+template <class T>
+__host__ __device__ inline T subcell_offset(int k, int n) {
+  return (T)((k + 0.5) / n - 0.5);
+}
+
 // Fraction of the n x n sub-cell centres of the cell centred at (dx, dy) strictly inside the
 // disk; out of line, like cut_cell_fraction, so that it does not enlarge the caller's registers.
+// off: the n offsets (subcell_offset) from a table, or null to evaluate them here.
 template <class T>
-__host__ __device__ __noinline__ T subcell_count(T r, T dx, T dy, int n) {
+__host__ __device__ __noinline__ T subcell_count(T r, T dx, T dy, int n, const T* off) {
   int inside = 0;
   for (int j = 0; j < n; ++j) {
-    const T yc = dy + (T)((j + 0.5) / n - 0.5);
+    const T yc = dy + (off ? off[j] : subcell_offset<T>(j, n));
     for (int i = 0; i < n; ++i) {
-      const T xc = dx + (T)((i + 0.5) / n - 0.5);
+      const T xc = dx + (off ? off[i] : subcell_offset<T>(i, n));
       inside += xc * xc + yc * yc < r * r ? 1 : 0;
     }
   }
@@ -327,8 +335,8 @@ __host__ __device__ __noinline__ T subcell_count(T r, T dx, T dy, int n) {
 
 // A cut cell's ratio under the selected estimate (out of line: one call site in the caller).
 template <class T>
-__host__ __device__ __noinline__ T cut_ratio(T r, T dx, T dy, int n) {
-  if (n > 0) return subcell_count(r, dx, dy, n);
+__host__ __device__ __noinline__ T cut_ratio(T r, T dx, T dy, int n, const T* off) {
+  if (n > 0) return subcell_count(r, dx, dy, n, off);
   return cut_cell_fraction(r, dx, dy);
 }
 
@@ -337,8 +345,9 @@ __host__ __device__ __noinline__ T cut_ratio(T r, T dx, T dy, int n) {
 // inside the disk.  Both share the test for cells wholly outside (nearest point not inside: 0)
 // or inside (farthest corner inside or on the circle: 1; every sub-cell centre is then at least
 // 1/(2n) further in or out), so only cut cells reach the out-of-line part.
+// off: a table of the n sub-cell offsets (subcell_offset), or null.
 template <class T>
-__host__ __device__ inline T cell_solid_ratio(T r, T dx, T dy, int n) {
+__host__ __device__ inline T cell_solid_ratio(T r, T dx, T dy, int n, const T* off = nullptr) {
   const T x0 = dx - T(0.5), x1 = dx + T(0.5), y0 = dy - T(0.5), y1 = dy + T(0.5);
   const T nx = x0 > T(0) ? x0 : (x1 < T(0) ? x1 : T(0));
   const T ny = y0 > T(0) ? y0 : (y1 < T(0) ? y1 : T(0));
@@ -350,7 +359,7 @@ __host__ __device__ inline T cell_solid_ratio(T r, T dx, T dy, int n) {
     float e;
     if (n == 0 && one_arc_fraction(r, dx, dy, &e)) return e;
   }
-  return cut_ratio(r, dx, dy, n);
+  return cut_ratio(r, dx, dy, n, off);
 }
 
 template <class T>

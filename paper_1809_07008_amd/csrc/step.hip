@@ -43,7 +43,11 @@ __global__ __launch_bounds__(BLOCK) void k_solid_field(LatticeArgs a, double* ep
   __shared__ int s_cnt[2 * WAVES];
   __shared__ int s_pid[LMAX], s_slot[LMAX];
   __shared__ CellScratch<T> cs;
+  __shared__ T s_off[64];  // sub-cell offsets when eps_sub > 0 (eps_sub <= 64)
   const int tid = threadIdx.x;
+  // the sub-cell offsets of the paper's estimate, read after the tile list's barriers
+  if (tid < a.eps_sub) s_off[tid] = subcell_offset<T>(tid, a.eps_sub);
+  const T* off = a.eps_sub > 0 ? s_off : nullptr;
   const int tile = blockIdx.x;
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
   const int tw = 1 << a.tw_log, th = BLOCK >> a.tw_log;
@@ -53,7 +57,7 @@ __global__ __launch_bounds__(BLOCK) void k_solid_field(LatticeArgs a, double* ep
   for (int rr = 0; rr < a.rows; ++rr) {
     const int y = ybase + rr * th;
     if (x >= a.nx || y >= a.ny) continue;
-    const int nc = covering_disks<T>(a, s_pl, n, x, y, cs);
+    const int nc = covering_disks<T>(a, s_pl, n, x, y, cs, off);
     double s = 0.0;
     for (int k = 0; k < nc; ++k) s += (double)cs.ce[k][tid];
     eps_out[(long long)y * a.nx + x] = s;

@@ -123,13 +123,13 @@ __device__ inline void lever_arm(const LatticeArgs& a, const PEntry<T>& e, int x
 // (used by the solid-ratio diagnostic).  Returns their count.
 template <class T>
 __device__ inline int covering_disks(const LatticeArgs& a, const PEntry<T>* pl, int n, int x,
-                                     int y, CellScratch<T>& cs) {
+                                     int y, CellScratch<T>& cs, const T* off) {
   const int tid = threadIdx.x;
   int nc = 0;
   for (int j = 0; j < n; ++j) {
     T dx, dy;
     lever_arm(a, pl[j], x, y, &dx, &dy);
-    const T eps = cell_solid_ratio<T>(pl[j].r, dx, dy, a.eps_sub);
+    const T eps = cell_solid_ratio<T>(pl[j].r, dx, dy, a.eps_sub, off);
     if (eps > T(0)) {
       if (nc < MAXC) {
         cs.cj[nc][tid] = j;
