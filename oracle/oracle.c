@@ -199,12 +199,16 @@ double o_solid_fraction(double r_, double dx, double dy) {
   int nc = 0;
   cand[nc++] = -r;
   cand[nc++] = r;
-  if (fabsl(y0) < r) {
+  /* where the circle meets the lines y = y0 and y = y1; a line tangent to the circle (|y| = r)
+   * meets it at x = 0, which must split the pieces too: each piece is classified at its
+   * midpoint, and a midpoint on the tangent point would take the line for the chord's end over
+   * the whole piece */
+  if (fabsl(y0) <= r) {
     ld w = half_chord(r, y0);
     cand[nc++] = -w;
     cand[nc++] = w;
   }
-  if (fabsl(y1) < r) {
+  if (fabsl(y1) <= r) {
     ld w = half_chord(r, y1);
     cand[nc++] = -w;
     cand[nc++] = w;
@@ -237,6 +241,10 @@ double o_solid_fraction(double r_, double dx, double dy) {
     ld bot_int = bot_is_circle ? -semi : y0 * (b - a);
     area += top_int - bot_int;
   }
+  /* a fraction (Sec. 2.2); rounding can leave a cell that the circle only grazes a few units of
+   * the last place outside [0, 1] */
+  if (area < 0.0L) area = 0.0L;
+  if (area > 1.0L) area = 1.0L;
   return (double)area;
 }
 

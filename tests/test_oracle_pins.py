@@ -80,6 +80,34 @@ def test_solid_fraction_sums_to_disk_area(seed):
     assert abs(tot - math.pi * r * r) <= 1e-12 * math.pi * r * r + 1e-13
 
 
+@pytest.mark.parametrize("r", [0.5, 1.5, 4.5, 6.5, 2.0 ** -0.5, 6.5 ** 0.5, 12.5 ** 0.5])
+def test_solid_fraction_degenerate_disks_on_a_node(r):
+    """A disk centred on a node with a half-integer radius is tangent to four cell edges at
+    their midpoints; with r^2 = a^2 + b^2 (a, b half-integers) the circle runs through cell
+    corners.  The fractions still sum to pi r^2, keep the x-y symmetry, and lie within the
+    brute-force bracket; a tangent cell's fraction equals the integral of its clipped chord
+    (independent quadrature)."""
+    R = int(math.ceil(r)) + 2
+    tot = 0.0
+    for i in range(-R, R + 1):
+        for j in range(-R, R + 1):
+            e = oracle.solid_fraction(r, float(i), float(j))
+            assert 0.0 <= e <= 1.0
+            assert abs(e - oracle.solid_fraction(r, float(j), float(i))) < 1e-15
+            assert abs(e - oracle.solid_fraction(r, float(-i), float(j))) < 1e-15
+            if 0.0 < e < 1.0 and abs(i) <= R - 2 and abs(j) <= R - 2 and (i + j) % 3 == 0:
+                lo, hi = brute_bracket(r, float(i), float(j), n=400)
+                assert lo - 1e-12 <= e <= hi + 1e-12, (r, i, j, lo, e, hi)
+            tot += e
+    assert abs(tot - math.pi * r * r) <= 1e-12 * math.pi * r * r + 1e-13
+    if r > 1.0 and (2 * r) % 2 == 1:  # half-integer: the cell below the disk touches it at (0, -r)
+        from scipy import integrate
+        want = integrate.quad(lambda u: math.sqrt(r * r - u * u) - (r - 1.0), -0.5, 0.5,
+                              epsabs=1e-15, epsrel=1e-15)[0]
+        for dx, dy in ((0.0, -(r - 0.5)), (0.0, r - 0.5), (r - 0.5, 0.0), (-(r - 0.5), 0.0)):
+            assert abs(oracle.solid_fraction(r, dx, dy) - want) < 1e-13
+
+
 def test_solid_fraction_symmetries_and_range():
     rng = np.random.default_rng(3)
     for _ in range(400):
