@@ -287,8 +287,8 @@ int imb_get_adjoint_timing(imb_sim* sim, double* forward_ms, double* reverse_ms,
  * The method per channel is the coupled step of imb_step (Sec. 2; Eqs. 1-2, 12-17), and a
  * channel evolves bit for bit as the same channel would alone with the same tile shape, under
  * either schedule.
- * Limits: 1..128 channels, F32 storage, at most 256 disks and ny <= 3071 per channel
- * (IMB_EINVAL / IMB_EUNSUPPORTED otherwise).  A barrier that does not open within 2 s aborts
+ * Limits: 1..128 channels, F32 storage, at most 256 disks per channel (IMB_EINVAL /
+ * IMB_EUNSUPPORTED otherwise).  A barrier that does not open within 2 s aborts
  * the kernel (every workgroup exits) and the next synchronising call returns IMB_EHIP. */
 typedef struct imb_batch imb_batch;
 

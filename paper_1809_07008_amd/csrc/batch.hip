@@ -288,10 +288,6 @@ int validate_batch(int32_t nsim, const imb_config* cfgs, std::string* why) {
       *why = "channel " + std::to_string(c) + ": at most 256 disks per batched channel";
       return IMB_EINVAL;
     }
-    if (cfgs[c].ny + 1 > 2 * PP_LDS) {
-      *why = "channel " + std::to_string(c) + ": ny too large for a batched channel";
-      return IMB_EINVAL;
-    }
     imb_config l = layout_config(cfgs[c]);
     if (validate_config(&l, &w)) {
       *why = "channel " + std::to_string(c) + ": " + w;

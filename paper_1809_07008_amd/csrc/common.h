@@ -18,7 +18,6 @@ constexpr int WAVES = BLOCK / 64;
 constexpr int LMAX = 32;           // disks whose boxes may touch one tile
 constexpr int MAXC = 4;            // disks covering one cell (three cannot unless they overlap)
 constexpr int MAXSLOT = 64;        // tiles per disk box (partial-sum slots per disk)
-constexpr int MAX_BANDS = 6144;    // tile rows (bands) of one lattice
 constexpr int NBMAX = 32;          // DEM neighbour-list capacity per disk
 constexpr int MAX_PARTICLES = 512;
 constexpr int MASK_WORDS = MAX_PARTICLES / 64;  // 64-bit words of a tile row's disk mask

@@ -134,9 +134,6 @@ int validate_config(const imb_config* c, std::string* why) {
   const int rows = c->tile_rows ? c->tile_rows : 1;
   if (rows != 1 && rows != 2 && rows != 4) return bad("tile_rows must be 1, 2 or 4");
   if (c->flags & ~IMB_FLAG_WALLS) return bad("unknown flag");
-  Geometry g;
-  sim_geometry(*c, &g);
-  if (g.tiles_y > MAX_BANDS) return bad("too many tile rows (ny / tile height > 6144)");
   return IMB_OK;
 }
 

@@ -207,3 +207,33 @@ def test_moving_walls_in_a_batch_match_single():
         s = single(c, (32, 2))
         s.step(20)
         assert_same(b, k, s)
+
+
+@pytest.mark.parametrize("schedule", [imb.IMB_BATCH_PER_STEP, imb.IMB_BATCH_PERSISTENT])
+def test_tall_channel_matches_single(schedule):
+    """A 128x4096 channel beside a small one: 256 tile rows of 32x2 tiles, more than one round of
+    the particle phase's band masks holds in a batched workgroup's LDS (224 rows), so the masks
+    are built in two rounds; disks sit on both sides of the rounds' boundary (tile row 224, y
+    about 3584).  Bit for bit as the channel alone."""
+    rng = np.random.default_rng(23)
+    x, y, r = W.place_disks(rng, 128, 4096, 40, 8.0, 14.0, gap=1.0, wall_gap=1.0)
+    away = np.abs(y - 3584.0) > 60.0  # keep the random ones clear of the placed ones
+    bx = np.array([16.0, 48.0, 80.0, 112.0, 30.0, 95.0])
+    by = 3584.0 + np.array([-20.0, -9.0, 0.5, 9.0, 20.0, 31.0])  # around the boundary
+    x = np.concatenate([x[away], bx])
+    y = np.concatenate([y[away], by])
+    r = np.concatenate([r[away], np.full(6, 5.0)])
+    n = len(x)
+    p = W.Particles(x, y, r, rng.normal(0, 0.01, n), rng.normal(0, 0.01, n), np.zeros(n),
+                    np.zeros(n, np.int32))
+    tall = W.Case("tall", 128, 4096, tau0=0.6, steps=0, storage="f32", walls=True, gx=1e-5,
+                  particles=p)
+    cases = [tall, mixed_cases()[0]]
+    b = imb.batch_from_cases(cases, tile_w=32, tile_rows=2)
+    b.set_schedule(schedule)
+    b.step(9)
+    b.sync()
+    for k, c in enumerate(cases):
+        s = single(c, (32, 2))
+        s.step(9)
+        assert_same(b, k, s)

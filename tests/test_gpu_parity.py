@@ -186,6 +186,43 @@ def test_maximum_disk_count_fp64_parity():
         imb.Simulation(cfg)
 
 
+def test_disks_tangent_to_cell_edges_fp64_parity():
+    """Degenerate geometry of the exact solid ratio: disks centred on nodes with half-integer
+    radii (the circle touches four cell edges at their midpoints) and with r^2 = 12.5 (the
+    circle runs through cell corners), fixed, prescribed and free: FP64 parity for 6 steps."""
+    xs = np.array([20.0, 50.0, 84.0, 110.0])
+    ys = np.array([20.0, 30.0, 16.0, 34.0])
+    rs = np.array([6.5, 4.5, 12.5 ** 0.5, 5.5])
+    p = W.Particles(xs, ys, rs, np.array([0.0, 0.01, 0.0, -0.01]), np.array([0.0, 0.0, 0.005, 0.0]),
+                    np.array([0.0, 0.0, 0.001, 0.0]), np.array([1, 2, 0, 0], np.int32))
+    case = W.Case("tangent", 128, 48, tau0=0.65, steps=6, storage="f64", walls=True, gx=1e-5,
+                  particles=p)
+    sim, ref = gpu_for(case, tile_w=32, tile_rows=2), oracle_for(case)
+    assert np.abs(sim.solid_field() - ref.solid_field()).max() < 1e-13
+    sim.step(6)
+    ref.step(6)
+    assert_parity(sim, ref)
+
+
+def test_band_masks_in_several_rounds_fp64_parity():
+    """525 tile rows (64x1 tiles on a 64x2100 lattice), more than one round of the particle
+    phase's band masks holds (512 rows): disks on both sides of the rounds' boundary (tile row
+    512, y about 2048) and near both walls, FP64 parity for 8 coupled steps."""
+    rng = np.random.default_rng(29)
+    xs = np.array([20.0, 44.0, 12.0, 52.0, 30.0, 18.0, 46.0])
+    ys = np.array([2040.0, 2049.5, 2058.0, 2031.0, 8.0, 2090.0, 1000.0])
+    rs = np.array([6.0, 5.5, 5.0, 4.5, 6.5, 5.0, 7.0])
+    p = W.Particles(xs, ys, rs, rng.normal(0, 0.01, 7), rng.normal(0, 0.01, 7), np.zeros(7),
+                    np.zeros(7, np.int32))
+    case = W.Case("tall", 64, 2100, tau0=0.6, steps=8, storage="f64", walls=True, gx=1e-5,
+                  particles=p)
+    sim, ref = gpu_for(case, tile_w=64, tile_rows=1), oracle_for(case)
+    sim.step(8)
+    ref.step(8)
+    assert_forces_fp64(sim, ref)
+    assert rel_inf(sim.populations(), ref.populations()) < 1e-12
+
+
 def test_no_particles_and_minimal_grid():
     rng = np.random.default_rng(9)
     for nx, ny, walls in ((2, 2, True), (3, 2, False), (5, 7, True)):
