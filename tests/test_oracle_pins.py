@@ -101,11 +101,16 @@ def test_solid_fraction_degenerate_disks_on_a_node(r):
             tot += e
     assert abs(tot - math.pi * r * r) <= 1e-12 * math.pi * r * r + 1e-13
     if r > 1.0 and (2 * r) % 2 == 1:  # half-integer: the cell below the disk touches it at (0, -r)
-        from scipy import integrate
-        want = integrate.quad(lambda u: math.sqrt(r * r - u * u) - (r - 1.0), -0.5, 0.5,
-                              epsabs=1e-15, epsrel=1e-15)[0]
+        # its area: the chord height above the cell's far edge, integrated over the cell's width;
+        # by the antiderivative of sqrt(r^2 - u^2), and by 40-point Gauss-Legendre quadrature
+        # of 1 - u^2 / (r + sqrt(r^2 - u^2)) (the same height, written without cancellation)
+        closed = 0.5 * math.sqrt(r * r - 0.25) + r * r * math.asin(0.5 / r) - (r - 1.0)
+        u, w = np.polynomial.legendre.leggauss(40)
+        u = 0.5 * u
+        gauss = 0.5 * float(np.sum(w * (1.0 - u * u / (r + np.sqrt(r * r - u * u)))))
+        assert abs(closed - gauss) < 1e-14
         for dx, dy in ((0.0, -(r - 0.5)), (0.0, r - 0.5), (r - 0.5, 0.0), (-(r - 0.5), 0.0)):
-            assert abs(oracle.solid_fraction(r, dx, dy) - want) < 1e-13
+            assert abs(oracle.solid_fraction(r, dx, dy) - closed) < 1e-13
 
 
 def test_solid_fraction_symmetries_and_range():
