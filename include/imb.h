@@ -287,8 +287,11 @@ int imb_get_adjoint_timing(imb_sim* sim, double* forward_ms, double* reverse_ms,
  * The method per channel is the coupled step of imb_step (Sec. 2; Eqs. 1-2, 12-17), and a
  * channel evolves bit for bit as the same channel would alone with the same tile shape, under
  * either schedule.
- * Limits: 1..128 channels, F32 storage, at most 256 disks per channel (IMB_EINVAL /
- * IMB_EUNSUPPORTED otherwise).  A barrier that does not open within 2 s aborts
+ * Limits: 1..128 channels, F32 storage (IMB_EINVAL / IMB_EUNSUPPORTED otherwise), at most 512
+ * disks per channel (max_particles), of which the persistent schedule takes 256: a batch with
+ * a channel of max_particles > 256 starts on the per-step schedule, refuses the persistent one
+ * (IMB_EUNSUPPORTED) and the autotuner tries only the per-step one.  A barrier that does not
+ * open within 2 s aborts
  * the kernel (every workgroup exits) and the next synchronising call returns IMB_EHIP. */
 typedef struct imb_batch imb_batch;
 
@@ -322,7 +325,8 @@ int imb_batch_set_launch(imb_batch* b, int32_t grid, int32_t tile_w, int32_t til
 int imb_batch_get_launch(imb_batch* b, int32_t* grid, int32_t* tile_w, int32_t* tile_rows,
                          int32_t* max_grid);
 /* Schedule of the batch (IMB_BATCH_PERSISTENT, the default, or IMB_BATCH_PER_STEP; other values
- * IMB_EINVAL).  set synchronises. */
+ * IMB_EINVAL; IMB_BATCH_PERSISTENT on a batch with a channel of more than 256 disks
+ * IMB_EUNSUPPORTED).  set synchronises. */
 int imb_batch_set_schedule(imb_batch* b, int32_t schedule);
 int imb_batch_get_schedule(imb_batch* b, int32_t* schedule);
 /* Autotuner: times trial_steps steps (after 2 warm-up steps) for each candidate tile shape

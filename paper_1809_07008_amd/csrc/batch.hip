@@ -35,8 +35,14 @@
 namespace imb {
 
 constexpr int MAX_BATCH = 128;   // channels per batch
-constexpr int PP_LDS = 256 * PP_DOUBLES;  // doubles of particle-phase scratch: 256 disks
-constexpr int BATCH_MAX_DISKS = 256;
+// Disks per channel: the persistent kernel runs a channel's particle phase in one of its own
+// 256-thread workgroups (one disk per thread), so it takes channels of at most 256 disks; the
+// per-step schedule launches the particle phases on their own and takes up to MAX_PARTICLES with
+// 512-thread workgroups, as a single simulation does.
+constexpr int PERSISTENT_MAX_DISKS = BLOCK;
+constexpr int PP_LDS = PERSISTENT_MAX_DISKS * PP_DOUBLES;  // doubles of particle-phase scratch
+constexpr int PP_WIDE = MAX_PARTICLES;                     // threads of the wide particle phase
+constexpr int PP_LDS_WIDE = PP_WIDE * PP_DOUBLES;
 constexpr int SYNC_WORDS = 8;    // [0] arrivals [1] generation [2],[3] item counters [4] abort
 constexpr int TILE_CHUNK = 8;    // consecutive tiles taken with one atomic increment
 constexpr int DISK_CHUNK = 2;    // consecutive disks taken with one atomic increment
@@ -224,6 +230,14 @@ __global__ __launch_bounds__(BLOCK) void k_batch_particles(const BatchChannel* _
   particle_phase<BLOCK>(ch[blockIdx.x].pa[parity], pp_lds);
 }
 
+// The same for batches holding a channel of more than PERSISTENT_MAX_DISKS disks (per-step
+// schedule only).
+__global__ __launch_bounds__(PP_WIDE) void k_batch_particles_wide(
+    const BatchChannel* __restrict__ ch, int parity) {
+  __shared__ double pp_lds[PP_LDS_WIDE];
+  particle_phase<PP_WIDE>(ch[blockIdx.x].pa[parity], pp_lds);
+}
+
 }  // namespace imb
 
 using namespace imb;
@@ -247,6 +261,7 @@ struct imb_batch {
   int half_n[2] = {0, 0}, half_t[2] = {0, 0}, half_d[2] = {0, 0};
   int all_d = 0, all_t = 0;    // disk items (dparts per disk) and tiles of all channels
   int schedule = IMB_BATCH_PERSISTENT;
+  bool wide = false;          // a channel holds more disks than the persistent kernel takes
   int grid = 0, grid_user = 0, occupancy = 0;
   int tile_w = 32, tile_rows = 2;
   int cur = 0;
@@ -283,10 +298,6 @@ int validate_batch(int32_t nsim, const imb_config* cfgs, std::string* why) {
     if (cfgs[c].storage != IMB_STORAGE_F32) {
       *why = "channel " + std::to_string(c) + ": batched channels use F32 storage";
       return IMB_EUNSUPPORTED;
-    }
-    if (cfgs[c].max_particles > BATCH_MAX_DISKS) {
-      *why = "channel " + std::to_string(c) + ": at most 256 disks per batched channel";
-      return IMB_EINVAL;
     }
     imb_config l = layout_config(cfgs[c]);
     if (validate_config(&l, &w)) {
@@ -345,7 +356,7 @@ int refresh(imb_batch* b) {
       pa.do_finalize = 1;
       pa.do_dem = 1;
       pa.do_table = 1;
-      pa.lds_doubles = PP_LDS;
+      pa.lds_doubles = b->wide ? PP_LDS_WIDE : PP_LDS;
       b->h_ch[c].la[k] = lattice_args(s, v.d->f[k], v.d->f[k ^ 1]);
       b->h_ch[c].pa[k] = pa;
     }
@@ -452,7 +463,11 @@ void enqueue_batch(imb_batch* b, int nsteps, int parity, hipStream_t s) {
       const int par = (parity + n) & 1;
       hipLaunchKernelGGL(k_batch_lattice, dim3(b->all_d + b->all_t), dim3(BLOCK), 0, s, b->d_ch,
                          (const unsigned*)b->d_blk, b->all_d, b->all_t, par);
-      hipLaunchKernelGGL(k_batch_particles, dim3(b->nch), dim3(BLOCK), 0, s, b->d_ch, par);
+      if (b->wide)
+        hipLaunchKernelGGL(k_batch_particles_wide, dim3(b->nch), dim3(PP_WIDE), 0, s, b->d_ch,
+                           par);
+      else
+        hipLaunchKernelGGL(k_batch_particles, dim3(b->nch), dim3(BLOCK), 0, s, b->d_ch, par);
     }
     return;
   }
@@ -595,6 +610,9 @@ int imb_batch_create(int32_t nsim, const imb_config* cfgs, void* hip_stream, voi
   if (!b) return IMB_ENOMEM;
   b->nch = nsim;
   b->stream = (hipStream_t)hip_stream;
+  for (int c = 0; c < nsim; ++c)
+    if (cfgs[c].max_particles > PERSISTENT_MAX_DISKS) b->wide = true;
+  if (b->wide) b->schedule = IMB_BATCH_PER_STEP;
   if (dev_buf) {
     if (dev_bytes < need || ((uintptr_t)dev_buf & 255)) {
       g_batch_error = "bound device buffer too small or not 256-byte aligned";
@@ -750,6 +768,10 @@ int imb_batch_get_launch(imb_batch* b, int32_t* grid, int32_t* tile_w, int32_t* 
 int imb_batch_set_schedule(imb_batch* b, int32_t schedule) {
   if (!b || (schedule != IMB_BATCH_PERSISTENT && schedule != IMB_BATCH_PER_STEP))
     return IMB_EINVAL;
+  if (schedule == IMB_BATCH_PERSISTENT && b->wide) {
+    b->err = "the persistent schedule takes at most 256 disks per channel";
+    return IMB_EUNSUPPORTED;
+  }
   hipStreamSynchronize(b->stream);
   if (schedule != b->schedule) drop_batch_graphs(b);
   b->schedule = schedule;
@@ -808,6 +830,7 @@ int imb_batch_autotune(imb_batch* b, int32_t trial_steps, double* trial_ms, int3
       const int sched = gsel == 0 ? IMB_BATCH_PER_STEP : IMB_BATCH_PERSISTENT;
       const int g = gsel == 2 ? b->occupancy - cu_count : 0;
       if (gsel == 2 && g < cu_count) continue;
+      if (sched == IMB_BATCH_PERSISTENT && b->wide) continue;
       // the disk tables were restored with the state: rebuild them for this trial's shape
       if (set_shape(b, shapes[k][0], shapes[k][1]) != IMB_OK) {  // shape not valid here
         restore();

@@ -492,8 +492,10 @@ def simulation_from_case(case, storage=None, tile_w=64, tile_rows=1, max_particl
 
 
 class Batch:
-    """Independent channels advanced by one persistent kernel per step call (imb_batch_*).
-    Device memory is a torch uint8 tensor owned by this object."""
+    """Independent channels advanced together (imb_batch_*): one persistent kernel per step
+    call, or two launches per step (the per-step schedule, the only one for a batch holding a
+    channel of more than 256 disks).  Device memory is a torch uint8 tensor owned by this
+    object."""
 
     def __init__(self, cfgs, stream=None, device="cuda"):
         import torch

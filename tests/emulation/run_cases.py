@@ -218,6 +218,32 @@ def batch():
     b.step(1)
     b.sync()
     check("batch autotune", True, str(b.launch()))
+    # a channel of 300 small disks, more than the persistent kernel takes: per-step schedule
+    # with the 512-thread particle phase
+    rng = np.random.default_rng(17)
+    x, y, r = W.place_disks(rng, 160, 120, 300, 2.0, 3.0, gap=1.0, wall_gap=1.0)
+    p = W.Particles(x, y, r, rng.normal(0, 0.01, 300), rng.normal(0, 0.01, 300), np.zeros(300),
+                    np.zeros(300, np.int32))
+    cases = [moving_case().with_(nx=160, ny=120, particles=p), moving_case()]
+    b = imb.Batch([imb.config_from_case(c, None, 32, 2, "f32") for c in cases], S, device="cpu")
+    for k, c in enumerate(cases):
+        b.set_case_particles(k, c.particles)
+    refused = False
+    try:
+        b.set_schedule(imb.IMB_BATCH_PERSISTENT)
+    except imb.ImbError:
+        refused = True
+    check("wide batch refuses the persistent schedule", refused and
+          b.launch()["schedule"] == "per_step", "")
+    b.step(2)
+    b.sync()
+    for k, c in enumerate(cases):
+        s = sim_of(c, "f32")
+        s.step(2)
+        same = np.array_equal(b.populations(k), s.populations()) and all(
+            np.array_equal(u, v) for u, v in zip(b.forces(k) + b.particles(k),
+                                                  s.forces() + s.particles()))
+        check("wide batch channel %d equals the channel alone" % k, same, "%d disks" % c.particles.n)
 
 
 def no_allocation_step():
@@ -231,6 +257,29 @@ def no_allocation_step():
             np.array_equal(u, v) for u, v in zip(a.forces() + a.particles(),
                                                   b.forces() + b.particles()))
         check("step_noalloc equals step (%s)" % case.name, same, "")
+
+
+def mask_rounds():
+    """600 tile rows of 256x1 tiles on a 20-wide lattice, more than the 512 rows one round of the
+    particle phase's LDS holds, so the band masks are built in two rounds: disks astride the
+    rounds' boundary (tile row 512) and near both walls, FP64 parity for 3 coupled steps."""
+    xs = np.array([6.0, 15.0, 10.0, 8.0, 12.0])
+    ys = np.array([506.0, 514.5, 521.0, 4.5, 594.0])
+    rs = np.array([4.5, 3.5, 2.5, 3.0, 4.0])
+    p = W.Particles(xs, ys, rs, np.array([0.01, -0.01, 0.0, 0.0, 0.0]),
+                    np.array([0.0, 0.02, -0.01, 0.0, 0.0]), np.zeros(5),
+                    np.array([0, 0, 2, 0, 1], np.int32))
+    case = W.Case("emu_rounds", 20, 600, tau0=0.6, steps=3, gx=1e-5, cs=0.1, particles=p)
+    s = sim_of(case, "f64", (256, 1))
+    s.step(case.steps)
+    ref = oracle_of(case)
+    ref.step(case.steps)
+    fg, fo = np.array(s.forces()), np.array(ref.forces())
+    ferr = np.abs(fg - fo).max() / np.abs(fo).max()
+    perr = np.abs(s.populations() - ref.populations()).max()
+    xerr = max(np.abs(a - b).max() for a, b in zip(s.particles(), ref.particles()))
+    check("fp64 parity, band masks in two rounds", ferr < 1e-12 and perr < 1e-13 and xerr < 1e-12,
+          "force %.2e populations %.2e disks %.2e" % (ferr, perr, xerr))
 
 
 def slab_cases():
@@ -323,7 +372,7 @@ def three_d():
 
 
 ALL = (slab_cases, three_d, no_allocation_step, spring_table_limit, fp64_parity, wide_tiles,
-       reduced_precision, roundtrip, adjoint, batch)
+       reduced_precision, roundtrip, adjoint, batch, mask_rounds)
 
 
 if __name__ == "__main__":

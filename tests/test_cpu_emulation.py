@@ -23,7 +23,7 @@ def _asan_runtime():
 GROUPS = (["fp64_parity:0/2", "slab_cases"],
           ["fp64_parity:1/2", "batch", "roundtrip", "reduced_precision"],
           ["three_d", "adjoint", "spring_table_limit"],
-          ["wide_tiles", "no_allocation_step"])
+          ["wide_tiles", "no_allocation_step", "mask_rounds"])
 
 
 @pytest.mark.skipif(_asan_runtime() is None, reason="g++ with AddressSanitizer not available")

@@ -142,11 +142,17 @@ def test_batch_rejects_invalid():
     c = imb.make_config(64, 32, 0.6, storage="f64")
     with pytest.raises(imb.ImbError):
         imb.Batch([c])
-    c = imb.make_config(64, 32, 0.6, storage="f32", max_particles=300)
+    c = imb.make_config(64, 32, 0.6, storage="f32", max_particles=513)
     with pytest.raises(imb.ImbError):
         imb.Batch([c])
     with pytest.raises(imb.ImbError):
         imb.Batch([])
+    # more disks than the persistent kernel takes: accepted, on the per-step schedule only
+    w = imb.Batch([imb.make_config(64, 32, 0.6, storage="f32", max_particles=300)])
+    assert w.launch()["schedule"] == "per_step"
+    with pytest.raises(imb.ImbError):
+        w.set_schedule(imb.IMB_BATCH_PERSISTENT)
+    w.set_schedule(imb.IMB_BATCH_PER_STEP)
     b = imb.Batch([imb.make_config(64, 32, 0.6, storage="f32")])
     with pytest.raises(imb.ImbError):
         b.set_schedule(2)
@@ -237,3 +243,28 @@ def test_tall_channel_matches_single(schedule):
         s = single(c, (32, 2))
         s.step(9)
         assert_same(b, k, s)
+
+
+def test_channel_of_512_disks_runs_per_step():
+    """A channel of 512 disks (more than the persistent kernel's 256-thread particle phase
+    takes) beside two small ones: the batch starts on the per-step schedule with 512-thread
+    particle phases, refuses the persistent one, and every channel evolves bit for bit as alone,
+    across both buffer parities; the autotuner keeps the per-step schedule."""
+    big = W.moving_disks(seed=5, nx=1536, ny=768, n=512, storage="f32")
+    assert big.particles.n == 512
+    cases = [big, mixed_cases()[0], mixed_cases()[4]]
+    b = imb.batch_from_cases(cases, tile_w=32, tile_rows=2)
+    assert b.launch()["schedule"] == "per_step"
+    with pytest.raises(imb.ImbError):
+        b.set_schedule(imb.IMB_BATCH_PERSISTENT)
+    b.step(7)
+    b.step(4)
+    b.sync()
+    for k, c in enumerate(cases):
+        s = single(c, (32, 2))
+        s.step(11)
+        assert_same(b, k, s)
+    b.autotune(trial_steps=1, max_trials=4)
+    assert b.launch()["schedule"] == "per_step"
+    b.step(2)
+    b.sync()
