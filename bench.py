@@ -240,14 +240,13 @@ def slab_share(storage: str, tile, nslabs: int = 8, steps: int = 200):
             "all_slabs_one_device_ms_per_step": round(all_s * 1e3, 4)}
 
 
-def hbm_control_density(tile, steps: int = 50, nch: int = 32):
-    """The headline's disk density at the HBM-resident size: 32 independent 2048x512 channels of
-    the moving-disk workload with 250 disks each (33.5 M cells and 8000 disks, as many cells as
-    the 8192x4096 control and the 2048x1024 channel's 500 disks per 2.1 M cells; 2.4 GB per
-    population copy), advanced by the batched form's per-step schedule.  Whole-step time per
-    step (HIP events around one graph replay)."""
+def hbm_control_density(tile, steps: int = 50, nch: int = 16):
+    """The headline's disk density at the HBM-resident size: 16 independent 2048x1024 channels
+    of the moving-disk workload with 500 disks each, seeds 0-15 (33.5 M cells and 8000 disks, as
+    many cells as the 8192x4096 control; 2.4 GB per population copy), advanced by the batched
+    form's per-step schedule.  Whole-step time per step (HIP events around one graph replay)."""
     from paper_1809_07008_amd import imb, workloads
-    cases = [workloads.moving_disks(seed=k, nx=2048, ny=512, n=250, storage="f32")
+    cases = [workloads.moving_disks(seed=k, nx=2048, ny=1024, n=500, storage="f32")
              for k in range(nch)]
     cells = sum(c.cells for c in cases)
     b = imb.batch_from_cases(cases, tile_w=tile[0], tile_rows=tile[1])
@@ -255,7 +254,7 @@ def hbm_control_density(tile, steps: int = 50, nch: int = 32):
     b.step(4)
     ms = b.timed_steps(steps) / steps
     b.close()
-    return {"workload": "%d channels of moving_disks_2048x512_n250" % nch, "cells": cells,
+    return {"workload": "%d channels of moving_disks_2048x1024_n500" % nch, "cells": cells,
             "disks": int(sum(c.particles.n for c in cases)), "ms_per_step": round(ms, 4),
             "mlups": round(cells / (ms * 1e-3) / 1e6, 1),
             "whole_step_GBps": round(cells * bytes_per_lup("f32") / (ms * 1e-3) / 1e9, 1),
