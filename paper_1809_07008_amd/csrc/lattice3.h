@@ -125,8 +125,49 @@ __device__ inline T axis_d3(int c, double X, int n, bool periodic) {
 // decomposition): the share of its n^3 sub-cell centres strictly inside.  A cell whose nearest
 // point is not inside gives 0, one whose farthest corner is inside or on the surface gives 1
 // (every sub-cell centre is then strictly inside), so only cut cells count centres.
+// N fixed at compile time: the offsets and each column's x term in registers and every loop
+// unrolled (the general loop reads an offset from LDS per centre).  The same sums and
+// comparisons as the general loop, so the same count.
+template <class T, int N>
+__device__ inline T sphere_subcells_n(T r, T dx, T dy, T dz, const T* off) {
+  const T r2 = r * r;
+  T o[N], x2[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) o[i] = off[i];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const T xc = dx + o[i];
+    x2[i] = xc * xc;
+  }
+  int inside = 0;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const T zc = dz + o[k];
+    const T z2 = zc * zc;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const T yc = dy + o[j];
+      const T yz2 = yc * yc + z2;
+#pragma unroll
+      for (int i = 0; i < N; ++i) inside += x2[i] + yz2 < r2 ? 1 : 0;
+    }
+  }
+  return (T)inside / ((T)N * (T)N * (T)N);
+}
+
 template <class T>
 __device__ __noinline__ T sphere_subcells(T r, T dx, T dy, T dz, int n, const T* off) {
+  switch (n) {
+    case 1: return sphere_subcells_n<T, 1>(r, dx, dy, dz, off);
+    case 2: return sphere_subcells_n<T, 2>(r, dx, dy, dz, off);
+    case 3: return sphere_subcells_n<T, 3>(r, dx, dy, dz, off);
+    case 4: return sphere_subcells_n<T, 4>(r, dx, dy, dz, off);
+    case 5: return sphere_subcells_n<T, 5>(r, dx, dy, dz, off);
+    case 6: return sphere_subcells_n<T, 6>(r, dx, dy, dz, off);
+    case 7: return sphere_subcells_n<T, 7>(r, dx, dy, dz, off);
+    case 8: return sphere_subcells_n<T, 8>(r, dx, dy, dz, off);
+    default: break;
+  }
   const T r2 = r * r;
   int inside = 0;
   for (int k = 0; k < n; ++k) {
