@@ -27,7 +27,7 @@ constexpr int MASK_WORDS = MAX_PARTICLES / 64;  // 64-bit words of a tile row's 
 // slab); on a whole lattice the tiles hide it and one per disk is faster.
 constexpr int DISK_PARTS = 2;
 constexpr int PBLOCK = 512;        // threads of the particle-phase workgroup (one per disk)
-constexpr int HK = 6;         // tangential springs per disk (disks touching it at once)
+constexpr int HK = 8;         // tangential springs per disk (disks touching it at once)
 constexpr double DEM_SKIN = 5.0;   // neighbour-list skin (lattice units)
 constexpr double MAX_MOVE = 1.0;   // largest displacement of a disk in one lattice step
 constexpr float F16_SCALE = 16384.0f;  // power-of-two scale of FP16 deviations

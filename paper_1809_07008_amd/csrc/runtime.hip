@@ -158,7 +158,8 @@ std::string describe_device_error(int bits) {
   if (bits & ERR_NBR) s += "DEM neighbour list overflow; ";
   if (bits & ERR_MOVE) s += "a disk moved more than one cell in one step; ";
   if (bits & ERR_LEFT) s += "a disk centre left the channel; ";
-  if (bits & ERR_CONTACTS) s += "a disk touches more than 6 others at once; ";
+  if (bits & ERR_CONTACTS)
+    s += "a disk touches more than " + std::to_string(HK) + " others at once; ";
   return s;
 }
 

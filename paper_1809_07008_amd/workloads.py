@@ -179,7 +179,7 @@ def frictional_disks(rows: int = 6, walls: bool = True, steps: int = 4, kt: floa
 def crowded_disk(n_small: int = 7, kt: float = 10.0, mu: float = 0.3) -> Case:
     """64x48 channel with walls: a free disk of radius 6 at (32, 24) and n_small free disks of
     radius 2 around it, centres 7.95 away at equal angles, each overlapping it by 0.05 (and
-    apart from one another); with seven or more the large disk has more simultaneous contacts
+    apart from one another, up to nine); with nine the large disk has more simultaneous contacts
     than its tangential spring table holds."""
     a = 2.0 * np.pi * np.arange(n_small) / n_small
     x = [32.0] + list(32.0 + 7.95 * np.cos(a))

@@ -103,24 +103,24 @@ def fp64_parity(part=(0, 1)):
 
 
 def spring_table_limit():
-    """Six simultaneous tangential contacts fit a disk's spring table; a seventh latches the
+    """Eight simultaneous tangential contacts fit a disk's spring table; a ninth latches the
     device error."""
-    case = W.crowded_disk(6)
+    case = W.crowded_disk(8)
     s = sim_of(case, "f64")
     s.step(case.steps)
     ref = oracle_of(case)
     ref.step(case.steps)
     kerr = np.abs(np.array(s.particles()) - np.array(ref.particles())).max()
-    check("six tangential contacts on one disk", kerr < 1e-12, "disks %.2e" % kerr)
-    seven = W.crowded_disk(7)
+    check("eight tangential contacts on one disk", kerr < 1e-12, "disks %.2e" % kerr)
+    nine = W.crowded_disk(9)
     try:
-        s = sim_of(seven, "f64")
+        s = sim_of(nine, "f64")
         s.step(1)
         s.sync()
         msg = None
     except imb.ImbError as e:
         msg = "%d %s" % (e.code, e)
-    check("a seventh latches the device error", msg is not None and "more than 6" in msg,
+    check("a ninth latches the device error", msg is not None and "more than 8" in msg,
           str(msg))
 
 

@@ -282,21 +282,21 @@ def test_error_paths():
 
 
 def test_tangential_spring_table_limit():
-    """Six simultaneous tangential contacts per disk fit its spring table (parity with the
-    oracle); a seventh is reported as a device error, and without friction there is no limit."""
-    six = W.crowded_disk(6).with_(storage="f64")
-    sim, ref = gpu_for(six), oracle_for(six)
-    sim.step(six.steps)
-    ref.step(six.steps)
+    """Eight simultaneous tangential contacts per disk fit its spring table (parity with the
+    oracle); a ninth is reported as a device error, and without friction there is no limit."""
+    eight = W.crowded_disk(8).with_(storage="f64")
+    sim, ref = gpu_for(eight), oracle_for(eight)
+    sim.step(eight.steps)
+    ref.step(eight.steps)
     assert_parity(sim, ref)
-    seven = W.crowded_disk(7).with_(storage="f64")
-    sim = imb.simulation_from_case(seven.with_(particles=W.Particles.empty()), max_particles=8)
+    nine = W.crowded_disk(9).with_(storage="f64")
+    sim = imb.simulation_from_case(nine.with_(particles=W.Particles.empty()), max_particles=10)
     with pytest.raises(imb.ImbError) as e:
-        sim.set_case_particles(seven.particles)
+        sim.set_case_particles(nine.particles)
         sim.step(1)
         sim.sync()
-    assert e.value.code == -4 and "more than 6" in str(e.value)
-    plain = seven.with_(kt=0.0, mu=0.0)
+    assert e.value.code == -4 and "more than 8" in str(e.value)
+    plain = nine.with_(kt=0.0, mu=0.0)
     sim, ref = gpu_for(plain), oracle_for(plain)
     sim.step(plain.steps)
     ref.step(plain.steps)
