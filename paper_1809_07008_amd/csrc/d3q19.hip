@@ -308,6 +308,17 @@ __global__ __launch_bounds__(BLOCK) void k_step3(Lattice3Args a) {
 __global__ __launch_bounds__(BLOCK) void k_finalize3(Lattice3Args a) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int tw = 1 << a.tw_log;
+  // this thread's first sphere's mode, position and velocity and the list's count, loaded beside
+  // the sums' loads (nothing writes them before the barrier below)
+  const int p0 = threadIdx.x;
+  int mode0 = IMB_MODE_FIXED;
+  double4 ps0 = make_double4(0.0, 0.0, 0.0, 0.0), v0 = ps0;
+  if (p0 < a.np) {
+    mode0 = a.mode[p0];
+    ps0 = a.pos[p0];
+    v0 = a.vel[p0];
+  }
+  const int count0 = threadIdx.x == 0 ? *a.sph_count : 0;
   for (int p = wave; p < a.np; p += WAVES) {
     const double4 ps = a.pos[p];
     const Box3 bx = sphere_box3(ps.x, ps.y, ps.z, ps.w, a.nx, a.ny, a.nz, a.walls, tw, a.th,
@@ -331,9 +342,10 @@ __global__ __launch_bounds__(BLOCK) void k_finalize3(Lattice3Args a) {
   }
   __syncthreads();  // every box of this step is read before a sphere moves
   for (int p = threadIdx.x; p < a.np; p += blockDim.x) {
-    if (a.mode[p] != IMB_MODE_PRESCRIBED) continue;
-    double4 ps = a.pos[p];
-    const double4 v = a.vel[p];
+    const bool first = p == p0;
+    if ((first ? mode0 : a.mode[p]) != IMB_MODE_PRESCRIBED) continue;
+    double4 ps = first ? ps0 : a.pos[p];
+    const double4 v = first ? v0 : a.vel[p];
     double nxp = ps.x + v.x, nyp = ps.y + v.y, nzp = ps.z + v.z;
     nxp = nxp >= a.nx ? nxp - a.nx : (nxp < 0.0 ? nxp + a.nx : nxp);
     nzp = nzp >= a.nz ? nzp - a.nz : (nzp < 0.0 ? nzp + a.nz : nzp);
@@ -348,7 +360,7 @@ __global__ __launch_bounds__(BLOCK) void k_finalize3(Lattice3Args a) {
     a.pos[p] = ps;
   }
   if (threadIdx.x == 0) {  // the sphere tiles of this step are done: clear the list
-    if (*a.sph_count > a.sph_grid) atomicOr(a.err, ERR_TILE_LIST);
+    if (count0 > a.sph_grid) atomicOr(a.err, ERR_TILE_LIST);
     *a.sph_count = 0;
   }
 }
